@@ -1,0 +1,213 @@
+"""TEST INFRASTRUCTURE ONLY -- Python access to the oracle.
+
+The oracle is a plain FP64 C++ reference (``lbm_oracle.cpp``) of the D2Q9 BGK step with
+half-way bounce-back and the per-step forces of Kaushal, Succi & Ansumali,
+arXiv:2210.10377 (Sec. II-IV and the Appendix).  Only ``tests/``, the smoke check and
+the CPU-baseline leg of the benchmark may import this package; the product package
+never does, and the two share no code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+BCX_INLET_OUTLET, BCX_PERIODIC = 0, 1
+BCY_WALL, BCY_PERIODIC = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no FMA contraction, so that it is plain IEEE)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-shared",
+                               "-fPIC", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_x", ctypes.c_int32),
+                ("bc_y", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
+                ("rho_w", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        u8 = ctypes.POINTER(ctypes.c_uint8)
+        cp = ctypes.POINTER(_Cfg)
+        L.orc_lattice.argtypes = [ip, ip, ip, dp, dp]
+        L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
+        L.orc_collide_node.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_box_admissible.argtypes = [cp, u8]
+        L.orc_box_admissible.restype = ctypes.c_int
+        L.orc_links.argtypes = [cp, u8, ip, ctypes.c_int64]
+        L.orc_links.restype = ctypes.c_int64
+        L.orc_create.argtypes = [cp, u8, ctypes.c_double, dp]
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        for name in ("orc_set_state", "orc_get_state", "orc_get_pre", "orc_records",
+                     "orc_forces"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, dp]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.orc_nrec.argtypes = [ctypes.c_void_p]
+        L.orc_nrec.restype = ctypes.c_int64
+        L.orc_clear_records.argtypes = [ctypes.c_void_p]
+        L.orc_momentum_of.argtypes = [ctypes.c_void_p, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g):
+    c = _Cfg()
+    c.nx, c.ny, c.bc_x, c.bc_y = int(nx), int(ny), int(bc_x), int(bc_y)
+    b = (-1, -1, -1, -1) if box is None else tuple(int(v) for v in box)
+    for k in range(4):
+        c.box[k] = b[k]
+    c.rho_w = float(rho_w)
+    c.gx, c.gy = float(g[0]), float(g[1])
+    return c
+
+
+def lattice():
+    """(cx, cy, opp, w, theta0) as the oracle holds them."""
+    cx = np.zeros(9, np.int32)
+    cy = np.zeros(9, np.int32)
+    opp = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    th = np.zeros(1)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib().orc_lattice(cx.ctypes.data_as(ip), cy.ctypes.data_as(ip), opp.ctypes.data_as(ip),
+                      _dp(w), _dp(th))
+    return cx, cy, opp, w, float(th[0])
+
+
+def equilibrium(rho, ux, uy):
+    out = np.zeros(9)
+    lib().orc_equilibrium(float(rho), float(ux), float(uy), _dp(out))
+    return out
+
+
+def collide_node(f, omega, g=(0.0, 0.0)):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), _dp(out))
+    return out
+
+
+def _mask(mask):
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def box_admissible(mask, box, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL):
+    m, mp = _mask(mask)
+    ny, nx = m.shape
+    c = _cfg(nx, ny, bc_x, bc_y, box, 1.0, (0.0, 0.0))
+    return bool(lib().orc_box_admissible(ctypes.byref(c), mp))
+
+
+def links(mask, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL):
+    """Canonical fluid-solid links as an int32 array [L, 2] of (y*nx + x, i)."""
+    m, mp = _mask(mask)
+    ny, nx = m.shape
+    c = _cfg(nx, ny, bc_x, bc_y, None, 1.0, (0.0, 0.0))
+    n = lib().orc_links(ctypes.byref(c), mp, None, 0)
+    if n < 0:
+        raise ValueError("invalid configuration")
+    out = np.zeros((max(n, 1), 2), np.int32)
+    lib().orc_links(ctypes.byref(c), mp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n)
+    return out[:n]
+
+
+class OracleSim:
+    """FP64 reference simulation.  ``tau`` is the lattice relaxation time tau_lb
+    (omega = 1/tau_lb); pass ``omega`` directly for the pure-streaming fixture
+    (omega = 0)."""
+
+    def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL,
+                 box=None, rho_w=1.0, g=(0.0, 0.0), omega=None):
+        m, mp = _mask(mask)
+        self.ny, self.nx = m.shape
+        if omega is None:
+            omega = 1.0 / float(tau)
+        self.omega = float(omega)
+        self.box = box
+        self._cfg = _cfg(self.nx, self.ny, bc_x, bc_y, box, rho_w, g)
+        u = None
+        if uin is not None:
+            self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),
+                                                             (self.ny,)))
+            u = _dp(self._uin)
+        self._h = lib().orc_create(ctypes.byref(self._cfg), mp, self.omega, u)
+        if not self._h:
+            raise ValueError("oracle rejected the configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    @property
+    def shape(self):
+        return (9, self.ny, self.nx)
+
+    def set_state(self, S):
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(self.shape)
+        lib().orc_set_state(self._h, _dp(S))
+
+    def state(self):
+        out = np.zeros(self.shape)
+        lib().orc_get_state(self._h, _dp(out))
+        return out
+
+    def pre(self):
+        out = np.zeros(self.shape)
+        lib().orc_get_pre(self._h, _dp(out))
+        return out
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    def records(self):
+        n = lib().orc_nrec(self._h)
+        out = np.zeros((n, 8))
+        if n:
+            lib().orc_records(self._h, _dp(out))
+        return out
+
+    def forces(self):
+        """[t, scheme (A, B, DRTT), component (x, y)] of every recorded step."""
+        n = lib().orc_nrec(self._h)
+        out = np.zeros((n, 3, 2))
+        if n:
+            lib().orc_forces(self._h, _dp(out))
+        return out
+
+    def clear_records(self):
+        lib().orc_clear_records(self._h)
+
+    def momentum_of(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.shape)
+        J = np.zeros(2)
+        lib().orc_momentum_of(self._h, _dp(g), _dp(J))
+        return J

@@ -1,0 +1,440 @@
+// TEST INFRASTRUCTURE ONLY -- the oracle.
+//
+// A plain, slow reference of the D2Q9 lattice Boltzmann time step with half-way
+// bounce-back and the three per-step flow-force estimators of Kaushal, Succi &
+// Ansumali, "Flow force calculation in Lattice Boltzmann Method" (arXiv:2210.10377):
+// momentum exchange under algorithm A and algorithm B (Sec. IV, Eq. rtt4/rtt5) and the
+// discrete Reynolds-transport-theorem control-volume force DRTT (Sec. IV, second
+// Eq. rtt7; Appendix).
+//
+// Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark load
+// this library.  The product (the HIP library) never links, calls or reads it, and the
+// two share no code, tables or constants.
+//
+// Everything is written as loops over nodes (y, x) and directions i in the order the
+// paper's Appendix gives for one time step.  No blocking, no fusion, no reordering.
+// The scalar type is a template parameter, so the same code runs in
+// std::complex<double> for complex-step derivatives.  Build with
+//   g++ -O2 -ffp-contract=off -shared -fPIC
+//
+// Readings of passages where the paper is silent or ambiguous (all documented with the
+// design notes of the repository):
+//  * node (x, y) sits at the point (x, y); directions are numbered
+//      0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1);
+//  * tau is the lattice relaxation time tau_lb = tau_paper + 1/2, so that the factor
+//    2*beta = 2/(2*tau_paper + 1) of Eq. CollideAdv equals omega = 1/tau_lb;
+//  * the stored state is the post-collision field; one step pulls it (streaming with
+//    the boundary rules), records J over the control volume from the pulled,
+//    pre-collision populations (Appendix: "before collide"), collides, and evaluates
+//    the forces;
+//  * pull rules, first match wins: periodic wrap > no-slip wall > inlet > outlet >
+//    body bounce-back > plain streaming;
+//  * the inlet is the moving-wall bounce-back of Sec. II at x = -1/2 with wall
+//    velocity (u_in(y), 0) and wall density rho_w;
+//  * the outlet copies the post-collision populations of column nx-1 into a ghost
+//    column nx (zero gradient);
+//  * algorithm A uses the pre-collision outgoing population f_i(x,t) in the lost
+//    momentum, algorithm B the post-collision one (Eq. rtt4); both use the populations
+//    returned by the boundary at t+1 for the gained momentum (Eq. rtt3);
+//  * a population crosses a surface when its streaming link crosses it (the normal
+//    tests "c.n > 0" / "c.n <= 0" of Eq. rtt3-rtt7 read as link crossings);
+//  * the control volume V is the set of fluid nodes in the half-open box
+//    [x0, x1) x [y0, y1).
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Lattice: D2Q9 velocity set and weights (Sec. II, Table I), theta0 = 1/3.
+// ---------------------------------------------------------------------------------
+const int NQ = 9;
+const int CX[NQ] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int CY[NQ] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double W[NQ] = {16.0 / 36.0, 4.0 / 36.0, 4.0 / 36.0, 4.0 / 36.0, 4.0 / 36.0,
+                      1.0 / 36.0,  1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+const double THETA0 = 1.0 / 3.0;
+
+// Direction opposite to i (Sec. II, bounce-back), found by search over the table.
+int opposite(int i) {
+  for (int k = 0; k < NQ; ++k)
+    if (CX[k] == -CX[i] && CY[k] == -CY[i]) return k;
+  return -1;
+}
+
+enum { BCX_INLET_OUTLET = 0, BCX_PERIODIC = 1 };
+enum { BCY_WALL = 0, BCY_PERIODIC = 1 };
+
+// Second-order equilibrium (Sec. II):
+//   f_i^eq = w_i rho [1 + (u.c_i)/theta0 + ((u.c_i)^2 - theta0 u^2) / (2 theta0^2)].
+template <class T>
+T equilibrium(int i, T rho, T ux, T uy) {
+  T cu = double(CX[i]) * ux + double(CY[i]) * uy;
+  T usq = ux * ux + uy * uy;
+  return W[i] * rho *
+         (1.0 + cu / THETA0 + (cu * cu - THETA0 * usq) / (2.0 * THETA0 * THETA0));
+}
+
+// One node of the BGK collision, Eq. CollideAdv (first line):
+//   f~_i = f_i + 2 beta (f_i^eq(rho, u) - f_i),  rho = sum f_i, rho u = sum c_i f_i
+// (Sec. II, moments).  2 beta is passed as omega.  When a body force g is given (test
+// fixtures only; the paper has none) the Guo, Zheng & Shi (2002) forcing is added:
+//   u = (sum c_i f_i + g/2) / rho,  extra term (1 - omega/2) w_i [3(c_i - u) + 9 (c_i.u) c_i].g
+template <class T>
+void collide_node(const T* f, T omega, double gx, double gy, T* out) {
+  T rho = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    jx += double(CX[i]) * f[i];
+    jy += double(CY[i]) * f[i];
+  }
+  T ux = (jx + 0.5 * gx) / rho;
+  T uy = (jy + 0.5 * gy) / rho;
+  for (int i = 0; i < NQ; ++i) {
+    out[i] = f[i] + omega * (equilibrium<T>(i, rho, ux, uy) - f[i]);
+    if (gx != 0.0 || gy != 0.0) {
+      T cu = double(CX[i]) * ux + double(CY[i]) * uy;
+      T fx = 3.0 * (double(CX[i]) - ux) + 9.0 * cu * double(CX[i]);
+      T fy = 3.0 * (double(CY[i]) - uy) + 9.0 * cu * double(CY[i]);
+      out[i] += (1.0 - 0.5 * omega) * W[i] * (fx * gx + fy * gy);
+    }
+  }
+}
+
+struct Config {
+  int32_t nx, ny, bc_x, bc_y;
+  int32_t box[4];  // x0, x1, y0, y1; x0 < 0 means no control volume
+  double rho_w;    // inlet wall density
+  double gx, gy;   // body force (test fixtures only)
+};
+
+template <class T>
+struct Sim {
+  Config cfg;
+  std::vector<uint8_t> solid;  // [ny][nx]
+  std::vector<T> uin;          // [ny]
+  T omega;
+  std::vector<T> S;   // post-collision state of the last step, [9][ny][nx]
+  std::vector<T> f;   // pulled (pre-collision) populations of the last step
+  std::vector<T> Sn;  // scratch for the next state
+  // per-step records: FA(2), FB(2), J(2), Phi(2)
+  std::vector<T> rec;
+
+  int nx() const { return cfg.nx; }
+  int ny() const { return cfg.ny; }
+  size_t idx(int i, int x, int y) const {
+    return (size_t(i) * cfg.ny + size_t(y)) * cfg.nx + size_t(x);
+  }
+  bool is_solid(int x, int y) const { return solid[size_t(y) * cfg.nx + x] != 0; }
+  bool in_box(int x, int y) const {
+    return cfg.box[0] >= 0 && x >= cfg.box[0] && x < cfg.box[1] && y >= cfg.box[2] &&
+           y < cfg.box[3];
+  }
+  // V: the fluid nodes inside the control-volume box.
+  bool in_V(int x, int y) const { return in_box(x, y) && !is_solid(x, y); }
+
+  // Population arriving at fluid node (x, y) in direction i, pulled from state St
+  // (streaming, Eq. CollideAdv second line) with the boundary rules in the order
+  // periodic > wall > inlet > outlet > body > stream.
+  T pull(const std::vector<T>& St, int x, int y, int i) const {
+    const int o = opposite(i);
+    int sx = x - CX[i], sy = y - CY[i];
+    if (cfg.bc_x == BCX_PERIODIC) sx = (sx + cfg.nx) % cfg.nx;
+    if (cfg.bc_y == BCY_PERIODIC) sy = (sy + cfg.ny) % cfg.ny;
+    // No-slip wall half-way between rows -1|0 and ny-1|ny: stationary-wall
+    // bounce-back (Sec. II).
+    if (cfg.bc_y == BCY_WALL && (sy < 0 || sy >= cfg.ny)) return St[idx(o, x, y)];
+    // Inlet at x = -1/2: moving-wall bounce-back (Sec. II) with u_w = (u_in(y), 0).
+    // The population leaving towards the wall is o; the one returned is i:
+    //   f~_i(x, t+1) = f~_o(x, t) - 2 w_o rho_w (c_o . u_w) / c_s^2,  c_s^2 = theta0.
+    if (cfg.bc_x == BCX_INLET_OUTLET && sx < 0) {
+      T cu = double(CX[o]) * uin[y];
+      return St[idx(o, x, y)] - 2.0 * W[o] * cfg.rho_w * cu / THETA0;
+    }
+    // Outlet at x = nx - 1/2: ghost column nx holds a copy of column nx-1.
+    if (cfg.bc_x == BCX_INLET_OUTLET && sx >= cfg.nx) {
+      if (is_solid(cfg.nx - 1, sy)) return St[idx(o, x, y)];
+      return St[idx(i, cfg.nx - 1, sy)];
+    }
+    // Body: stationary-wall half-way bounce-back (Sec. II).
+    if (is_solid(sx, sy)) return St[idx(o, x, y)];
+    return St[idx(i, sx, sy)];
+  }
+
+  // Fluid node (x, y) and direction i form a fluid-solid link when x + c_i is a body
+  // node (Sec. III, momentum exchange; Fig. 1 caption: boundary point half-way along
+  // the link).  Periodic axes wrap; leaving the domain along a bounded axis is not a
+  // body link (walls, inlet and outlet are not part of the body).
+  bool is_link(int x, int y, int i) const {
+    if (i == 0 || is_solid(x, y)) return false;
+    int tx = x + CX[i], ty = y + CY[i];
+    if (cfg.bc_x == BCX_PERIODIC) tx = (tx + cfg.nx) % cfg.nx;
+    if (cfg.bc_y == BCY_PERIODIC) ty = (ty + cfg.ny) % cfg.ny;
+    if (tx < 0 || tx >= cfg.nx || ty < 0 || ty >= cfg.ny) return false;
+    return is_solid(tx, ty);
+  }
+
+  // Control-volume momentum J^Omega (Eq. rtt1) of a population field.
+  void box_momentum(const std::vector<T>& g, T* J) const {
+    J[0] = 0.0;
+    J[1] = 0.0;
+    for (int y = 0; y < cfg.ny; ++y)
+      for (int x = 0; x < cfg.nx; ++x) {
+        if (!in_V(x, y)) continue;
+        for (int i = 0; i < NQ; ++i) {
+          J[0] += double(CX[i]) * g[idx(i, x, y)];
+          J[1] += double(CY[i]) * g[idx(i, x, y)];
+        }
+      }
+  }
+
+  void stream_all(const std::vector<T>& St, std::vector<T>& out) const {
+    for (int y = 0; y < cfg.ny; ++y)
+      for (int x = 0; x < cfg.nx; ++x) {
+        if (is_solid(x, y)) continue;
+        for (int i = 0; i < NQ; ++i) out[idx(i, x, y)] = pull(St, x, y, i);
+      }
+  }
+
+  // One time step (Appendix order): J(t) before collision, collide, boundary flux
+  // through the control-volume surface, advection with bounce-back, MEA forces.
+  void step() {
+    const int nx = cfg.nx, ny = cfg.ny;
+    // Streaming of the previous post-collision state gives f(., t).
+    stream_all(S, f);
+    // Control-volume momentum before collision (Appendix).
+    T J[2];
+    box_momentum(f, J);
+    // Collision of the entire fluid domain (Eq. CollideAdv, first line).
+    Sn = S;  // body nodes keep whatever they hold; it is never read
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        if (is_solid(x, y)) continue;
+        T fin[NQ], fout[NQ];
+        for (int i = 0; i < NQ; ++i) fin[i] = f[idx(i, x, y)];
+        collide_node<T>(fin, omega, cfg.gx, cfg.gy, fout);
+        for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y)] = fout[i];
+      }
+    // Momentum exchange on every fluid-solid link (Sec. III; Eq. rtt4, rtt5):
+    // lost momentum c_i f_i (A: pre-collision) or c_i f~_i (B: post-collision) plus
+    // the momentum -c_o f_o(x, t+1) = c_i f_o(x, t+1) returned by the boundary.
+    T FA[2] = {0.0, 0.0}, FB[2] = {0.0, 0.0};
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        for (int i = 1; i < NQ; ++i) {
+          if (!is_link(x, y, i)) continue;
+          const int o = opposite(i);
+          T back = pull(Sn, x, y, o);  // f_o(x, t+1)
+          FA[0] += double(CX[i]) * (f[idx(i, x, y)] + back);
+          FA[1] += double(CY[i]) * (f[idx(i, x, y)] + back);
+          FB[0] += double(CX[i]) * (Sn[idx(i, x, y)] + back);
+          FB[1] += double(CY[i]) * (Sn[idx(i, x, y)] + back);
+        }
+    // DRTT surface terms on the outer surface of the control volume (second Eq. rtt7):
+    //  + populations f~_i(x - c_i, t) entering a node x of V from outside V,
+    //  - populations f~_i(x, t) leaving a node x of V for a node outside V.
+    T Phi[2] = {0.0, 0.0};
+    if (cfg.box[0] >= 0) {
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          if (!in_V(x, y)) continue;
+          for (int i = 1; i < NQ; ++i) {
+            int ux = x - CX[i], uy = y - CY[i];  // upstream node
+            if (!in_box(ux, uy)) {
+              Phi[0] += double(CX[i]) * Sn[idx(i, ux, uy)];
+              Phi[1] += double(CY[i]) * Sn[idx(i, ux, uy)];
+            }
+            int dx = x + CX[i], dy = y + CY[i];  // downstream node
+            if (!in_box(dx, dy)) {
+              Phi[0] -= double(CX[i]) * Sn[idx(i, x, y)];
+              Phi[1] -= double(CY[i]) * Sn[idx(i, x, y)];
+            }
+          }
+        }
+    }
+    S.swap(Sn);
+    const T r[8] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1], Phi[0], Phi[1]};
+    rec.insert(rec.end(), r, r + 8);
+  }
+
+  // Forces of every recorded step: [t][scheme A, B, DRTT][x, y].  DRTT (second
+  // Eq. rtt7): F(t) = J(t) - J(t+1) + Phi(t); the J of the step after the last recorded
+  // one is the control-volume momentum of the populations the next pull would give.
+  void forces(T* out) const {
+    const size_t n = rec.size() / 8;
+    T Jlast[2] = {0.0, 0.0};
+    if (cfg.box[0] >= 0) {
+      std::vector<T> g(S.size(), T(0.0));
+      stream_all(S, g);
+      box_momentum(g, Jlast);
+    }
+    for (size_t t = 0; t < n; ++t) {
+      const T* r = &rec[8 * t];
+      T* o = out + 6 * t;
+      o[0] = r[0];
+      o[1] = r[1];
+      o[2] = r[2];
+      o[3] = r[3];
+      if (cfg.box[0] >= 0) {
+        T jx1 = (t + 1 < n) ? rec[8 * (t + 1) + 4] : Jlast[0];
+        T jy1 = (t + 1 < n) ? rec[8 * (t + 1) + 5] : Jlast[1];
+        o[4] = r[4] - jx1 + r[6];
+        o[5] = r[5] - jy1 + r[7];
+      } else {
+        o[4] = NAN;
+        o[5] = NAN;
+      }
+    }
+  }
+};
+
+// Admissible control volume: the box lies at least one node inside the domain on
+// every side, and every body node lies strictly inside it with a fluid ring between
+// the body and the box surface (so every fluid-solid link is inside V and no
+// population crossing the box surface comes from a boundary rule).
+bool box_admissible(const Config& c, const uint8_t* mask) {
+  if (c.box[0] < 0) return true;
+  const int x0 = c.box[0], x1 = c.box[1], y0 = c.box[2], y1 = c.box[3];
+  if (x0 < 1 || y0 < 1 || x1 > c.nx - 1 || y1 > c.ny - 1 || x1 - x0 < 3 || y1 - y0 < 3)
+    return false;
+  for (int y = 0; y < c.ny; ++y)
+    for (int x = 0; x < c.nx; ++x)
+      if (mask[size_t(y) * c.nx + x] &&
+          !(x >= x0 + 1 && x < x1 - 1 && y >= y0 + 1 && y < y1 - 1))
+        return false;
+  return true;
+}
+
+bool config_valid(const Config& c, const uint8_t* mask) {
+  if (c.nx < 2 || c.ny < 2) return false;
+  if (c.bc_x != BCX_INLET_OUTLET && c.bc_x != BCX_PERIODIC) return false;
+  if (c.bc_y != BCY_WALL && c.bc_y != BCY_PERIODIC) return false;
+  for (size_t k = 0; k < size_t(c.nx) * c.ny; ++k)
+    if (mask[k] > 1) return false;
+  return box_admissible(c, mask);
+}
+
+template <class T>
+Sim<T>* make_sim(const Config* c, const uint8_t* mask, T omega) {
+  if (!config_valid(*c, mask)) return nullptr;
+  Sim<T>* s = new Sim<T>();
+  s->cfg = *c;
+  const size_t n = size_t(c->nx) * c->ny;
+  s->solid.assign(mask, mask + n);
+  s->uin.assign(c->ny, T(0.0));
+  s->omega = omega;
+  s->S.assign(NQ * n, T(0.0));
+  // Start from rest: every node holds the zero-velocity equilibrium w_i at rho = 1.
+  for (int i = 0; i < NQ; ++i)
+    for (size_t k = 0; k < n; ++k) s->S[size_t(i) * n + k] = W[i];
+  s->f = s->S;
+  s->Sn = s->S;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+typedef Config orc_cfg;
+
+// Lattice tables of the oracle (for pins against the paper's Table I).
+void orc_lattice(int32_t* cx, int32_t* cy, int32_t* opp, double* w, double* theta0) {
+  for (int i = 0; i < NQ; ++i) {
+    cx[i] = CX[i];
+    cy[i] = CY[i];
+    opp[i] = opposite(i);
+    w[i] = W[i];
+  }
+  *theta0 = THETA0;
+}
+
+void orc_equilibrium(double rho, double ux, double uy, double* feq) {
+  for (int i = 0; i < NQ; ++i) feq[i] = equilibrium<double>(i, rho, ux, uy);
+}
+
+void orc_collide_node(const double* f, double omega, double gx, double gy, double* out) {
+  collide_node<double>(f, omega, gx, gy, out);
+}
+
+int orc_box_admissible(const orc_cfg* c, const uint8_t* mask) {
+  return box_admissible(*c, mask) ? 1 : 0;
+}
+
+// Canonical list of fluid-solid links: pairs (y*nx + x, i), sorted by node index then
+// direction.  Returns the number of links (or -1 on an invalid configuration); writes
+// at most cap pairs.
+int64_t orc_links(const orc_cfg* c, const uint8_t* mask, int32_t* out, int64_t cap) {
+  Sim<double>* s = make_sim<double>(c, mask, 1.0);
+  if (!s) return -1;
+  int64_t n = 0;
+  for (int y = 0; y < c->ny; ++y)
+    for (int x = 0; x < c->nx; ++x)
+      for (int i = 1; i < NQ; ++i)
+        if (s->is_link(x, y, i)) {
+          if (n < cap) {
+            out[2 * n] = int32_t(y * c->nx + x);
+            out[2 * n + 1] = i;
+          }
+          ++n;
+        }
+  delete s;
+  return n;
+}
+
+void* orc_create(const orc_cfg* c, const uint8_t* mask, double omega, const double* uin) {
+  Sim<double>* s = make_sim<double>(c, mask, omega);
+  if (!s) return nullptr;
+  if (uin)
+    for (int y = 0; y < c->ny; ++y) s->uin[y] = uin[y];
+  return s;
+}
+
+void orc_destroy(void* h) { delete static_cast<Sim<double>*>(h); }
+
+void orc_set_state(void* h, const double* S) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  std::memcpy(s->S.data(), S, s->S.size() * sizeof(double));
+}
+
+void orc_get_state(void* h, double* S) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  std::memcpy(S, s->S.data(), s->S.size() * sizeof(double));
+}
+
+// Pre-collision populations f(., t) of the last step (pulled state).
+void orc_get_pre(void* h, double* f) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  std::memcpy(f, s->f.data(), s->f.size() * sizeof(double));
+}
+
+void orc_step(void* h, int32_t n) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  for (int32_t k = 0; k < n; ++k) s->step();
+}
+
+int64_t orc_nrec(void* h) { return int64_t(static_cast<Sim<double>*>(h)->rec.size() / 8); }
+
+// Raw per-step records [t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy].
+void orc_records(void* h, double* out) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  std::memcpy(out, s->rec.data(), s->rec.size() * sizeof(double));
+}
+
+// Forces [t][A, B, DRTT][x, y] of all recorded steps.
+void orc_forces(void* h, double* out) { static_cast<Sim<double>*>(h)->forces(out); }
+
+void orc_clear_records(void* h) { static_cast<Sim<double>*>(h)->rec.clear(); }
+
+// Control-volume momentum of an arbitrary population field g (Eq. rtt1).
+void orc_momentum_of(void* h, const double* g, double* J) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  std::vector<double> v(g, g + s->S.size());
+  s->box_momentum(v, J);
+}
+
+}  // extern "C"

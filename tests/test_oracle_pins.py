@@ -1,0 +1,570 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Kaushal, Succi & Ansumali, arXiv:2210.10377.  Each test names the passage it checks.
+None of these compares the oracle with itself: they use exact rationals, closed forms,
+conservation laws, brute-force tracking of single populations, Newton's law for the
+whole fluid, and the worked one-dimensional example of the introduction.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import BCX_INLET_OUTLET, BCX_PERIODIC, BCY_PERIODIC, BCY_WALL, OracleSim
+
+
+# --------------------------------------------------------------------------------------
+# Lattice and equilibrium (Sec. II, Table I and the moment conditions)
+# --------------------------------------------------------------------------------------
+
+def test_lattice_matches_table_I(orc):
+    cx, cy, opp, w, th = orc.lattice()
+    shells = {}
+    for i in range(9):
+        shells.setdefault(int(cx[i] ** 2 + cy[i] ** 2), []).append((int(cx[i]), int(cy[i]), w[i]))
+    assert sorted((a, b) for a, b, _ in shells[0]) == [(0, 0)]
+    assert sorted((a, b) for a, b, _ in shells[1]) == sorted([(1, 0), (-1, 0), (0, 1), (0, -1)])
+    assert sorted((a, b) for a, b, _ in shells[2]) == sorted([(1, 1), (1, -1), (-1, 1), (-1, -1)])
+    for s, wt in ((0, Fraction(16, 36)), (1, Fraction(4, 36)), (2, Fraction(1, 36))):
+        for _, _, wi in shells[s]:
+            assert wi == float(wt)
+    assert th == float(Fraction(1, 3))
+    for i in range(9):
+        assert cx[opp[i]] == -cx[i] and cy[opp[i]] == -cy[i]
+
+
+def test_weight_moment_conditions_exact(orc):
+    """Sum w = 1, sum w c_a c_b = theta0 delta_ab, sum w c_a c_b c_c c_d = theta0^2 Delta
+    (Sec. II), in exact rational arithmetic on the weights the oracle holds."""
+    cx, cy, _, w, _ = orc.lattice()
+    wf = [Fraction(x).limit_denominator(36) for x in w]
+    for a, b in zip(wf, w):
+        assert float(a) == b
+    c = list(zip(cx.tolist(), cy.tolist()))
+    th = Fraction(1, 3)
+    assert sum(wf) == 1
+    for a in range(2):
+        assert sum(wf[i] * c[i][a] for i in range(9)) == 0
+        for b in range(2):
+            assert sum(wf[i] * c[i][a] * c[i][b] for i in range(9)) == (th if a == b else 0)
+            for g in range(2):
+                assert sum(wf[i] * c[i][a] * c[i][b] * c[i][g] for i in range(9)) == 0
+                for d in range(2):
+                    delta = ((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g))
+                    m4 = sum(wf[i] * c[i][a] * c[i][b] * c[i][g] * c[i][d] for i in range(9))
+                    assert m4 == th * th * delta
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_equilibrium_moments(orc, seed):
+    """sum f^eq = rho, sum c f^eq = rho u, sum c c f^eq = rho u u + rho theta0 I (Sec. II)."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.8, 1.2)
+    u = rng.uniform(-0.1, 0.1, 2)
+    feq = orc.equilibrium(rho, u[0], u[1])
+    cx, cy, _, _, th = orc.lattice()
+    c = np.stack([cx, cy], 1).astype(float)
+    assert abs(feq.sum() - rho) <= 1e-15 * rho
+    np.testing.assert_allclose(c.T @ feq, rho * u, rtol=0, atol=1e-16)
+    P = np.einsum("i,ia,ib->ab", feq, c, c)
+    np.testing.assert_allclose(P, rho * np.outer(u, u) + rho * th * np.eye(2), rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_collision_conserves_mass_and_momentum(orc, seed):
+    """BGK (Eq. CollideAdv) relaxes towards an equilibrium with the node's own rho and
+    rho u, so it conserves both."""
+    rng = np.random.default_rng(seed)
+    f = workloads.NEAR_REST_BASE * (1 + 0.05 * rng.uniform(-1, 1, 9))
+    cx, cy, _, _, _ = orc.lattice()
+    for omega in (0.3, 1.0, 1.7):
+        g = orc.collide_node(f, omega)
+        assert abs(g.sum() - f.sum()) <= 1e-15  # 4 ulp of 1
+        assert abs(cx @ g - cx @ f) <= 1e-15
+        assert abs(cy @ g - cy @ f) <= 1e-15
+
+
+def test_collision_omega_one_gives_equilibrium(orc):
+    """With 2 beta = 1 the post-collision state is the equilibrium of the node's own
+    moments (special case of Eq. CollideAdv)."""
+    rng = np.random.default_rng(7)
+    f = workloads.NEAR_REST_BASE * (1 + 0.05 * rng.uniform(-1, 1, 9))
+    cx, cy, _, _, _ = orc.lattice()
+    rho = f.sum()
+    feq = orc.equilibrium(rho, (cx @ f) / rho, (cy @ f) / rho)
+    np.testing.assert_allclose(orc.collide_node(f, 1.0), feq, rtol=0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------------------
+# Streaming and boundary rules, by tracking single populations (omega = 0)
+# --------------------------------------------------------------------------------------
+
+def _delta_state(nx, ny, i, x, y, val=1.0):
+    """A lone extra population ``val`` in direction i at (x, y) on top of a uniform
+    positive background (omega = 0 leaves every population as it is; the background
+    keeps rho > 0 so the collision stays defined)."""
+    S = np.broadcast_to(workloads.NEAR_REST_BASE[:, None, None], (9, ny, nx)).copy()
+    S[i, y, x] += val
+    return S
+
+
+@pytest.mark.parametrize("i", range(9))
+def test_pure_streaming_moves_by_c_i(orc, i):
+    """Eq. CollideAdv, second line: f_i(x + c_i, t+1) = f~_i(x, t) -- with omega = 0 a
+    lone population moves exactly c_i per step on a periodic lattice."""
+    nx, ny = 7, 5
+    cx, cy, _, _, _ = orc.lattice()
+    s = OracleSim(np.zeros((ny, nx), np.uint8), omega=0.0, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    s.set_state(_delta_state(nx, ny, i, 3, 2, 0.25))
+    for k in range(1, 12):
+        s.step()
+        S = s.state()
+        want = _delta_state(nx, ny, i, (3 + k * cx[i]) % nx, (2 + k * cy[i]) % ny, 0.25)
+        assert np.array_equal(S, want)
+
+
+def test_wall_bounce_back_half_way(orc):
+    """Stationary-wall bounce-back (Sec. II): a population moving down from row 1
+    reaches row 0, meets the wall half-way to row -1 and returns reversed to row 0 one
+    step later, then moves up."""
+    nx, ny = 5, 6
+    s = OracleSim(np.zeros((ny, nx), np.uint8), omega=0.0, bc_x=BCX_PERIODIC, bc_y=BCY_WALL)
+    s.set_state(_delta_state(nx, ny, 4, 2, 1, 0.5))   # direction 4 = (0,-1)
+    s.step()
+    assert np.array_equal(s.state(), _delta_state(nx, ny, 4, 2, 0, 0.5))
+    s.step()
+    assert np.array_equal(s.state(), _delta_state(nx, ny, 2, 2, 0, 0.5))  # reversed
+    s.step()
+    assert np.array_equal(s.state(), _delta_state(nx, ny, 2, 2, 1, 0.5))
+    # Diagonal (1,-1) at row 0 comes back as (-1,1) at the same node.
+    s.set_state(_delta_state(nx, ny, 8, 2, 0, 0.5))
+    s.step()
+    assert np.array_equal(s.state(), _delta_state(nx, ny, 6, 2, 0, 0.5))
+
+
+def test_body_bounce_back_half_way(orc):
+    """Sec. II: the boundary point sits half-way along the fluid-solid link; the
+    population heading into the solid node comes back reversed at the same fluid node."""
+    nx, ny = 7, 7
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[3, 4] = 1
+    s = OracleSim(mask, omega=0.0, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    s.set_state(_delta_state(nx, ny, 1, 2, 3, 0.5))   # (1,0) at (2,3) -> (3,3) -> back
+    s.step()
+    assert np.array_equal(s.state()[:, :, :4], _delta_state(nx, ny, 1, 3, 3, 0.5)[:, :, :4])
+    s.step()
+    assert np.array_equal(s.state()[:, :, :4], _delta_state(nx, ny, 3, 3, 3, 0.5)[:, :, :4])
+
+
+def test_inlet_returns_with_moving_wall_term(orc):
+    """Moving-wall bounce-back (Sec. II) at the inlet x = -1/2 with u_w = (u_in, 0):
+    a population leaving through the inlet comes back reversed plus 2 w rho c.u_w / c_s^2."""
+    nx, ny, u = 6, 5, 0.03
+    s = OracleSim(np.zeros((ny, nx), np.uint8), omega=0.0, uin=np.full(ny, u),
+                  bc_x=BCX_INLET_OUTLET, bc_y=BCY_PERIODIC)
+    b = workloads.NEAR_REST_BASE
+    s.set_state(np.broadcast_to(b[:, None, None], (9, ny, nx)).copy())
+    s.step()
+    S = s.state()
+    # Only the inlet column changes: (1,0) gains 6 w1 u, (1,+-1) gain 6 w5 u, where
+    # 2 w / c_s^2 = 6 w with w1 = 4/36 and w5 = 1/36.
+    want = np.broadcast_to(b[:, None, None], (9, ny, nx)).copy()
+    want[1, :, 0] += 6 * (4 / 36) * u
+    want[5, :, 0] += 6 * (1 / 36) * u
+    want[8, :, 0] += 6 * (1 / 36) * u
+    np.testing.assert_allclose(S, want, rtol=1e-15, atol=0)
+
+
+def test_outlet_zero_gradient_ghost_copy(orc):
+    """Outlet reading (zero gradient): the ghost column nx holds the post-collision
+    populations of column nx-1, so a population moving left from the last column is
+    both streamed on and copied back into the last column."""
+    nx, ny = 6, 5
+    s = OracleSim(np.zeros((ny, nx), np.uint8), omega=0.0, uin=np.zeros(ny),
+                  bc_x=BCX_INLET_OUTLET, bc_y=BCY_PERIODIC)
+    s.set_state(_delta_state(nx, ny, 3, nx - 1, 2, 0.5))   # (-1,0) at the last column
+    s.step()
+    want = _delta_state(nx, ny, 3, nx - 2, 2, 0.5)
+    want[3, 2, nx - 1] = want[3, 2, nx - 2]
+    assert np.array_equal(s.state(), want)
+    # A population moving right out of the last column is lost.
+    s.set_state(_delta_state(nx, ny, 1, nx - 1, 2, 0.5))
+    s.step()
+    assert np.array_equal(s.state(), _delta_state(nx, ny, 1, 0, 0, 0.0))
+
+
+# --------------------------------------------------------------------------------------
+# Conservation, fixed points and the inlet mass flux
+# --------------------------------------------------------------------------------------
+
+def test_periodic_conservation(orc):
+    """Fully periodic lattice, no body: total mass and momentum are invariants of the
+    collide-stream step (Sec. II)."""
+    nx, ny = 24, 16
+    cx, cy, _, _, _ = orc.lattice()
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.7, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    S0 = workloads.near_rest_state(nx, ny, seed=3, amp=0.05)
+    s.set_state(S0)
+    m0 = S0.sum()
+    j0 = np.array([np.tensordot(cx, S0, 1).sum(), np.tensordot(cy, S0, 1).sum()])
+    s.step(1000)
+    S = s.state()
+    assert abs(S.sum() - m0) <= 1e-13 * m0
+    j = np.array([np.tensordot(cx, S, 1).sum(), np.tensordot(cy, S, 1).sum()])
+    np.testing.assert_allclose(j, j0, rtol=0, atol=1e-13 * m0)
+
+
+def test_closed_box_conserves_mass(orc):
+    """Walls top and bottom, a body, and a solid column closing the channel: bounce-back
+    returns every population, so mass is conserved."""
+    nx, ny = 30, 14
+    mask = workloads.cylinder_mask(nx, ny, 12, 7, 3)
+    mask[:, 0] = 1
+    mask[:, -1] = 1
+    s = OracleSim(mask, tau=0.6, uin=np.zeros(ny), bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL)
+    S0 = workloads.near_rest_state(nx, ny, seed=4, amp=0.05)
+    s.set_state(S0)
+    fl = mask == 0
+    m0 = S0[:, fl].sum()
+    s.step(1000)
+    assert abs(s.state()[:, fl].sum() - m0) <= 1e-13 * m0
+
+
+def test_inlet_mass_injection_closed_form(orc):
+    """Each inlet row gains 2 rho_w u_in sum_{c_x=+1} w_i / c_s^2 = u_in of mass per step;
+    the two corner rows lose the diagonal that meets the wall first (5/6 u_in)."""
+    nx, ny = 20, 9
+    rng = np.random.default_rng(11)
+    uin = rng.uniform(0.01, 0.08, ny)
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[:, -1] = 1  # close the outlet
+    s = OracleSim(mask, tau=0.8, uin=uin, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL)
+    S0 = workloads.near_rest_state(nx, ny, seed=5, amp=0.02)
+    s.set_state(S0)
+    fl = mask == 0
+    gain = uin.sum() - (uin[0] + uin[-1]) / 6.0
+    m = S0[:, fl].sum()
+    for _ in range(50):
+        s.step()
+        m_new = s.state()[:, fl].sum()
+        assert abs((m_new - m) - gain) <= 1e-13
+        m = m_new
+
+
+def test_rest_state_is_fixed_point_and_forceless(orc):
+    """With no inflow the rest state w_i is kept (to rounding: sum w_i is 1 only to an
+    ulp in binary64), and every force vanishes."""
+    w = workloads.cylinder_channel_200x80()
+    s = OracleSim(w.mask, tau=w.tau, uin=np.zeros(w.ny), box=w.box)
+    S0 = s.state()
+    s.step(20)
+    np.testing.assert_allclose(s.state(), S0, rtol=0, atol=1e-15)
+    F = s.forces()
+    assert np.abs(F).max() <= 1e-14
+
+
+def test_uniform_flow_is_fixed_point_with_inlet_and_outlet(orc):
+    """Uniform f^eq(1, (u, 0)) in a channel periodic in y: the moving-wall inlet returns
+    exactly the equilibrium populations and the outlet copy keeps them."""
+    nx, ny, u = 16, 6, 0.05
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.7, uin=np.full(ny, u),
+                  bc_x=BCX_INLET_OUTLET, bc_y=BCY_PERIODIC)
+    feq = orc.equilibrium(1.0, u, 0.0)
+    S0 = np.broadcast_to(feq[:, None, None], (9, ny, nx)).copy()
+    s.set_state(S0)
+    s.step(50)
+    np.testing.assert_allclose(s.state(), S0, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------------
+# Links (Sec. III: fluid-solid links, boundary point half-way)
+# --------------------------------------------------------------------------------------
+
+def test_links_single_solid_node(orc):
+    m = np.zeros((5, 5), np.uint8)
+    m[2, 2] = 1
+    L = orc.links(m)
+    # fluid node 12 - c_i links in direction i
+    want = sorted(((2 - cy) * 5 + (2 - cx), i) for i, (cx, cy) in enumerate(
+        [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]) if i)
+    assert [tuple(r) for r in L] == want
+    assert len(L) == 8
+
+
+def test_links_domino(orc):
+    m = np.zeros((5, 6), np.uint8)
+    m[2, 2] = m[2, 3] = 1
+    assert len(orc.links(m)) == 14
+
+
+def _brute_links(mask, px, py):
+    ny, nx = mask.shape
+    C = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    out = []
+    for y in range(ny):
+        for x in range(nx):
+            if mask[y, x]:
+                continue
+            for i in range(1, 9):
+                tx, ty = x + C[i][0], y + C[i][1]
+                if px:
+                    tx %= nx
+                if py:
+                    ty %= ny
+                if 0 <= tx < nx and 0 <= ty < ny and mask[ty, tx]:
+                    out.append((y * nx + x, i))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_links_random_masks_brute_force(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    m = (rng.uniform(size=(10, 12)) < 0.25).astype(np.uint8)
+    for bcx, bcy in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        L = orc.links(m, bc_x=bcx, bc_y=bcy)
+        assert [tuple(r) for r in L] == _brute_links(m, bcx == 1, bcy == 1)
+
+
+# --------------------------------------------------------------------------------------
+# Forces
+# --------------------------------------------------------------------------------------
+
+def test_newton_global_momentum_balance(orc):
+    """Newton's law for the whole fluid: with body force g on N fluid nodes and every
+    solid node counted as body, J(t) - J(t+1) + N g = F_B(t) at every step, where J is
+    the momentum of all fluid nodes before collision (Eq. rtt2 with the whole fluid as
+    control volume).  Pins MEA-B (sign, factor 2, link set) independently of its
+    formula."""
+    nx, ny = 32, 20
+    mask = workloads.cylinder_mask(nx, ny, 15.5, 9.5, 4.0)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    g = (2e-6, -1e-6)
+    s = OracleSim(mask, tau=0.8, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC, g=g)
+    cx, cy, _, _, _ = orc.lattice()
+    fl = mask == 0
+    N = fl.sum()
+    Jprev = None
+    for t in range(300):
+        s.step()
+        f = s.pre()
+        J = np.array([np.tensordot(cx, f, 1)[fl].sum(), np.tensordot(cy, f, 1)[fl].sum()])
+        if Jprev is not None:
+            FB = s.forces()[t - 1, 1]
+            np.testing.assert_allclose(Jprev - J + N * np.array(g), FB, rtol=0, atol=1e-13)
+        Jprev = J
+
+
+def test_poiseuille_magic_tau_exact(orc):
+    """Body-force-driven channel between half-way bounce-back walls at y = -1/2 and
+    ny - 1/2: u(y) = g/(2 nu) (y + 1/2)(ny - 1/2 - y), nu = (tau - 1/2)/3.  At
+    (tau - 1/2)^2 = 3/16 the BGK bounce-back solution is the parabola itself; at steady
+    state the wall force (the populations bounced at the walls) equals N g."""
+    nx, ny = 2, 16
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    nu = (tau - 0.5) / 3.0
+    g = 1e-6
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=tau, bc_x=BCX_PERIODIC, bc_y=BCY_WALL,
+                  g=(g, 0.0))
+    s.step(8000)
+    s.step(1)
+    f = s.pre()
+    cx, _, _, _, _ = orc.lattice()
+    rho = f.sum(0)
+    u = ((np.tensordot(cx, f, 1) + 0.5 * g) / rho)[:, 0]
+    y = np.arange(ny)
+    exact = g / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    np.testing.assert_allclose(u, exact, rtol=1e-10, atol=0)
+
+
+def test_poiseuille_second_order_convergence(orc):
+    """Away from the special tau the half-way bounce-back wall is second-order accurate:
+    the max relative profile error falls by about 4x per doubling of ny."""
+    tau, errs = 0.8, []
+    for ny in (8, 16, 32):
+        nu = (tau - 0.5) / 3.0
+        g = 1e-6 * (8.0 / ny) ** 2
+        s = OracleSim(np.zeros((ny, 2), np.uint8), tau=tau, bc_x=BCX_PERIODIC, bc_y=BCY_WALL,
+                      g=(g, 0.0))
+        s.step(int(40 * ny * ny / nu / 10))
+        s.step(1)
+        f = s.pre()
+        cx, _, _, _, _ = orc.lattice()
+        u = ((np.tensordot(cx, f, 1) + 0.5 * g) / f.sum(0))[:, 0]
+        y = np.arange(ny)
+        exact = g / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+        errs.append(np.abs(u - exact).max() / exact.max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+
+
+def test_channel_wall_force_equals_body_force(orc):
+    """Steady body-force-driven channel whose walls are solid rows: the total momentum
+    exchange on the walls equals the applied body force on all fluid nodes."""
+    nx, ny = 4, 18
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0, :] = 1
+    mask[-1, :] = 1
+    g = 1e-6
+    s = OracleSim(mask, tau=0.9, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC, g=(g, 0.0))
+    s.step(6000)
+    FB = s.forces()[-1, 1]
+    N = (mask == 0).sum()
+    np.testing.assert_allclose(FB, [N * g, 0.0], rtol=1e-9, atol=1e-9 * N * g)
+
+
+def test_drtt_equals_mea_b_and_is_box_invariant(orc):
+    """With half-way bounce-back, collision conserving momentum node by node and an
+    admissible box, J(t) - J(t+1) = (out - in through the box surface) + 2 sum_L c_i f~_i,
+    so the DRTT force of the second Eq. rtt7 equals MEA-B (Eq. rtt5) step by step, for
+    any such box."""
+    w = workloads.cylinder_channel_200x80()
+    F = []
+    for box in ((10, 70, 10, 70), (25, 56, 24, 57), (5, 120, 3, 77)):
+        s = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=box)
+        s.step(400)
+        F.append(s.forces())
+    for Fi in F:
+        scale = np.abs(Fi[:, 1]).max()
+        assert np.abs(Fi[:, 2] - Fi[:, 1]).max() <= 1e-11 * scale
+    assert np.abs(F[0][:, 2] - F[1][:, 2]).max() <= 1e-11 * np.abs(F[0][:, 1]).max()
+
+
+def test_drtt_empty_box_is_zero(orc):
+    """No body inside the control volume: inflow minus outflow balances the change of
+    box momentum exactly, so the DRTT force vanishes (second Eq. rtt7)."""
+    nx, ny = 60, 30
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.7, uin=np.full(ny, 0.05),
+                  box=(10, 40, 5, 25))
+    s.set_state(workloads.near_rest_state(nx, ny, seed=9, amp=0.05))
+    s.step(100)
+    F = s.forces()
+    R = s.records()
+    # |F| at the rounding level of the box momentum (~30) versus fluxes of order 0.1
+    assert np.abs(R[:, 6:8]).max() > 1e-2
+    assert np.abs(F[:, 2]).max() <= 1e-12
+
+
+def test_a_minus_b_is_the_collision_of_the_outgoing_populations(orc):
+    """Eq. rtt4: algorithm A takes the outgoing population before collision, B after, with
+    the same returned populations, so F_A - F_B = 2 beta sum_L c_i (f_i - f_i^eq) -- the
+    two-dimensional form of the term that Eq. lbb3 has and algorithm A misses."""
+    w = workloads.cylinder_channel_200x80()
+    s = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+    links = orc.links(w.mask)
+    cx, cy, _, _, _ = orc.lattice()
+    for t in range(60):
+        s.step()
+        f = s.pre()
+        d = np.zeros(2)
+        for node, i in links:
+            y, x = divmod(int(node), w.nx)
+            fn = f[:, y, x]
+            rho = fn.sum()
+            feq = orc.equilibrium(rho, (cx @ fn) / rho, (cy @ fn) / rho)
+            d += (fn[i] - feq[i]) * np.array([cx[i], cy[i]])
+        F = s.forces()[t]
+        np.testing.assert_allclose(F[0] - F[1], s.omega * d, rtol=1e-12, atol=1e-14)
+
+
+def test_first_step_pure_streaming_single_solid(orc):
+    """Uniform flow f^eq(1, u) around one solid node with omega = 0: every direction has
+    exactly one link and the outgoing populations are the equilibrium ones, so
+    F_A(0) = F_B(0) = F_DRTT(0) = 2 sum_i c_i f_i^eq = 2 rho u."""
+    nx, ny = 9, 9
+    m = np.zeros((ny, nx), np.uint8)
+    m[4, 4] = 1
+    u = np.array([0.04, -0.02])
+    s = OracleSim(m, omega=0.0, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC, box=(2, 7, 2, 7))
+    feq = orc.equilibrium(1.0, u[0], u[1])
+    s.set_state(np.broadcast_to(feq[:, None, None], (9, ny, nx)).copy())
+    s.step(1)
+    F = s.forces()[0]
+    for k in range(3):
+        np.testing.assert_allclose(F[k], 2 * u, rtol=1e-14, atol=1e-17)
+
+
+def test_symmetric_cylinder_has_no_lift(orc):
+    """Cylinder on the channel centre line (walls at -1/2 and ny-1/2, centre row
+    (ny-1)/2): mirror symmetry gives F_y = 0 for every scheme."""
+    nx, ny = 90, 41
+    mask = workloads.cylinder_mask(nx, ny, 20, 20, 5)
+    s = OracleSim(mask, tau=0.65, uin=np.full(ny, 0.05), box=(8, 34, 8, 33))
+    s.step(600)
+    F = s.forces()
+    for k in range(3):
+        assert np.abs(F[:, k, 1]).max() <= 1e-12 * np.abs(F[:, k, 0]).max()
+    assert F[-1, 1, 0] > 0  # drag points downstream
+
+
+def test_positive_incidence_gives_positive_lift(orc):
+    """NACA0012 at +8 deg (nose up) in a uniform stream: the lift of every scheme points
+    to +y once the flow is established."""
+    w = workloads.naca_channel(192, 96, 48, 8.0, 100.0, 0)
+    s = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+    s.step(1500)
+    F = s.forces()[-200:].mean(0)
+    assert np.all(F[:, 1] > 0) and np.all(F[:, 0] > 0)
+
+
+# --------------------------------------------------------------------------------------
+# The one-dimensional toy of the introduction (Eq. lbb1-lbb4)
+# --------------------------------------------------------------------------------------
+
+def _toy_state(n, seed):
+    from oracle import d1q3
+    rng = np.random.default_rng(seed)
+    return [[d1q3.W[i] * (1 + 0.1 * rng.uniform(-1, 1)) for i in range(3)] for _ in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_d1q3_momentum_balance(seed):
+    from oracle import d1q3
+    beta = 0.37
+    nodes = _toy_state(8, seed)
+    f1, fm1 = nodes[0][1], nodes[0][2]
+    J0 = d1q3.momentum(nodes, len(nodes))
+    for collided in (False, True):
+        new, post = d1q3.step(nodes, beta, collided)
+        # momentum through the far right surface is bookkept separately (the toy's
+        # control volume is semi-infinite)
+        right = -post[-1][1] - new[-1][2]
+        dJ = d1q3.momentum(new, len(new)) - J0 - right
+        F1 = new[0][1]
+        # Eq. lbb2
+        assert abs(dJ - (F1 + fm1 - f1 + post[0][1])) <= 1e-15
+        rho = sum(nodes[0])
+        feq = d1q3.equilibrium(rho, (f1 - fm1) / rho)
+        if not collided:   # Eq. lbb3: un-collided return
+            assert abs(dJ - (2 * fm1 + 2 * beta * (feq[1] - f1))) <= 1e-15
+        else:              # Eq. lbb4: collided return
+            assert abs(dJ - 2 * post[0][2]) <= 1e-15
+
+
+# --------------------------------------------------------------------------------------
+# Input geometry (the synthetic stand-ins for the paper's bodies)
+# --------------------------------------------------------------------------------------
+
+def test_cylinder_mask_gauss_circle():
+    """Integer points with a^2 + b^2 <= 100: N(10) = 317 (Gauss circle problem); 12 of
+    them on the circle (a^2 + b^2 = 100)."""
+    m = workloads.cylinder_mask(200, 80, 40, 40, 10)
+    assert int(m.sum()) == 317
+    iy, ix = np.nonzero(m)
+    assert int(((ix - 40) ** 2 + (iy - 40) ** 2 == 100).sum()) == 12
+
+
+def test_naca_mask_area_symmetry_and_incidence():
+    c = 256
+    m0 = workloads.naca0012_mask(1024, 512, c, 320, 256, 0.0)
+    # area of the open-trailing-edge NACA0012: 10 t c^2 (0.2969*2/3 - 0.126/2 - 0.3516/3
+    # + 0.2843/4 - 0.1015/5)
+    area = 10 * 0.12 * c * c * (0.2969 * 2 / 3 - 0.126 / 2 - 0.3516 / 3 + 0.2843 / 4 - 0.1015 / 5)
+    assert abs(m0.sum() - area) <= 0.02 * area
+    assert np.array_equal(m0[256 + 1:256 + 100], m0[256 - 1:256 - 100:-1])
+    ys, xs = np.nonzero(m0)
+    assert xs.min() == 256 and xs.max() in (511, 512)
+    m8 = workloads.naca0012_mask(1024, 512, c, 320, 256, 8.0)
+    ys, xs = np.nonzero(m8)
+    assert ys[xs == xs.min()].mean() > 256 > ys[xs == xs.max()].mean()  # nose up
