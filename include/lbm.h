@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice Boltzmann library with per-step
+ * flow forces.
+ *
+ * The library advances a two-dimensional D2Q9 BGK lattice Boltzmann model (Kaushal,
+ * Succi & Ansumali, "Flow force calculation in Lattice Boltzmann Method",
+ * arXiv:2210.10377, Sec. II: Eq. CollideAdv, the second-order equilibrium, Table I)
+ * around a body given as a solid mask on the Cartesian grid, with half-way bounce-back
+ * on every fluid-solid link (Sec. II, stationary wall) and, at every step, the force of
+ * the fluid on the body by three estimators:
+ *   - momentum exchange, algorithm A (Sec. IV, Eq. rtt4 "Algorithm A"),
+ *   - momentum exchange, algorithm B (Sec. IV, Eq. rtt4 "Algorithm B", Eq. rtt5),
+ *   - the discrete Reynolds-transport-theorem control-volume force DRTT (Sec. IV,
+ *     second Eq. rtt7; Appendix).
+ * The paper's problem statement is a body in a channel, a relaxation time, an inlet,
+ * and the force on the body at every step (Sec. V, Appendix); the calls below follow it.
+ *
+ * Conventions used throughout:
+ *   - Node (x, y) with 0 <= x < nx, 0 <= y < ny sits at the point (x, y).  Host arrays
+ *     over the grid are row-major [ny][nx]; population arrays are [9][ny][nx].
+ *   - Directions: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
+ *     8:(1,-1); weights 4/9, 1/9, 1/36 (Table I), c_s^2 = theta0 = 1/3.
+ *   - tau is the lattice relaxation time tau_lb: the factor 2 beta of Eq. CollideAdv is
+ *     1/tau_lb, and the kinematic viscosity is (tau_lb - 1/2)/3.
+ *   - The stored state is the post-collision field of the last step.  One step pulls it
+ *     along -c_i with the boundary rules, collides, and stores the result.  Pull
+ *     rules, first match wins: periodic wrap; no-slip wall (half-way bounce-back at
+ *     y = -1/2 and y = ny - 1/2); inlet (moving-wall bounce-back of Sec. II at
+ *     x = -1/2 with wall velocity (u_in(y), 0) and density rho_w); outlet (ghost
+ *     column nx copies the post-collision column nx-1; bounce-back if that node is
+ *     solid); body (half-way bounce-back); otherwise plain streaming.
+ *   - Forces are those of the fluid on the body, in lattice units, indexed by the
+ *     collision step t, accumulated in FP64 from the populations as stored:
+ *       A(t)    = sum_{links (x,i)} c_i [f_i(x,t) + f~_i(x,t)]   (pre-collision out)
+ *       B(t)    = sum_{links (x,i)} 2 c_i f~_i(x,t)               (post-collision out)
+ *       DRTT(t) = J(t) - J(t+1) + Phi(t), J(t) the momentum of the pre-collision
+ *                 populations of the control volume V (the fluid nodes of the box),
+ *                 Phi(t) = sum of c_i f~_i(x,t) over populations entering V minus those
+ *                 leaving V.
+ *     A link is a fluid node x and a direction i with x + c_i a solid mask node.
+ *
+ * Memory: the caller owns all memory.  lbm_create copies the mask and inlet profile.
+ * The device workspace (lbm_workspace_bytes) is allocated by the caller, bound with
+ * lbm_bind, and must outlive the handle's use; the library itself allocates no device
+ * memory.  The HIP stream is the caller's.
+ *
+ * Synchronisation: lbm_step only enqueues work on the bound stream.  lbm_forces,
+ * lbm_get_* and lbm_set_* synchronise that stream before returning.
+ *
+ * Threading: one host thread at a time per handle; separate handles are independent.
+ *
+ * Errors: every call returns LBM_OK (0) or a negative code; lbm_last_error gives a
+ * message for the last failing call on a handle.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* invalid argument or configuration            */
+#define LBM_ENOMEM (-2)     /* grid too large / workspace too small         */
+#define LBM_EHIP (-3)       /* a HIP runtime call failed                    */
+#define LBM_ENONFINITE (-4) /* a requested force was NaN or infinite        */
+#define LBM_ESTATE (-5)     /* call not valid in the handle's current state */
+#define LBM_EOVERFLOW (-6)  /* the force ring cannot hold the steps asked   */
+
+/* Population storage precision. */
+#define LBM_FP64 0    /* binary64 populations, binary64 arithmetic                  */
+#define LBM_FP32 1    /* binary32 populations, binary32 arithmetic                  */
+#define LBM_FP16DEV 2 /* binary16 deviations h_i = f_i - w_i, binary32 arithmetic   */
+
+#define LBM_BCX_INLET_OUTLET 0 /* x: inlet at x = -1/2, outlet at x = nx - 1/2      */
+#define LBM_BCX_PERIODIC 1
+#define LBM_BCY_WALL 0         /* y: no-slip walls at y = -1/2 and y = ny - 1/2      */
+#define LBM_BCY_PERIODIC 1
+
+/* Force schemes (bit mask for lbm_step). */
+#define LBM_FORCE_MEA_A 1u
+#define LBM_FORCE_MEA_B 2u
+#define LBM_FORCE_DRTT 4u
+#define LBM_FORCE_ALL 7u
+
+typedef struct lbm_grid {
+  int32_t nx, ny;     /* grid size, each >= 3                                      */
+  int32_t bc_x, bc_y; /* LBM_BCX_*, LBM_BCY_*                                      */
+  int32_t precision;  /* LBM_FP64 / LBM_FP32 / LBM_FP16DEV                         */
+  int32_t box[4];     /* DRTT control volume [x0, x1) x [y0, y1); x0 < 0: none.
+                         Must satisfy 1 <= x0, x1 <= nx - 1, 1 <= y0, y1 <= ny - 1,
+                         and hold every solid node strictly inside
+                         [x0+1, x1-1) x [y0+1, y1-1).                              */
+  int32_t max_record; /* force-ring capacity in steps (>= 1)                        */
+  double rho_ref, u_ref, l_ref; /* normalisation of the force coefficients (Sec. V:
+                                   C = 2 F / (rho U^2 L))                           */
+} lbm_grid;
+
+typedef struct lbm_inlet {
+  const double* ux; /* ny inlet velocities u_in(y) (host); ignored (may be NULL)
+                       when bc_x is periodic                                       */
+  double rho_w;     /* wall density of the moving-wall inlet rule (normally 1)     */
+} lbm_inlet;
+
+typedef struct lbm_t lbm_t;
+
+typedef struct lbm_info {
+  int64_t n_fluid;        /* fluid nodes                                             */
+  int64_t n_links;        /* fluid-solid links (x, i)                                */
+  int64_t n_tiles;        /* tiles of the step kernel                                */
+  int64_t n_general;      /* tiles that take the boundary / force path               */
+  int64_t n_box;          /* fluid nodes in the control volume                       */
+  int64_t steps_done;     /* steps taken since create (or the restored state)        */
+  int64_t n_recorded;     /* force rows waiting in the ring                          */
+  int32_t tile_w, tile_h; /* tile shape in nodes                                     */
+  int64_t plane_stride;   /* population plane stride in elements (device layout)     */
+  int32_t pitch;          /* row pitch in elements (device layout)                   */
+  int32_t elem_bytes;     /* bytes per stored population                             */
+} lbm_info;
+
+/* Validate the configuration, classify every node and link, and return a handle.
+ * solid_mask: host, ny*nx bytes, each 0 (fluid) or 1 (solid).  tau: tau_lb > 1/2.
+ * inlet may be NULL when bc_x is periodic.  Returns LBM_EINVAL for nx or ny < 3,
+ * non-finite or tau <= 1/2, a mask byte outside {0,1}, a missing, non-finite inlet,
+ * an inadmissible box, unknown codes or max_record < 1; LBM_ENOMEM for grids whose
+ * population planes exceed 2^31 elements.  Needs no GPU. */
+int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
+               const lbm_inlet* inlet, lbm_t** out);
+
+/* Device workspace the handle needs, in bytes (needs no GPU). */
+int lbm_workspace_bytes(const lbm_t* h, size_t* bytes);
+
+/* Bind a caller-owned device workspace (>= lbm_workspace_bytes, 256-byte aligned) and
+ * HIP stream (hipStream_t, NULL for the default stream), upload the tables and put
+ * every node in the rest state w_i.  Synchronises the stream.  LBM_ENOMEM if the
+ * workspace is too small, LBM_EINVAL if misaligned. */
+int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream);
+
+/* Enqueue n >= 0 time steps on the bound stream.  force_scheme is a mask of
+ * LBM_FORCE_*; when non-zero every step records one force row (all three estimators
+ * are evaluated; rows for schemes not asked for read NaN).  Returns LBM_EOVERFLOW
+ * without launching anything if the ring would overflow, LBM_ESTATE if unbound,
+ * LBM_EINVAL for n < 0 or unknown scheme bits. */
+int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme);
+
+/* Copy the force rows recorded since the last call into out[k][3][2] (host; scheme
+ * order A, B, DRTT; components x, y) and empty the ring.  At most cap rows are written
+ * (LBM_EINVAL if fewer than recorded).  Synchronises the stream.  Returns
+ * LBM_ENONFINITE (after writing everything) if any requested value is not finite. */
+int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out);
+
+/* Force coefficients 2 F / (rho_ref u_ref^2 l_ref) of k force rows (Sec. V: drag and
+ * lift coefficients, kept signed), host to host; in and out may alias. */
+int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out);
+
+int lbm_destroy(lbm_t* h);
+
+/* Canonical fluid-solid links (node = y*nx + x, direction i), sorted by node then
+ * direction, into node_dir[L][2] (host); writes min(L, cap) pairs and returns L in
+ * *n.  Needs no GPU. */
+int lbm_get_links(const lbm_t* h, int32_t* node_dir, int64_t cap, int64_t* n);
+
+int lbm_get_info(const lbm_t* h, lbm_info* info);
+
+/* Current stored (post-collision) populations as binary64, out[9][ny][nx] (host;
+ * FP16DEV reads w_i + h_i).  Synchronises the stream. */
+int lbm_get_populations(lbm_t* h, double* out);
+
+/* Replace the stored populations (host, [9][ny][nx]); values are rounded to the
+ * storage precision (FP16DEV stores h_i = f_i - w_i rounded to nearest even).
+ * Synchronises the stream. */
+int lbm_set_populations(lbm_t* h, const double* in);
+
+/* Checkpoint: the exact stored state (raw storage bytes plus the step counter) as an
+ * opaque host blob of lbm_state_bytes bytes; lbm_set_state accepts a blob of a handle
+ * with the same grid size and precision.  Both synchronise the stream. */
+int lbm_state_bytes(const lbm_t* h, size_t* bytes);
+int lbm_get_state(lbm_t* h, void* blob, size_t cap);
+int lbm_set_state(lbm_t* h, const void* blob, size_t n);
+
+/* Message of the last failing call on h (or of the last failing lbm_create when h is
+ * NULL).  The string lives until the next call on the handle. */
+const char* lbm_last_error(const lbm_t* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

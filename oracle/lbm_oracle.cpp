@@ -59,12 +59,20 @@ const double W[NQ] = {16.0 / 36.0, 4.0 / 36.0, 4.0 / 36.0, 4.0 / 36.0, 4.0 / 36.
                       1.0 / 36.0,  1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 const double THETA0 = 1.0 / 3.0;
 
-// Direction opposite to i (Sec. II, bounce-back), found by search over the table.
-int opposite(int i) {
+// Direction opposite to i (Sec. II, bounce-back), found once by search over the table.
+int search_opposite(int i) {
   for (int k = 0; k < NQ; ++k)
     if (CX[k] == -CX[i] && CY[k] == -CY[i]) return k;
   return -1;
 }
+struct OppTable {
+  int o[NQ];
+  OppTable() {
+    for (int i = 0; i < NQ; ++i) o[i] = search_opposite(i);
+  }
+};
+const OppTable OPP;
+int opposite(int i) { return OPP.o[i]; }
 
 enum { BCX_INLET_OUTLET = 0, BCX_PERIODIC = 1 };
 enum { BCY_WALL = 0, BCY_PERIODIC = 1 };

@@ -1,0 +1,102 @@
+"""ctypes binding of the C ABI declared in include/lbm.h (argument marshalling only).
+
+Every function of the header is bound under its own name.  Loading fails loudly when
+the HIP library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE, LBM_EOVERFLOW = (
+    0, -1, -2, -3, -4, -5, -6)
+LBM_FP64, LBM_FP32, LBM_FP16DEV = 0, 1, 2
+LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
+LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
+LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_ALL = 1, 2, 4, 7
+
+ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
+               -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EOVERFLOW"}
+
+# Every entry point of include/lbm.h.
+EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_forces",
+           "lbm_coefficients", "lbm_destroy", "lbm_get_links", "lbm_get_info",
+           "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes", "lbm_get_state",
+           "lbm_set_state", "lbm_last_error")
+
+
+class lbm_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
+                ("max_record", ctypes.c_int32),
+                ("rho_ref", ctypes.c_double), ("u_ref", ctypes.c_double),
+                ("l_ref", ctypes.c_double)]
+
+
+class lbm_inlet(ctypes.Structure):
+    _fields_ = [("ux", ctypes.POINTER(ctypes.c_double)), ("rho_w", ctypes.c_double)]
+
+
+class lbm_info(ctypes.Structure):
+    _fields_ = [("n_fluid", ctypes.c_int64), ("n_links", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("n_general", ctypes.c_int64),
+                ("n_box", ctypes.c_int64), ("steps_done", ctypes.c_int64),
+                ("n_recorded", ctypes.c_int64), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("plane_stride", ctypes.c_int64),
+                ("pitch", ctypes.c_int32), ("elem_bytes", ctypes.c_int32)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load liblbm.so (built in-tree by ``paper_2210_10377_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run "
+                          "`python -m paper_2210_10377_amd.build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                             ctypes.c_uint32, ctypes.POINTER(ctypes.c_double))
+    sz = ctypes.c_size_t
+    L.lbm_create.argtypes = [ctypes.POINTER(lbm_grid), ctypes.POINTER(ctypes.c_uint8),
+                             ctypes.c_double, ctypes.POINTER(lbm_inlet), ctypes.POINTER(vp)]
+    L.lbm_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.lbm_bind.argtypes = [vp, vp, sz, vp]
+    L.lbm_step.argtypes = [vp, i32, u32]
+    L.lbm_forces.argtypes = [vp, dp, i64, ctypes.POINTER(i64)]
+    L.lbm_coefficients.argtypes = [vp, dp, i64, dp]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_get_links.argtypes = [vp, ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    L.lbm_get_info.argtypes = [vp, ctypes.POINTER(lbm_info)]
+    L.lbm_get_populations.argtypes = [vp, dp]
+    L.lbm_set_populations.argtypes = [vp, dp]
+    L.lbm_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.lbm_get_state.argtypes = [vp, vp, sz]
+    L.lbm_set_state.argtypes = [vp, vp, sz]
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "lbm_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc, handle=None):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error(handle)
+        raise LbmError(rc, msg.decode() if msg else "")
+    return rc

@@ -1,0 +1,482 @@
+// The C ABI of include/lbm.h: handle life cycle, workspace layout, step scheduling,
+// the force ring, state transfer and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "lbm.h"
+#include "plan.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kRow = 10;  // FAx FAy FBx FBy Jx Jy Phix Phiy Jnext_x Jnext_y
+constexpr uint64_t kStateMagic = 0x4c424d5332443951ull;  // "LBMS2D9Q"
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t elem_bytes(int precision) {
+  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2);
+}
+
+std::string g_create_error;
+
+struct StateHeader {
+  uint64_t magic;
+  int32_t nx, ny, precision, pad;
+  int64_t plane;
+  int32_t pitch, pad2;
+  int64_t steps_done;
+};
+
+// Host-side value of the lattice weight in the storage's arithmetic precision.
+double host_weight(int precision, int i) {
+  if (precision == LBM_FP16DEV) {
+    const float w = i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+    return double(w);
+  }
+  return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+}  // namespace
+
+struct lbm_t {
+  lbm_grid g;
+  double tau = 0.0, omega = 0.0, rho_w = 1.0;
+  std::vector<double> uin;
+  Plan plan;
+  // device layout
+  int32_t pitch = 0;
+  int64_t plane = 0;  // elements
+  size_t esz = 0;
+  size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_part = 0,
+         off_jpart = 0, off_ring = 0, total = 0;
+  int njblocks = 0;
+  // binding
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;  // buffer holding the current state
+  int64_t steps_done = 0;
+  int64_t nrec = 0;
+  std::vector<uint32_t> rec_scheme;  // scheme mask per recorded row
+  std::string err;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EHIP;
+  }
+  void* buf(int k) const { return ws + off_buf[k]; }
+  double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
+  double* part(int k) const {
+    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * size_t(plan.nslots) * 8;
+  }
+};
+
+extern "C" {
+
+int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
+               const lbm_inlet* inlet, lbm_t** out) {
+  g_create_error.clear();
+  if (!grid || !solid_mask || !out) {
+    g_create_error = "null argument";
+    return LBM_EINVAL;
+  }
+  *out = nullptr;
+  if (!std::isfinite(tau) || tau <= 0.5) {
+    g_create_error = "tau must be finite and > 1/2";
+    return LBM_EINVAL;
+  }
+  const lbm_grid& g = *grid;
+  std::vector<double> uin;
+  double rho_w = 1.0;
+  if (g.bc_x == LBM_BCX_INLET_OUTLET) {
+    if (!inlet || !inlet->ux) {
+      g_create_error = "an inlet profile is required when bc_x is inlet/outlet";
+      return LBM_EINVAL;
+    }
+    if (g.ny > 0) uin.assign(inlet->ux, inlet->ux + g.ny);
+    for (double v : uin)
+      if (!std::isfinite(v)) {
+        g_create_error = "inlet velocity is not finite";
+        return LBM_EINVAL;
+      }
+    rho_w = inlet->rho_w;
+    if (!std::isfinite(rho_w) || rho_w <= 0.0) {
+      g_create_error = "inlet wall density must be finite and > 0";
+      return LBM_EINVAL;
+    }
+  }
+  lbm_t* h = new (std::nothrow) lbm_t();
+  if (!h) return LBM_ENOMEM;
+  std::string perr;
+  const int rc = build_plan(g, solid_mask, h->plan, perr);
+  if (rc != LBM_OK) {
+    g_create_error = perr;
+    delete h;
+    return rc;
+  }
+  h->g = g;
+  h->tau = tau;
+  h->omega = 1.0 / tau;
+  h->rho_w = rho_w;
+  h->uin = uin;
+  h->uin.resize(size_t(g.ny), 0.0);
+  // Device layout: rows padded to 64 elements; planes padded so that consecutive
+  // planes do not sit a power of two apart.
+  h->esz = elem_bytes(g.precision);
+  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64);
+  const int64_t raw = int64_t(h->pitch) * g.ny;
+  const int64_t quantum = int64_t(4096 / h->esz);
+  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(512 / h->esz);
+  size_t off = 0;
+  for (int k = 0; k < 2; ++k) {
+    h->off_buf[k] = off;
+    off = align256(off + size_t(h->plane) * kQ * h->esz);
+  }
+  h->off_node = off;
+  off = align256(off + h->plan.node.size() * sizeof(uint32_t));
+  h->off_tiles = off;
+  off = align256(off + h->plan.tile_slot.size() * sizeof(int32_t));
+  h->off_uin = off;
+  off = align256(off + size_t(g.ny) * sizeof(double));
+  h->off_part = off;
+  off = align256(off + 2 * size_t(h->plan.nslots) * 8 * sizeof(double));
+  h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
+  h->off_jpart = off;
+  off = align256(off + size_t(h->njblocks) * 2 * sizeof(double));
+  h->off_ring = off;
+  off = align256(off + size_t(g.max_record) * kRow * sizeof(double));
+  h->total = off;
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_t* h, size_t* bytes) {
+  if (!h || !bytes) return LBM_EINVAL;
+  *bytes = h->total;
+  return LBM_OK;
+}
+
+int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
+  if (!h) return LBM_EINVAL;
+  if (!device_workspace) return h->fail(LBM_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(device_workspace) % 256)
+    return h->fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < h->total) return h->fail(LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes");
+  h->ws = static_cast<char*>(device_workspace);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  e = hipMemcpyAsync(h->ws + h->off_node, h->plan.node.data(),
+                     h->plan.node.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload node codes");
+  e = hipMemcpyAsync(h->ws + h->off_tiles, h->plan.tile_slot.data(),
+                     h->plan.tile_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload tiles");
+  e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(), h->uin.size() * sizeof(double),
+                     hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload inlet");
+  for (int k = 0; k < 2; ++k) {
+    e = launch_fill_rest(h->g.precision, h->buf(k), h->plane, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
+  }
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "bind synchronize");
+  h->bound = true;
+  h->cur = 0;
+  h->steps_done = 0;
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  return LBM_OK;
+}
+
+int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
+  if (force_scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
+  const bool forces = force_scheme != 0;
+  if (forces && h->nrec + n > h->g.max_record)
+    return h->fail(LBM_EOVERFLOW, "force ring would overflow; read lbm_forces first");
+  if (n == 0) return LBM_OK;
+  const Plan& p = h->plan;
+  StepArgs a{};
+  a.plane = h->plane;
+  a.pitch = h->pitch;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.ntx = p.ntx;
+  a.ntiles = int32_t(p.tile_slot.size());
+  if (p.has_box) {
+    a.bx0 = p.box[0];
+    a.bx1 = p.box[1];
+    a.by0 = p.box[2];
+    a.by1 = p.box[3];
+  } else {
+    a.bx0 = 1;
+    a.bx1 = 0;
+    a.by0 = 1;
+    a.by1 = 0;
+  }
+  a.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
+  a.tile_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
+  a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  a.rho_w6 = 6.0 * h->rho_w;
+  a.omega = h->omega;
+  a.nslots = p.nslots;
+  double* ring = h->ring();
+  const int64_t r0 = h->nrec;
+  for (int32_t k = 0; k < n; ++k) {
+    a.src = h->buf(h->cur);
+    a.dst = h->buf(1 - h->cur);
+    a.part_out = forces ? h->part(k & 1) : nullptr;
+    a.red_in = nullptr;
+    a.red_row = nullptr;
+    a.red_prev_jnext = nullptr;
+    if (forces && k >= 1) {
+      a.red_in = h->part((k - 1) & 1);
+      a.red_row = ring + (r0 + k - 1) * kRow;
+      a.red_prev_jnext = k >= 2 ? ring + (r0 + k - 2) * kRow + 8 : nullptr;
+    }
+    hipError_t e = launch_step(h->g.precision, forces, a, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "launch step");
+    h->cur = 1 - h->cur;
+  }
+  if (forces) {
+    if (p.has_box) {
+      BoxArgs b{};
+      b.src = h->buf(h->cur);
+      b.plane = h->plane;
+      b.pitch = h->pitch;
+      b.nx = p.nx;
+      b.ny = p.ny;
+      b.bx0 = p.box[0];
+      b.bx1 = p.box[1];
+      b.by0 = p.box[2];
+      b.by1 = p.box[3];
+      b.box_bx = p.box_bx;
+      b.node = a.node;
+      b.uin = a.uin;
+      b.rho_w6 = a.rho_w6;
+      b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+      hipError_t e = launch_box_momentum(h->g.precision, b, h->njblocks, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "launch box momentum");
+    }
+    FinalArgs f{};
+    f.red_in = h->part((n - 1) & 1);
+    f.nslots = p.nslots;
+    f.row = ring + (r0 + n - 1) * kRow;
+    f.prev_jnext = n >= 2 ? ring + (r0 + n - 2) * kRow + 8 : nullptr;
+    f.jpart = p.has_box ? reinterpret_cast<const double*>(h->ws + h->off_jpart) : nullptr;
+    f.njblocks = h->njblocks;
+    hipError_t e = launch_finalize(f, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "launch finalize");
+    h->nrec += n;
+    h->rec_scheme.insert(h->rec_scheme.end(), size_t(n), force_scheme);
+  }
+  h->steps_done += n;
+  return LBM_OK;
+}
+
+int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (k_out) *k_out = h->nrec;
+  if (h->nrec == 0) return LBM_OK;
+  if (!out || cap < h->nrec) return h->fail(LBM_EINVAL, "output holds fewer rows than recorded");
+  std::vector<double> rows(size_t(h->nrec) * kRow);
+  hipError_t e = hipMemcpyAsync(rows.data(), h->ring(), rows.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download force ring");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "forces synchronize");
+  bool finite = true;
+  const double nan = std::nan("");
+  for (int64_t t = 0; t < h->nrec; ++t) {
+    const double* r = &rows[size_t(t) * kRow];
+    const uint32_t sch = h->rec_scheme[size_t(t)];
+    double* o = out + t * 6;
+    const double v[6] = {r[0], r[1], r[2], r[3], r[4] - r[8] + r[6], r[5] - r[9] + r[7]};
+    const bool want[3] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
+                          (sch & LBM_FORCE_DRTT) != 0 && h->plan.has_box};
+    for (int s = 0; s < 3; ++s)
+      for (int c = 0; c < 2; ++c) {
+        o[2 * s + c] = want[s] ? v[2 * s + c] : nan;
+        if (want[s] && !std::isfinite(v[2 * s + c])) finite = false;
+      }
+  }
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  if (!finite) return h->fail(LBM_ENONFINITE, "a recorded force is not finite");
+  return LBM_OK;
+}
+
+int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out) {
+  if (!h || (k > 0 && (!forces || !out)) || k < 0) return LBM_EINVAL;
+  const double q = 0.5 * h->g.rho_ref * h->g.u_ref * h->g.u_ref * h->g.l_ref;
+  for (int64_t j = 0; j < k * 6; ++j) out[j] = forces[j] / q;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_t* h) {
+  delete h;
+  return LBM_OK;
+}
+
+int lbm_get_links(const lbm_t* h, int32_t* node_dir, int64_t cap, int64_t* n) {
+  if (!h || !n) return LBM_EINVAL;
+  const int64_t L = int64_t(h->plan.links.size() / 2);
+  *n = L;
+  const int64_t m = L < cap ? L : cap;
+  if (m > 0) {
+    if (!node_dir) return LBM_EINVAL;
+    std::memcpy(node_dir, h->plan.links.data(), size_t(m) * 2 * sizeof(int32_t));
+  }
+  return LBM_OK;
+}
+
+int lbm_get_info(const lbm_t* h, lbm_info* info) {
+  if (!h || !info) return LBM_EINVAL;
+  info->n_fluid = h->plan.n_fluid;
+  info->n_links = int64_t(h->plan.links.size() / 2);
+  info->n_tiles = int64_t(h->plan.tile_slot.size());
+  info->n_general = h->plan.nslots;
+  info->n_box = h->plan.n_box;
+  info->steps_done = h->steps_done;
+  info->n_recorded = h->nrec;
+  info->tile_w = kTileW;
+  info->tile_h = kTileH;
+  info->plane_stride = h->plane;
+  info->pitch = h->pitch;
+  info->elem_bytes = int32_t(h->esz);
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_t* h, double* out) {
+  if (!h || !out) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  std::vector<unsigned char> raw(bytes);
+  hipError_t e = hipMemcpyAsync(raw.data(), h->buf(h->cur), bytes, hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download populations");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "populations synchronize");
+  const int nx = h->g.nx, ny = h->g.ny, prec = h->g.precision;
+  for (int i = 0; i < kQ; ++i) {
+    const double w = host_weight(prec, i);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t k = size_t(i) * h->plane + size_t(y) * h->pitch + x;
+        double v;
+        if (prec == LBM_FP64) {
+          std::memcpy(&v, &raw[k * 8], 8);
+        } else if (prec == LBM_FP32) {
+          float f;
+          std::memcpy(&f, &raw[k * 4], 4);
+          v = f;
+        } else {
+          _Float16 hv;
+          std::memcpy(&hv, &raw[k * 2], 2);
+          v = double(float(float(w) + float(hv)));
+        }
+        out[(size_t(i) * ny + y) * nx + x] = v;
+      }
+  }
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_t* h, const double* in) {
+  if (!h || !in) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  std::vector<unsigned char> raw(bytes, 0);
+  const int nx = h->g.nx, ny = h->g.ny, prec = h->g.precision;
+  for (int i = 0; i < kQ; ++i) {
+    const double w = host_weight(prec, i);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t k = size_t(i) * h->plane + size_t(y) * h->pitch + x;
+        const double v = in[(size_t(i) * ny + y) * nx + x];
+        if (prec == LBM_FP64) {
+          std::memcpy(&raw[k * 8], &v, 8);
+        } else if (prec == LBM_FP32) {
+          const float f = float(v);
+          std::memcpy(&raw[k * 4], &f, 4);
+        } else {
+          const _Float16 hv = _Float16(float(v - w));
+          std::memcpy(&raw[k * 2], &hv, 2);
+        }
+      }
+  }
+  hipError_t e = hipMemcpyAsync(h->buf(h->cur), raw.data(), bytes, hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload populations");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "populations synchronize");
+  return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_t* h, size_t* bytes) {
+  if (!h || !bytes) return LBM_EINVAL;
+  *bytes = sizeof(StateHeader) + size_t(h->plane) * kQ * h->esz;
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_t* h, void* blob, size_t cap) {
+  if (!h || !blob) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  size_t need = 0;
+  lbm_state_bytes(h, &need);
+  if (cap < need) return h->fail(LBM_EINVAL, "state buffer too small");
+  StateHeader hd{};
+  hd.magic = kStateMagic;
+  hd.nx = h->g.nx;
+  hd.ny = h->g.ny;
+  hd.precision = h->g.precision;
+  hd.plane = h->plane;
+  hd.pitch = h->pitch;
+  hd.steps_done = h->steps_done;
+  std::memcpy(blob, &hd, sizeof hd);
+  hipError_t e = hipMemcpyAsync(static_cast<char*>(blob) + sizeof hd, h->buf(h->cur),
+                                need - sizeof hd, hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download state");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "state synchronize");
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_t* h, const void* blob, size_t n) {
+  if (!h || !blob) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  size_t need = 0;
+  lbm_state_bytes(h, &need);
+  StateHeader hd{};
+  if (n < sizeof hd) return h->fail(LBM_EINVAL, "state blob too small");
+  std::memcpy(&hd, blob, sizeof hd);
+  if (hd.magic != kStateMagic || hd.nx != h->g.nx || hd.ny != h->g.ny ||
+      hd.precision != h->g.precision || hd.plane != h->plane || hd.pitch != h->pitch || n != need)
+    return h->fail(LBM_EINVAL, "state blob does not match this handle");
+  hipError_t e = hipMemcpyAsync(h->buf(h->cur), static_cast<const char*>(blob) + sizeof hd,
+                                need - sizeof hd, hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload state");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "state synchronize");
+  h->steps_done = hd.steps_done;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_t* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Host-side classification of every node and direction (the pull rules), the canonical
+// link list, and the interior/general tile split of the step kernel.
+#include "plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace lbm {
+
+namespace {
+
+bool in_box(const Plan& p, int x, int y) {
+  return p.has_box && x >= p.box[0] && x < p.box[1] && y >= p.box[2] && y < p.box[3];
+}
+
+// Code of the pull rule for fluid node (x, y), direction i (first match wins:
+// periodic wrap > wall > inlet > outlet > body > stream).
+uint32_t classify(const Plan& p, const uint8_t* mask, int x, int y, int i) {
+  int sx = x - kCx[i], sy = y - kCy[i];
+  bool wrapped = false;
+  if (p.bc_x == LBM_BCX_PERIODIC && (sx < 0 || sx >= p.nx)) {
+    sx = (sx + p.nx) % p.nx;
+    wrapped = true;
+  }
+  if (p.bc_y == LBM_BCY_PERIODIC && (sy < 0 || sy >= p.ny)) {
+    sy = (sy + p.ny) % p.ny;
+    wrapped = true;
+  }
+  if (p.bc_y == LBM_BCY_WALL && (sy < 0 || sy >= p.ny)) return kWall;
+  if (p.bc_x == LBM_BCX_INLET_OUTLET && sx < 0) return kInlet;
+  if (p.bc_x == LBM_BCX_INLET_OUTLET && sx >= p.nx)
+    return mask[size_t(sy) * p.nx + (p.nx - 1)] ? kWall : kOutlet;
+  if (mask[size_t(sy) * p.nx + sx]) return kBody;
+  return wrapped ? kWrap : kStream;
+}
+
+}  // namespace
+
+int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err) {
+  char buf[256];
+  if (g.nx < 3 || g.ny < 3) {
+    err = "nx and ny must be >= 3";
+    return LBM_EINVAL;
+  }
+  if (g.bc_x != LBM_BCX_INLET_OUTLET && g.bc_x != LBM_BCX_PERIODIC) {
+    err = "unknown bc_x";
+    return LBM_EINVAL;
+  }
+  if (g.bc_y != LBM_BCY_WALL && g.bc_y != LBM_BCY_PERIODIC) {
+    err = "unknown bc_y";
+    return LBM_EINVAL;
+  }
+  if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP16DEV) {
+    err = "unknown precision";
+    return LBM_EINVAL;
+  }
+  if (g.max_record < 1) {
+    err = "max_record must be >= 1";
+    return LBM_EINVAL;
+  }
+  // One population plane must stay below 2^31 elements (32-bit in-plane offsets).
+  const int64_t pitch = (int64_t(g.nx) + 63) / 64 * 64;
+  if (pitch * int64_t(g.ny) + 4096 >= (int64_t(1) << 31)) {
+    err = "grid too large";
+    return LBM_ENOMEM;
+  }
+  const size_t n = size_t(g.nx) * size_t(g.ny);
+  for (size_t k = 0; k < n; ++k)
+    if (mask[k] > 1) {
+      std::snprintf(buf, sizeof buf, "mask byte %zu is %d (must be 0 or 1)", k, int(mask[k]));
+      err = buf;
+      return LBM_EINVAL;
+    }
+  p = Plan();
+  p.nx = g.nx;
+  p.ny = g.ny;
+  p.bc_x = g.bc_x;
+  p.bc_y = g.bc_y;
+  p.has_box = g.box[0] >= 0;
+  for (int k = 0; k < 4; ++k) p.box[k] = g.box[k];
+  if (p.has_box) {
+    const int x0 = g.box[0], x1 = g.box[1], y0 = g.box[2], y1 = g.box[3];
+    if (x0 < 1 || y0 < 1 || x1 > g.nx - 1 || y1 > g.ny - 1 || x1 - x0 < 3 || y1 - y0 < 3) {
+      err = "control-volume box must lie one node inside the domain and span >= 3 nodes";
+      return LBM_EINVAL;
+    }
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x)
+        if (mask[size_t(y) * g.nx + x] && !(x >= x0 + 1 && x < x1 - 1 && y >= y0 + 1 && y < y1 - 1)) {
+          std::snprintf(buf, sizeof buf,
+                        "solid node (%d,%d) is not strictly inside the control-volume box", x, y);
+          err = buf;
+          return LBM_EINVAL;
+        }
+  }
+
+  // Per-node pull codes.
+  p.node.assign(n, 0u);
+  for (int y = 0; y < g.ny; ++y)
+    for (int x = 0; x < g.nx; ++x) {
+      const size_t k = size_t(y) * g.nx + x;
+      if (mask[k]) {
+        p.node[k] = kSolidBit;
+        continue;
+      }
+      ++p.n_fluid;
+      if (in_box(p, x, y)) ++p.n_box;
+      uint32_t w = 0;
+      for (int i = 1; i < kQ; ++i) w |= classify(p, mask, x, y, i) << (3 * (i - 1));
+      p.node[k] = w;
+    }
+
+  // Canonical link list: (x, i) with x + c_i a solid mask node, i.e. the pull of the
+  // opposite direction bounces back from the body.
+  for (int y = 0; y < g.ny; ++y)
+    for (int x = 0; x < g.nx; ++x) {
+      const size_t k = size_t(y) * g.nx + x;
+      if (p.node[k] & kSolidBit) continue;
+      for (int i = 1; i < kQ; ++i)
+        if (pull_code(p.node[k], kOpp[i]) == kBody) {
+          p.links.push_back(int32_t(k));
+          p.links.push_back(i);
+        }
+    }
+
+  // Tiles: interior tiles are fully inside the grid, hold only fluid nodes that stream
+  // in every direction, and do not touch the control-volume band; every other tile
+  // takes the general path and owns a slot for its force partial sums.
+  p.ntx = (g.nx + kTileW - 1) / kTileW;
+  p.nty = (g.ny + kTileH - 1) / kTileH;
+  p.tile_slot.assign(size_t(p.ntx) * p.nty, -1);
+  for (int ty = 0; ty < p.nty; ++ty)
+    for (int tx = 0; tx < p.ntx; ++tx) {
+      bool general = (tx + 1) * kTileW > g.nx || (ty + 1) * kTileH > g.ny;
+      for (int y = ty * kTileH; !general && y < (ty + 1) * kTileH; ++y)
+        for (int x = tx * kTileW; x < (tx + 1) * kTileW; ++x) {
+          const uint32_t w = p.node[size_t(y) * g.nx + x];
+          const bool band = p.has_box && x >= p.box[0] - 1 && x <= p.box[1] &&
+                            y >= p.box[2] - 1 && y <= p.box[3];
+          if (w != 0u || band) {
+            general = true;
+            break;
+          }
+        }
+      if (general) p.tile_slot[size_t(ty) * p.ntx + tx] = p.nslots++;
+    }
+  if (p.has_box) {
+    p.box_bx = (p.box[1] - p.box[0] + kTileW - 1) / kTileW;
+    p.box_rows = p.box[3] - p.box[2];
+  }
+  return LBM_OK;
+}
+
+}  // namespace lbm

@@ -1,0 +1,202 @@
+"""Python front end of the HIP library: torch supplies the device workspace and the
+stream; every step of the lattice Boltzmann path runs in the library's kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi as C
+
+PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV}
+SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT}
+
+
+def scheme_mask(schemes) -> int:
+    if isinstance(schemes, int):
+        return schemes
+    m = 0
+    for s in schemes:
+        m |= SCHEMES[s]
+    return m
+
+
+class Sim:
+    """One lattice with a body, bound to a torch-allocated device workspace.
+
+    mask: uint8 [ny, nx] (1 = solid).  tau: lattice relaxation time tau_lb.
+    uin: inlet velocity per row (scalar or [ny]); ignored for periodic x.
+    box: control-volume box (x0, x1, y0, y1) for the DRTT force, or None.
+    """
+
+    def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
+                 bc_y=C.LBM_BCY_WALL, box=None, max_record=4096, rho_ref=1.0, u_ref=1.0,
+                 l_ref=1.0, rho_w=1.0, device="cuda", stream=None):
+        import torch
+
+        self._lib = C.load()
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.ny, self.nx = mask.shape
+        self.precision = precision
+        g = C.lbm_grid()
+        g.nx, g.ny, g.bc_x, g.bc_y = self.nx, self.ny, int(bc_x), int(bc_y)
+        g.precision = PRECISIONS[precision]
+        b = (-1, -1, -1, -1) if box is None else tuple(int(v) for v in box)
+        for k in range(4):
+            g.box[k] = b[k]
+        g.max_record = int(max_record)
+        g.rho_ref, g.u_ref, g.l_ref = float(rho_ref), float(u_ref), float(l_ref)
+        self._grid = g
+        inlet = None
+        if uin is not None:
+            self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),
+                                                             (self.ny,)))
+            inlet = C.lbm_inlet(self._uin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                float(rho_w))
+        h = ctypes.c_void_p()
+        rc = self._lib.lbm_create(ctypes.byref(g),
+                                  mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  float(tau), ctypes.byref(inlet) if inlet else None,
+                                  ctypes.byref(h))
+        C.check(rc, None)
+        self._h = h
+        self.max_record = int(max_record)
+        nbytes = ctypes.c_size_t()
+        C.check(self._lib.lbm_workspace_bytes(self._h, ctypes.byref(nbytes)), self._h)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        C.check(self._lib.lbm_bind(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                   int(nbytes.value), ctypes.c_void_p(self.stream.cuda_stream)),
+                self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lbm_destroy(h)
+            self._h = None
+
+    # -- stepping ---------------------------------------------------------------------
+    def step(self, n: int, schemes=("A", "B", "DRTT")):
+        """Enqueue n steps on the stream; force rows are read back with ``forces``."""
+        m = scheme_mask(schemes)
+        C.check(self._lib.lbm_step(self._h, int(n), m), self._h)
+
+    def forces(self) -> np.ndarray:
+        """[k, 3 (A, B, DRTT), 2 (x, y)] float64 forces of the steps since the last call."""
+        info = self.info()
+        k = info.n_recorded
+        out = np.zeros((max(k, 1), 3, 2))
+        got = ctypes.c_int64()
+        rc = self._lib.lbm_forces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  max(k, 1), ctypes.byref(got))
+        if rc not in (C.LBM_OK, C.LBM_ENONFINITE):
+            C.check(rc, self._h)
+        self.last_nonfinite = rc == C.LBM_ENONFINITE
+        return out[:got.value]
+
+    def run(self, n: int, schemes=("A", "B", "DRTT")) -> np.ndarray:
+        """n steps with forces, chunked to the ring capacity."""
+        outs = []
+        left = int(n)
+        while left > 0:
+            k = min(left, self.max_record)
+            self.step(k, schemes)
+            outs.append(self.forces())
+            left -= k
+        return np.concatenate(outs) if outs else np.zeros((0, 3, 2))
+
+    def coefficients(self, forces: np.ndarray) -> np.ndarray:
+        f = np.ascontiguousarray(forces, dtype=np.float64)
+        out = np.empty_like(f)
+        C.check(self._lib.lbm_coefficients(self._h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           f.shape[0], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                self._h)
+        return out
+
+    # -- inspection -------------------------------------------------------------------
+    def info(self) -> C.lbm_info:
+        inf = C.lbm_info()
+        C.check(self._lib.lbm_get_info(self._h, ctypes.byref(inf)), self._h)
+        return inf
+
+    def links(self) -> np.ndarray:
+        return links_of(self._h)
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros((9, self.ny, self.nx))
+        C.check(self._lib.lbm_get_populations(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                self._h)
+        return out
+
+    def set_populations(self, S) -> None:
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(9, self.ny, self.nx)
+        C.check(self._lib.lbm_set_populations(self._h, S.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                self._h)
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        C.check(self._lib.lbm_state_bytes(self._h, ctypes.byref(n)), self._h)
+        buf = ctypes.create_string_buffer(n.value)
+        C.check(self._lib.lbm_get_state(self._h, buf, n.value), self._h)
+        return buf.raw
+
+    def set_state(self, blob: bytes) -> None:
+        C.check(self._lib.lbm_set_state(self._h, blob, len(blob)), self._h)
+
+
+def links_of(handle) -> np.ndarray:
+    lib = C.load()
+    n = ctypes.c_int64()
+    C.check(lib.lbm_get_links(handle, None, 0, ctypes.byref(n)), handle)
+    out = np.zeros((max(n.value, 1), 2), np.int32)
+    C.check(lib.lbm_get_links(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              n.value, ctypes.byref(n)), handle)
+    return out[:n.value]
+
+
+class Plan:
+    """A handle created but never bound: host-side classification only (no GPU)."""
+
+    def __init__(self, mask, tau=0.8, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
+                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16):
+        self._lib = C.load()
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        ny, nx = mask.shape
+        g = C.lbm_grid()
+        g.nx, g.ny, g.bc_x, g.bc_y = nx, ny, int(bc_x), int(bc_y)
+        g.precision = PRECISIONS[precision]
+        b = (-1, -1, -1, -1) if box is None else tuple(int(v) for v in box)
+        for k in range(4):
+            g.box[k] = b[k]
+        g.max_record = int(max_record)
+        g.rho_ref = g.u_ref = g.l_ref = 1.0
+        inlet = None
+        if uin is not None:
+            self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (ny,)))
+            inlet = C.lbm_inlet(self._uin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0)
+        h = ctypes.c_void_p()
+        rc = self._lib.lbm_create(ctypes.byref(g), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  float(tau), ctypes.byref(inlet) if inlet else None, ctypes.byref(h))
+        C.check(rc, None)
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lbm_destroy(h)
+            self._h = None
+
+    def links(self):
+        return links_of(self._h)
+
+    def info(self):
+        inf = C.lbm_info()
+        C.check(self._lib.lbm_get_info(self._h, ctypes.byref(inf)), self._h)
+        return inf
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        C.check(self._lib.lbm_workspace_bytes(self._h, ctypes.byref(n)), self._h)
+        return n.value

@@ -1,0 +1,195 @@
+"""CPU tests of the C ABI library: it loads, exports every entry point the header
+declares, and its host-side plan (validation, link classification) matches the oracle's
+bit for bit.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2210_10377_amd import _capi
+    return _capi
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(capi):
+    lib = capi.load()
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(capi.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(capi, tmp_path):
+    """The ctypes mirrors of lbm_grid, lbm_inlet and lbm_info have the C compiler's
+    sizes and field offsets."""
+    import subprocess
+    structs = {"lbm_grid": capi.lbm_grid, "lbm_inlet": capi.lbm_inlet, "lbm_info": capi.lbm_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_links_bitwise_vs_oracle_random_masks(orc, seed):
+    from paper_2210_10377_amd import Plan
+    rng = np.random.default_rng(500 + seed)
+    ny, nx = rng.integers(3, 30, size=2)
+    m = (rng.uniform(size=(ny, nx)) < rng.uniform(0.05, 0.5)).astype(np.uint8)
+    for bcx in (0, 1):
+        for bcy in (0, 1):
+            p = Plan(m, 0.8, np.full(ny, 0.01), bc_x=bcx, bc_y=bcy)
+            assert np.array_equal(p.links(), orc.links(m, bc_x=bcx, bc_y=bcy))
+
+
+def test_links_bitwise_workload_geometries(orc):
+    from paper_2210_10377_amd import Plan
+    w = workloads.cylinder_channel_200x80()
+    p = Plan(w.mask, w.tau, w.uin, box=w.box)
+    assert np.array_equal(p.links(), orc.links(w.mask))
+    for aoa in (0.0, 4.0, 8.0):
+        m = workloads.naca0012_mask(1024, 512, 256, 320, 256, aoa)
+        p = Plan(m, 0.6, np.full(512, 0.05))
+        L = p.links()
+        assert np.array_equal(L, orc.links(m))
+        assert len(L) > 1500
+
+
+def test_info_counts():
+    from paper_2210_10377_amd import Plan
+    w = workloads.cylinder_channel_200x80()
+    p = Plan(w.mask, w.tau, w.uin, box=w.box)
+    inf = p.info()
+    assert inf.n_fluid == 200 * 80 - 317
+    assert inf.n_box == 60 * 60 - 317
+    assert inf.n_links == len(p.links())
+
+
+def _create(capi, mask, tau=0.8, uin=0.05, box=None, **kw):
+    from paper_2210_10377_amd import Plan
+    return Plan(mask, tau, None if uin is None else np.full(mask.shape[0], uin), box=box, **kw)
+
+
+@pytest.mark.parametrize("case", ["small", "tau", "tau_nan", "mask", "box_edge", "box_body",
+                                  "bcx", "prec", "no_inlet", "inlet_nan", "max_record"])
+def test_create_rejects_invalid(capi, case):
+    from paper_2210_10377_amd import LbmError
+    m = np.zeros((20, 30), np.uint8)
+    m[8:11, 10:13] = 1
+    kw = {}
+    if case == "small":
+        m = np.zeros((2, 10), np.uint8)
+    elif case == "tau":
+        kw["tau"] = 0.5
+    elif case == "tau_nan":
+        kw["tau"] = float("nan")
+    elif case == "mask":
+        m[0, 0] = 2
+    elif case == "box_edge":
+        kw["box"] = (0, 20, 2, 18)
+    elif case == "box_body":
+        kw["box"] = (5, 12, 2, 18)    # body column 12 not strictly inside
+    elif case == "bcx":
+        kw["bc_x"] = 7
+    elif case == "prec":
+        pass
+    elif case == "no_inlet":
+        kw["uin"] = None
+    elif case == "inlet_nan":
+        kw["uin"] = float("nan")
+    elif case == "max_record":
+        kw["max_record"] = 0
+    with pytest.raises(LbmError) as e:
+        if case == "prec":
+            from paper_2210_10377_amd import sim
+            sim.PRECISIONS["bogus"] = 9
+            try:
+                _create(capi, m, precision="bogus", **kw)
+            finally:
+                del sim.PRECISIONS["bogus"]
+        else:
+            _create(capi, m, **kw)
+    assert e.value.code == capi.LBM_EINVAL
+
+
+def test_box_admissibility_agrees_with_oracle(capi, orc):
+    """The library and the oracle accept and reject the same boxes."""
+    from paper_2210_10377_amd import LbmError
+    w = workloads.cylinder_channel_200x80()
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        x0, y0 = rng.integers(0, 40, 2)
+        x1, y1 = x0 + rng.integers(1, 100), y0 + rng.integers(1, 60)
+        box = (int(x0), int(x1), int(y0), int(y1))
+        want = orc.box_admissible(w.mask, box)
+        try:
+            _create(capi, w.mask, box=box)
+            got = True
+        except LbmError:
+            got = False
+        assert got == want, box
+
+
+def test_grid_too_large_is_enomem(capi):
+    from paper_2210_10377_amd import LbmError
+    m = np.zeros((3, 3), np.uint8)
+    g = capi.lbm_grid()
+    g.nx, g.ny = 1 << 16, 1 << 16
+    g.precision = capi.LBM_FP32
+    for k in range(4):
+        g.box[k] = -1
+    g.max_record = 1
+    g.bc_x = capi.LBM_BCX_PERIODIC
+    big = np.zeros(1, np.uint8)  # never read: the size check comes first
+    h = ctypes.c_void_p()
+    rc = capi.load().lbm_create(ctypes.byref(g), big.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                0.8, None, ctypes.byref(h))
+    assert rc == capi.LBM_ENOMEM
+    del m
+
+
+def test_step_unbound_is_estate(capi):
+    from paper_2210_10377_amd import Plan
+    p = Plan(np.zeros((8, 8), np.uint8), 0.8, np.full(8, 0.01))
+    assert capi.load().lbm_step(p._h, 1, 7) == capi.LBM_ESTATE
+    out = np.zeros(6)
+    k = ctypes.c_int64()
+    assert capi.load().lbm_forces(p._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1,
+                                  ctypes.byref(k)) == capi.LBM_ESTATE
+
+
+def test_workspace_size_accounts_for_buffers(capi):
+    from paper_2210_10377_amd import Plan
+    for prec, s in (("fp64", 8), ("fp32", 4), ("fp16dev", 2)):
+        p = Plan(np.zeros((100, 300), np.uint8), 0.8, np.full(100, 0.01), precision=prec)
+        inf = p.info()
+        assert inf.elem_bytes == s
+        assert inf.pitch >= 300 and inf.pitch % 64 == 0
+        assert inf.plane_stride >= inf.pitch * 100
+        assert p.workspace_bytes() >= 2 * 9 * inf.plane_stride * s + 300 * 100 * 4
