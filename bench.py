@@ -146,10 +146,12 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "wall_s": round(wall, 3),
-        "forces_finite": bool(np.all(np.isfinite(F[:, [k for k, s in enumerate(('A', 'B', 'DRTT')) if s in schemes]]))),
-        "last_coefficients": {"A": C[-1, 0].tolist(), "B": C[-1, 1].tolist(),
-                              "DRTT": C[-1, 2].tolist()},
     }
+    if len(F):
+        cols = [k for k, s in enumerate(("A", "B", "DRTT")) if s in schemes]
+        out["forces_finite"] = bool(np.all(np.isfinite(F[:, cols])))
+        out["last_coefficients"] = {s: C[-1, k].tolist() for k, s in enumerate(("A", "B", "DRTT"))
+                                    if s in schemes}
     del sim
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -17,6 +17,16 @@ using namespace lbm;
 
 namespace {
 
+#ifndef LBM_PITCH_PAD
+#define LBM_PITCH_PAD 128
+#endif
+#ifndef LBM_PLANE_PAD_ROWS
+#define LBM_PLANE_PAD_ROWS 0
+#endif
+#ifndef LBM_PLANE_PAD_BYTES
+#define LBM_PLANE_PAD_BYTES 512
+#endif
+
 constexpr int kRow = 10;  // FAx FAy FBx FBy Jx Jy Phix Phiy Jnext_x Jnext_y
 constexpr uint64_t kStateMagic = 0x4c424d5332443951ull;  // "LBMS2D9Q"
 
@@ -78,6 +88,12 @@ struct lbm_t {
     return LBM_EHIP;
   }
   void* buf(int k) const { return ws + off_buf[k]; }
+  // Size of one state buffer for buffer-resource addressing, or 0 when it needs 64-bit
+  // addresses.
+  uint32_t buf_bytes32() const {
+    const uint64_t b = uint64_t(plane) * kQ * esz;
+    return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u;
+  }
   double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
   double* part(int k) const {
     return reinterpret_cast<double*>(ws + off_part) + size_t(k) * size_t(plan.nslots) * 8;
@@ -136,10 +152,10 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   // Device layout: rows padded to 64 elements; planes padded so that consecutive
   // planes do not sit a power of two apart.
   h->esz = elem_bytes(g.precision);
-  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64);
-  const int64_t raw = int64_t(h->pitch) * g.ny;
+  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64 + LBM_PITCH_PAD);
+  const int64_t raw = int64_t(h->pitch) * (g.ny + LBM_PLANE_PAD_ROWS);
   const int64_t quantum = int64_t(4096 / h->esz);
-  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(512 / h->esz);
+  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(LBM_PLANE_PAD_BYTES / h->esz);
   size_t off = 0;
   for (int k = 0; k < 2; ++k) {
     h->off_buf[k] = off;
@@ -148,7 +164,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   h->off_node = off;
   off = align256(off + h->plan.node.size() * sizeof(uint32_t));
   h->off_tiles = off;
-  off = align256(off + h->plan.tile_slot.size() * sizeof(int32_t));
+  off = align256(off + h->plan.strip_slot.size() * sizeof(int32_t));
   h->off_uin = off;
   off = align256(off + size_t(g.ny) * sizeof(double));
   h->off_part = off;
@@ -181,8 +197,8 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
   e = hipMemcpyAsync(h->ws + h->off_node, h->plan.node.data(),
                      h->plan.node.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload node codes");
-  e = hipMemcpyAsync(h->ws + h->off_tiles, h->plan.tile_slot.data(),
-                     h->plan.tile_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
+  e = hipMemcpyAsync(h->ws + h->off_tiles, h->plan.strip_slot.data(),
+                     h->plan.strip_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload tiles");
   e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(), h->uin.size() * sizeof(double),
                      hipMemcpyHostToDevice, h->stream);
@@ -213,11 +229,17 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
   const Plan& p = h->plan;
   StepArgs a{};
   a.plane = h->plane;
+  a.buf_bytes = h->buf_bytes32();
   a.pitch = h->pitch;
   a.nx = p.nx;
   a.ny = p.ny;
   a.ntx = p.ntx;
-  a.ntiles = int32_t(p.tile_slot.size());
+  a.nty = p.nty;
+  a.gx0 = p.gx0;
+  a.gx1 = p.gx1;
+  a.gy0 = p.gy0;
+  a.gy1 = p.gy1;
+  a.ntiles = p.ntiles;
   if (p.has_box) {
     a.bx0 = p.box[0];
     a.bx1 = p.box[1];
@@ -230,7 +252,7 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
     a.by1 = 0;
   }
   a.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
-  a.tile_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
+  a.strip_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
   a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
   a.rho_w6 = 6.0 * h->rho_w;
   a.omega = h->omega;
@@ -258,6 +280,7 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
       BoxArgs b{};
       b.src = h->buf(h->cur);
       b.plane = h->plane;
+      b.buf_bytes = a.buf_bytes;
       b.pitch = h->pitch;
       b.nx = p.nx;
       b.ny = p.ny;
@@ -350,8 +373,8 @@ int lbm_get_info(const lbm_t* h, lbm_info* info) {
   if (!h || !info) return LBM_EINVAL;
   info->n_fluid = h->plan.n_fluid;
   info->n_links = int64_t(h->plan.links.size() / 2);
-  info->n_tiles = int64_t(h->plan.tile_slot.size());
-  info->n_general = h->plan.nslots;
+  info->n_tiles = h->plan.ntiles;
+  info->n_general = h->plan.ngeneral;
   info->n_box = h->plan.n_box;
   info->steps_done = h->steps_done;
   info->n_recorded = h->nrec;

@@ -12,12 +12,16 @@ struct StepArgs {
   const void* src;  // post-collision state of the previous step (storage type)
   void* dst;        // post-collision state of this step
   int64_t plane;    // population plane stride, elements
+  uint32_t buf_bytes;  // bytes of one state buffer when below 4 GiB (buffer-resource
+                       // addressing), 0 for 64-bit global addressing
   int32_t pitch;    // row pitch, elements
   int32_t nx, ny;
-  int32_t ntx, ntiles;
+  int32_t ntx, nty, ntiles;
+  int32_t gx0, gx1, gy0, gy1;  // node rectangle (inclusive) of every non-border node that
+                               // needs the general path; empty when gx0 > gx1
   int32_t bx0, bx1, by0, by1;  // control-volume box; bx0 > bx1 when there is none
   const uint32_t* node;        // per-node pull codes
-  const int32_t* tile_slot;    // per-tile partial slot, -1 for interior tiles
+  const int32_t* strip_slot;   // per 64-node strip: force partial slot, or -1
   const double* uin;           // [ny] inlet velocity
   double rho_w6;               // 2 rho_w / c_s^2 = 6 rho_w
   double omega;                // 1 / tau_lb
@@ -33,6 +37,7 @@ struct StepArgs {
 struct BoxArgs {
   const void* src;
   int64_t plane;
+  uint32_t buf_bytes;
   int32_t pitch, nx, ny;
   int32_t bx0, bx1, by0, by1;
   int32_t box_bx;             // blocks per box row

@@ -59,7 +59,7 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     return LBM_EINVAL;
   }
   // One population plane must stay below 2^31 elements (32-bit in-plane offsets).
-  const int64_t pitch = (int64_t(g.nx) + 63) / 64 * 64;
+  const int64_t pitch = (int64_t(g.nx) + 63) / 64 * 64 + 256;  // row padding margin
   if (pitch * int64_t(g.ny) + 4096 >= (int64_t(1) << 31)) {
     err = "grid too large";
     return LBM_ENOMEM;
@@ -123,27 +123,48 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         }
     }
 
-  // Tiles: interior tiles are fully inside the grid, hold only fluid nodes that stream
-  // in every direction, and do not touch the control-volume band; every other tile
-  // takes the general path and owns a slot for its force partial sums.
+  // Rectangle of every node off the domain border that needs the general path.
+  auto band = [&](int x, int y) {
+    return p.has_box && x >= p.box[0] - 1 && x <= p.box[1] && y >= p.box[2] - 1 &&
+           y <= p.box[3];
+  };
+  for (int y = 1; y < g.ny - 1; ++y)
+    for (int x = 1; x < g.nx - 1; ++x) {
+      if (p.node[size_t(y) * g.nx + x] == 0u && !band(x, y)) continue;
+      if (p.gx0 > p.gx1) {
+        p.gx0 = p.gx1 = x;
+        p.gy0 = p.gy1 = y;
+      } else {
+        p.gx0 = std::min(p.gx0, x);
+        p.gx1 = std::max(p.gx1, x);
+        p.gy0 = std::min(p.gy0, y);
+        p.gy1 = std::max(p.gy1, y);
+      }
+    }
+  // Tiles and strips.  A strip outside that rectangle and off the border streams
+  // plainly; the others take the general path, and those holding a link node or a
+  // control-volume-band node own a force-partial slot.
   p.ntx = (g.nx + kTileW - 1) / kTileW;
   p.nty = (g.ny + kTileH - 1) / kTileH;
-  p.tile_slot.assign(size_t(p.ntx) * p.nty, -1);
+  p.ntiles = p.ntx * p.nty;
+  p.strip_slot.assign(size_t(p.ntiles) * kStrips, -1);
   for (int ty = 0; ty < p.nty; ++ty)
-    for (int tx = 0; tx < p.ntx; ++tx) {
-      bool general = (tx + 1) * kTileW > g.nx || (ty + 1) * kTileH > g.ny;
-      for (int y = ty * kTileH; !general && y < (ty + 1) * kTileH; ++y)
-        for (int x = tx * kTileW; x < (tx + 1) * kTileW; ++x) {
-          const uint32_t w = p.node[size_t(y) * g.nx + x];
-          const bool band = p.has_box && x >= p.box[0] - 1 && x <= p.box[1] &&
-                            y >= p.box[2] - 1 && y <= p.box[3];
-          if (w != 0u || band) {
-            general = true;
-            break;
+    for (int tx = 0; tx < p.ntx; ++tx)
+      for (int w = 0; w < kStrips; ++w) {
+        const int x0 = tx * kTileW + w * kStripW, y0 = ty * kTileH;
+        if (strip_is_plain(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, x0, y0)) continue;
+        ++p.ngeneral;
+        bool forces = false;
+        for (int y = y0; y < std::min(y0 + kTileH, g.ny); ++y)
+          for (int x = x0; x < std::min(x0 + kStripW, g.nx); ++x) {
+            const uint32_t wd = p.node[size_t(y) * g.nx + x];
+            bool link = false;
+            if (!(wd & kSolidBit))
+              for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
+            forces = forces || link || band(x, y);
           }
-        }
-      if (general) p.tile_slot[size_t(ty) * p.ntx + tx] = p.nslots++;
-    }
+        if (forces) p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.nslots++;
+      }
   if (p.has_box) {
     p.box_bx = (p.box[1] - p.box[0] + kTileW - 1) / kTileW;
     p.box_rows = p.box[3] - p.box[2];

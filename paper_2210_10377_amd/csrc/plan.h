@@ -31,9 +31,24 @@ constexpr uint32_t kSolidBit = 1u << 31;
 
 constexpr uint32_t pull_code(uint32_t word, int i) { return (word >> (3 * (i - 1))) & 7u; }
 
-// Tile shape of the step kernel: one 256-thread block covers kTileW x kTileH nodes.
+// Tile shape of the step kernel: one 256-thread block covers kTileW x kTileH nodes,
+// each of its four waves a 64 x kTileH strip.
+#ifndef LBM_TILE_H
+#define LBM_TILE_H 2
+#endif
 constexpr int kTileW = 256;
-constexpr int kTileH = 4;
+constexpr int kTileH = LBM_TILE_H;
+constexpr int kStripW = 64;
+constexpr int kStrips = kTileW / kStripW;
+
+// A strip streams plainly when it stays off the domain border and outside the
+// rectangle [gx0, gx1] x [gy0, gy1] that holds every other boundary, body and
+// control-volume-band node.  Host plan and step kernel share this rule.
+constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int x0,
+                              int y0) {
+  return x0 > 0 && x0 + kStripW < nx && y0 > 0 && y0 + kTileH < ny &&
+         !(y0 <= gy1 && y0 + kTileH - 1 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
+}
 
 struct Plan {
   int nx = 0, ny = 0, bc_x = 0, bc_y = 0;
@@ -41,9 +56,16 @@ struct Plan {
   int box[4] = {-1, -1, -1, -1};
   std::vector<uint32_t> node;     // [ny*nx] pull codes + solid bit
   std::vector<int32_t> links;     // [L][2] (y*nx + x, i), canonical order
-  int ntx = 0, nty = 0;           // tiles per row / column
-  std::vector<int32_t> tile_slot; // -1: interior tile; >= 0: general tile, partial slot
-  int nslots = 0;                 // general tiles
+  int ntx = 0, nty = 0, ntiles = 0;  // tiles per row / column / total
+  // Inclusive node rectangle holding every node off the domain border that needs the
+  // general path (a solid node, a pull that is not plain streaming, a node of the
+  // control-volume band); empty when gx0 > gx1.
+  int gx0 = 0, gx1 = -1, gy0 = 0, gy1 = -1;
+  // Per strip (tile-major, kStrips per tile): the index >= 0 of its force-partial slot
+  // when it holds a link node or a control-volume-band node, else -1.
+  std::vector<int32_t> strip_slot;
+  int nslots = 0;                 // strips with force terms
+  int ngeneral = 0;               // strips that take the general path
   int64_t n_fluid = 0, n_box = 0;
   // tail control-volume momentum sweep: blocks of kTileW nodes along each box row
   int box_bx = 0, box_rows = 0;

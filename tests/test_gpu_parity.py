@@ -194,7 +194,11 @@ def test_chunked_calls_match_single_call():
     for n in (1, 2, 30, 57):
         g2.step(n)
     F2 = g2.forces()
-    assert np.array_equal(F1, F2)
+    # A and B are per-step sums: identical.  DRTT needs J(t+1), which at the end of a
+    # call comes from a separate control-volume sweep whose partial sums are grouped
+    # differently from the step kernel's: equal to rounding.
+    assert np.array_equal(F1[:, :2], F2[:, :2])
+    assert np.abs(F1[:, 2] - F2[:, 2]).max() <= 1e-12 * np.abs(F1[:, 2]).max()
 
 
 def test_checkpoint_restore_bitwise():
