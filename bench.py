@@ -25,13 +25,17 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS incl. per-step force + HBM GB/s % peak; adjoint MLUPS; Cd rel err vs FP64"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16dev": 36}
-KERNEL_SRC = os.path.join(ROOT, "paper_2210_10377_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2210_10377_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the library sources (kernel, launch layout and plan)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload: str, precision: str):
@@ -43,7 +47,7 @@ def measured_traffic(workload: str, precision: str):
     except (OSError, ValueError):
         return None
     rec = t.get(f"{workload}/{precision}")
-    if not rec or rec.get("kernel_sha256") != kernel_hash():
+    if not rec or rec.get("sources_sha256") != kernel_hash():
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -76,6 +80,9 @@ def main():
     ap.add_argument("--schemes", default="A,B,DRTT")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device-to-device copy of 1 GiB five times (the "
+                         "known-size reference for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -85,6 +92,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}), flush=True)
+        return
 
     import workloads
     from paper_2210_10377_amd import Sim

@@ -156,6 +156,21 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
   }
 }
 
+// Block index -> tile index.  Blocks are dealt round-robin over the 8 XCDs; this
+// mapping hands each XCD runs of kGroup consecutive row-major tiles, so the cache
+// lines shared by horizontally adjacent tiles (the +-1-shifted pulls) meet in one L2,
+// while the XCDs together still sweep one region of memory at a time.  The tail that
+// does not fill a whole round keeps the identity mapping.
+#ifndef LBM_XCD_GROUP
+#define LBM_XCD_GROUP 4
+#endif
+__device__ __forceinline__ int block_tile(int b, int n) {
+  constexpr int kGroup = LBM_XCD_GROUP, kRound = 8 * kGroup;
+  if (kGroup == 1 || b >= n / kRound * kRound) return b;
+  const int xcd = b & 7, k = b >> 3;
+  return ((k / kGroup) * 8 + xcd) * kGroup + (k % kGroup);
+}
+
 __device__ __forceinline__ bool in_box(const StepArgs& a, int x, int y) {
   return x >= a.bx0 && x < a.bx1 && y >= a.by0 && y < a.by1;
 }
@@ -373,7 +388,7 @@ __device__ __forceinline__ double reduce_partials8(const double* in, int nslots)
 template <int P, bool BUF, bool FORCES>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
-  int tile = blockIdx.x;
+  int tile = block_tile(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
   if (a.red_in) {
     // Block 0 is dispatched first: it reduces the previous step's force partials while
     // the tiles stream.

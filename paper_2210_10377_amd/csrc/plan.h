@@ -34,7 +34,7 @@ constexpr uint32_t pull_code(uint32_t word, int i) { return (word >> (3 * (i - 1
 // Tile shape of the step kernel: one 256-thread block covers kTileW x kTileH nodes,
 // each of its four waves a 64 x kTileH strip.
 #ifndef LBM_TILE_H
-#define LBM_TILE_H 2
+#define LBM_TILE_H 1
 #endif
 constexpr int kTileW = 256;
 constexpr int kTileH = LBM_TILE_H;
