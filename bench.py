@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS incl. per-step force + HBM GB/s % peak; adjoint MLUPS; Cd rel err vs FP64"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16dev": 36}
+BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp32dev": 72, "fp16dev": 36}
 CSRC = os.path.join(ROOT, "paper_2210_10377_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
@@ -68,6 +68,56 @@ def cpu_baseline(w, steps: int):
                       f"({dt:.1f} s, FP64, one thread)"}
 
 
+def precision_study(steps: int):
+    """FP32 and FP16-deviation storage against FP64 storage (itself matched to the
+    oracle to 1e-10) on the 2048x1024 NACA0012 channel.  Coefficient errors are relative
+    to the largest FP64 coefficient magnitude of the run (per step) and to the FP64 mean
+    over the last 2000 steps (window means); velocity errors are relative to the inlet
+    speed."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    def velocity(S):
+        cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+        cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)
+        rho = S.sum(0)
+        return np.tensordot(cx, S, 1) / rho, np.tensordot(cy, S, 1) / rho
+
+    for aoa in (0.0, 4.0, 8.0):
+        for re in (100.0, 1000.0):
+            w = workloads.naca_2048x1024(aoa=aoa, re=re)
+            runs = {}
+            for prec in ("fp64", "fp32", "fp32dev", "fp16dev"):
+                sim = Sim(w.mask, w.tau, w.uin, precision=prec, box=w.box, max_record=5000,
+                          u_ref=w.u_ref, l_ref=w.l_ref)
+                t0 = time.perf_counter()
+                F = sim.run(steps)
+                C = sim.coefficients(F)
+                runs[prec] = (C, velocity(sim.populations()), time.perf_counter() - t0)
+                del sim
+            C64, (u64, v64), _ = runs["fp64"]
+            fl = w.mask == 0
+            out = {"case": w.name, "steps": steps, "tau": w.tau,
+                   "fp64_window_mean": {s: C64[-2000:, k].mean(0).tolist()
+                                        for k, s in enumerate(("A", "B", "DRTT"))}}
+            for prec in ("fp32", "fp32dev", "fp16dev"):
+                C, (u, v), wall = runs[prec]
+                e = {}
+                for k, s in enumerate(("A", "B", "DRTT")):
+                    scale = np.abs(C64[:, k]).max(0)
+                    e[s] = {"step_max_rel_cd_cl": (np.abs(C[:, k] - C64[:, k]).max(0) / scale).tolist(),
+                            "window_mean_rel_cd_cl": (np.abs(C[-2000:, k].mean(0) - C64[-2000:, k].mean(0))
+                                                      / np.abs(C64[-2000:, k].mean(0))).tolist()}
+                du = np.hypot(u - u64, v - v64)[fl]
+                e["velocity_linf_over_U"] = float(du.max() / w.u_ref)
+                e["velocity_l2_rel"] = float(np.sqrt((du ** 2).sum() / (u64[fl] ** 2 + v64[fl] ** 2).sum()))
+                e["finite"] = bool(np.all(np.isfinite(C)))
+                out[prec] = e
+            print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +130,11 @@ def main():
     ap.add_argument("--schemes", default="A,B,DRTT")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32 and FP16-deviation storage against FP64 on the NACA0012 "
+                         "2048x1024 channel (AoA 0/4/8, Re 100/1000): force, coefficient "
+                         "and velocity-field errors; one JSON line per case")
+    ap.add_argument("--study-steps", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
@@ -105,6 +160,10 @@ def main():
 
     import workloads
     from paper_2210_10377_amd import Sim
+
+    if args.precision_study:
+        precision_study(args.study_steps)
+        return
 
     if args.workload == "naca8192":
         w = workloads.naca_8192x4096(aoa=args.aoa, re=args.re)
@@ -153,7 +212,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16 storage / f32 arithmetic"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
+                  "fp16dev": "f16 storage / f32 arithmetic"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "tau": w.tau,
                    "storage": args.precision, "schemes": list(schemes),

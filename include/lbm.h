@@ -20,6 +20,10 @@
  *     over the grid are row-major [ny][nx]; population arrays are [9][ny][nx].
  *   - Directions: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
  *     8:(1,-1); weights 4/9, 1/9, 1/36 (Table I), c_s^2 = theta0 = 1/3.
+ *   - Deviation storages (LBM_FP16DEV, LBM_FP32DEV) keep h_i = f_i - w_i and do the
+ *     collision in deviation form (rho - 1 = sum h_i, rho u = sum c_i h_i, h~ = h +
+ *     omega (f^eq - w - h)), which avoids the cancellation of rho ~ 1 in binary32; the
+ *     boundary rules act on h exactly as on f because w_i = w_opposite(i).
  *   - tau is the lattice relaxation time tau_lb: the factor 2 beta of Eq. CollideAdv is
  *     1/tau_lb, and the kinematic viscosity is (tau_lb - 1/2)/3.
  *   - The stored state is the post-collision field of the last step.  One step pulls it
@@ -74,6 +78,7 @@ extern "C" {
 #define LBM_FP64 0    /* binary64 populations, binary64 arithmetic                  */
 #define LBM_FP32 1    /* binary32 populations, binary32 arithmetic                  */
 #define LBM_FP16DEV 2 /* binary16 deviations h_i = f_i - w_i, binary32 arithmetic   */
+#define LBM_FP32DEV 3 /* binary32 deviations h_i = f_i - w_i, binary32 arithmetic   */
 
 #define LBM_BCX_INLET_OUTLET 0 /* x: inlet at x = -1/2, outlet at x = nx - 1/2      */
 #define LBM_BCX_PERIODIC 1
@@ -89,7 +94,7 @@ extern "C" {
 typedef struct lbm_grid {
   int32_t nx, ny;     /* grid size, each >= 3                                      */
   int32_t bc_x, bc_y; /* LBM_BCX_*, LBM_BCY_*                                      */
-  int32_t precision;  /* LBM_FP64 / LBM_FP32 / LBM_FP16DEV                         */
+  int32_t precision;  /* LBM_FP64 / LBM_FP32 / LBM_FP16DEV / LBM_FP32DEV           */
   int32_t box[4];     /* DRTT control volume [x0, x1) x [y0, y1); x0 < 0: none.
                          Must satisfy 1 <= x0, x1 <= nx - 1, 1 <= y0, y1 <= ny - 1,
                          and hold every solid node strictly inside
@@ -111,7 +116,7 @@ typedef struct lbm_info {
   int64_t n_fluid;        /* fluid nodes                                             */
   int64_t n_links;        /* fluid-solid links (x, i)                                */
   int64_t n_tiles;        /* tiles of the step kernel                                */
-  int64_t n_general;      /* tiles that take the boundary / force path               */
+  int64_t n_general;      /* 64-node strips that take the boundary / force path      */
   int64_t n_box;          /* fluid nodes in the control volume                       */
   int64_t steps_done;     /* steps taken since create (or the restored state)        */
   int64_t n_recorded;     /* force rows waiting in the ring                          */
@@ -166,11 +171,13 @@ int lbm_get_links(const lbm_t* h, int32_t* node_dir, int64_t cap, int64_t* n);
 int lbm_get_info(const lbm_t* h, lbm_info* info);
 
 /* Current stored (post-collision) populations as binary64, out[9][ny][nx] (host;
- * FP16DEV reads w_i + h_i).  Synchronises the stream. */
+ * the deviation storages read w_i + h_i, summed in binary64).  Synchronises the
+ * stream. */
 int lbm_get_populations(lbm_t* h, double* out);
 
 /* Replace the stored populations (host, [9][ny][nx]); values are rounded to the
- * storage precision (FP16DEV stores h_i = f_i - w_i rounded to nearest even).
+ * storage precision (the deviation storages keep h_i = f_i - w_i, computed in binary64
+ * and rounded once to nearest even).
  * Synchronises the stream. */
 int lbm_set_populations(lbm_t* h, const double* in);
 

@@ -33,8 +33,10 @@ constexpr uint64_t kStateMagic = 0x4c424d5332443951ull;  // "LBMS2D9Q"
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 size_t elem_bytes(int precision) {
-  return precision == LBM_FP64 ? 8 : (precision == LBM_FP32 ? 4 : 2);
+  return precision == LBM_FP64 ? 8 : (precision == LBM_FP16DEV ? 2 : 4);
 }
+
+bool is_dev(int precision) { return precision == LBM_FP16DEV || precision == LBM_FP32DEV; }
 
 std::string g_create_error;
 
@@ -46,14 +48,8 @@ struct StateHeader {
   int64_t steps_done;
 };
 
-// Host-side value of the lattice weight in the storage's arithmetic precision.
-double host_weight(int precision, int i) {
-  if (precision == LBM_FP16DEV) {
-    const float w = i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
-    return double(w);
-  }
-  return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
-}
+// Lattice weight (Table I) of direction i: the base of the deviation storages.
+double host_weight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
 }  // namespace
 
@@ -397,23 +393,23 @@ int lbm_get_populations(lbm_t* h, double* out) {
   if (e != hipSuccess) return h->hip_fail(e, "populations synchronize");
   const int nx = h->g.nx, ny = h->g.ny, prec = h->g.precision;
   for (int i = 0; i < kQ; ++i) {
-    const double w = host_weight(prec, i);
+    const double base = is_dev(prec) ? host_weight(i) : 0.0;
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const size_t k = size_t(i) * h->plane + size_t(y) * h->pitch + x;
         double v;
         if (prec == LBM_FP64) {
           std::memcpy(&v, &raw[k * 8], 8);
-        } else if (prec == LBM_FP32) {
+        } else if (prec == LBM_FP16DEV) {
+          _Float16 hv;
+          std::memcpy(&hv, &raw[k * 2], 2);
+          v = double(hv);
+        } else {
           float f;
           std::memcpy(&f, &raw[k * 4], 4);
           v = f;
-        } else {
-          _Float16 hv;
-          std::memcpy(&hv, &raw[k * 2], 2);
-          v = double(float(float(w) + float(hv)));
         }
-        out[(size_t(i) * ny + y) * nx + x] = v;
+        out[(size_t(i) * ny + y) * nx + x] = base + v;
       }
   }
   return LBM_OK;
@@ -426,19 +422,19 @@ int lbm_set_populations(lbm_t* h, const double* in) {
   std::vector<unsigned char> raw(bytes, 0);
   const int nx = h->g.nx, ny = h->g.ny, prec = h->g.precision;
   for (int i = 0; i < kQ; ++i) {
-    const double w = host_weight(prec, i);
+    const double base = is_dev(prec) ? host_weight(i) : 0.0;
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const size_t k = size_t(i) * h->plane + size_t(y) * h->pitch + x;
-        const double v = in[(size_t(i) * ny + y) * nx + x];
+        const double v = in[(size_t(i) * ny + y) * nx + x] - base;
         if (prec == LBM_FP64) {
           std::memcpy(&raw[k * 8], &v, 8);
-        } else if (prec == LBM_FP32) {
+        } else if (prec == LBM_FP16DEV) {
+          const _Float16 hv = _Float16(v);
+          std::memcpy(&raw[k * 2], &hv, 2);
+        } else {
           const float f = float(v);
           std::memcpy(&raw[k * 4], &f, 4);
-        } else {
-          const _Float16 hv = _Float16(float(v - w));
-          std::memcpy(&raw[k * 2], &hv, 2);
         }
       }
   }

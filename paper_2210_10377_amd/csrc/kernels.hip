@@ -39,7 +39,8 @@ __device__ __forceinline__ constexpr C weight(int i) {
   return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
 }
 
-// Storage of a population and the arithmetic type it is computed in.
+// Storage of a population and the arithmetic type it is computed in.  Deviation
+// storages keep h_i = f_i - w_i; their arithmetic stays in deviation form.
 template <int P>
 struct Storage;
 
@@ -47,27 +48,45 @@ template <>
 struct Storage<LBM_FP64> {
   using T = double;
   using C = double;
-  static __device__ __forceinline__ C unpack(T v, int) { return v; }
-  static __device__ __forceinline__ T pack(C v, int) { return v; }
+  static constexpr bool kDev = false;
 };
 
 template <>
 struct Storage<LBM_FP32> {
   using T = float;
   using C = float;
-  static __device__ __forceinline__ C unpack(T v, int) { return v; }
-  static __device__ __forceinline__ T pack(C v, int) { return v; }
+  static constexpr bool kDev = false;
 };
 
-// Deviation from the lattice weight stored in binary16 (round to nearest even);
-// arithmetic in binary32.
+template <>
+struct Storage<LBM_FP32DEV> {
+  using T = float;
+  using C = float;
+  static constexpr bool kDev = true;
+};
+
 template <>
 struct Storage<LBM_FP16DEV> {
   using T = _Float16;
   using C = float;
-  static __device__ __forceinline__ C unpack(T v, int i) { return weight<float>(i) + float(v); }
-  static __device__ __forceinline__ T pack(C v, int i) { return T(v - weight<float>(i)); }
+  static constexpr bool kDev = true;
 };
+
+// Stored value -> arithmetic value (f, or h for deviation storages) and back (binary16:
+// round to nearest even).
+template <int P>
+__device__ __forceinline__ typename Storage<P>::C unpack(typename Storage<P>::T v) {
+  return typename Storage<P>::C(v);
+}
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T pack(typename Storage<P>::C v) {
+  return typename Storage<P>::T(v);
+}
+// The population f_i in binary64 from a stored value of direction i.
+template <int P>
+__device__ __forceinline__ double to_f64(typename Storage<P>::T v, int i) {
+  return Storage<P>::kDev ? weight<double>(i) + double(v) : double(v);
+}
 
 // Raw buffer access of one stored population (cache policy `aux`: 0 default, 2 nt).
 template <class T>
@@ -138,12 +157,16 @@ struct Planes<T, false> {
 };
 
 // BGK collision of one node (Eq. CollideAdv, first line, with 2 beta = omega) towards
-// the second-order equilibrium w_i rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2].
-template <class C>
+// the second-order equilibrium w_i rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2].  In
+// deviation form (DEV) the inputs and outputs are h_i = f_i - w_i: rho - 1 = sum h_i,
+// rho u = sum c_i h_i, and f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 -
+// 1.5 u^2)], so no quantity of order one is formed.
+template <class C, bool DEV>
 __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
-  const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const C s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const C jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
   const C jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+  const C rho = DEV ? C(1) + s : s;
   const C ir = C(1) / rho;
   const C ux = jx * ir, uy = jy * ir;
   const C usq = C(1.5) * (ux * ux + uy * uy);
@@ -151,7 +174,8 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy;
-    const C feq = weight<C>(i) * rho * (C(1) + C(3) * cu + C(4.5) * cu * cu - usq);
+    const C poly = C(3) * cu + C(4.5) * cu * cu - usq;
+    const C feq = DEV ? weight<C>(i) * (s + rho * poly) : weight<C>(i) * rho * (C(1) + poly);
     g[i] = f[i] + om * (feq - f[i]);
   }
 }
@@ -204,11 +228,11 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
   for (int r = 0; r < kTileH; ++r) {
     C f[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[i] = S::unpack(v[r][i], i);
+    for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[r][i]);
     C g[kQ];
-    collide<C>(f, C(a.omega), g);
+    collide<C, S::kDev>(f, C(a.omega), g);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, S::pack(g[i], i));
+    for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, pack<P>(g[i]));
   }
 }
 
@@ -244,11 +268,12 @@ __device__ __forceinline__ void pull_all(const A& src, int pitch, int nx, int ny
   typename S::T v[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) v[i] = src.ld_lane(pl[i], off[i]);
-  // Opposite directions share a weight, so the deviation base of plane i serves both.
+  // The inlet term is additive, so it applies to f and to h = f - w alike (opposite
+  // directions share a weight).
   const C uw = C(rho_w6 * uin[y]);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    f[i] = S::unpack(v[i], i);
+    f[i] = unpack<P>(v[i]);
     if (i > 0 && kCx[i] != 0 && pull_code(w, i) == kInlet) f[i] += uw * (weight<C>(i) * C(kCx[i]));
   }
 }
@@ -294,11 +319,11 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
     C g[kQ];
-    collide<C>(f, C(a.omega), g);
+    collide<C, S::kDev>(f, C(a.omega), g);
     T s[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      s[i] = S::pack(g[i], i);
+      s[i] = pack<P>(g[i]);
       dst.st(i, o, s[i]);
     }
     if (forces) {
@@ -308,8 +333,8 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
         if (pull_code(w, kOpp[i]) != kBody) continue;
-        const double sv = double(S::unpack(s[i], i));
-        const double fa = double(f[i]) + sv;
+        const double sv = to_f64<P>(s[i], i);
+        const double fa = (S::kDev ? weight<double>(i) + double(f[i]) : double(f[i])) + sv;
         acc[0] += kCx[i] * fa;
         acc[1] += kCy[i] * fa;
         acc[2] += kCx[i] * (sv + sv);
@@ -321,15 +346,16 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
         double jx = 0.0, jy = 0.0;
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-          jx += kCx[i] * double(f[i]);
-          jy += kCy[i] * double(f[i]);
+          const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+          jx += kCx[i] * fi;
+          jy += kCy[i] * fi;
         }
         acc[4] += jx;
         acc[5] += jy;
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
           if (!in_box(a, x + kCx[i], y + kCy[i])) {
-            const double sv = double(S::unpack(s[i], i));
+            const double sv = to_f64<P>(s[i], i);
             acc[6] -= kCx[i] * sv;
             acc[7] -= kCy[i] * sv;
           }
@@ -337,7 +363,7 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
           if (in_box(a, x + kCx[i], y + kCy[i])) {
-            const double sv = double(S::unpack(s[i], i));
+            const double sv = to_f64<P>(s[i], i);
             acc[6] += kCx[i] * sv;
             acc[7] += kCy[i] * sv;
           }
@@ -439,8 +465,9 @@ __global__ __launch_bounds__(kThreads) void box_momentum_kernel(BoxArgs a) {
       pull_all<P>(src, a.pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
-        v[0] += kCx[i] * double(f[i]);
-        v[1] += kCy[i] * double(f[i]);
+        const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+        v[0] += kCx[i] * fi;
+        v[1] += kCy[i] * fi;
       }
     }
   }
@@ -485,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t 
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
     const int i = int(k / plane);
-    p[k] = S::pack(weight<typename S::C>(i), i);
+    p[k] = S::kDev ? T(0) : T(weight<typename S::C>(i));
   }
 }
 
@@ -519,6 +546,7 @@ hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_
   switch (precision) {
     case LBM_FP64: return step_dispatch<LBM_FP64>(forces, a, s);
     case LBM_FP32: return step_dispatch<LBM_FP32>(forces, a, s);
+    case LBM_FP32DEV: return step_dispatch<LBM_FP32DEV>(forces, a, s);
     default: return step_dispatch<LBM_FP16DEV>(forces, a, s);
   }
 }
@@ -527,6 +555,7 @@ hipError_t launch_box_momentum(int precision, const BoxArgs& a, int blocks, hipS
   switch (precision) {
     case LBM_FP64: return box_dispatch<LBM_FP64>(a, blocks, s);
     case LBM_FP32: return box_dispatch<LBM_FP32>(a, blocks, s);
+    case LBM_FP32DEV: return box_dispatch<LBM_FP32DEV>(a, blocks, s);
     default: return box_dispatch<LBM_FP16DEV>(a, blocks, s);
   }
 }
@@ -544,6 +573,9 @@ hipError_t launch_fill_rest(int precision, void* buf, int64_t plane, hipStream_t
       break;
     case LBM_FP32:
       hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      break;
+    case LBM_FP32DEV:
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
       break;
     default:
       hipLaunchKernelGGL(fill_rest_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);

@@ -50,7 +50,8 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     err = "unknown bc_y";
     return LBM_EINVAL;
   }
-  if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP16DEV) {
+  if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP16DEV &&
+      g.precision != LBM_FP32DEV) {
     err = "unknown precision";
     return LBM_EINVAL;
   }

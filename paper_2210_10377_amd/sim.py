@@ -8,7 +8,8 @@ import numpy as np
 
 from . import _capi as C
 
-PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV}
+PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV,
+              "fp32dev": C.LBM_FP32DEV}
 SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT}
 
 

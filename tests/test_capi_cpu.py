@@ -186,7 +186,7 @@ def test_step_unbound_is_estate(capi):
 
 def test_workspace_size_accounts_for_buffers(capi):
     from paper_2210_10377_amd import Plan
-    for prec, s in (("fp64", 8), ("fp32", 4), ("fp16dev", 2)):
+    for prec, s in (("fp64", 8), ("fp32", 4), ("fp16dev", 2), ("fp32dev", 4)):
         p = Plan(np.zeros((100, 300), np.uint8), 0.8, np.full(100, 0.01), precision=prec)
         inf = p.info()
         assert inf.elem_bytes == s

@@ -126,11 +126,12 @@ def test_fp64_cylinder_channel_full_run(cylinder_reference):
     np.testing.assert_allclose(C, Fg * 2 / (w.u_ref ** 2 * w.l_ref), rtol=1e-15)
 
 
-def test_fp32_cylinder_channel_full_run(cylinder_reference):
+@pytest.mark.parametrize("precision", ["fp32", "fp32dev"])
+def test_fp32_cylinder_channel_full_run(cylinder_reference, precision):
     w, So, Fo = cylinder_reference
-    g, Fg = _run_gpu(w, "fp32")
+    g, Fg = _run_gpu(w, precision)
     e = _force_err(Fg, Fo)
-    print("fp32 force errors (A, B, DRTT):", e)
+    print(precision, "force errors (A, B, DRTT):", e)
     assert np.all(e <= TOL32_FORCE), e
     assert _pop_err(g.populations(), So, w.mask) <= 1e-4
 
@@ -240,23 +241,26 @@ def test_fp16dev_roundtrip_and_rest_state():
     S0 = g.populations()
     g.step(20)
     assert np.array_equal(g.populations(), S0)
-    assert np.abs(g.forces()).max() == 0.0
+    assert np.abs(g.forces()).max() <= 1e-14  # sums of the weights round at 1 ulp
     S = workloads.near_rest_state_fp16dev(w.nx, w.ny, seed=2)
     g.set_populations(S)
     back = g.populations()
     fl = w.mask == 0
-    assert np.abs(back - S)[:, fl].max() <= 1e-7
+    assert np.array_equal(back[:, fl], S[:, fl])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32dev", "fp64"])
 def test_full_size_naca_one_step(precision):
     """The 8192x4096 NACA0012 channel (chord 1024, 4 deg, Re 1e4) in the launch
     configuration the benchmark times: from a seeded random state (exactly representable
     in the storage), two steps on both sides; every fluid population and every force row
     is compared."""
     w = workloads.naca_8192x4096()
-    dt = np.float32 if precision == "fp32" else np.float64
-    S0 = workloads.near_rest_state(w.nx, w.ny, seed=77, amp=0.02, dtype=dt)
+    if precision == "fp32dev":
+        S0 = workloads.near_rest_state_dev(w.nx, w.ny, seed=77, amp=0.02, dtype=np.float32)
+    else:
+        dt = np.float32 if precision == "fp32" else np.float64
+        S0 = workloads.near_rest_state(w.nx, w.ny, seed=77, amp=0.02, dtype=dt)
     g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision=precision, box=w.box, max_record=4)
     g.set_populations(S0)
     g.step(2)
@@ -269,7 +273,7 @@ def test_full_size_naca_one_step(precision):
     Fo = o.forces()
     So = o.state()
     fl = w.mask == 0
-    tol_pop = 1e-10 if precision == "fp64" else 2e-6
+    tol_pop = {"fp64": 1e-10, "fp32": 2e-6, "fp32dev": 2e-7}[precision]
     err = 0.0
     for i in range(9):
         err = max(err, float((np.abs(Sg[i] - So[i])[fl] / So[i][fl]).max()))
@@ -277,6 +281,7 @@ def test_full_size_naca_one_step(precision):
     e = _force_err(Fg, Fo)
     # The DRTT force of a random field is a small difference of large box momenta; its
     # FP32 error is set by the rounding of ~1e6 stored populations (see design notes).
-    tol_f = np.array([1e-10] * 3) if precision == "fp64" else np.array([1e-4, 1e-4, 1e-2])
+    tol_f = {"fp64": np.array([1e-10] * 3), "fp32": np.array([1e-4, 1e-4, 1e-2]),
+             "fp32dev": np.array([1e-5, 1e-5, 1e-3])}[precision]
     print(precision, "full-size population error", err, "force errors", e)
     assert np.all(e <= tol_f), e

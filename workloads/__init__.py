@@ -104,13 +104,18 @@ def near_rest_state(nx: int, ny: int, seed: int, amp: float = 0.01,
     return S.astype(dtype).astype(np.float64)
 
 
-def near_rest_state_fp16dev(nx: int, ny: int, seed: int, amp: float = 0.01) -> np.ndarray:
+def near_rest_state_dev(nx: int, ny: int, seed: int, amp: float = 0.01,
+                        dtype=np.float16) -> np.ndarray:
     """Like ``near_rest_state`` but every value is base_i + h with h representable in
-    IEEE binary16, so the field is exactly representable as deviations from the base."""
+    ``dtype``, so the field is exactly representable as deviations from the base."""
     rng = np.random.default_rng(seed)
     xi = rng.uniform(-1.0, 1.0, size=(9, ny, nx))
-    h = (NEAR_REST_BASE[:, None, None] * amp * xi).astype(np.float16).astype(np.float64)
+    h = (NEAR_REST_BASE[:, None, None] * amp * xi).astype(dtype).astype(np.float64)
     return NEAR_REST_BASE[:, None, None] + h
+
+
+def near_rest_state_fp16dev(nx: int, ny: int, seed: int, amp: float = 0.01) -> np.ndarray:
+    return near_rest_state_dev(nx, ny, seed, amp, np.float16)
 
 
 @dataclass
