@@ -118,6 +118,45 @@ def precision_study(steps: int):
             print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(precision: str):
+    """Forward (checkpointed) and backward (recompute + reverse kernels) throughput of
+    the adjoint workload; MLUPS = nx * ny * steps / wall time of each phase."""
+    import torch
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    w = workloads.naca_1024x512_adjoint()
+    n, every, t0, T = 10000, 500, 8000, 2000
+    sim = Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=8,
+              u_ref=w.u_ref, l_ref=w.l_ref)
+    sim.adjoint_forward(n, every, t0, T)   # warm-up and workspace allocation
+    sim.adjoint_backward(1.0)
+    sim.reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    J = sim.adjoint_forward(n, every, t0, T)
+    t_f = time.perf_counter() - t
+    t = time.perf_counter()
+    gu, gt = sim.adjoint_backward(1.0)
+    t_b = time.perf_counter() - t
+    sim.reset()
+    t = time.perf_counter()
+    sim.step(n, schemes=())
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    nodes = w.nx * w.ny
+    print(json.dumps({
+        "metric": "adjoint MLUPS", "workload": w.name, "storage": precision, "steps": n,
+        "checkpoint_every": every, "J_mean_drag": J, "dJ_dtau": gt,
+        "dJ_duin_norm": float((gu ** 2).sum() ** 0.5),
+        "forward_s": round(t_f, 4), "backward_s": round(t_b, 4), "plain_run_s": round(t_plain, 4),
+        "forward_mlups": round(nodes * n / t_f / 1e6, 1),
+        "backward_mlups": round(nodes * n / t_b / 1e6, 1),
+        "plain_mlups": round(nodes * n / t_plain / 1e6, 1),
+        "fwd_plus_bwd_over_plain": round((t_f + t_b) / t_plain, 3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +174,10 @@ def main():
                          "2048x1024 channel (AoA 0/4/8, Re 100/1000): force, coefficient "
                          "and velocity-field errors; one JSON line per case")
     ap.add_argument("--study-steps", type=int, default=20000)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="adjoint workload: NACA0012 chord 256 in 1024x512, Re 500, 10000 "
+                         "steps, mean drag over the last 2000, checkpoint every 500; "
+                         "forward and backward MLUPS")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
@@ -163,6 +206,9 @@ def main():
 
     if args.precision_study:
         precision_study(args.study_steps)
+        return
+    if args.adjoint:
+        adjoint_bench(args.precision if args.precision != "fp32" else "fp32dev")
         return
 
     if args.workload == "naca8192":

@@ -188,6 +188,45 @@ int lbm_state_bytes(const lbm_t* h, size_t* bytes);
 int lbm_get_state(lbm_t* h, void* blob, size_t cap);
 int lbm_set_state(lbm_t* h, const void* blob, size_t n);
 
+/* Replace the inlet profile (ny host values, copied) or the relaxation time tau_lb
+ * (> 1/2) of a handle; later steps use the new values.  lbm_set_inlet synchronises the
+ * stream when the handle is bound. */
+int lbm_set_inlet(lbm_t* h, const double* ux);
+int lbm_set_tau(lbm_t* h, double tau);
+
+/* Put every node back in the rest state w_i, zero the step counter and empty the force
+ * ring.  Synchronises the stream. */
+int lbm_reset(lbm_t* h);
+
+/* Adjoint (reverse mode) of the time-averaged body force, for gradients with respect
+ * to the inlet profile u_in(y) and tau (the collide-stream-bounce-back map of
+ * Eq. CollideAdv and Sec. II differentiated step by step).  The objective is
+ *   J = (1/T) sum_{t = t0}^{t0+T-1} (wx F_Bx(t) + wy F_By(t)),
+ * F_B the momentum-exchange force of algorithm B (Eq. rtt5; the bounce-back force of
+ * Sec. IV) at step t of a run of n_steps steps from the handle's current state.
+ *
+ * lbm_adjoint_bytes: device workspace for a run of n_steps with a checkpoint every
+ * `every` steps (1 <= every <= n_steps): ceil(n/every) checkpoints, every-1 recomputed
+ * states, two adjoint fields and the per-step force rows.
+ *
+ * lbm_adjoint_forward: run the n_steps (the handle's state advances, as lbm_step would
+ * advance it; the force ring is not touched), storing the checkpoints in the caller's
+ * workspace ws (256-byte aligned, >= lbm_adjoint_bytes; it must stay untouched until the
+ * backward call), and return J (FP64) in *J.  Synchronises the stream.  LBM_EINVAL for
+ * t0 < 0, T < 1, t0 + T > n_steps or bad sizes; LBM_ENONFINITE if J is not finite.
+ *
+ * lbm_adjoint_backward: reverse sweep over the stored run: each segment between
+ * checkpoints is recomputed forward, then the adjoint kernel runs one launch per step
+ * backwards.  Writes dJ/du_in(y) * dJ (ny host values) to grad_uin and dJ/dtau * dJ to
+ * *grad_tau, where dJ is the incoming seed.  The adjoint fields are kept in the
+ * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
+ * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is
+ * still valid (any step, set_* or reset since invalidates it). */
+int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes);
+int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
+                        int32_t t0, int32_t T, double wx, double wy, double* J);
+int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau);
+
 /* Message of the last failing call on h (or of the last failing lbm_create when h is
  * NULL).  The string lives until the next call on the handle. */
 const char* lbm_last_error(const lbm_t* h);

@@ -68,6 +68,10 @@ def lib():
         L.orc_nrec.restype = ctypes.c_int64
         L.orc_clear_records.argtypes = [ctypes.c_void_p]
         L.orc_momentum_of.argtypes = [ctypes.c_void_p, dp, dp]
+        L.orc_objective_cs.argtypes = [cp, u8, ctypes.c_double, ctypes.c_double, dp, dp,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_double, dp]
+        L.orc_objective_cs.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -211,3 +215,25 @@ class OracleSim:
         J = np.zeros(2)
         lib().orc_momentum_of(self._h, _dp(g), _dp(J))
         return J
+
+
+def objective(mask, omega, uin, nsteps, t0, T, w=(1.0, 0.0), bc_x=BCX_INLET_OUTLET,
+              bc_y=BCY_WALL, rho_w=1.0):
+    """J = (1/T) sum_{t0 <= t < t0+T} w . F_B(t) of a run from rest, evaluated in complex
+    arithmetic: ``omega`` and ``uin`` may be complex (complex-step derivatives).
+    Returns a complex number."""
+    m, mp = _mask(mask)
+    ny, nx = m.shape
+    c = _cfg(nx, ny, bc_x, bc_y, None, rho_w, (0.0, 0.0))
+    om = complex(omega)
+    u = np.asarray(uin, dtype=np.complex128)
+    ure = np.ascontiguousarray(u.real)
+    uim = np.ascontiguousarray(u.imag)
+    out = np.zeros(2)
+    rc = lib().orc_objective_cs(ctypes.byref(c), mp, om.real, om.imag, _dp(ure), _dp(uim),
+                                int(nsteps), int(t0), int(T), float(w[0]), float(w[1]),
+                                _dp(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the configuration")
+    return complex(out[0], out[1])
+

@@ -438,6 +438,29 @@ void orc_forces(void* h, double* out) { static_cast<Sim<double>*>(h)->forces(out
 
 void orc_clear_records(void* h) { static_cast<Sim<double>*>(h)->rec.clear(); }
 
+// Time-averaged momentum-exchange force of algorithm B,
+//   J = (1/T) sum_{t=t0}^{t0+T-1} (wx F_Bx(t) + wy F_By(t)),
+// of a run of nsteps steps from rest, in complex arithmetic: with omega and u_in given
+// a small imaginary part h v, Im J / h is the directional derivative of J (complex
+// step).  Every operation of the step is analytic, so no cancellation enters.
+int orc_objective_cs(const orc_cfg* c, const uint8_t* mask, double om_re, double om_im,
+                     const double* uin_re, const double* uin_im, int32_t nsteps, int32_t t0,
+                     int32_t T, double wx, double wy, double* out) {
+  typedef std::complex<double> Z;
+  Sim<Z>* s = make_sim<Z>(c, mask, Z(om_re, om_im));
+  if (!s) return -1;
+  for (int y = 0; y < c->ny; ++y)
+    s->uin[y] = Z(uin_re ? uin_re[y] : 0.0, uin_im ? uin_im[y] : 0.0);
+  for (int32_t k = 0; k < nsteps; ++k) s->step();
+  Z J = 0.0;
+  for (int32_t t = t0; t < t0 + T; ++t) J += wx * s->rec[8 * size_t(t) + 2] + wy * s->rec[8 * size_t(t) + 3];
+  J /= double(T);
+  out[0] = J.real();
+  out[1] = J.imag();
+  delete s;
+  return 0;
+}
+
 // Control-volume momentum of an arbitrary population field g (Eq. rtt1).
 void orc_momentum_of(void* h, const double* g, double* J) {
   Sim<double>* s = static_cast<Sim<double>*>(h);

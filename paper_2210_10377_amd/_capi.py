@@ -25,7 +25,8 @@ ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
 EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_forces",
            "lbm_coefficients", "lbm_destroy", "lbm_get_links", "lbm_get_info",
            "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes", "lbm_get_state",
-           "lbm_set_state", "lbm_last_error")
+           "lbm_set_state", "lbm_last_error", "lbm_set_inlet", "lbm_set_tau", "lbm_reset",
+           "lbm_adjoint_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
 
 
 class lbm_grid(ctypes.Structure):
@@ -86,6 +87,13 @@ def load():
     L.lbm_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
     L.lbm_get_state.argtypes = [vp, vp, sz]
     L.lbm_set_state.argtypes = [vp, vp, sz]
+    L.lbm_set_inlet.argtypes = [vp, dp]
+    L.lbm_set_tau.argtypes = [vp, ctypes.c_double]
+    L.lbm_reset.argtypes = [vp]
+    L.lbm_adjoint_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+    L.lbm_adjoint_forward.argtypes = [vp, vp, sz, i32, i32, i32, i32, ctypes.c_double,
+                                      ctypes.c_double, dp]
+    L.lbm_adjoint_backward.argtypes = [vp, ctypes.c_double, dp, dp]
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

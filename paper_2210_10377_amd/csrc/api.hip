@@ -2,13 +2,16 @@
 // the force ring, state transfer and checkpoints.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
@@ -74,6 +77,13 @@ struct lbm_t {
   int64_t nrec = 0;
   std::vector<uint32_t> rec_scheme;  // scheme mask per recorded row
   std::string err;
+  // adjoint: workspace and the forward run it holds
+  bool adj_valid = false;
+  char* aws = nullptr;
+  size_t aws_bytes = 0;
+  int32_t adj_n = 0, adj_every = 0, adj_t0 = 0, adj_T = 0;
+  double adj_wx = 0.0, adj_wy = 0.0;
+  std::vector<uint32_t> adj_codes;
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -213,15 +223,11 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
   return LBM_OK;
 }
 
-int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
-  if (!h) return LBM_EINVAL;
-  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
-  if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
-  if (force_scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
-  const bool forces = force_scheme != 0;
-  if (forces && h->nrec + n > h->g.max_record)
-    return h->fail(LBM_EOVERFLOW, "force ring would overflow; read lbm_forces first");
-  if (n == 0) return LBM_OK;
+}  // extern "C"
+
+namespace {
+
+StepArgs step_args(const lbm_t* h) {
   const Plan& p = h->plan;
   StepArgs a{};
   a.plane = h->plane;
@@ -253,28 +259,39 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
   a.rho_w6 = 6.0 * h->rho_w;
   a.omega = h->omega;
   a.nslots = p.nslots;
-  double* ring = h->ring();
-  const int64_t r0 = h->nrec;
+  return a;
+}
+
+// Enqueue n >= 1 steps; step k reads io(k).first and writes io(k).second.  With a
+// non-null ring, the force row of step k goes to ring row k (rows are self-contained:
+// the J of the following step, or of the pull after the last one, is stored with it).
+template <class IO>
+int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
+  const Plan& p = h->plan;
+  const bool forces = ring != nullptr;
+  StepArgs a = step_args(h);
+  const void* last = nullptr;
   for (int32_t k = 0; k < n; ++k) {
-    a.src = h->buf(h->cur);
-    a.dst = h->buf(1 - h->cur);
+    const auto sd = io(k);
+    a.src = sd.first;
+    a.dst = sd.second;
+    last = sd.second;
     a.part_out = forces ? h->part(k & 1) : nullptr;
     a.red_in = nullptr;
     a.red_row = nullptr;
     a.red_prev_jnext = nullptr;
     if (forces && k >= 1) {
       a.red_in = h->part((k - 1) & 1);
-      a.red_row = ring + (r0 + k - 1) * kRow;
-      a.red_prev_jnext = k >= 2 ? ring + (r0 + k - 2) * kRow + 8 : nullptr;
+      a.red_row = ring + int64_t(k - 1) * kRow;
+      a.red_prev_jnext = k >= 2 ? ring + int64_t(k - 2) * kRow + 8 : nullptr;
     }
     hipError_t e = launch_step(h->g.precision, forces, a, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "launch step");
-    h->cur = 1 - h->cur;
   }
   if (forces) {
     if (p.has_box) {
       BoxArgs b{};
-      b.src = h->buf(h->cur);
+      b.src = last;
       b.plane = h->plane;
       b.buf_bytes = a.buf_bytes;
       b.pitch = h->pitch;
@@ -295,16 +312,50 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
     FinalArgs f{};
     f.red_in = h->part((n - 1) & 1);
     f.nslots = p.nslots;
-    f.row = ring + (r0 + n - 1) * kRow;
-    f.prev_jnext = n >= 2 ? ring + (r0 + n - 2) * kRow + 8 : nullptr;
+    f.row = ring + int64_t(n - 1) * kRow;
+    f.prev_jnext = n >= 2 ? ring + int64_t(n - 2) * kRow + 8 : nullptr;
     f.jpart = p.has_box ? reinterpret_cast<const double*>(h->ws + h->off_jpart) : nullptr;
     f.njblocks = h->njblocks;
     hipError_t e = launch_finalize(f, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "launch finalize");
+  }
+  return LBM_OK;
+}
+
+// n steps on the handle's own ping-pong state buffers.
+int enqueue_own_steps(lbm_t* h, int32_t n, double* ring) {
+  const int c0 = h->cur;
+  const int rc = enqueue_steps(h, n, ring, [&](int32_t k) {
+    const int s = (c0 + k) & 1;
+    return std::pair<const void*, void*>(h->buf(s), h->buf(1 - s));
+  });
+  if (rc == LBM_OK) {
+    h->cur = (c0 + n) & 1;
+    h->steps_done += n;
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
+  if (force_scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
+  const bool forces = force_scheme != 0;
+  if (forces && h->nrec + n > h->g.max_record)
+    return h->fail(LBM_EOVERFLOW, "force ring would overflow; read lbm_forces first");
+  if (n == 0) return LBM_OK;
+  h->adj_valid = false;
+  const int rc = enqueue_own_steps(h, n, forces ? h->ring() + h->nrec * kRow : nullptr);
+  if (rc != LBM_OK) return rc;
+  if (forces) {
     h->nrec += n;
     h->rec_scheme.insert(h->rec_scheme.end(), size_t(n), force_scheme);
   }
-  h->steps_done += n;
   return LBM_OK;
 }
 
@@ -417,6 +468,7 @@ int lbm_get_populations(lbm_t* h, double* out) {
 
 int lbm_set_populations(lbm_t* h, const double* in) {
   if (!h || !in) return LBM_EINVAL;
+  h->adj_valid = false;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   const size_t bytes = size_t(h->plane) * kQ * h->esz;
   std::vector<unsigned char> raw(bytes, 0);
@@ -476,6 +528,7 @@ int lbm_get_state(lbm_t* h, void* blob, size_t cap) {
 
 int lbm_set_state(lbm_t* h, const void* blob, size_t n) {
   if (!h || !blob) return LBM_EINVAL;
+  h->adj_valid = false;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   size_t need = 0;
   lbm_state_bytes(h, &need);
@@ -491,6 +544,232 @@ int lbm_set_state(lbm_t* h, const void* blob, size_t n) {
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "state synchronize");
   h->steps_done = hd.steps_done;
+  return LBM_OK;
+}
+
+int lbm_set_inlet(lbm_t* h, const double* ux) {
+  if (!h || !ux) return LBM_EINVAL;
+  for (int y = 0; y < h->g.ny; ++y)
+    if (!std::isfinite(ux[y])) return h->fail(LBM_EINVAL, "inlet velocity is not finite");
+  h->uin.assign(ux, ux + h->g.ny);
+  h->adj_valid = false;
+  if (h->bound) {
+    hipError_t e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(), h->uin.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "upload inlet");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "inlet synchronize");
+  }
+  return LBM_OK;
+}
+
+int lbm_set_tau(lbm_t* h, double tau) {
+  if (!h) return LBM_EINVAL;
+  if (!std::isfinite(tau) || tau <= 0.5) return h->fail(LBM_EINVAL, "tau must be finite and > 1/2");
+  h->tau = tau;
+  h->omega = 1.0 / tau;
+  h->adj_valid = false;
+  return LBM_OK;
+}
+
+int lbm_reset(lbm_t* h) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = launch_fill_rest(h->g.precision, h->buf(k), h->plane, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "reset synchronize");
+  h->cur = 0;
+  h->steps_done = 0;
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  h->adj_valid = false;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct AdjLayout {
+  size_t state = 0, mu = 0;  // bytes of one state / adjoint buffer
+  int32_t ncp = 0;           // checkpoints
+  size_t off_cp = 0, off_seg = 0, off_mu = 0, off_adj = 0, off_dom = 0, off_duin = 0,
+         off_ring = 0, total = 0;
+};
+
+AdjLayout adj_layout(const lbm_t* h, int32_t n, int32_t every) {
+  AdjLayout L;
+  const size_t cbytes = h->g.precision == LBM_FP64 ? 8 : 4;
+  L.state = size_t(h->plane) * kQ * h->esz;
+  L.mu = size_t(h->plane) * kQ * cbytes;
+  L.ncp = (n + every - 1) / every;
+  size_t off = 0;
+  L.off_cp = off;
+  off = align256(off + size_t(L.ncp) * align256(L.state));
+  L.off_seg = off;
+  off = align256(off + size_t(every - 1) * align256(L.state));
+  L.off_mu = off;
+  off = align256(off + 2 * align256(L.mu));
+  L.off_adj = off;
+  off = align256(off + size_t(h->g.nx) * h->g.ny * sizeof(uint32_t));
+  L.off_dom = off;
+  off = align256(off + size_t(h->plan.ntiles) * kStrips * sizeof(double));
+  L.off_duin = off;
+  off = align256(off + size_t(h->g.ny) * sizeof(double));
+  L.off_ring = off;
+  off = align256(off + size_t(n) * kRow * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+uint32_t bytes32(size_t b) { return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u; }
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes) {
+  if (!h || !bytes || n_steps < 1 || every < 1 || every > n_steps) return LBM_EINVAL;
+  *bytes = adj_layout(h, n_steps, every).total;
+  return LBM_OK;
+}
+
+int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
+                        int32_t t0, int32_t T, double wx, double wy, double* J) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (!ws || !J || n_steps < 1 || every < 1 || every > n_steps || t0 < 0 || T < 1 ||
+      int64_t(t0) + T > n_steps || !std::isfinite(wx) || !std::isfinite(wy))
+    return h->fail(LBM_EINVAL, "invalid adjoint run parameters");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return h->fail(LBM_EINVAL, "adjoint workspace must be 256-byte aligned");
+  const AdjLayout L = adj_layout(h, n_steps, every);
+  if (bytes < L.total) return h->fail(LBM_ENOMEM, "adjoint workspace smaller than lbm_adjoint_bytes");
+  h->adj_valid = false;
+  char* aws = static_cast<char*>(ws);
+  if (h->adj_codes.empty()) build_adjoint_codes(h->plan, h->adj_codes);
+  hipError_t e = hipMemcpyAsync(aws + L.off_adj, h->adj_codes.data(),
+                                h->adj_codes.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload adjoint codes");
+  double* ring = reinterpret_cast<double*>(aws + L.off_ring);
+  for (int32_t c = 0; c < L.ncp; ++c) {
+    const int32_t len = std::min(every, n_steps - c * every);
+    e = hipMemcpyAsync(aws + L.off_cp + size_t(c) * align256(L.state), h->buf(h->cur), L.state,
+                       hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "store checkpoint");
+    const int rc = enqueue_own_steps(h, len, ring + int64_t(c) * every * kRow);
+    if (rc != LBM_OK) return rc;
+  }
+  std::vector<double> rows(size_t(T) * kRow);
+  e = hipMemcpyAsync(rows.data(), ring + int64_t(t0) * kRow, rows.size() * sizeof(double),
+                     hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download forces");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "adjoint forward synchronize");
+  double acc = 0.0;
+  for (int32_t t = 0; t < T; ++t) acc += wx * rows[size_t(t) * kRow + 2] + wy * rows[size_t(t) * kRow + 3];
+  *J = acc / T;
+  h->aws = aws;
+  h->aws_bytes = bytes;
+  h->adj_n = n_steps;
+  h->adj_every = every;
+  h->adj_t0 = t0;
+  h->adj_T = T;
+  h->adj_wx = wx;
+  h->adj_wy = wy;
+  h->adj_valid = true;
+  if (!std::isfinite(*J)) return h->fail(LBM_ENONFINITE, "objective is not finite");
+  return LBM_OK;
+}
+
+int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
+  if (!h) return LBM_EINVAL;
+  if (!h->adj_valid)
+    return h->fail(LBM_ESTATE, "no adjoint forward run matches the handle's current parameters");
+  if (!grad_uin || !grad_tau || !std::isfinite(dJ)) return h->fail(LBM_EINVAL, "invalid arguments");
+  const AdjLayout L = adj_layout(h, h->adj_n, h->adj_every);
+  char* aws = h->aws;
+  const Plan& p = h->plan;
+  const size_t cbytes = h->g.precision == LBM_FP64 ? 8 : 4;
+  void* mu[2] = {aws + L.off_mu, aws + L.off_mu + align256(L.mu)};
+  double* dom = reinterpret_cast<double*>(aws + L.off_dom);
+  double* duin = reinterpret_cast<double*>(aws + L.off_duin);
+  hipError_t e;
+  if (cbytes == 8)
+    e = launch_zero_f64(static_cast<double*>(mu[0]), int64_t(L.mu / 8), h->stream);
+  else
+    e = launch_zero_f32(static_cast<float*>(mu[0]), int64_t(L.mu / 4), h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "zero adjoint");
+  if ((e = launch_zero_f64(dom, int64_t(p.ntiles) * kStrips, h->stream)) != hipSuccess)
+    return h->hip_fail(e, "zero adjoint sums");
+  if ((e = launch_zero_f64(duin, p.ny, h->stream)) != hipSuccess)
+    return h->hip_fail(e, "zero adjoint sums");
+  AdjArgs a{};
+  a.plane = h->plane;
+  a.state_bytes = bytes32(L.state);
+  a.mu_bytes = bytes32(L.mu);
+  a.pitch = h->pitch;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.ntx = p.ntx;
+  a.ntiles = p.ntiles;
+  a.gx0 = p.gx0;
+  a.gx1 = p.gx1;
+  a.gy0 = p.gy0;
+  a.gy1 = p.gy1;
+  a.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
+  a.adj = reinterpret_cast<const uint32_t*>(aws + L.off_adj);
+  a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  a.rho_w6 = 6.0 * h->rho_w;
+  a.omega = h->omega;
+  a.domega = dom;
+  a.duin = duin;
+  int cur = 0;  // mu[cur] holds mu(t+1)
+  for (int32_t c = L.ncp - 1; c >= 0; --c) {
+    const int32_t t_first = c * h->adj_every;
+    const int32_t len = std::min(h->adj_every, h->adj_n - t_first);
+    // seg(j) = S(t_first - 1 + j): the checkpoint, then recomputed states.
+    auto seg = [&](int32_t j) -> void* {
+      return j == 0 ? static_cast<void*>(aws + L.off_cp + size_t(c) * align256(L.state))
+                    : static_cast<void*>(aws + L.off_seg + size_t(j - 1) * align256(L.state));
+    };
+    if (len > 1) {
+      const int rc = enqueue_steps(h, len - 1, nullptr, [&](int32_t k) {
+        return std::pair<const void*, void*>(seg(k), seg(k + 1));
+      });
+      if (rc != LBM_OK) return rc;
+    }
+    for (int32_t t = t_first + len - 1; t >= t_first; --t) {
+      const bool in_window = t >= h->adj_t0 && t < h->adj_t0 + h->adj_T;
+      const double g = in_window ? dJ * 2.0 / h->adj_T : 0.0;
+      a.gx = g * h->adj_wx;
+      a.gy = g * h->adj_wy;
+      a.state = seg(t - t_first);
+      a.mu_in = mu[cur];
+      a.mu_out = mu[1 - cur];
+      e = launch_adjoint(h->g.precision, a, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "launch adjoint");
+      cur = 1 - cur;
+    }
+  }
+  std::vector<double> hdom(size_t(p.ntiles) * kStrips);
+  e = hipMemcpyAsync(hdom.data(), dom, hdom.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download adjoint sums");
+  e = hipMemcpyAsync(grad_uin, duin, size_t(p.ny) * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download adjoint sums");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "adjoint synchronize");
+  double domega = 0.0;
+  for (double v : hdom) domega += v;
+  // omega = 1 / tau
+  *grad_tau = -domega / (h->tau * h->tau);
+  bool finite = std::isfinite(*grad_tau);
+  for (int y = 0; y < p.ny; ++y) finite = finite && std::isfinite(grad_uin[y]);
+  if (!finite) return h->fail(LBM_ENONFINITE, "gradient is not finite");
   return LBM_OK;
 }
 

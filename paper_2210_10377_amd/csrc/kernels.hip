@@ -23,6 +23,7 @@
 // Larger buffers use 64-bit global addresses.
 #include <hip/hip_runtime.h>
 
+#include "device.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -30,170 +31,7 @@ namespace lbm {
 
 namespace {
 
-constexpr int kThreads = kTileW;
-
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-template <class C>
-__device__ __forceinline__ constexpr C weight(int i) {
-  return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
-}
-
-// Storage of a population and the arithmetic type it is computed in.  Deviation
-// storages keep h_i = f_i - w_i; their arithmetic stays in deviation form.
-template <int P>
-struct Storage;
-
-template <>
-struct Storage<LBM_FP64> {
-  using T = double;
-  using C = double;
-  static constexpr bool kDev = false;
-};
-
-template <>
-struct Storage<LBM_FP32> {
-  using T = float;
-  using C = float;
-  static constexpr bool kDev = false;
-};
-
-template <>
-struct Storage<LBM_FP32DEV> {
-  using T = float;
-  using C = float;
-  static constexpr bool kDev = true;
-};
-
-template <>
-struct Storage<LBM_FP16DEV> {
-  using T = _Float16;
-  using C = float;
-  static constexpr bool kDev = true;
-};
-
-// Stored value -> arithmetic value (f, or h for deviation storages) and back (binary16:
-// round to nearest even).
-template <int P>
-__device__ __forceinline__ typename Storage<P>::C unpack(typename Storage<P>::T v) {
-  return typename Storage<P>::C(v);
-}
-template <int P>
-__device__ __forceinline__ typename Storage<P>::T pack(typename Storage<P>::C v) {
-  return typename Storage<P>::T(v);
-}
-// The population f_i in binary64 from a stored value of direction i.
-template <int P>
-__device__ __forceinline__ double to_f64(typename Storage<P>::T v, int i) {
-  return Storage<P>::kDev ? weight<double>(i) + double(v) : double(v);
-}
-
-// Raw buffer access of one stored population (cache policy `aux`: 0 default, 2 nt).
-template <class T>
-struct RawBuf;
-template <>
-struct RawBuf<double> {
-  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
-  }
-  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, double x) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, 2);
-  }
-};
-template <>
-struct RawBuf<float> {
-  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
-  }
-  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, float x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 2);
-  }
-};
-template <>
-struct RawBuf<_Float16> {
-  static __device__ __forceinline__ _Float16 ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
-  }
-  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, _Float16 x) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 2);
-  }
-};
-
-// The nine population planes of one state buffer.  Offsets are element offsets
-// inside a plane (y * pitch + x); plane i starts i * plane elements into the buffer.
-template <class T, bool BUF>
-struct Planes;
-
-template <class T>
-struct Planes<T, true> {
-  __amdgpu_buffer_rsrc_t r;
-  uint32_t plane_bytes;
-  __device__ __forceinline__ Planes(const void* base, int64_t plane, uint32_t bytes)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000)),
-        plane_bytes(uint32_t(plane * int64_t(sizeof(T)))) {}
-  __device__ __forceinline__ T ld(int i, int32_t off) const {
-    return RawBuf<T>::ld(r, uint32_t(off) * uint32_t(sizeof(T)), uint32_t(i) * plane_bytes);
-  }
-  // Plane index varying per lane.
-  __device__ __forceinline__ T ld_lane(int i, int32_t off) const {
-    return RawBuf<T>::ld(r, uint32_t(i) * plane_bytes + uint32_t(off) * uint32_t(sizeof(T)), 0u);
-  }
-  __device__ __forceinline__ void st(int i, int32_t off, T v) const {
-    RawBuf<T>::st(r, uint32_t(off) * uint32_t(sizeof(T)), uint32_t(i) * plane_bytes, v);
-  }
-};
-
-template <class T>
-struct Planes<T, false> {
-  T* p;
-  int64_t plane;
-  __device__ __forceinline__ Planes(const void* base, int64_t pl, uint32_t)
-      : p(static_cast<T*>(const_cast<void*>(base))), plane(pl) {}
-  __device__ __forceinline__ T ld(int i, int32_t off) const { return p[i * plane + off]; }
-  __device__ __forceinline__ T ld_lane(int i, int32_t off) const { return p[i * plane + off]; }
-  __device__ __forceinline__ void st(int i, int32_t off, T v) const {
-    __builtin_nontemporal_store(v, p + i * plane + off);
-  }
-};
-
-// BGK collision of one node (Eq. CollideAdv, first line, with 2 beta = omega) towards
-// the second-order equilibrium w_i rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2].  In
-// deviation form (DEV) the inputs and outputs are h_i = f_i - w_i: rho - 1 = sum h_i,
-// rho u = sum c_i h_i, and f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 -
-// 1.5 u^2)], so no quantity of order one is formed.
-template <class C, bool DEV>
-__device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
-  const C s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const C jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
-  const C jy = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
-  const C rho = DEV ? C(1) + s : s;
-  const C ir = C(1) / rho;
-  const C ux = jx * ir, uy = jy * ir;
-  const C usq = C(1.5) * (ux * ux + uy * uy);
-  const C om = omega;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy;
-    const C poly = C(3) * cu + C(4.5) * cu * cu - usq;
-    const C feq = DEV ? weight<C>(i) * (s + rho * poly) : weight<C>(i) * rho * (C(1) + poly);
-    g[i] = f[i] + om * (feq - f[i]);
-  }
-}
-
-// Block index -> tile index.  Blocks are dealt round-robin over the 8 XCDs; this
-// mapping hands each XCD runs of kGroup consecutive row-major tiles, so the cache
-// lines shared by horizontally adjacent tiles (the +-1-shifted pulls) meet in one L2,
-// while the XCDs together still sweep one region of memory at a time.  The tail that
-// does not fill a whole round keeps the identity mapping.
-#ifndef LBM_XCD_GROUP
-#define LBM_XCD_GROUP 4
-#endif
-__device__ __forceinline__ int block_tile(int b, int n) {
-  constexpr int kGroup = LBM_XCD_GROUP, kRound = 8 * kGroup;
-  if (kGroup == 1 || b >= n / kRound * kRound) return b;
-  const int xcd = b & 7, k = b >> 3;
-  return ((k / kGroup) * 8 + xcd) * kGroup + (k % kGroup);
-}
+using namespace dev;
 
 __device__ __forceinline__ bool in_box(const StepArgs& a, int x, int y) {
   return x >= a.bx0 && x < a.bx1 && y >= a.by0 && y < a.by1;
@@ -233,68 +71,6 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
     collide<C, S::kDev>(f, C(a.omega), g);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, pack<P>(g[i]));
-  }
-}
-
-// Populations arriving at fluid node (x, y) (streaming of Eq. CollideAdv with the
-// boundary rules), from the node's pull codes.  The source plane and offset of every
-// direction are selected first and the nine loads issued together, so a node costs one
-// memory latency whatever its boundary rules:
-//   stream: S_i(x - c_i); body or wall: S_o(x) (half-way bounce-back, o = opposite);
-//   inlet: S_o(x) + 2 w_i rho_w (c_i . u_w) / c_s^2 (moving-wall bounce-back, Sec. II);
-//   outlet: S_i(nx-1, y - c_iy) (ghost column); wrap: S_i at the periodic image.
-template <int P, class A>
-__device__ __forceinline__ void pull_all(const A& src, int pitch, int nx, int ny,
-                                         const double* uin, double rho_w6, uint32_t w, int x,
-                                         int y, typename Storage<P>::C (&f)[kQ]) {
-  using S = Storage<P>;
-  using C = typename S::C;
-  const int32_t own = y * pitch + x;
-  int32_t off[kQ];
-  int pl[kQ];
-  off[0] = own;
-  pl[0] = 0;
-#pragma unroll
-  for (int i = 1; i < kQ; ++i) {
-    const uint32_t code = pull_code(w, i);
-    int sx = x - kCx[i], sy = y - kCy[i];
-    sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-    sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-    const bool back = code == kBody || code == kWall || code == kInlet;
-    const int32_t o_far = code == kOutlet ? sy * pitch + (nx - 1) : sy * pitch + sx;
-    off[i] = back ? own : o_far;
-    pl[i] = back ? kOpp[i] : i;
-  }
-  typename S::T v[kQ];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) v[i] = src.ld_lane(pl[i], off[i]);
-  // The inlet term is additive, so it applies to f and to h = f - w alike (opposite
-  // directions share a weight).
-  const C uw = C(rho_w6 * uin[y]);
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    f[i] = unpack<P>(v[i]);
-    if (i > 0 && kCx[i] != 0 && pull_code(w, i) == kInlet) f[i] += uw * (weight<C>(i) * C(kCx[i]));
-  }
-}
-
-// Sum 8 doubles over the block in a fixed order; thread k < 8 writes out[k].
-__device__ __forceinline__ void block_sum8(double (&v)[8], double* out) {
-  __shared__ double red[kThreads / 64][8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) red[wave][k] = v[k];
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    double s = red[0][threadIdx.x];
-#pragma unroll
-    for (int wv = 1; wv < kThreads / 64; ++wv) s += red[wv][threadIdx.x];
-    out[threadIdx.x] = s;
   }
 }
 
@@ -370,45 +146,6 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
       }
     }
   }
-}
-
-// Sum 8 doubles over the wave in a fixed (butterfly) order; lanes 0..7 store out[0..7].
-__device__ __forceinline__ void wave_sum8_store(double (&v)[8], double* out) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  const int lane = threadIdx.x & 63;
-  double mine = v[0];
-#pragma unroll
-  for (int k = 1; k < 8; ++k) mine = lane == k ? v[k] : mine;
-  if (lane < 8) out[lane] = mine;
-}
-
-// Fixed-order reduction of [nslots][8] partials by one 256-thread block; returns the
-// eight sums in threads 0..7.
-__device__ __forceinline__ double reduce_partials8(const double* in, int nslots) {
-  __shared__ double red[kThreads / 8][8];
-  constexpr int kG = kThreads / 8;  // slot groups
-  const int k = threadIdx.x & 7, grp = threadIdx.x >> 3;
-  // Four independent partial sums per lane keep four loads in flight; they are
-  // combined in a fixed order, so the result depends on nslots only.
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = grp;
-  for (; j + 3 * kG < nslots; j += 4 * kG) {
-    s0 += in[int64_t(j) * 8 + k];
-    s1 += in[int64_t(j + kG) * 8 + k];
-    s2 += in[int64_t(j + 2 * kG) * 8 + k];
-    s3 += in[int64_t(j + 3 * kG) * 8 + k];
-  }
-  for (; j < nslots; j += kG) s0 += in[int64_t(j) * 8 + k];
-  const double s = (s0 + s1) + (s2 + s3);
-  red[grp][k] = s;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x < 8)
-    for (int gI = 0; gI < kThreads / 8; ++gI) t += red[gI][threadIdx.x];
-  return t;
 }
 
 template <int P, bool BUF, bool FORCES>

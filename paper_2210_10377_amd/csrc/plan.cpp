@@ -173,4 +173,31 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
   return LBM_OK;
 }
 
+void build_adjoint_codes(const Plan& p, std::vector<uint32_t>& adj) {
+  adj.assign(p.node.size(), 0u);
+  for (int y = 0; y < p.ny; ++y)
+    for (int x = 0; x < p.nx; ++x) {
+      const uint32_t w = p.node[size_t(y) * p.nx + x];
+      if (w & kSolidBit) continue;
+      for (int i = 1; i < kQ; ++i) {
+        const uint32_t c = pull_code(w, i);
+        int sx = x - kCx[i], sy = y - kCy[i];
+        sx = (sx + p.nx) % p.nx;
+        sy = (sy + p.ny) % p.ny;
+        uint32_t bit = 0;
+        if (c == kStream) {
+          bit = kAdjStream;
+        } else if (c == kWrap) {
+          bit = kAdjWrap;
+        } else if (c == kOutlet) {
+          bit = kAdjOutlet;
+          sx = p.nx - 1;
+        } else {
+          continue;  // bounce-back: read back from the node itself
+        }
+        adj[size_t(sy) * p.nx + sx] |= bit << (3 * (i - 1));
+      }
+    }
+}
+
 }  // namespace lbm

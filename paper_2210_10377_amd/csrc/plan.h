@@ -74,4 +74,12 @@ struct Plan {
 // Validate and classify.  Returns LBM_OK or an error code with a message in err.
 int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err);
 
+// Adjoint codes: for a fluid node s and direction k (three bits at 3*(k-1)), which
+// pulls read S_k(s) apart from the bounce-back of s itself: the node s + c_k streams it
+// (kAdjStream), through a periodic wrap (kAdjWrap), or the outlet node
+// (nx-1, s_y + c_ky) copies it from the ghost column (kAdjOutlet).  Built by inverting
+// the pull codes, so the transposed pull reads exactly what the pull wrote.
+constexpr uint32_t kAdjStream = 1u, kAdjWrap = 2u, kAdjOutlet = 4u;
+void build_adjoint_codes(const Plan& p, std::vector<uint32_t>& adj);
+
 }  // namespace lbm

@@ -146,6 +146,48 @@ class Sim:
     def set_state(self, blob: bytes) -> None:
         C.check(self._lib.lbm_set_state(self._h, blob, len(blob)), self._h)
 
+    # -- parameters -------------------------------------------------------------------
+    def set_inlet(self, ux) -> None:
+        u = np.ascontiguousarray(np.broadcast_to(np.asarray(ux, np.float64), (self.ny,)))
+        C.check(self._lib.lbm_set_inlet(self._h, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                self._h)
+
+    def set_tau(self, tau: float) -> None:
+        C.check(self._lib.lbm_set_tau(self._h, float(tau)), self._h)
+
+    def reset(self) -> None:
+        C.check(self._lib.lbm_reset(self._h), self._h)
+
+    # -- adjoint ----------------------------------------------------------------------
+    def adjoint_forward(self, n_steps: int, every: int, t0: int, T: int, w=(1.0, 0.0)) -> float:
+        """Run n_steps from the current state with checkpoints every `every` steps and
+        return J = (1/T) sum_{t0 <= t < t0+T} w . F_B(t)."""
+        import torch
+        nb = ctypes.c_size_t()
+        C.check(self._lib.lbm_adjoint_bytes(self._h, int(n_steps), int(every), ctypes.byref(nb)),
+                self._h)
+        ws = getattr(self, "adjoint_workspace", None)
+        if ws is None or ws.numel() < nb.value:
+            self.adjoint_workspace = None
+            with torch.cuda.device(self.device):
+                self.adjoint_workspace = torch.empty(int(nb.value), dtype=torch.uint8,
+                                                     device=self.device)
+        J = ctypes.c_double()
+        C.check(self._lib.lbm_adjoint_forward(
+            self._h, ctypes.c_void_p(self.adjoint_workspace.data_ptr()),
+            int(self.adjoint_workspace.numel()), int(n_steps), int(every), int(t0), int(T),
+            float(w[0]), float(w[1]), ctypes.byref(J)), self._h)
+        return J.value
+
+    def adjoint_backward(self, seed: float = 1.0):
+        """(dJ/du_in [ny], dJ/dtau), each times `seed`, of the last adjoint_forward run."""
+        g = np.zeros(self.ny)
+        gt = ctypes.c_double()
+        C.check(self._lib.lbm_adjoint_backward(self._h, float(seed),
+                                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               ctypes.byref(gt)), self._h)
+        return g, gt.value
+
 
 def links_of(handle) -> np.ndarray:
     lib = C.load()

@@ -1,0 +1,160 @@
+"""Adjoint (reverse-mode) gradients of the time-averaged body force.
+
+Reference values: directional derivatives by complex step through the FP64 oracle
+(miniature channels), and FP64 central differences of the GPU FP64 path (the NACA0012
+1024x512 channel of the adjoint workload, 10 000 steps, checkpoint every 500).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(mask, tau, uin, precision, box=None, bc_x=0, bc_y=0):
+    from paper_2210_10377_amd import Sim
+    return Sim(mask, tau, uin, precision=precision, box=box, bc_x=bc_x, bc_y=bc_y,
+               max_record=8)
+
+
+MINI = [
+    # nx, ny, body, bc_y, n, every, t0, T, w
+    ("cylinder_walls", 96, 48, lambda: workloads.cylinder_mask(96, 48, 24, 23.5, 4), 0, 300, 40, 200, 100, (1.0, 0.0)),
+    ("cylinder_periodic_y_lift", 80, 40, lambda: workloads.cylinder_mask(80, 40, 20, 17.0, 4), 1, 240, 60, 150, 90, (0.3, 1.0)),
+    ("naca_walls", 160, 64, lambda: workloads.naca0012_mask(160, 64, 48, 52, 32, 6.0), 0, 200, 200, 100, 100, (1.0, 0.5)),
+]
+
+
+@pytest.fixture(scope="module")
+def mini_refs(orc):
+    out = {}
+    for name, nx, ny, mk, bcy, n, every, t0, T, w in MINI:
+        mask = mk()
+        y = np.arange(ny)
+        uin = 0.03 + 0.02 * np.sin(np.pi * (y + 0.5) / ny)
+        tau = 0.75
+        h = 1e-30
+        v = np.random.default_rng(len(name)).normal(size=ny)
+        J = orc.objective(mask, 1 / tau, uin, n, t0, T, w=w, bc_y=bcy)
+        d_tau = orc.objective(mask, 1 / complex(tau, h), uin, n, t0, T, w=w, bc_y=bcy).imag / h
+        d_v = orc.objective(mask, 1 / tau, uin + 1j * h * v, n, t0, T, w=w, bc_y=bcy).imag / h
+        # every inlet row individually on the first few rows (full gradient spot check)
+        rows = [0, 1, ny // 2, ny - 1]
+        d_rows = []
+        for r in rows:
+            e = np.zeros(ny)
+            e[r] = 1.0
+            d_rows.append(orc.objective(mask, 1 / tau, uin + 1j * h * e, n, t0, T, w=w,
+                                        bc_y=bcy).imag / h)
+        out[name] = dict(mask=mask, uin=uin, tau=tau, v=v, J=J.real, d_tau=d_tau, d_v=d_v,
+                         rows=rows, d_rows=np.array(d_rows), cfg=(n, every, t0, T, w, bcy))
+    return out
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MINI])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 2e-4), ("fp32", 2e-3)])
+def test_adjoint_matches_complex_step(mini_refs, name, precision, tol):
+    r = mini_refs[name]
+    n, every, t0, T, w, bcy = r["cfg"]
+    g = _sim(r["mask"], r["tau"], r["uin"], precision, bc_y=bcy)
+    J = g.adjoint_forward(n, every, t0, T, w)
+    gu, gt = g.adjoint_backward(1.0)
+    scale_j = max(abs(r["J"]), 1e-12)
+    assert abs(J - r["J"]) <= (1e-12 if precision == "fp64" else 1e-4) * scale_j
+    e_tau = abs(gt - r["d_tau"]) / abs(r["d_tau"])
+    e_v = abs(gu @ r["v"] - r["d_v"]) / abs(r["d_v"])
+    e_rows = np.abs(gu[r["rows"]] - r["d_rows"]).max() / np.abs(gu).max()
+    print(name, precision, "rel errors tau", e_tau, "direction", e_v, "rows", e_rows)
+    assert e_tau <= tol and e_v <= tol and e_rows <= tol
+
+
+def test_adjoint_seed_scales_and_is_deterministic(mini_refs):
+    r = mini_refs["cylinder_walls"]
+    n, every, t0, T, w, bcy = r["cfg"]
+    g = _sim(r["mask"], r["tau"], r["uin"], "fp32")
+    g.adjoint_forward(n, every, t0, T, w)
+    a_u, a_t = g.adjoint_backward(1.0)
+    b_u, b_t = g.adjoint_backward(1.0)
+    c_u, c_t = g.adjoint_backward(-2.5)
+    assert np.array_equal(a_u, b_u) and a_t == b_t
+    np.testing.assert_allclose(c_u, -2.5 * a_u, rtol=1e-6, atol=1e-12)
+    assert abs(c_t + 2.5 * a_t) <= 1e-6 * abs(a_t)
+
+
+def test_adjoint_checkpoint_interval_does_not_change_gradient(mini_refs):
+    r = mini_refs["cylinder_walls"]
+    n, every, t0, T, w, bcy = r["cfg"]
+    out = []
+    for k in (1, 7, n):
+        g = _sim(r["mask"], r["tau"], r["uin"], "fp64")
+        g.adjoint_forward(n, k, t0, T, w)
+        out.append(g.adjoint_backward(1.0))
+    for gu, gt in out[1:]:
+        np.testing.assert_allclose(gu, out[0][0], rtol=1e-12, atol=1e-16)
+        assert abs(gt - out[0][1]) <= 1e-12 * abs(out[0][1])
+
+
+def test_adjoint_backward_needs_valid_forward(mini_refs):
+    from paper_2210_10377_amd import LbmError
+    r = mini_refs["cylinder_walls"]
+    g = _sim(r["mask"], r["tau"], r["uin"], "fp32")
+    with pytest.raises(LbmError):
+        g.adjoint_backward(1.0)
+    g.adjoint_forward(20, 5, 10, 10)
+    g.set_tau(0.9)
+    with pytest.raises(LbmError):
+        g.adjoint_backward(1.0)
+
+
+def test_autograd_function(mini_refs):
+    import torch
+
+    from paper_2210_10377_amd.autograd import ObjectiveSpec, objective
+    r = mini_refs["cylinder_walls"]
+    n, every, t0, T, w, bcy = r["cfg"]
+    g = _sim(r["mask"], r["tau"], r["uin"], "fp64")
+    u = torch.tensor(r["uin"], dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(r["tau"], dtype=torch.float64, requires_grad=True)
+    J = objective(u, tau, g, ObjectiveSpec(n, every, t0, T, w))
+    J.backward()
+    assert abs(J.item() - r["J"]) <= 1e-12 * abs(r["J"])
+    assert abs(tau.grad.item() - r["d_tau"]) <= 1e-9 * abs(r["d_tau"])
+    assert abs(u.grad.numpy() @ r["v"] - r["d_v"]) <= 1e-9 * abs(r["d_v"])
+
+
+def test_adjoint_naca_1024x512_against_fp64_central_differences():
+    """The adjoint workload: NACA0012 chord 256 in a 1024x512 channel, Re 500, 10 000
+    steps from rest, J = mean drag (algorithm B) over the last 2000 steps, checkpoint
+    every 500.  FP32-deviation adjoint against FP64 central differences of the FP64 GPU
+    path in two random inlet directions and in tau."""
+    w = workloads.naca_1024x512_adjoint()
+    n, every, t0, T = 10000, 500, 8000, 2000
+    g = _sim(w.mask, w.tau, w.uin, "fp32dev", box=w.box)
+    J32 = g.adjoint_forward(n, every, t0, T)
+    gu, gt = g.adjoint_backward(1.0)
+    from paper_2210_10377_amd import Sim
+    ref = Sim(w.mask, w.tau, w.uin, precision="fp64", box=w.box, max_record=T)
+
+    def J64(uin, tau):
+        ref.set_inlet(uin)
+        ref.set_tau(tau)
+        ref.reset()
+        ref.step(t0, schemes=())
+        ref.step(T, schemes=("B",))
+        return ref.forces()[:, 1, 0].mean()
+
+    J0 = J64(w.uin, w.tau)
+    assert abs(J32 - J0) <= 1e-4 * abs(J0)
+    e = 1e-6 * w.tau
+    d_tau = (J64(w.uin, w.tau + e) - J64(w.uin, w.tau - e)) / (2 * e)
+    errs = [abs(gt - d_tau) / abs(d_tau)]
+    rng = np.random.default_rng(500)
+    for _ in range(2):
+        v = rng.normal(size=w.ny)
+        v /= np.linalg.norm(v)
+        h = 1e-7
+        d_v = (J64(w.uin + h * v, w.tau) - J64(w.uin - h * v, w.tau)) / (2 * h)
+        errs.append(abs(gu @ v - d_v) / abs(d_v))
+    print("naca 1024x512 adjoint rel errors (tau, v1, v2):", errs, "J", J0, "dJ/dtau", d_tau)
+    assert max(errs) <= 1e-4, errs

@@ -568,3 +568,37 @@ def test_naca_mask_area_symmetry_and_incidence():
     m8 = workloads.naca0012_mask(1024, 512, c, 320, 256, 8.0)
     ys, xs = np.nonzero(m8)
     assert ys[xs == xs.min()].mean() > 256 > ys[xs == xs.max()].mean()  # nose up
+
+
+# --------------------------------------------------------------------------------------
+# Complex-step derivatives of the time-averaged force (the adjoint's reference)
+# --------------------------------------------------------------------------------------
+
+def test_complex_step_matches_central_differences(orc):
+    """The oracle in complex arithmetic (Im J(theta + i h v) / h) gives the same
+    directional derivatives of the mean algorithm-B drag as FP64 central differences of
+    the real oracle, for tau and for the inlet profile."""
+    nx, ny = 64, 32
+    mask = workloads.cylinder_mask(nx, ny, 18, 15.5, 3)
+    y = np.arange(ny)
+    uin = 0.03 + 0.02 * np.sin(np.pi * (y + 0.5) / ny)
+    tau, n, t0, T = 0.8, 160, 100, 60
+    h = 1e-30
+    # tau
+    cs = orc.objective(mask, 1 / complex(tau, h), uin, n, t0, T).imag / h
+    e = 1e-6
+    fd = (orc.objective(mask, 1 / (tau + e), uin, n, t0, T).real
+          - orc.objective(mask, 1 / (tau - e), uin, n, t0, T).real) / (2 * e)
+    assert abs(cs - fd) <= 1e-6 * abs(cs)
+    # inlet direction
+    v = np.random.default_rng(5).normal(size=ny)
+    cs = orc.objective(mask, 1 / tau, uin + 1j * h * v, n, t0, T).imag / h
+    e = 1e-7
+    fd = (orc.objective(mask, 1 / tau, uin + e * v, n, t0, T).real
+          - orc.objective(mask, 1 / tau, uin - e * v, n, t0, T).real) / (2 * e)
+    assert abs(cs - fd) <= 1e-6 * abs(cs)
+    # the real part is the real objective
+    Jr = orc.objective(mask, 1 / tau, uin, n, t0, T)
+    o = OracleSim(mask, tau=tau, uin=uin)
+    o.step(n)
+    assert abs(Jr.real - o.forces()[t0:t0 + T, 1, 0].mean()) <= 1e-15
