@@ -231,6 +231,100 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
  * NULL).  The string lives until the next call on the handle. */
 const char* lbm_last_error(const lbm_t* h);
 
+/* ---- Batches -------------------------------------------------------------------------
+ * Not in the paper: a throughput form for sweeps over many small problems of the kind
+ * of Sec. V (cylinders and airfoils in walled channels, each with its own grid, body,
+ * relaxation time, inlet and control volume).  A batch groups bound handles of one
+ * precision and advances all of them together: each step is ONE kernel launch that
+ * updates every instance (a sweep over the concatenated tile lists of all instances,
+ * optionally by a persistent grid), and runs of launches can be replayed from captured
+ * HIP graphs.  Every instance computes exactly what lbm_step computes for it (same
+ * kernels per tile, same force reduction order): populations and forces are bitwise
+ * those of the member stepped alone with the same call lengths.
+ *
+ * Ownership: the members stay owned by the caller and must outlive the batch; their
+ * workspaces hold the states, which lbm_get_populations etc. read as usual.  While a
+ * batch call runs, members must not be used on another stream.  A member may still be
+ * stepped or changed (lbm_set_tau, lbm_set_inlet, lbm_set_populations, lbm_reset)
+ * between batch calls; the batch picks the change up at its next call.  lbm_batch_step
+ * advances every member's state and step count; the force rows it records go to the
+ * batch's own ring ([n][max_record] rows), not to the members' rings. */
+typedef struct lbm_batch_t lbm_batch_t;
+
+typedef struct lbm_batch_schedule {
+  int32_t grid_blocks; /* tile workgroups per launch: 0 = one per tile; otherwise a
+                          persistent grid, rounded up to a multiple of 8             */
+  int32_t graph_steps; /* launches per captured HIP graph: 0 = direct launches;
+                          otherwise an even count >= 2                               */
+  uint32_t tile_order; /* 0: instance-major tile list; otherwise the seed of a
+                          pseudo-random permutation of it (results do not depend on
+                          the order; it changes only the schedule)                    */
+} lbm_batch_schedule;
+
+typedef struct lbm_batch_info {
+  int32_t n_inst;          /* instances                                              */
+  int32_t n_recorded;      /* force rows waiting in the batch ring                    */
+  int64_t total_tiles;     /* tiles over all instances                               */
+  int64_t total_fluid;     /* fluid nodes over all instances                         */
+  int64_t total_nodes;     /* nodes over all instances                               */
+  int64_t steps_done;      /* steps taken by lbm_batch_step (and autotuning)          */
+  int32_t n_graphs;        /* captured graphs held                                   */
+  int32_t compute_units;   /* of the bound device (0 before bind)                    */
+  lbm_batch_schedule schedule;
+} lbm_batch_info;
+
+/* Group n >= 1 distinct, bound handles of one precision into a batch whose ring holds
+ * max_record >= 1 force rows per instance.  LBM_EINVAL for a NULL, repeated or unbound
+ * member, mixed precisions, or a member whose state buffer is 4 GiB or more.  Needs no
+ * GPU work. */
+int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_batch_t** out);
+
+/* Device workspace of the batch (instance table, tile and sweep lists, force ring). */
+int lbm_batch_workspace_bytes(const lbm_batch_t* b, size_t* bytes);
+
+/* Bind a caller-allocated device workspace (256-byte aligned, at least
+ * lbm_batch_workspace_bytes) and a HIP stream (NULL = the null stream); uploads the
+ * tables and synchronises.  Creates one private stream of default priority, used only
+ * to capture graphs (graphs are launched on the bound stream). */
+int lbm_batch_bind(lbm_batch_t* b, void* device_workspace, size_t bytes, void* hip_stream);
+
+/* Choose the schedule (see lbm_batch_schedule).  LBM_EINVAL for negative values or an
+ * odd graph_steps.  Drops captured graphs. */
+int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s);
+
+/* Time candidate schedules (one block per tile and persistent grids of 1, 2, 4 and 8
+ * workgroups per compute unit, each with direct launches and with graphs of up to 64
+ * launches; the tile order is kept) over `steps` steps each, after a warm-up run of the
+ * same length, with forces force_scheme (0 = none).  Keeps the fastest and returns it in
+ * *best and its milliseconds per step in *ms_per_step (either may be NULL).  Every
+ * instance advances by 2 x steps per candidate (20 x steps in all); those force rows are
+ * not kept.  LBM_EOVERFLOW if the ring cannot hold `steps` rows beside the rows
+ * recorded.  Synchronises the stream. */
+int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
+                       lbm_batch_schedule* best, double* ms_per_step);
+
+/* Enqueue n >= 0 steps of every instance on the bound stream with the forces of
+ * force_scheme (as lbm_step).  LBM_EOVERFLOW when force rows would exceed max_record. */
+int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme);
+
+/* Drain the batch ring: out[i][t][scheme][component] (host, n_inst x cap x 3 x 2
+ * doubles) receives instance i's forces of the t-th recorded step, as lbm_forces
+ * gives them; *k_out the number of rows (also when out is NULL and nothing is
+ * recorded).  nonfinite (host, n_inst bytes, may be NULL) flags instances with a
+ * non-finite requested force.  Returns LBM_ENONFINITE when any flag is set (the rows
+ * are delivered and the ring drained all the same).  Synchronises the stream. */
+int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
+                     uint8_t* nonfinite);
+
+int lbm_batch_get_info(const lbm_batch_t* b, lbm_batch_info* info);
+
+/* Free the batch's host state, graphs and private stream (not the members). */
+int lbm_batch_destroy(lbm_batch_t* b);
+
+/* Message of the last failing call on b (or of the last failing lbm_batch_create when
+ * b is NULL). */
+const char* lbm_batch_last_error(const lbm_batch_t* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,3 +7,4 @@ kernels for gfx950 behind the C ABI of include/lbm.h.
 """
 from ._capi import LbmError  # noqa: F401
 from .sim import Plan, Sim, scheme_mask  # noqa: F401
+from .batch import Batch  # noqa: F401

@@ -26,7 +26,11 @@ EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_for
            "lbm_coefficients", "lbm_destroy", "lbm_get_links", "lbm_get_info",
            "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_last_error", "lbm_set_inlet", "lbm_set_tau", "lbm_reset",
-           "lbm_adjoint_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward")
+           "lbm_adjoint_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
+           "lbm_batch_create", "lbm_batch_workspace_bytes", "lbm_batch_bind",
+           "lbm_batch_set_schedule", "lbm_batch_autotune", "lbm_batch_step",
+           "lbm_batch_forces", "lbm_batch_get_info", "lbm_batch_destroy",
+           "lbm_batch_last_error")
 
 
 class lbm_grid(ctypes.Structure):
@@ -49,6 +53,19 @@ class lbm_info(ctypes.Structure):
                 ("n_recorded", ctypes.c_int64), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("plane_stride", ctypes.c_int64),
                 ("pitch", ctypes.c_int32), ("elem_bytes", ctypes.c_int32)]
+
+
+class lbm_batch_schedule(ctypes.Structure):
+    _fields_ = [("grid_blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("tile_order", ctypes.c_uint32)]
+
+
+class lbm_batch_info(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("n_recorded", ctypes.c_int32),
+                ("total_tiles", ctypes.c_int64), ("total_fluid", ctypes.c_int64),
+                ("total_nodes", ctypes.c_int64), ("steps_done", ctypes.c_int64),
+                ("n_graphs", ctypes.c_int32), ("compute_units", ctypes.c_int32),
+                ("schedule", lbm_batch_schedule)]
 
 
 class LbmError(RuntimeError):
@@ -96,8 +113,21 @@ def load():
     L.lbm_adjoint_backward.argtypes = [vp, ctypes.c_double, dp, dp]
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+    L.lbm_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.lbm_batch_bind.argtypes = [vp, vp, sz, vp]
+    L.lbm_batch_set_schedule.argtypes = [vp, ctypes.POINTER(lbm_batch_schedule)]
+    L.lbm_batch_autotune.argtypes = [vp, i32, u32, ctypes.POINTER(lbm_batch_schedule),
+                                     ctypes.POINTER(ctypes.c_double)]
+    L.lbm_batch_step.argtypes = [vp, i32, u32]
+    L.lbm_batch_forces.argtypes = [vp, dp, i64, ctypes.POINTER(i64),
+                                   ctypes.POINTER(ctypes.c_uint8)]
+    L.lbm_batch_get_info.argtypes = [vp, ctypes.POINTER(lbm_batch_info)]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_last_error.argtypes = [vp]
+    L.lbm_batch_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name != "lbm_last_error":
+        if not name.endswith("last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -106,5 +136,12 @@ def load():
 def check(rc, handle=None):
     if rc != LBM_OK:
         msg = load().lbm_last_error(handle)
+        raise LbmError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check_batch(rc, batch=None):
+    if rc != LBM_OK:
+        msg = load().lbm_batch_last_error(batch)
         raise LbmError(rc, msg.decode() if msg else "")
     return rc

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "adjoint.h"
+#include "handle.h"
 #include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
@@ -56,55 +57,6 @@ double host_weight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0
 
 }  // namespace
 
-struct lbm_t {
-  lbm_grid g;
-  double tau = 0.0, omega = 0.0, rho_w = 1.0;
-  std::vector<double> uin;
-  Plan plan;
-  // device layout
-  int32_t pitch = 0;
-  int64_t plane = 0;  // elements
-  size_t esz = 0;
-  size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_part = 0,
-         off_jpart = 0, off_ring = 0, total = 0;
-  int njblocks = 0;
-  // binding
-  char* ws = nullptr;
-  hipStream_t stream = nullptr;
-  bool bound = false;
-  int cur = 0;  // buffer holding the current state
-  int64_t steps_done = 0;
-  int64_t nrec = 0;
-  std::vector<uint32_t> rec_scheme;  // scheme mask per recorded row
-  std::string err;
-  // adjoint: workspace and the forward run it holds
-  bool adj_valid = false;
-  char* aws = nullptr;
-  size_t aws_bytes = 0;
-  int32_t adj_n = 0, adj_every = 0, adj_t0 = 0, adj_T = 0;
-  double adj_wx = 0.0, adj_wy = 0.0;
-  std::vector<uint32_t> adj_codes;
-
-  int fail(int code, const std::string& msg) {
-    err = msg;
-    return code;
-  }
-  int hip_fail(hipError_t e, const char* what) {
-    err = std::string(what) + ": " + hipGetErrorString(e);
-    return LBM_EHIP;
-  }
-  void* buf(int k) const { return ws + off_buf[k]; }
-  // Size of one state buffer for buffer-resource addressing, or 0 when it needs 64-bit
-  // addresses.
-  uint32_t buf_bytes32() const {
-    const uint64_t b = uint64_t(plane) * kQ * esz;
-    return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u;
-  }
-  double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
-  double* part(int k) const {
-    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * size_t(plan.nslots) * 8;
-  }
-};
 
 extern "C" {
 
@@ -225,7 +177,7 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
 
 }  // extern "C"
 
-namespace {
+namespace lbm {
 
 StepArgs step_args(const lbm_t* h) {
   const Plan& p = h->plan;
@@ -235,6 +187,7 @@ StepArgs step_args(const lbm_t* h) {
   a.pitch = h->pitch;
   a.nx = p.nx;
   a.ny = p.ny;
+  a.bc_x = p.bc_x;
   a.ntx = p.ntx;
   a.nty = p.nty;
   a.gx0 = p.gx0;
@@ -261,6 +214,31 @@ StepArgs step_args(const lbm_t* h) {
   a.nslots = p.nslots;
   return a;
 }
+
+BoxArgs box_args(const lbm_t* h, const void* src) {
+  const Plan& p = h->plan;
+  BoxArgs b{};
+  b.src = src;
+  b.plane = h->plane;
+  b.buf_bytes = h->buf_bytes32();
+  b.pitch = h->pitch;
+  b.nx = p.nx;
+  b.ny = p.ny;
+  b.bx0 = p.box[0];
+  b.bx1 = p.box[1];
+  b.by0 = p.box[2];
+  b.by1 = p.box[3];
+  b.box_bx = p.box_bx;
+  b.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
+  b.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  b.rho_w6 = 6.0 * h->rho_w;
+  b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+  return b;
+}
+
+}  // namespace lbm
+
+namespace {
 
 // Enqueue n >= 1 steps; step k reads io(k).first and writes io(k).second.  With a
 // non-null ring, the force row of step k goes to ring row k (rows are self-contained:
@@ -290,22 +268,7 @@ int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
   }
   if (forces) {
     if (p.has_box) {
-      BoxArgs b{};
-      b.src = last;
-      b.plane = h->plane;
-      b.buf_bytes = a.buf_bytes;
-      b.pitch = h->pitch;
-      b.nx = p.nx;
-      b.ny = p.ny;
-      b.bx0 = p.box[0];
-      b.bx1 = p.box[1];
-      b.by0 = p.box[2];
-      b.by1 = p.box[3];
-      b.box_bx = p.box_bx;
-      b.node = a.node;
-      b.uin = a.uin;
-      b.rho_w6 = a.rho_w6;
-      b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+      const BoxArgs b = box_args(h, last);
       hipError_t e = launch_box_momentum(h->g.precision, b, h->njblocks, h->stream);
       if (e != hipSuccess) return h->hip_fail(e, "launch box momentum");
     }

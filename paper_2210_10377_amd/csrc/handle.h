@@ -1,0 +1,72 @@
+// The handle of the C ABI (include/lbm.h), shared by the single-lattice entry points
+// (api.hip) and the batched ones (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "lbm.h"
+#include "plan.h"
+
+struct lbm_t {
+  lbm_grid g;
+  double tau = 0.0, omega = 0.0, rho_w = 1.0;
+  std::vector<double> uin;
+  lbm::Plan plan;
+  // device layout
+  int32_t pitch = 0;
+  int64_t plane = 0;  // elements
+  size_t esz = 0;
+  size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_part = 0,
+         off_jpart = 0, off_ring = 0, total = 0;
+  int njblocks = 0;
+  // binding
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;  // buffer holding the current state
+  int64_t steps_done = 0;
+  int64_t nrec = 0;
+  std::vector<uint32_t> rec_scheme;  // scheme mask per recorded row
+  std::string err;
+  // adjoint: workspace and the forward run it holds
+  bool adj_valid = false;
+  char* aws = nullptr;
+  size_t aws_bytes = 0;
+  int32_t adj_n = 0, adj_every = 0, adj_t0 = 0, adj_T = 0;
+  double adj_wx = 0.0, adj_wy = 0.0;
+  std::vector<uint32_t> adj_codes;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EHIP;
+  }
+  void* buf(int k) const { return ws + off_buf[k]; }
+  // Size of one state buffer for buffer-resource addressing, or 0 when it needs 64-bit
+  // addresses.
+  uint32_t buf_bytes32() const {
+    const uint64_t b = uint64_t(plane) * lbm::kQ * esz;
+    return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u;
+  }
+  double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
+  double* part(int k) const {
+    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * size_t(plan.nslots) * 8;
+  }
+};
+
+namespace lbm {
+
+// Kernel arguments of the handle's step (src, dst and the force buffers unset).
+StepArgs step_args(const lbm_t* h);
+// Control-volume sweep arguments of the handle over the state `src`.
+BoxArgs box_args(const lbm_t* h, const void* src);
+
+}  // namespace lbm

@@ -16,6 +16,7 @@ struct StepArgs {
                        // addressing), 0 for 64-bit global addressing
   int32_t pitch;    // row pitch, elements
   int32_t nx, ny;
+  int32_t bc_x;     // LBM_BCX_*
   int32_t ntx, nty, ntiles;
   int32_t gx0, gx1, gy0, gy1;  // node rectangle (inclusive) of every non-border node that
                                // needs the general path; empty when gx0 > gx1
@@ -56,7 +57,39 @@ struct FinalArgs {
   int32_t njblocks;
 };
 
+// Force-ring row: FAx FAy FBx FBy Jx Jy Phix Phiy Jnext_x Jnext_y.
+constexpr int kRingRow = 10;
+
+// One instance of a batch, as the batched kernels read it from device memory.
+struct BatchInst {
+  StepArgs a;               // geometry, tables and physics (src/dst/partials unused)
+  void* buf[2];             // the two state buffers
+  double* part[2];          // force partial buffers of alternate steps
+  double* ring;             // force rows of the current chunk [rows][kRingRow]
+  BoxArgs box;              // control-volume sweep (src chosen per launch)
+  int32_t njblocks;         // blocks of that sweep (0 without a box)
+};
+
+struct BatchLaunch {
+  const BatchInst* inst;     // [n_inst], device
+  const int32_t* tile_inst;  // [total_tiles] instance of each tile, device
+  const int32_t* tile_local; // [total_tiles] tile index inside its instance, device
+  const int32_t* box_inst;   // [total_box_blocks] instance of each box-sweep block
+  const int32_t* box_local;  // [total_box_blocks] block index inside its instance's sweep
+  const int32_t* ctl;        // {first force row of the launch sequence, steps before it}
+  int32_t n_inst, nred;      // instances; reducer blocks (n_inst rounded up to 8)
+  int32_t total_tiles, total_box_blocks;
+  int32_t grid_blocks;       // tile blocks per launch (0: one block per tile)
+};
+
 hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, int32_t parity,
+                             int32_t k, hipStream_t s);
+hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s);
+// Control-volume sweeps over buffer `parity` and finalization of force row `row` of every
+// instance (the last step of a call; its partials are in part[part_parity]).
+hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity, int32_t row,
+                             int32_t part_parity, bool has_prev, hipStream_t s);
 hipError_t launch_box_momentum(int precision, const BoxArgs& a, int blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 // Rest state w_i in every element of a population buffer (padding included).

@@ -23,6 +23,8 @@
 // Larger buffers use 64-bit global addresses.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
@@ -71,6 +73,32 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
     collide<C, S::kDev>(f, C(a.omega), g);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, pack<P>(g[i]));
+  }
+}
+
+// Plain strip holding x = 0, x = nx - 1 or lanes past the row end: the pull codes are
+// those of edge_word (inlet or wrap, outlet or wrap, plain streaming elsewhere), made
+// from the lane's x alone, with no per-node metadata; no forces.
+template <int P, bool BUF>
+__device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
+  using S = Storage<P>;
+  using T = typename S::T;
+  using C = typename S::C;
+  const Planes<T, BUF> src(a.src, a.plane, a.buf_bytes);
+  const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
+  const int pitch = a.pitch;
+  const int x = tx * kTileW + int(threadIdx.x);
+  if (x >= a.nx) return;
+  const uint32_t w = edge_word(a.nx, a.bc_x, x);
+  for (int r = 0; r < kTileH; ++r) {
+    const int y = ty * kTileH + r;
+    C f[kQ];
+    pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
+    C g[kQ];
+    collide<C, S::kDev>(f, C(a.omega), g);
+    const int32_t o = y * pitch + x;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
   }
 }
 
@@ -148,6 +176,42 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
   }
 }
 
+// Force row of the previous step from its partial slots (fixed order).
+__device__ __forceinline__ void reduce_row(const double* red_in, int nslots, double* row,
+                                           double* prev_jnext) {
+  const double t = reduce_partials8(red_in, nslots);
+  if (threadIdx.x < 8) {
+    row[threadIdx.x] = t;
+    if (prev_jnext && (threadIdx.x == 4 || threadIdx.x == 5)) prev_jnext[threadIdx.x - 4] = t;
+  }
+}
+
+// One 256 x kTileH tile of a step.
+template <int P, bool BUF, bool FORCES>
+__device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
+                                          const int32_t* __restrict__ strip_slot) {
+  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
+  // Each 64-lane wave covers a 64 x kTileH strip, classified from its coordinates
+  // alone (no memory access before the first population load).
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int x0 = tx * kTileW + 64 * wave;
+  if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, x0, ty * kTileH)) {
+    if (strip_is_interior(a.nx, x0)) {
+      typename Storage<P>::T v[kTileH][kQ];
+      interior_load<P, BUF>(a, tx, ty, v);
+      interior_finish<P, BUF>(a, tx, ty, v);
+    } else {
+      edge_rows<P, BUF>(a, tx, ty);
+    }
+    return;
+  }
+  const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
+  // FA(x,y), FB(x,y), J(x,y), Phi(x,y)
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  general_rows<P, BUF>(a, tx, ty, slot >= 0, acc);
+  if (slot >= 0) wave_sum8_store(acc, a.part_out + int64_t(slot) * 8);
+}
+
 template <int P, bool BUF, bool FORCES>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
@@ -156,43 +220,67 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
     // Block 0 is dispatched first: it reduces the previous step's force partials while
     // the tiles stream.
     if (tile == 0) {
-      const double t = reduce_partials8(a.red_in, a.nslots);
-      if (threadIdx.x < 8) {
-        a.red_row[threadIdx.x] = t;
-        if (a.red_prev_jnext && (threadIdx.x == 4 || threadIdx.x == 5))
-          a.red_prev_jnext[threadIdx.x - 4] = t;
-      }
+      reduce_row(a.red_in, a.nslots, a.red_row, a.red_prev_jnext);
       return;
     }
     --tile;
   }
-  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
-  // Each 64-lane wave covers a 64 x kTileH strip, classified from its coordinates
-  // alone (no memory access before the first population load).
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, tx * kTileW + 64 * wave,
-                     ty * kTileH)) {
-    typename Storage<P>::T v[kTileH][kQ];
-    interior_load<P, BUF>(a, tx, ty, v);
-    interior_finish<P, BUF>(a, tx, ty, v);
-    return;
-  }
-  const int slot = FORCES ? strip_slot[tile * (kTileW / 64) + wave] : -1;
-  // FA(x,y), FB(x,y), J(x,y), Phi(x,y)
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  general_rows<P, BUF>(a, tx, ty, slot >= 0, acc);
-  if (slot >= 0) wave_sum8_store(acc, a.part_out + int64_t(slot) * 8);
+  step_tile<P, BUF, FORCES>(a, tile, strip_slot);
 }
 
-// J over the control volume of the populations one pull of src gives.
+// Batched step: every instance of a batch advances one step in one launch.  The first
+// b.nred blocks (when forces are recorded) reduce the previous step's force row, one
+// instance each; the other blocks sweep the concatenated tile list of all instances,
+// `stride` tiles apart (a persistent sweep when the grid is smaller than the tile count,
+// one tile per block otherwise).  nred and a persistent grid are multiples of 8, so the
+// tile a block takes lies on the block's own XCD in the grouping of block_tile.
+// Step k of a launch sequence writes force row ctl[0] + k; ctl[1] counts the steps of
+// the same call enqueued before the sequence (their last row is still to be reduced).
+template <int P, bool FORCES, bool PERSIST>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 8)))
+void batch_step_kernel(
+    const BatchInst* __restrict__ inst, const int32_t* __restrict__ tile_inst,
+    const int32_t* __restrict__ tile_local, BatchLaunch b, int32_t parity, int32_t k) {
+  const int nred = FORCES ? b.nred : 0;
+  if (int(blockIdx.x) < nred) {
+    if (int(blockIdx.x) >= b.n_inst) return;
+    const int32_t row_base = b.ctl[0], nprev = b.ctl[1];
+    if (k == 0 && nprev == 0) return;
+    const BatchInst& I = inst[blockIdx.x];
+    const int64_t r = int64_t(row_base) + k - 1;
+    reduce_row(I.part[(k - 1) & 1], I.a.nslots, I.ring + r * kRingRow,
+               k + nprev >= 2 ? I.ring + (r - 1) * kRingRow + 8 : nullptr);
+    return;
+  }
+  const int stride = PERSIST ? int(gridDim.x) - nred : b.total_tiles;
+  for (int v = int(blockIdx.x) - nred; v < b.total_tiles; v += stride) {
+    const int t = block_tile(v, b.total_tiles);
+    const BatchInst& I = inst[tile_inst[t]];
+    StepArgs a = I.a;
+    a.src = I.buf[parity];
+    a.dst = I.buf[1 - parity];
+    a.part_out = I.part[k & 1];
+    step_tile<P, true, FORCES>(a, tile_local[t], a.strip_slot);
+  }
+}
+
+__global__ void batch_ctl_kernel(int32_t* ctl, int32_t row_base, int32_t nprev) {
+  if (threadIdx.x == 0) {
+    ctl[0] = row_base;
+    ctl[1] = nprev;
+  }
+}
+
+// J over the control volume of the populations one pull of src gives: block `blk` of
+// the box sweep (kTileW nodes of one box row) writes its two partial sums.
 template <int P, bool BUF>
-__global__ __launch_bounds__(kThreads) void box_momentum_kernel(BoxArgs a) {
+__device__ __forceinline__ void box_block(const BoxArgs& a, int blk) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
   const Planes<T, BUF> src(a.src, a.plane, a.buf_bytes);
-  const int row = blockIdx.x / a.box_bx;
-  const int x = a.bx0 + (blockIdx.x - row * a.box_bx) * kTileW + int(threadIdx.x);
+  const int row = blk / a.box_bx;
+  const int x = a.bx0 + (blk - row * a.box_bx) * kTileW + int(threadIdx.x);
   const int y = a.by0 + row;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (x < a.bx1) {
@@ -210,15 +298,25 @@ __global__ __launch_bounds__(kThreads) void box_momentum_kernel(BoxArgs a) {
   }
   __shared__ double out[8];
   block_sum8(v, out);
-  if (threadIdx.x < 2) a.jpart[int64_t(blockIdx.x) * 2 + threadIdx.x] = out[threadIdx.x];
+  if (threadIdx.x < 2) a.jpart[int64_t(blk) * 2 + threadIdx.x] = out[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kThreads) void finalize_kernel(FinalArgs a) {
-  const double t = reduce_partials8(a.red_in, a.nslots);
-  if (threadIdx.x < 8) {
-    a.row[threadIdx.x] = t;
-    if (a.prev_jnext && (threadIdx.x == 4 || threadIdx.x == 5)) a.prev_jnext[threadIdx.x - 4] = t;
-  }
+template <int P, bool BUF>
+__global__ __launch_bounds__(kThreads) void box_momentum_kernel(BoxArgs a) {
+  box_block<P, BUF>(a, blockIdx.x);
+}
+
+// Box sweeps of all instances of a batch (block b -> instance box_inst[b]).
+template <int P>
+__global__ __launch_bounds__(kThreads) void batch_box_kernel(BatchLaunch b, int32_t parity) {
+  const BatchInst& I = b.inst[b.box_inst[blockIdx.x]];
+  BoxArgs x = I.box;
+  x.src = I.buf[parity];
+  box_block<P, true>(x, b.box_local[blockIdx.x]);
+}
+
+__device__ __forceinline__ void finalize_body(const FinalArgs& a) {
+  reduce_row(a.red_in, a.nslots, a.row, a.prev_jnext);
   if (a.jpart) {
     __syncthreads();
     __shared__ double red[kThreads][2];
@@ -238,6 +336,24 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(FinalArgs a) {
   } else if (threadIdx.x < 2) {
     a.row[8 + threadIdx.x] = __builtin_nan("");
   }
+}
+
+__global__ __launch_bounds__(kThreads) void finalize_kernel(FinalArgs a) { finalize_body(a); }
+
+// Finalize of every instance of a batch (one block each): force row `row` from the
+// partials part[part_parity] and, without a box, NaN for its Jnext.
+__global__ __launch_bounds__(kThreads) void batch_finalize_kernel(BatchLaunch b, int32_t row,
+                                                                  int32_t part_parity,
+                                                                  int32_t has_prev) {
+  const BatchInst& I = b.inst[blockIdx.x];
+  FinalArgs f{};
+  f.red_in = I.part[part_parity];
+  f.nslots = I.a.nslots;
+  f.row = I.ring + int64_t(row) * kRingRow;
+  f.prev_jnext = has_prev ? I.ring + (int64_t(row) - 1) * kRingRow + 8 : nullptr;
+  f.jpart = I.njblocks > 0 ? I.box.jpart : nullptr;
+  f.njblocks = I.njblocks;
+  finalize_body(f);
 }
 
 template <int P>
@@ -295,6 +411,61 @@ hipError_t launch_box_momentum(int precision, const BoxArgs& a, int blocks, hipS
     case LBM_FP32DEV: return box_dispatch<LBM_FP32DEV>(a, blocks, s);
     default: return box_dispatch<LBM_FP16DEV>(a, blocks, s);
   }
+}
+
+hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, int32_t parity,
+                             int32_t k, hipStream_t s) {
+  const bool persist = b.grid_blocks > 0 && b.grid_blocks < b.total_tiles;
+  const int tiles = persist ? b.grid_blocks : b.total_tiles;
+  const dim3 grid((forces ? b.nred : 0) + tiles);
+#define LBM_BATCH_GO(P, F, R) \
+  hipLaunchKernelGGL((batch_step_kernel<P, F, R>), grid, dim3(kThreads), 0, s, b.inst, \
+                     b.tile_inst, b.tile_local, b, parity, k)
+#define LBM_BATCH_LAUNCH(P)                                          \
+  if (forces) {                                                      \
+    if (persist) LBM_BATCH_GO(P, true, true); else LBM_BATCH_GO(P, true, false);   \
+  } else {                                                           \
+    if (persist) LBM_BATCH_GO(P, false, true); else LBM_BATCH_GO(P, false, false); \
+  }
+  switch (precision) {
+    case LBM_FP64: LBM_BATCH_LAUNCH(LBM_FP64) break;
+    case LBM_FP32: LBM_BATCH_LAUNCH(LBM_FP32) break;
+    case LBM_FP32DEV: LBM_BATCH_LAUNCH(LBM_FP32DEV) break;
+    default: LBM_BATCH_LAUNCH(LBM_FP16DEV)
+  }
+#undef LBM_BATCH_LAUNCH
+#undef LBM_BATCH_GO
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s) {
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3(1), dim3(64), 0, s, ctl, row_base, nprev);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity, int32_t row,
+                             int32_t part_parity, bool has_prev, hipStream_t s) {
+  if (b.total_box_blocks > 0) {
+    const dim3 grid(b.total_box_blocks);
+    switch (precision) {
+      case LBM_FP64:
+        hipLaunchKernelGGL(batch_box_kernel<LBM_FP64>, grid, dim3(kThreads), 0, s, b, parity);
+        break;
+      case LBM_FP32:
+        hipLaunchKernelGGL(batch_box_kernel<LBM_FP32>, grid, dim3(kThreads), 0, s, b, parity);
+        break;
+      case LBM_FP32DEV:
+        hipLaunchKernelGGL(batch_box_kernel<LBM_FP32DEV>, grid, dim3(kThreads), 0, s, b, parity);
+        break;
+      default:
+        hipLaunchKernelGGL(batch_box_kernel<LBM_FP16DEV>, grid, dim3(kThreads), 0, s, b, parity);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(b.n_inst), dim3(kThreads), 0, s, b, row,
+                     part_parity, int32_t(has_prev ? 1 : 0));
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {

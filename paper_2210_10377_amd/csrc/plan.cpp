@@ -124,14 +124,14 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         }
     }
 
-  // Rectangle of every node off the domain border that needs the general path.
+  // Rectangle of every node off the first and last rows that needs the general path.
   auto band = [&](int x, int y) {
     return p.has_box && x >= p.box[0] - 1 && x <= p.box[1] && y >= p.box[2] - 1 &&
            y <= p.box[3];
   };
   for (int y = 1; y < g.ny - 1; ++y)
-    for (int x = 1; x < g.nx - 1; ++x) {
-      if (p.node[size_t(y) * g.nx + x] == 0u && !band(x, y)) continue;
+    for (int x = 0; x < g.nx; ++x) {
+      if (p.node[size_t(y) * g.nx + x] == edge_word(g.nx, g.bc_x, x) && !band(x, y)) continue;
       if (p.gx0 > p.gx1) {
         p.gx0 = p.gx1 = x;
         p.gy0 = p.gy1 = y;
@@ -142,9 +142,9 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         p.gy1 = std::max(p.gy1, y);
       }
     }
-  // Tiles and strips.  A strip outside that rectangle and off the border streams
-  // plainly; the others take the general path, and those holding a link node or a
-  // control-volume-band node own a force-partial slot.
+  // Tiles and strips.  A strip outside that rectangle and off the first and last rows
+  // needs no per-node metadata; the others take the general path, and those holding a
+  // link node or a control-volume-band node own a force-partial slot.
   p.ntx = (g.nx + kTileW - 1) / kTileW;
   p.nty = (g.ny + kTileH - 1) / kTileH;
   p.ntiles = p.ntx * p.nty;

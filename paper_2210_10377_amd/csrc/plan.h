@@ -41,14 +41,34 @@ constexpr int kTileH = LBM_TILE_H;
 constexpr int kStripW = 64;
 constexpr int kStrips = kTileW / kStripW;
 
-// A strip streams plainly when it stays off the domain border and outside the
-// rectangle [gx0, gx1] x [gy0, gy1] that holds every other boundary, body and
-// control-volume-band node.  Host plan and step kernel share this rule.
+// Pull-code word of a node off the first and last rows that no body, wall, outlet
+// bounce-back or control volume touches: plain streaming, except that at x = 0 the
+// directions with c_x = +1 take the inlet rule (periodic x: the wrap) and at x = nx - 1
+// those with c_x = -1 take the outlet rule (periodic x: the wrap).
+constexpr uint32_t edge_word(int nx, int bc_x, int x) {
+  uint32_t w = 0;
+  for (int i = 1; i < kQ; ++i) {
+    if (x == 0 && kCx[i] == 1)
+      w |= uint32_t(bc_x == LBM_BCX_PERIODIC ? kWrap : kInlet) << (3 * (i - 1));
+    if (x == nx - 1 && kCx[i] == -1)
+      w |= uint32_t(bc_x == LBM_BCX_PERIODIC ? kWrap : kOutlet) << (3 * (i - 1));
+  }
+  return w;
+}
+
+// A strip is "plain" when it stays off the first and last rows and outside the
+// rectangle [gx0, gx1] x [gy0, gy1] that holds every node of the other rows whose pull
+// codes are not edge_word (bodies, their links, outlet bounce-backs) and every node of
+// the control-volume band: its nodes need no per-node metadata.  A plain strip is
+// "interior" when it also holds neither x = 0 nor x = nx - 1 nor any x >= nx (plain
+// streaming in every direction).  Host plan and kernels share these rules.
 constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int x0,
                               int y0) {
-  return x0 > 0 && x0 + kStripW < nx && y0 > 0 && y0 + kTileH < ny &&
+  (void)nx;
+  return y0 > 0 && y0 + kTileH < ny &&
          !(y0 <= gy1 && y0 + kTileH - 1 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
 }
+constexpr bool strip_is_interior(int nx, int x0) { return x0 > 0 && x0 + kStripW < nx; }
 
 struct Plan {
   int nx = 0, ny = 0, bc_x = 0, bc_y = 0;
@@ -57,8 +77,8 @@ struct Plan {
   std::vector<uint32_t> node;     // [ny*nx] pull codes + solid bit
   std::vector<int32_t> links;     // [L][2] (y*nx + x, i), canonical order
   int ntx = 0, nty = 0, ntiles = 0;  // tiles per row / column / total
-  // Inclusive node rectangle holding every node off the domain border that needs the
-  // general path (a solid node, a pull that is not plain streaming, a node of the
+  // Inclusive node rectangle holding every node off the first and last rows that needs
+  // the general path (a solid node, pull codes other than edge_word, a node of the
   // control-volume band); empty when gx0 > gx1.
   int gx0 = 0, gx1 = -1, gy0 = 0, gy1 = -1;
   // Per strip (tile-major, kStrips per tile): the index >= 0 of its force-partial slot

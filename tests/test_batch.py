@@ -1,0 +1,212 @@
+"""Batched stepping: every instance of a batch equals the same instance stepped alone.
+
+The batch runs the single-lattice tile code of every instance inside one launch per
+step, so the populations and all three forces of each instance must be bitwise those of
+``Sim.step`` with the same call lengths, whatever the schedule (one workgroup per tile or
+a persistent grid, direct launches or graph replays, any tile order).  The single path is
+itself held to the oracle (test_gpu_parity.py); an FP64 mini batch is also compared with
+the oracle directly.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _members(ws, precision="fp32"):
+    from paper_2210_10377_amd import Sim
+    return [Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=512,
+                u_ref=w.u_ref, l_ref=w.l_ref) for w in ws]
+
+
+def _batch(ws, precision="fp32", max_record=512):
+    from paper_2210_10377_amd import Batch
+    return Batch(_members(ws, precision), max_record=max_record)
+
+
+def _seed_states(sims, ws, seed0=100):
+    for i, (s, w) in enumerate(zip(sims, ws)):
+        S = workloads.near_rest_state(w.nx, w.ny, seed0 + i, amp=0.02, dtype=np.float32)
+        s.set_populations(S)
+
+
+def _singles(ws, calls, precision="fp32", seed0=100):
+    """Each instance stepped alone with the given call lengths; (populations, forces)."""
+    sims = _members(ws, precision)
+    _seed_states(sims, ws, seed0)
+    pops, forces = [], []
+    for s in sims:
+        F = []
+        for n in calls:
+            s.step(n)
+            F.append(s.forces())
+        pops.append(s.populations())
+        forces.append(np.concatenate(F))
+    return pops, forces
+
+
+def _batched(ws, calls, precision="fp32", schedule=None, seed0=100):
+    b = _batch(ws, precision)
+    _seed_states(b.members, ws, seed0)
+    if schedule:
+        b.set_schedule(**schedule)
+    F = []
+    for n in calls:
+        b.step(n)
+        Fi, bad = b.forces()
+        assert not bad.any()
+        F.append(Fi)
+    return [m.populations() for m in b.members], np.concatenate(F, axis=1), b
+
+
+def _assert_same(pa, fa, pb, fb):
+    for i in range(len(pa)):
+        np.testing.assert_array_equal(pa[i], pb[i], err_msg=f"populations of instance {i}")
+        np.testing.assert_array_equal(fa[i], fb[i], err_msg=f"forces of instance {i}")
+
+
+MINI = workloads.batched_instances(8)
+CALLS = (37, 6, 1)
+
+SCHEDULES = {
+    "one_block_per_tile": dict(grid_blocks=0, graph_steps=0),
+    "persistent_small_grid": dict(grid_blocks=24, graph_steps=0),
+    "graph_chunks": dict(grid_blocks=0, graph_steps=8),
+    "persistent_graph_shuffled": dict(grid_blocks=40, graph_steps=4, tile_order=12345),
+}
+
+
+@pytest.fixture(scope="module")
+def mini_singles():
+    return _singles(MINI, CALLS)
+
+
+@pytest.mark.parametrize("name", list(SCHEDULES))
+def test_mini_batch_bitwise_equals_singles(name, mini_singles):
+    pb, fb, b = _batched(MINI, CALLS, schedule=SCHEDULES[name])
+    ps, fs = mini_singles
+    _assert_same(ps, [f for f in fs], pb, [fb[i] for i in range(len(MINI))])
+    inf = b.info()
+    assert inf.steps_done == sum(CALLS)
+    for m in b.members:
+        assert m.info().steps_done == sum(CALLS)
+
+
+def test_fp64_mini_batch_against_oracle():
+    ws = workloads.batched_instances(4)
+    b = _batch(ws, "fp64")
+    _seed_states(b.members, ws)
+    n = 40
+    b.step(n)
+    F, bad = b.forces()
+    assert not bad.any()
+    for i, w in enumerate(ws):
+        o = OracleSim(w.mask, w.tau, w.uin, box=w.box)
+        o.set_state(workloads.near_rest_state(w.nx, w.ny, 100 + i, amp=0.02, dtype=np.float32))
+        o.step(n)
+        Fo = o.forces()
+        So = o.state()
+        Sg = b.members[i].populations()
+        fl = w.mask == 0
+        assert (np.abs(Sg - So)[:, fl] / np.abs(So)[:, fl]).max() <= TOL64
+        for k in range(3):
+            scale = np.abs(Fo[:, k]).max()
+            assert np.abs(F[i, :, k] - Fo[:, k]).max() / scale <= TOL64, (i, k)
+
+
+def test_members_changed_between_batch_calls():
+    """A member stepped alone, or given a new tau, between batch calls is picked up."""
+    ws = MINI[:4]
+    b = _batch(ws)
+    _seed_states(b.members, ws)
+    b.set_schedule(grid_blocks=0, graph_steps=4)
+    ref = _members(ws)
+    _seed_states(ref, ws)
+    b.step(5)
+    b.forces()
+    for r in ref:
+        r.step(5)
+        r.forces()
+    # instance 1 takes 3 steps alone (its buffers swap parity against the others)
+    b.members[1].step(3)
+    b.members[1].forces()
+    ref[1].step(3)
+    ref[1].forces()
+    # instance 2 gets a new relaxation time
+    b.members[2].set_tau(0.61)
+    ref[2].set_tau(0.61)
+    b.step(9)
+    Fb, _ = b.forces()
+    for i, r in enumerate(ref):
+        r.step(9)
+        np.testing.assert_array_equal(r.forces(), Fb[i])
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+
+
+def test_steps_without_forces_and_ring_overflow():
+    from paper_2210_10377_amd import LbmError
+    ws = MINI[:3]
+    b = _batch(ws, max_record=10)
+    _seed_states(b.members, ws)
+    ref = _members(ws)
+    _seed_states(ref, ws)
+    b.set_schedule(grid_blocks=16, graph_steps=6)
+    b.step(13, schemes=())
+    for r in ref:
+        r.step(13, schemes=())
+    for i, r in enumerate(ref):
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+    b.step(10)
+    with pytest.raises(LbmError):
+        b.step(1)
+    F, _ = b.forces()
+    assert F.shape == (3, 10, 3, 2)
+
+
+def test_nonfinite_instance_is_flagged_alone():
+    from paper_2210_10377_amd import Sim, Batch
+    ws = MINI[:3]
+    sims = _members(ws)
+    _seed_states(sims, ws)
+    # instance 1 starts from a field with a NaN population on a link node
+    S = sims[1].populations()
+    ys, xs = np.nonzero(ws[1].mask)
+    S[1, ys[0], xs[0] - 1] = np.nan
+    sims[1].set_populations(S)
+    b = Batch(sims, max_record=64)
+    b.step(20)
+    F, bad = b.forces()
+    assert bad.tolist() == [False, True, False]
+    assert np.isfinite(F[0]).all() and np.isfinite(F[2]).all()
+
+
+def test_autotune_keeps_results_bitwise():
+    ws = MINI
+    b = _batch(ws)
+    _seed_states(b.members, ws)
+    sched, ms = b.autotune(steps=4)
+    assert ms > 0
+    assert sched["graph_steps"] in (0, 4)
+    assert b.info().steps_done == 5 * 2 * 2 * 4
+    b.step(7)
+    Fb, _ = b.forces()
+    ref = _members(ws)
+    _seed_states(ref, ws)
+    for i, r in enumerate(ref):
+        r.step(5 * 2 * 2 * 4, schemes=())
+        r.step(7)
+        np.testing.assert_array_equal(r.forces(), Fb[i])
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+
+
+def test_full_256_instance_batch_bitwise_equals_singles():
+    ws = workloads.batched_instances()
+    calls = (10,)
+    pb, fb, b = _batched(ws, calls, schedule=dict(grid_blocks=2048, graph_steps=4))
+    ps, fs = _singles(ws, calls)
+    _assert_same(ps, fs, pb, [fb[i] for i in range(len(ws))])

@@ -38,7 +38,9 @@ def test_struct_layout_matches_header(capi, tmp_path):
     """The ctypes mirrors of lbm_grid, lbm_inlet and lbm_info have the C compiler's
     sizes and field offsets."""
     import subprocess
-    structs = {"lbm_grid": capi.lbm_grid, "lbm_inlet": capi.lbm_inlet, "lbm_info": capi.lbm_info}
+    structs = {"lbm_grid": capi.lbm_grid, "lbm_inlet": capi.lbm_inlet, "lbm_info": capi.lbm_info,
+               "lbm_batch_schedule": capi.lbm_batch_schedule,
+               "lbm_batch_info": capi.lbm_batch_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -193,3 +195,34 @@ def test_workspace_size_accounts_for_buffers(capi):
         assert inf.pitch >= 300 and inf.pitch % 64 == 0
         assert inf.plane_stride >= inf.pitch * 100
         assert p.workspace_bytes() >= 2 * 9 * inf.plane_stride * s + 300 * 100 * 4
+
+
+def test_batch_create_rejects_bad_members(capi):
+    """lbm_batch_create validates its members without a GPU: null, unbound, repeated."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    p = Plan(workloads.cylinder_mask(40, 20, 10, 9.5, 3), uin=0.05)
+    out = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 2)(p._h.value, p._h.value)
+    assert L.lbm_batch_create(arr, 2, 8, ctypes.byref(out)) == capi.LBM_EINVAL
+    assert b"unbound" in L.lbm_batch_last_error(None)
+    assert L.lbm_batch_create(arr, 0, 8, ctypes.byref(out)) == capi.LBM_EINVAL
+    assert L.lbm_batch_create(None, 1, 8, ctypes.byref(out)) == capi.LBM_EINVAL
+    assert L.lbm_batch_create(arr, 1, 0, ctypes.byref(out)) == capi.LBM_EINVAL
+    nul = (ctypes.c_void_p * 1)(None)
+    assert L.lbm_batch_create(nul, 1, 8, ctypes.byref(out)) == capi.LBM_EINVAL
+    assert L.lbm_batch_destroy(None) == capi.LBM_OK
+
+
+def test_batched_instances_recipe():
+    """The batched instance list: sizes, body types and parameter ranges of the recipe,
+    and every control volume admissible."""
+    import oracle
+    ws = workloads.batched_instances()
+    assert len(ws) == 256
+    assert all(64 <= w.nx <= 512 and w.ny == w.nx // 2 for w in ws)
+    assert all(0.5 < w.tau < 0.7 for w in ws)
+    kinds = [w.meta["type"] for w in ws]
+    assert 100 < kinds.count("cylinder") < 156
+    assert all(oracle.box_admissible(w.mask, w.box) for w in ws[:32])
+    assert 12e6 < sum(w.nx * w.ny for w in ws) < 14e6

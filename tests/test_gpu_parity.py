@@ -49,6 +49,12 @@ CASES = {
                            lambda nx, ny: workloads.cylinder_mask(nx, ny, 30, 12.5, 4.5), (20, 41, 4, 22), 0.03),
     "solid_touching_outlet_and_wall": (50, 20, BCX_INLET_OUTLET, BCY_WALL,
                                        lambda nx, ny: _edge_mask(nx, ny), None, 0.05),
+    # solids on and next to the inlet column: links from x = 0, inlet beside bounce-back
+    "solid_touching_inlet": (90, 22, BCX_INLET_OUTLET, BCY_WALL,
+                             lambda nx, ny: _inlet_mask(nx, ny), None, 0.04),
+    # periodic x with a body crossing the seam (wrap beside bounce-back at both edges)
+    "periodic_x_body_on_seam": (70, 18, BCX_PERIODIC, BCY_WALL,
+                                lambda nx, ny: _seam_mask(nx, ny), None, None),
     # several tiles wide and tall, ragged in both directions, interior tiles present
     "multi_tile_ragged": (600, 37, BCX_INLET_OUTLET, BCY_WALL,
                           lambda nx, ny: workloads.cylinder_mask(nx, ny, 80, 18, 8), (60, 101, 6, 31), 0.05),
@@ -60,6 +66,21 @@ def _edge_mask(nx, ny):
     m[0:4, nx - 3:nx] = 1       # solid block in the outlet corner (touches wall and outlet)
     m[ny - 1, 10:14] = 1        # solid on the top wall row
     m[9:11, 20:22] = 1
+    return m
+
+
+def _inlet_mask(nx, ny):
+    m = np.zeros((ny, nx), np.uint8)
+    m[6:9, 0:2] = 1             # block on the inlet column
+    m[13, 1] = 1                # single node next to the inlet column
+    m[10:12, 70:73] = 1         # a body in the last strip, off the outlet column
+    return m
+
+
+def _seam_mask(nx, ny):
+    m = np.zeros((ny, nx), np.uint8)
+    m[7:10, nx - 2:nx] = 1
+    m[7:10, 0:2] = 1
     return m
 
 

@@ -169,3 +169,45 @@ def naca_8192x4096(aoa: float = 4.0, re: float = 1e4) -> Workload:
 
 def naca_1024x512_adjoint() -> Workload:
     return naca_channel(1024, 512, 256, 0.0, 500.0, 10000)
+
+
+BATCH_SEED = 2210_10377
+
+
+def batched_instances(n: int = 256, seed: int = BATCH_SEED, u: float = 0.05,
+                      steps: int = 10000) -> list[Workload]:
+    """``n`` independent channel problems of uneven size, drawn from
+    ``numpy.random.default_rng(seed)``; per instance, in this order: width
+    W ~ U{64..512} (height H = W // 2), body type (cylinder if U(0,1) < 1/2, else
+    NACA0012), angle of attack ~ U(0, 10) degrees (drawn for every instance, used by
+    airfoils), Re ~ U(20, 2000).
+
+    Cylinder: diameter D = 0.2 H centred at (0.25 W, 0.5 H), Re on D, control volume the
+    body box grown by D/4 (1.5 D across).  Airfoil: chord c = W // 4 with its leading
+    edge at W // 4 at zero incidence, pivot at the quarter chord on row H // 2, Re on
+    c, control volume the body box grown by c/4.  Uniform inlet u, walls, outlet."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W = int(rng.integers(64, 513))
+        H = W // 2
+        cyl = bool(rng.random() < 0.5)
+        aoa = float(rng.uniform(0.0, 10.0))
+        re = float(rng.uniform(20.0, 2000.0))
+        if cyl:
+            d = 0.2 * H
+            mask = cylinder_mask(W, H, 0.25 * W, 0.5 * H, d / 2.0)
+            box = default_box(mask, max(2, int(round(d / 4.0))))
+            out.append(Workload(f"b{i:03d}_cyl_{W}x{H}_re{re:.0f}", W, H, mask,
+                                tau_from_re(u, d, re), uniform_inlet(H, u), box, steps, u,
+                                d, meta={"type": "cylinder", "re": re, "d": d}))
+        else:
+            chord = W // 4
+            xq, yq = W // 4 + chord // 4, H // 2
+            mask = naca0012_mask(W, H, chord, xq, yq, aoa)
+            box = default_box(mask, max(2, chord // 4))
+            out.append(Workload(f"b{i:03d}_naca_{W}x{H}_a{aoa:.1f}_re{re:.0f}", W, H, mask,
+                                tau_from_re(u, chord, re), uniform_inlet(H, u), box, steps,
+                                u, float(chord), meta={"type": "naca0012", "re": re,
+                                                       "aoa": aoa, "chord": chord}))
+    return out
