@@ -35,7 +35,10 @@ def build(force: bool = True) -> str:
 class _Cfg(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_x", ctypes.c_int32),
                 ("bc_y", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
-                ("rho_w", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double)]
+                ("rho_w", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("collision", ctypes.c_int32)]
+
+COLLISIONS = {"bgk": 0, "regularized": 1}
 
 
 _lib = None
@@ -53,6 +56,7 @@ def lib():
         L.orc_lattice.argtypes = [ip, ip, ip, dp, dp]
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_collide_node.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_collide_node_regularized.argtypes = [dp, ctypes.c_double, dp]
         L.orc_box_admissible.argtypes = [cp, u8]
         L.orc_box_admissible.restype = ctypes.c_int
         L.orc_links.argtypes = [cp, u8, ip, ctypes.c_int64]
@@ -80,8 +84,9 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g):
+def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g, collision="bgk"):
     c = _Cfg()
+    c.collision = COLLISIONS[collision]
     c.nx, c.ny, c.bc_x, c.bc_y = int(nx), int(ny), int(bc_x), int(bc_y)
     b = (-1, -1, -1, -1) if box is None else tuple(int(v) for v in box)
     for k in range(4):
@@ -110,10 +115,15 @@ def equilibrium(rho, ux, uy):
     return out
 
 
-def collide_node(f, omega, g=(0.0, 0.0)):
+def collide_node(f, omega, g=(0.0, 0.0), collision="bgk"):
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros(9)
-    lib().orc_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), _dp(out))
+    if collision == "regularized":
+        if g[0] or g[1]:
+            raise ValueError("the regularized collision takes no body force")
+        lib().orc_collide_node_regularized(_dp(f), float(omega), _dp(out))
+    else:
+        lib().orc_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), _dp(out))
     return out
 
 
@@ -145,17 +155,18 @@ def links(mask, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL):
 class OracleSim:
     """FP64 reference simulation.  ``tau`` is the lattice relaxation time tau_lb
     (omega = 1/tau_lb); pass ``omega`` directly for the pure-streaming fixture
-    (omega = 0)."""
+    (omega = 0).  ``collision`` is "bgk" (Eq. CollideAdv) or "regularized" (the stated
+    variant for tau_lb close to 1/2)."""
 
     def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL,
-                 box=None, rho_w=1.0, g=(0.0, 0.0), omega=None):
+                 box=None, rho_w=1.0, g=(0.0, 0.0), omega=None, collision="bgk"):
         m, mp = _mask(mask)
         self.ny, self.nx = m.shape
         if omega is None:
             omega = 1.0 / float(tau)
         self.omega = float(omega)
         self.box = box
-        self._cfg = _cfg(self.nx, self.ny, bc_x, bc_y, box, rho_w, g)
+        self._cfg = _cfg(self.nx, self.ny, bc_x, bc_y, box, rho_w, g, collision)
         u = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),

@@ -113,11 +113,49 @@ void collide_node(const T* f, T omega, double gx, double gy, T* out) {
   }
 }
 
+// Regularized collision (Latt & Chopard, Math. Comput. Simul. 72 (2006) 165): the
+// stated variant for relaxation times close to 1/2, where BGK loses stability.  It is
+// not in the paper.  The non-equilibrium part of f is replaced by its projection on the
+// second-order Hermite subspace before relaxing:
+//   Pi^neq = sum_i c_i c_i (f_i - f_i^eq),
+//   f_i^(1) = w_i / (2 theta0^2) (c_i c_i - theta0 I) : Pi^neq,
+//   f~_i = f_i^eq + (1 - 2 beta) f_i^(1).
+// Mass and momentum are conserved as in BGK (f^(1) has neither).
+template <class T>
+void collide_node_regularized(const T* f, T omega, T* out) {
+  T rho = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    jx += double(CX[i]) * f[i];
+    jy += double(CY[i]) * f[i];
+  }
+  T ux = jx / rho;
+  T uy = jy / rho;
+  T feq[NQ];
+  T pxx = 0.0, pxy = 0.0, pyy = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    feq[i] = equilibrium<T>(i, rho, ux, uy);
+    T neq = f[i] - feq[i];
+    pxx += double(CX[i] * CX[i]) * neq;
+    pxy += double(CX[i] * CY[i]) * neq;
+    pyy += double(CY[i] * CY[i]) * neq;
+  }
+  for (int i = 0; i < NQ; ++i) {
+    T q = (double(CX[i] * CX[i]) - THETA0) * pxx + 2.0 * double(CX[i] * CY[i]) * pxy +
+          (double(CY[i] * CY[i]) - THETA0) * pyy;
+    T f1 = W[i] / (2.0 * THETA0 * THETA0) * q;
+    out[i] = feq[i] + (1.0 - omega) * f1;
+  }
+}
+
+enum { COLLISION_BGK = 0, COLLISION_REGULARIZED = 1 };
+
 struct Config {
   int32_t nx, ny, bc_x, bc_y;
   int32_t box[4];  // x0, x1, y0, y1; x0 < 0 means no control volume
   double rho_w;    // inlet wall density
-  double gx, gy;   // body force (test fixtures only)
+  double gx, gy;   // body force (test fixtures only; BGK only)
+  int32_t collision;  // COLLISION_BGK or COLLISION_REGULARIZED
 };
 
 template <class T>
@@ -224,7 +262,10 @@ struct Sim {
         if (is_solid(x, y)) continue;
         T fin[NQ], fout[NQ];
         for (int i = 0; i < NQ; ++i) fin[i] = f[idx(i, x, y)];
-        collide_node<T>(fin, omega, cfg.gx, cfg.gy, fout);
+        if (cfg.collision == COLLISION_REGULARIZED)
+          collide_node_regularized<T>(fin, omega, fout);
+        else
+          collide_node<T>(fin, omega, cfg.gx, cfg.gy, fout);
         for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y)] = fout[i];
       }
     // Momentum exchange on every fluid-solid link (Sec. III; Eq. rtt4, rtt5):
@@ -321,6 +362,8 @@ bool config_valid(const Config& c, const uint8_t* mask) {
   if (c.nx < 2 || c.ny < 2) return false;
   if (c.bc_x != BCX_INLET_OUTLET && c.bc_x != BCX_PERIODIC) return false;
   if (c.bc_y != BCY_WALL && c.bc_y != BCY_PERIODIC) return false;
+  if (c.collision != COLLISION_BGK && c.collision != COLLISION_REGULARIZED) return false;
+  if (c.collision == COLLISION_REGULARIZED && (c.gx != 0.0 || c.gy != 0.0)) return false;
   for (size_t k = 0; k < size_t(c.nx) * c.ny; ++k)
     if (mask[k] > 1) return false;
   return box_admissible(c, mask);
@@ -367,6 +410,10 @@ void orc_equilibrium(double rho, double ux, double uy, double* feq) {
 
 void orc_collide_node(const double* f, double omega, double gx, double gy, double* out) {
   collide_node<double>(f, omega, gx, gy, out);
+}
+
+void orc_collide_node_regularized(const double* f, double omega, double* out) {
+  collide_node_regularized<double>(f, omega, out);
 }
 
 int orc_box_admissible(const orc_cfg* c, const uint8_t* mask) {

@@ -602,3 +602,83 @@ def test_complex_step_matches_central_differences(orc):
     o = OracleSim(mask, tau=tau, uin=uin)
     o.step(n)
     assert abs(Jr.real - o.forces()[t0:t0 + T, 1, 0].mean()) <= 1e-15
+
+
+# --------------------------------------------------------------------------------------
+# Regularized collision (Latt & Chopard 2006; the stated variant for tau_lb -> 1/2, not
+# in the paper)
+# --------------------------------------------------------------------------------------
+
+def _random_f(seed, amp=0.2):
+    rng = np.random.default_rng(seed)
+    return workloads.NEAR_REST_BASE * (1.0 + amp * rng.uniform(-1.0, 1.0, 9))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_regularized_conserves_mass_and_momentum(orc, seed):
+    cx, cy, _, _, _ = orc.lattice()
+    f = _random_f(seed)
+    for omega in (0.3, 1.0, 1.7, 1.999):
+        g = orc.collide_node(f, omega, collision="regularized")
+        assert abs(g.sum() - f.sum()) <= 4e-16
+        assert abs(cx @ g - cx @ f) <= 4e-16 and abs(cy @ g - cy @ f) <= 4e-16
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_regularized_equals_bgk_on_second_order_hermite_subspace(orc, seed):
+    """For f = f^eq(rho, u) + w_i (c_i c_i - theta0 I) : A (A symmetric), the
+    non-equilibrium part already lies in the second-order Hermite subspace, so the
+    projection is the identity and the regularized collision is BGK (Eq. CollideAdv)."""
+    cx, cy, _, w, th = orc.lattice()
+    rng = np.random.default_rng(100 + seed)
+    rho, ux, uy = 1.0 + 0.1 * rng.uniform(), 0.05 * rng.uniform(-1, 1), 0.05 * rng.uniform(-1, 1)
+    a, b, c = 1e-3 * rng.uniform(-1, 1, 3)
+    q = (cx * cx - th) * a + 2 * cx * cy * b + (cy * cy - th) * c
+    f = orc.equilibrium(rho, ux, uy) + w * q
+    for omega in (0.5, 1.3, 1.95):
+        np.testing.assert_allclose(orc.collide_node(f, omega, collision="regularized"),
+                                   orc.collide_node(f, omega), rtol=0, atol=3e-16)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_regularized_discards_modes_above_second_order(orc, seed):
+    """Populations differing by a vector with no mass, momentum or second moment (the
+    null space of the six moments 1, c_x, c_y, c_x^2, c_x c_y, c_y^2) collide to the same
+    result under the regularized collision, while BGK keeps the difference."""
+    from scipy.linalg import null_space
+    cx, cy, _, _, _ = orc.lattice()
+    M = np.array([np.ones(9), cx, cy, cx * cx, cx * cy, cy * cy], dtype=np.float64)
+    K = null_space(M)
+    assert K.shape == (9, 3)
+    f = _random_f(seed)
+    g = f + 2e-3 * K @ np.random.default_rng(seed).uniform(-1, 1, 3)
+    omega = 1.6
+    r_f = orc.collide_node(f, omega, collision="regularized")
+    r_g = orc.collide_node(g, omega, collision="regularized")
+    np.testing.assert_allclose(r_f, r_g, rtol=0, atol=1e-16)
+    assert np.abs(orc.collide_node(f, omega) - orc.collide_node(g, omega)).max() > 1e-5
+
+
+def test_regularized_rest_and_uniform_flow_are_fixed_points(orc):
+    feq = orc.equilibrium(1.02, 0.04, -0.01)
+    np.testing.assert_allclose(orc.collide_node(feq, 1.8, collision="regularized"), feq,
+                               rtol=0, atol=1e-17)
+    nx, ny = 24, 12
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.5005, bc_x=BCX_PERIODIC,
+                  bc_y=BCY_PERIODIC, collision="regularized")
+    S0 = np.repeat(np.repeat(feq[:, None, None], ny, 1), nx, 2)
+    s.set_state(S0)
+    s.step(20)
+    np.testing.assert_allclose(s.state(), S0, rtol=0, atol=1e-16)
+
+
+def test_regularized_drtt_equals_mea_b(orc):
+    """The regularized collision conserves momentum node by node, so the identity
+    DRTT = MEA-B (second Eq. rtt7 against Eq. rtt5) holds for it as for BGK."""
+    w = workloads.cylinder_channel_200x80()
+    s = OracleSim(w.mask, tau=0.51, uin=w.uin, box=w.box, collision="regularized")
+    s.step(400)
+    F = s.forces()
+    scale = np.abs(F[:, 1]).max()
+    assert scale > 0
+    assert np.abs(F[:, 2] - F[:, 1]).max() <= 1e-11 * scale
