@@ -38,7 +38,7 @@ class _Cfg(ctypes.Structure):
                 ("rho_w", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
                 ("collision", ctypes.c_int32)]
 
-COLLISIONS = {"bgk": 0, "regularized": 1}
+COLLISIONS = {"bgk": 0, "regularized": 1, "kbc": 2}
 
 
 _lib = None
@@ -57,6 +57,7 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_collide_node.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_collide_node_regularized.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_collide_node_kbc.argtypes = [dp, ctypes.c_double, dp]
         L.orc_box_admissible.argtypes = [cp, u8]
         L.orc_box_admissible.restype = ctypes.c_int
         L.orc_links.argtypes = [cp, u8, ip, ctypes.c_int64]
@@ -118,10 +119,11 @@ def equilibrium(rho, ux, uy):
 def collide_node(f, omega, g=(0.0, 0.0), collision="bgk"):
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros(9)
-    if collision == "regularized":
+    if collision in ("regularized", "kbc"):
         if g[0] or g[1]:
-            raise ValueError("the regularized collision takes no body force")
-        lib().orc_collide_node_regularized(_dp(f), float(omega), _dp(out))
+            raise ValueError("only the BGK collision takes a body force")
+        fn = lib().orc_collide_node_regularized if collision == "regularized" else lib().orc_collide_node_kbc
+        fn(_dp(f), float(omega), _dp(out))
     else:
         lib().orc_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), _dp(out))
     return out
@@ -155,8 +157,8 @@ def links(mask, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL):
 class OracleSim:
     """FP64 reference simulation.  ``tau`` is the lattice relaxation time tau_lb
     (omega = 1/tau_lb); pass ``omega`` directly for the pure-streaming fixture
-    (omega = 0).  ``collision`` is "bgk" (Eq. CollideAdv) or "regularized" (the stated
-    variant for tau_lb close to 1/2)."""
+    (omega = 0).  ``collision`` is "bgk" (Eq. CollideAdv), "regularized" or "kbc" (the
+    stated variants for tau_lb close to 1/2)."""
 
     def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL,
                  box=None, rho_w=1.0, g=(0.0, 0.0), omega=None, collision="bgk"):

@@ -148,14 +148,72 @@ void collide_node_regularized(const T* f, T omega, T* out) {
   }
 }
 
-enum { COLLISION_BGK = 0, COLLISION_REGULARIZED = 1 };
+// Entropic multi-relaxation collision of Karlin, Boesch & Chikatamarla (Phys. Rev. E 90
+// (2014) 031302(R)), the "KBC" model, written here with the paper's second-order
+// polynomial equilibrium.  It is not in the paper.  The non-equilibrium part
+// d = f - f^eq (no mass, no momentum) is split into a shear part ds, built from the
+// deviatoric normal stress N = sum (c_x^2 - c_y^2) d and the shear stress
+// P = sum c_x c_y d of d alone:
+//   ds = 0 (rest),  +N/4 (c = (+-1, 0)),  -N/4 (c = (0, +-1)),  c_x c_y P / 4 (diagonals),
+// and the remainder dh = d - ds (trace, third and fourth moments).  Then
+//   f~ = f - beta (2 ds + gamma dh),  beta = omega / 2,
+// with gamma the entropic stabilizer that minimizes the quadratic entropy
+// <f~ - f^eq | f~ - f^eq>, <X|Y> = sum X_i Y_i / f^eq_i:
+//   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>.
+// When dh is within a few hundred rounding units of the populations
+// (<dh|dh> <= 2^-90 rho, against about 2^-106 rho for one unit in binary64), its
+// direction is rounding noise and gamma = 2 (BGK) is used.
+// The shear stress relaxes exactly as in BGK (same viscosity); mass and momentum are
+// conserved.
+template <class T>
+void collide_node_kbc(const T* f, T omega, T* out) {
+  T rho = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    jx += double(CX[i]) * f[i];
+    jy += double(CY[i]) * f[i];
+  }
+  T ux = jx / rho;
+  T uy = jy / rho;
+  T feq[NQ], d[NQ], ds[NQ], dh[NQ];
+  T dN = 0.0, dP = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    feq[i] = equilibrium<T>(i, rho, ux, uy);
+    d[i] = f[i] - feq[i];
+    dN += double(CX[i] * CX[i] - CY[i] * CY[i]) * d[i];
+    dP += double(CX[i] * CY[i]) * d[i];
+  }
+  for (int i = 0; i < NQ; ++i) {
+    if (CX[i] == 0 && CY[i] == 0)
+      ds[i] = 0.0;
+    else if (CY[i] == 0)
+      ds[i] = 0.25 * dN;
+    else if (CX[i] == 0)
+      ds[i] = -0.25 * dN;
+    else
+      ds[i] = 0.25 * double(CX[i] * CY[i]) * dP;
+    dh[i] = d[i] - ds[i];
+  }
+  T sh = 0.0, hh = 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    sh += ds[i] * dh[i] / feq[i];
+    hh += dh[i] * dh[i] / feq[i];
+  }
+  T beta = 0.5 * omega;
+  T gamma = 2.0;
+  if (std::real(hh) > std::ldexp(1.0, -90) * std::real(rho))
+    gamma = 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh;
+  for (int i = 0; i < NQ; ++i) out[i] = f[i] - beta * (2.0 * ds[i] + gamma * dh[i]);
+}
+
+enum { COLLISION_BGK = 0, COLLISION_REGULARIZED = 1, COLLISION_KBC = 2 };
 
 struct Config {
   int32_t nx, ny, bc_x, bc_y;
   int32_t box[4];  // x0, x1, y0, y1; x0 < 0 means no control volume
   double rho_w;    // inlet wall density
   double gx, gy;   // body force (test fixtures only; BGK only)
-  int32_t collision;  // COLLISION_BGK or COLLISION_REGULARIZED
+  int32_t collision;  // COLLISION_BGK, COLLISION_REGULARIZED or COLLISION_KBC
 };
 
 template <class T>
@@ -264,6 +322,8 @@ struct Sim {
         for (int i = 0; i < NQ; ++i) fin[i] = f[idx(i, x, y)];
         if (cfg.collision == COLLISION_REGULARIZED)
           collide_node_regularized<T>(fin, omega, fout);
+        else if (cfg.collision == COLLISION_KBC)
+          collide_node_kbc<T>(fin, omega, fout);
         else
           collide_node<T>(fin, omega, cfg.gx, cfg.gy, fout);
         for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y)] = fout[i];
@@ -362,8 +422,10 @@ bool config_valid(const Config& c, const uint8_t* mask) {
   if (c.nx < 2 || c.ny < 2) return false;
   if (c.bc_x != BCX_INLET_OUTLET && c.bc_x != BCX_PERIODIC) return false;
   if (c.bc_y != BCY_WALL && c.bc_y != BCY_PERIODIC) return false;
-  if (c.collision != COLLISION_BGK && c.collision != COLLISION_REGULARIZED) return false;
-  if (c.collision == COLLISION_REGULARIZED && (c.gx != 0.0 || c.gy != 0.0)) return false;
+  if (c.collision != COLLISION_BGK && c.collision != COLLISION_REGULARIZED &&
+      c.collision != COLLISION_KBC)
+    return false;
+  if (c.collision != COLLISION_BGK && (c.gx != 0.0 || c.gy != 0.0)) return false;
   for (size_t k = 0; k < size_t(c.nx) * c.ny; ++k)
     if (mask[k] > 1) return false;
   return box_admissible(c, mask);
@@ -414,6 +476,10 @@ void orc_collide_node(const double* f, double omega, double gx, double gy, doubl
 
 void orc_collide_node_regularized(const double* f, double omega, double* out) {
   collide_node_regularized<double>(f, omega, out);
+}
+
+void orc_collide_node_kbc(const double* f, double omega, double* out) {
+  collide_node_kbc<double>(f, omega, out);
 }
 
 int orc_box_admissible(const orc_cfg* c, const uint8_t* mask) {

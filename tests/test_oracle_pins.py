@@ -682,3 +682,122 @@ def test_regularized_drtt_equals_mea_b(orc):
     scale = np.abs(F[:, 1]).max()
     assert scale > 0
     assert np.abs(F[:, 2] - F[:, 1]).max() <= 1e-11 * scale
+
+
+# --------------------------------------------------------------------------------------
+# Entropic KBC collision (Karlin, Boesch & Chikatamarla 2014; a stated variant for tau_lb
+# -> 1/2, not in the paper).  Pinned by properties of its output only.
+# --------------------------------------------------------------------------------------
+
+def _moments9(cx, cy):
+    """Rows: 1, c_x, c_y, c_x^2 + c_y^2, c_x^2 - c_y^2, c_x c_y, c_x^2 c_y, c_x c_y^2,
+    c_x^2 c_y^2 (an invertible basis of D2Q9)."""
+    cx = cx.astype(np.float64)
+    cy = cy.astype(np.float64)
+    return np.array([np.ones(9), cx, cy, cx * cx + cy * cy, cx * cx - cy * cy, cx * cy,
+                     cx * cx * cy, cx * cy * cy, cx * cx * cy * cy])
+
+
+def _eq_of(orc, f):
+    cx, cy, _, _, _ = orc.lattice()
+    rho = f.sum()
+    return orc.equilibrium(rho, (cx @ f) / rho, (cy @ f) / rho)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kbc_conserves_mass_and_momentum(orc, seed):
+    cx, cy, _, _, _ = orc.lattice()
+    f = _random_f(seed)
+    for omega in (0.8, 1.5, 1.99, 1.999):
+        g = orc.collide_node(f, omega, collision="kbc")
+        assert abs(g.sum() - f.sum()) <= 4e-16
+        assert abs(cx @ g - cx @ f) <= 4e-16 and abs(cy @ g - cy @ f) <= 4e-16
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kbc_relaxes_shear_stress_as_bgk(orc, seed):
+    """The deviatoric stresses (c_x^2 - c_y^2 and c_x c_y moments) relax with the BGK
+    rate, (M f~ - M f^eq) = (1 - omega)(M f - M f^eq): same viscosity as Eq.
+    CollideAdv."""
+    cx, cy, _, _, _ = orc.lattice()
+    M = _moments9(cx, cy)
+    f = _random_f(seed)
+    feq = _eq_of(orc, f)
+    for omega in (1.2, 1.9, 1.995):
+        g = orc.collide_node(f, omega, collision="kbc")
+        for row in (4, 5):
+            np.testing.assert_allclose(M[row] @ g - M[row] @ feq,
+                                       (1 - omega) * (M[row] @ f - M[row] @ feq),
+                                       rtol=1e-12, atol=1e-17)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_kbc_equals_bgk_for_pure_shear_nonequilibrium(orc, seed):
+    """If f - f^eq carries only the deviatoric stresses (every other moment of the
+    invertible D2Q9 basis zero), the higher-order part vanishes and KBC is BGK."""
+    cx, cy, _, _, _ = orc.lattice()
+    M = _moments9(cx, cy)
+    rng = np.random.default_rng(7 + seed)
+    feq = orc.equilibrium(1.0 + 0.05 * rng.uniform(), 0.04 * rng.uniform(-1, 1),
+                          0.04 * rng.uniform(-1, 1))
+    target = np.zeros(9)
+    target[4], target[5] = 1e-3 * rng.uniform(-1, 1, 2)
+    f = feq + np.linalg.solve(M, target)
+    for omega in (1.3, 1.98):
+        np.testing.assert_allclose(orc.collide_node(f, omega, collision="kbc"),
+                                   orc.collide_node(f, omega), rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_kbc_stabilizer_minimizes_quadratic_entropy(orc, seed):
+    """The post-collision states of the KBC family differ by multiples of the
+    higher-order part dh, which the output itself reveals:
+    (f~ - f^eq) - (1 - omega)(f - f^eq) = beta (2 - gamma) dh.  The entropic stabilizer
+    makes f~ - f^eq orthogonal to dh in <X|Y> = sum X Y / f^eq (the stationarity of the
+    quadratic entropy along the family)."""
+    f = _random_f(seed, amp=0.3)
+    feq = _eq_of(orc, f)
+    for omega in (1.5, 1.99):
+        g = orc.collide_node(f, omega, collision="kbc")
+        post = g - feq
+        dh_dir = post - (1 - omega) * (f - feq)
+        assert np.abs(dh_dir).max() > 1e-6           # a genuine entropic correction
+        ip = np.sum(post * dh_dir / feq)
+        scale = np.sqrt(np.sum(post * post / feq) * np.sum(dh_dir * dh_dir / feq))
+        assert abs(ip) <= 1e-12 * scale
+
+
+def test_kbc_rest_and_uniform_flow_are_fixed_points(orc):
+    feq = orc.equilibrium(0.98, -0.03, 0.02)
+    np.testing.assert_allclose(orc.collide_node(feq, 1.99, collision="kbc"), feq, rtol=0,
+                               atol=4e-16)
+    nx, ny = 24, 12
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.5002, bc_x=BCX_PERIODIC,
+                  bc_y=BCY_PERIODIC, collision="kbc")
+    S0 = np.repeat(np.repeat(feq[:, None, None], ny, 1), nx, 2)
+    s.set_state(S0)
+    s.step(20)
+    np.testing.assert_allclose(s.state(), S0, rtol=0, atol=4e-16)
+
+
+def test_kbc_drtt_equals_mea_b(orc):
+    """KBC conserves momentum node by node: DRTT = MEA-B as for BGK."""
+    w = workloads.cylinder_channel_200x80()
+    s = OracleSim(w.mask, tau=0.505, uin=w.uin, box=w.box, collision="kbc")
+    s.step(400)
+    F = s.forces()
+    scale = np.abs(F[:, 1]).max()
+    assert scale > 0
+    assert np.abs(F[:, 2] - F[:, 1]).max() <= 1e-11 * scale
+
+
+def test_kbc_keeps_an_instance_finite_where_bgk_blows_up(orc):
+    """The reason for the entropic variant: a batched-workload cylinder (72x36, D 7.2,
+    Re 1305, tau_lb 0.50083) blows up under BGK within 1000 steps and stays finite under
+    KBC for 3000."""
+    w = [w for w in workloads.batched_instances() if w.name.startswith("b188_")][0]
+    assert abs(w.tau - 0.50083) < 1e-5
+    for coll, finite in (("bgk", False), ("kbc", True)):
+        s = OracleSim(w.mask, w.tau, w.uin, box=w.box, collision=coll)
+        s.step(1000 if coll == "bgk" else 3000)
+        assert bool(np.isfinite(s.forces()).all()) == finite, coll
