@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp32dev": 72, "fp16dev": 36}
 CSRC = os.path.join(ROOT, "paper_2210_10377_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+BATCH_WORKLOAD = "batched_256_cylinder_naca0012_64x32_to_512x256"
 
 
 def kernel_hash() -> str:
@@ -52,11 +53,11 @@ def measured_traffic(workload: str, precision: str):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(w, steps: int):
+def cpu_baseline(w, steps: int, collision: str = "bgk"):
     """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
     `steps` full-grid time steps with all three forces."""
     import oracle
-    o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+    o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision)
     t0 = time.perf_counter()
     o.step(steps)
     o.forces()
@@ -157,7 +158,7 @@ def adjoint_bench(precision: str):
         "fwd_plus_bwd_over_plain": round((t_f + t_b) / t_plain, 3)}), flush=True)
 
 
-def batched_bench(precision: str, steps: int, seq_steps: int):
+def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
     """The 256-instance batch (uneven cylinder and airfoil channels, one launch per step
     for all of them): autotuned schedule, then `steps` timed steps with all three forces.
     Beside it: the same instances stepped one after another through the single-lattice
@@ -172,7 +173,7 @@ def batched_bench(precision: str, steps: int, seq_steps: int):
     nodes = sum(w.nx * w.ny for w in ws)
 
     def timed_batch(prec, k, tune):
-        b = Batch.from_workloads(ws, precision=prec, max_record=max(k, 16))
+        b = Batch.from_workloads(ws, precision=prec, max_record=max(k, 16), collision=collision)
         sched, tune_ms = b.autotune(steps=8) if tune else (None, None)
         b.step(16)
         b.forces()
@@ -218,12 +219,13 @@ def batched_bench(precision: str, steps: int, seq_steps: int):
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
                   "fp16dev": "f16 storage / f32 arithmetic"}[precision],
         "data": "synthetic",
-        "config": {"workload": "batched_256_cylinder_naca0012_64x32_to_512x256",
+        "config": {"workload": BATCH_WORKLOAD,
                    "instances": len(ws), "nodes": nodes, "fluid_nodes": fluid,
-                   "storage": precision, "schedule": sched,
+                   "storage": precision, "collision": collision, "schedule": sched,
                    "autotune_ms_per_step": tune_ms},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(BATCH_WORKLOAD, precision)},
         "nonfinite_instances": int(bad.sum()),
         "sequential_single_calls_mlups": round(seq_mlups, 1),
         "batch_fp64_mlups": round(mlups64, 1),
@@ -241,7 +243,8 @@ def main():
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--aoa", type=float, default=4.0)
     ap.add_argument("--schemes", default="A,B,DRTT")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "regularized", "kbc"])
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32 and FP16-deviation storage against FP64 on the NACA0012 "
@@ -290,7 +293,7 @@ def main():
         adjoint_bench(args.precision if args.precision != "fp32" else "fp32dev")
         return
     if args.batched:
-        batched_bench(args.precision, args.steps, args.seq_steps)
+        batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
         return
 
     if args.workload == "naca8192":
@@ -306,7 +309,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box,
               max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
-              device=dev, stream=stream)
+              device=dev, stream=stream, collision=args.collision)
     info = sim.info()
     sim.step(W, schemes)
     sim.forces()
@@ -322,6 +325,14 @@ def main():
     ms = e0.elapsed_time(e1)
     F = sim.forces()
     C = sim.coefficients(F)
+    # The same step without force evaluation (no force strips, no reductions): the
+    # per-step cost of the three estimators is the difference.
+    k_off = min(K, 500)
+    e0.record(stream)
+    sim.step(k_off, ())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_off = e0.elapsed_time(e1) / k_off
 
     t_step = ms / 1e3 / K
     nodes = w.nx * w.ny
@@ -344,13 +355,16 @@ def main():
                   "fp16dev": "f16 storage / f32 arithmetic"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "tau": w.tau,
-                   "storage": args.precision, "schemes": list(schemes),
+                   "storage": args.precision, "collision": args.collision,
+                   "schemes": list(schemes),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
                    "box_nodes": int(info.n_box), **{k: v for k, v in w.meta.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "wall_s": round(wall, 3),
+        "forces_off_ms_per_step": round(ms_off, 5),
+        "force_cost_frac": round((ms / K - ms_off) / ms_off, 4),
     }
     if len(F):
         cols = [k for k, s in enumerate(("A", "B", "DRTT")) if s in schemes]
@@ -360,7 +374,7 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.collision)
     print(json.dumps(out), flush=True)
 
 

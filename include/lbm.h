@@ -85,6 +85,28 @@ extern "C" {
 #define LBM_BCY_WALL 0         /* y: no-slip walls at y = -1/2 and y = ny - 1/2      */
 #define LBM_BCY_PERIODIC 1
 
+/* Collision operator. */
+#define LBM_COLL_BGK 0         /* BGK, Eq. CollideAdv                                  */
+#define LBM_COLL_REGULARIZED 1 /* regularized BGK (Latt & Chopard 2006; not in the
+                                  paper): the non-equilibrium part is projected on the
+                                  second-order Hermite subspace before relaxation,
+                                  f~ = f^eq + (1 - 1/tau_lb) w_i (c_i c_i - I/3) : Pi^neq
+                                  / (2/9), Pi^neq = sum_i c_i c_i (f_i - f^eq_i).  Same
+                                  memory traffic; the variant for tau_lb close to 1/2,
+                                  where BGK loses stability.  Conserves mass and
+                                  momentum, so every force estimator applies unchanged. */
+#define LBM_COLL_KBC 2         /* entropic KBC collision (Karlin, Boesch & Chikatamarla
+                                  2014; not in the paper) with the same polynomial
+                                  equilibrium: d = f - f^eq splits into its shear part
+                                  ds (deviatoric stresses) and the rest dh;
+                                  f~ = f - (1/(2 tau_lb))(2 ds + gamma dh), gamma from
+                                  the entropic stabilizer (gamma = 2 is BGK; BGK is used
+                                  when dh is at rounding level).  Same shear viscosity
+                                  and memory traffic as BGK, far more stable near
+                                  tau_lb = 1/2; conserves mass and momentum.  In binary32
+                                  arithmetic the stabilizer is switched off below
+                                  |dh|^2 ~ 2^-40 (2^-90 in binary64).                    */
+
 /* Force schemes (bit mask for lbm_step). */
 #define LBM_FORCE_MEA_A 1u
 #define LBM_FORCE_MEA_B 2u
@@ -102,6 +124,7 @@ typedef struct lbm_grid {
   int32_t max_record; /* force-ring capacity in steps (>= 1)                        */
   double rho_ref, u_ref, l_ref; /* normalisation of the force coefficients (Sec. V:
                                    C = 2 F / (rho U^2 L))                           */
+  int32_t collision;  /* LBM_COLL_BGK (0), LBM_COLL_REGULARIZED or LBM_COLL_KBC         */
 } lbm_grid;
 
 typedef struct lbm_inlet {
@@ -130,7 +153,8 @@ typedef struct lbm_info {
  * solid_mask: host, ny*nx bytes, each 0 (fluid) or 1 (solid).  tau: tau_lb > 1/2.
  * inlet may be NULL when bc_x is periodic.  Returns LBM_EINVAL for nx or ny < 3,
  * non-finite or tau <= 1/2, a mask byte outside {0,1}, a missing, non-finite inlet,
- * an inadmissible box, unknown codes or max_record < 1; LBM_ENOMEM for grids whose
+ * an inadmissible box, unknown codes (precision, boundaries, collision) or
+ * max_record < 1; LBM_ENOMEM for grids whose
  * population planes exceed 2^31 elements.  Needs no GPU. */
 int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
                const lbm_inlet* inlet, lbm_t** out);
@@ -221,7 +245,8 @@ int lbm_reset(lbm_t* h);
  * *grad_tau, where dJ is the incoming seed.  The adjoint fields are kept in the
  * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
  * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is
- * still valid (any step, set_* or reset since invalidates it). */
+ * still valid (any step, set_* or reset since invalidates it).  The adjoint covers the
+ * BGK collision only: both calls return LBM_EINVAL for the other collisions. */
 int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes);
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J);
@@ -273,10 +298,10 @@ typedef struct lbm_batch_info {
   lbm_batch_schedule schedule;
 } lbm_batch_info;
 
-/* Group n >= 1 distinct, bound handles of one precision into a batch whose ring holds
- * max_record >= 1 force rows per instance.  LBM_EINVAL for a NULL, repeated or unbound
- * member, mixed precisions, or a member whose state buffer is 4 GiB or more.  Needs no
- * GPU work. */
+/* Group n >= 1 distinct, bound handles of one precision and one collision operator into
+ * a batch whose ring holds max_record >= 1 force rows per instance.  LBM_EINVAL for a
+ * NULL, repeated or unbound member, mixed precisions or collisions, or a member whose
+ * state buffer is 4 GiB or more.  Needs no GPU work. */
 int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_batch_t** out);
 
 /* Device workspace of the batch (instance table, tile and sweep lists, force ring). */

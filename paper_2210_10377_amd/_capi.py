@@ -17,6 +17,7 @@ LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_FP32DEV = 0, 1, 2, 3
 LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
 LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
 LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_ALL = 1, 2, 4, 7
+LBM_COLL_BGK, LBM_COLL_REGULARIZED, LBM_COLL_KBC = 0, 1, 2
 
 ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
                -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EOVERFLOW"}
@@ -39,7 +40,7 @@ class lbm_grid(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
                 ("max_record", ctypes.c_int32),
                 ("rho_ref", ctypes.c_double), ("u_ref", ctypes.c_double),
-                ("l_ref", ctypes.c_double)]
+                ("l_ref", ctypes.c_double), ("collision", ctypes.c_int32)]
 
 
 class lbm_inlet(ctypes.Structure):

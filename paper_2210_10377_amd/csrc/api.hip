@@ -211,6 +211,7 @@ StepArgs step_args(const lbm_t* h) {
   a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
   a.rho_w6 = 6.0 * h->rho_w;
   a.omega = h->omega;
+  a.collision = h->g.collision;
   a.nslots = p.nslots;
   return a;
 }
@@ -603,6 +604,8 @@ int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* by
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J) {
   if (!h) return LBM_EINVAL;
+  if (h->g.collision != LBM_COLL_BGK)
+    return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (!ws || !J || n_steps < 1 || every < 1 || every > n_steps || t0 < 0 || T < 1 ||
       int64_t(t0) + T > n_steps || !std::isfinite(wx) || !std::isfinite(wy))
@@ -651,6 +654,8 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
 
 int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
   if (!h) return LBM_EINVAL;
+  if (h->g.collision != LBM_COLL_BGK)
+    return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (!h->adj_valid)
     return h->fail(LBM_ESTATE, "no adjoint forward run matches the handle's current parameters");
   if (!grad_uin || !grad_tau || !std::isfinite(dJ)) return h->fail(LBM_EINVAL, "invalid arguments");

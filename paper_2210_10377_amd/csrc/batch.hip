@@ -133,6 +133,7 @@ struct lbm_batch_t {
     L.total_tiles = int32_t(total_tiles);
     L.total_box_blocks = int32_t(total_box);
     L.grid_blocks = sched.grid_blocks > 0 ? (sched.grid_blocks + 7) / 8 * 8 : 0;
+    L.collision = m[0]->g.collision;
     return L;
   }
 
@@ -264,6 +265,10 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
     }
     if (m[i]->g.precision != m[0]->g.precision) {
       g_batch_create_error = "members differ in precision";
+      return LBM_EINVAL;
+    }
+    if (m[i]->g.collision != m[0]->g.collision) {
+      g_batch_create_error = "members differ in collision operator";
       return LBM_EINVAL;
     }
     if (m[i]->buf_bytes32() == 0) {

@@ -1,5 +1,5 @@
 // Device building blocks shared by the forward step and the adjoint kernels: storage
-// formats, buffer addressing, the BGK collision, the pull of one node with its boundary
+// formats, buffer addressing, the BGK and regularized collisions, the pull of one node with its boundary
 // rules, and fixed-order wave / block reductions.
 #pragma once
 
@@ -136,12 +136,23 @@ struct Planes<T, false> {
   }
 };
 
-// BGK collision of one node (Eq. CollideAdv, first line, with 2 beta = omega) towards
-// the second-order equilibrium w_i rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2].  In
-// deviation form (DEV) the inputs and outputs are h_i = f_i - w_i: rho - 1 = sum h_i,
-// rho u = sum c_i h_i, and f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 -
-// 1.5 u^2)], so no quantity of order one is formed.
-template <class C, bool DEV>
+// Collision of one node; COLL selects the operator (LBM_COLL_*):
+//   BGK (Eq. CollideAdv, first line, with 2 beta = omega) towards the second-order
+//   equilibrium w_i rho [1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u^2];
+//   regularized (Latt & Chopard 2006): f~_i = f^eq_i + (1 - omega) (9/2) w_i
+//   (c_i c_i - I/3) : Pi^neq, with Pi^neq = sum c c f - rho u u - rho I/3;
+//   KBC (Karlin, Boesch & Chikatamarla 2014, with the same polynomial equilibrium):
+//   d = f - f^eq is split into the shear part ds (+-N/4 on the axes, c_x c_y P/4 on the
+//   diagonals, N = sum (c_x^2 - c_y^2) d, P = sum c_x c_y d) and dh = d - ds;
+//   f~ = f - (omega/2)(2 ds + gamma dh), with the entropic stabilizer
+//   gamma = 2/omega - (2 - 2/omega) <ds|dh>/<dh|dh>, <X|Y> = sum X Y / f^eq, and
+//   gamma = 2 (BGK) when <dh|dh> is within the rounding noise of the arithmetic
+//   (<= 2^-90 rho in binary64, 2^-40 rho in binary32).
+// In deviation form (DEV) the inputs and outputs are h_i = f_i - w_i: rho - 1 = sum h_i,
+// rho u = sum c_i h_i, f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 -
+// 1.5 u^2)] and Pi^neq = sum c c h - rho u u - (rho - 1) I/3, so no quantity of order one
+// is formed except the entropic weights f^eq_i.
+template <class C, bool DEV, int COLL>
 __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
   const C s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const C jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
@@ -151,12 +162,54 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
   const C ux = jx * ir, uy = jy * ir;
   const C usq = C(1.5) * (ux * ux + uy * uy);
   const C om = omega;
+  C fe[kQ];  // f^eq (DEV: f^eq - w)
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy;
     const C poly = C(3) * cu + C(4.5) * cu * cu - usq;
-    const C feq = DEV ? weight<C>(i) * (s + rho * poly) : weight<C>(i) * rho * (C(1) + poly);
-    g[i] = f[i] + om * (feq - f[i]);
+    fe[i] = DEV ? weight<C>(i) * (s + rho * poly) : weight<C>(i) * rho * (C(1) + poly);
+  }
+  if constexpr (COLL == LBM_COLL_BGK) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) g[i] = f[i] + om * (fe[i] - f[i]);
+  } else if constexpr (COLL == LBM_COLL_REGULARIZED) {
+    const C diag = (f[5] + f[6]) + (f[7] + f[8]);
+    const C r3 = (DEV ? s : rho) * C(1.0 / 3.0);
+    const C pxx = ((f[1] + f[3]) + diag) - rho * ux * ux - r3;
+    const C pyy = ((f[2] + f[4]) + diag) - rho * uy * uy - r3;
+    const C pxy = (f[5] + f[7]) - (f[6] + f[8]) - rho * ux * uy;
+    const C k = (C(1) - om) * C(4.5);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const C q = C(kCx[i] * kCx[i] - 1.0 / 3.0) * pxx + C(2 * kCx[i] * kCy[i]) * pxy +
+                  C(kCy[i] * kCy[i] - 1.0 / 3.0) * pyy;
+      g[i] = fe[i] + k * weight<C>(i) * q;
+    }
+  } else {
+    C d[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] = f[i] - fe[i];
+    const C qn = C(0.25) * ((d[1] + d[3]) - (d[2] + d[4]));
+    const C qp = C(0.25) * ((d[5] + d[7]) - (d[6] + d[8]));
+    C ds[kQ];
+    ds[0] = C(0);
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) ds[i] = i < 5 ? (kCy[i] == 0 ? qn : -qn) : C(kCx[i] * kCy[i]) * qp;
+    C sh = C(0), hh = C(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const C dh = d[i] - ds[i];
+      const C wi = C(1) / (DEV ? weight<C>(i) + fe[i] : fe[i]);
+      sh += ds[i] * dh * wi;
+      hh += dh * dh * wi;
+    }
+    const C beta = C(0.5) * om;
+    const C ib = C(1) / beta;
+    const C thr = sizeof(C) == 8 ? C(0x1p-90) : C(0x1p-40);
+    const C gamma = hh > thr * rho ? ib - (C(2) - ib) * sh / hh : C(2);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      g[i] = f[i] - beta * (C(2) * ds[i] + gamma * (d[i] - ds[i]));
   }
 }
 

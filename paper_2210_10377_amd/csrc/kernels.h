@@ -26,6 +26,7 @@ struct StepArgs {
   const double* uin;           // [ny] inlet velocity
   double rho_w6;               // 2 rho_w / c_s^2 = 6 rho_w
   double omega;                // 1 / tau_lb
+  int32_t collision;           // LBM_COLL_*
   double* part_out;            // [nslots][8] force partials of this step, or null
   const double* red_in;        // [nslots][8] partials of the previous step, or null
   int32_t nslots;
@@ -80,6 +81,7 @@ struct BatchLaunch {
   int32_t n_inst, nred;      // instances; reducer blocks (n_inst rounded up to 8)
   int32_t total_tiles, total_box_blocks;
   int32_t grid_blocks;       // tile blocks per launch (0: one block per tile)
+  int32_t collision;         // LBM_COLL_* of every instance
 };
 
 hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_t s);

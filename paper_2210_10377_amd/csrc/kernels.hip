@@ -55,7 +55,7 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, int tx, int ty,
     for (int i = 0; i < kQ; ++i) v[r][i] = src.ld(i, o0 + (r - kCy[i]) * pitch - kCx[i]);
 }
 
-template <int P, bool BUF>
+template <int P, bool BUF, int COLL>
 __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int ty,
                                                 const typename Storage<P>::T (&v)[kTileH][kQ]) {
   using S = Storage<P>;
@@ -70,7 +70,7 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
 #pragma unroll
     for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[r][i]);
     C g[kQ];
-    collide<C, S::kDev>(f, C(a.omega), g);
+    collide<C, S::kDev, COLL>(f, C(a.omega), g);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, pack<P>(g[i]));
   }
@@ -79,7 +79,7 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
 // Plain strip holding x = 0, x = nx - 1 or lanes past the row end: the pull codes are
 // those of edge_word (inlet or wrap, outlet or wrap, plain streaming elsewhere), made
 // from the lane's x alone, with no per-node metadata; no forces.
-template <int P, bool BUF>
+template <int P, bool BUF, int COLL>
 __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
   using S = Storage<P>;
   using T = typename S::T;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
     C g[kQ];
-    collide<C, S::kDev>(f, C(a.omega), g);
+    collide<C, S::kDev, COLL>(f, C(a.omega), g);
     const int32_t o = y * pitch + x;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
@@ -104,7 +104,7 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
 
 // General path of one lane's column of the tile: boundary rules from the pull codes,
 // and (when `forces`) the force sums of its nodes added to acc.
-template <int P, bool BUF>
+template <int P, bool BUF, int COLL>
 __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, bool forces,
                                              double (&acc)[8]) {
   using S = Storage<P>;
@@ -123,7 +123,7 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
     C g[kQ];
-    collide<C, S::kDev>(f, C(a.omega), g);
+    collide<C, S::kDev, COLL>(f, C(a.omega), g);
     T s[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
@@ -187,7 +187,7 @@ __device__ __forceinline__ void reduce_row(const double* red_in, int nslots, dou
 }
 
 // One 256 x kTileH tile of a step.
-template <int P, bool BUF, bool FORCES>
+template <int P, bool BUF, bool FORCES, int COLL>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
                                           const int32_t* __restrict__ strip_slot) {
   const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
@@ -199,20 +199,20 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
     if (strip_is_interior(a.nx, x0)) {
       typename Storage<P>::T v[kTileH][kQ];
       interior_load<P, BUF>(a, tx, ty, v);
-      interior_finish<P, BUF>(a, tx, ty, v);
+      interior_finish<P, BUF, COLL>(a, tx, ty, v);
     } else {
-      edge_rows<P, BUF>(a, tx, ty);
+      edge_rows<P, BUF, COLL>(a, tx, ty);
     }
     return;
   }
   const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
   // FA(x,y), FB(x,y), J(x,y), Phi(x,y)
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  general_rows<P, BUF>(a, tx, ty, slot >= 0, acc);
+  general_rows<P, BUF, COLL>(a, tx, ty, slot >= 0, acc);
   if (slot >= 0) wave_sum8_store(acc, a.part_out + int64_t(slot) * 8);
 }
 
-template <int P, bool BUF, bool FORCES>
+template <int P, bool BUF, bool FORCES, int COLL>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
   int tile = block_tile(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
     }
     --tile;
   }
-  step_tile<P, BUF, FORCES>(a, tile, strip_slot);
+  step_tile<P, BUF, FORCES, COLL>(a, tile, strip_slot);
 }
 
 // Batched step: every instance of a batch advances one step in one launch.  The first
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
 // tile a block takes lies on the block's own XCD in the grouping of block_tile.
 // Step k of a launch sequence writes force row ctl[0] + k; ctl[1] counts the steps of
 // the same call enqueued before the sequence (their last row is still to be reduced).
-template <int P, bool FORCES, bool PERSIST>
+template <int P, bool FORCES, bool PERSIST, int COLL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 8)))
 void batch_step_kernel(
     const BatchInst* __restrict__ inst, const int32_t* __restrict__ tile_inst,
@@ -260,7 +260,7 @@ void batch_step_kernel(
     a.src = I.buf[parity];
     a.dst = I.buf[1 - parity];
     a.part_out = I.part[k & 1];
-    step_tile<P, true, FORCES>(a, tile_local[t], a.strip_slot);
+    step_tile<P, true, FORCES, COLL>(a, tile_local[t], a.strip_slot);
   }
 }
 
@@ -369,14 +369,25 @@ __global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t 
   }
 }
 
-template <int P, bool BUF>
-hipError_t step_dispatch2(bool forces, const StepArgs& a, hipStream_t s) {
+template <int P, bool BUF, int COLL>
+hipError_t step_dispatch3(bool forces, const StepArgs& a, hipStream_t s) {
   const int grid = a.ntiles + (a.red_in ? 1 : 0);
   if (forces)
-    hipLaunchKernelGGL((step_kernel<P, BUF, true>), dim3(grid), dim3(kThreads), 0, s, a, a.strip_slot);
+    hipLaunchKernelGGL((step_kernel<P, BUF, true, COLL>), dim3(grid), dim3(kThreads), 0, s, a,
+                       a.strip_slot);
   else
-    hipLaunchKernelGGL((step_kernel<P, BUF, false>), dim3(grid), dim3(kThreads), 0, s, a, a.strip_slot);
+    hipLaunchKernelGGL((step_kernel<P, BUF, false, COLL>), dim3(grid), dim3(kThreads), 0, s, a,
+                       a.strip_slot);
   return hipGetLastError();
+}
+
+template <int P, bool BUF>
+hipError_t step_dispatch2(bool forces, const StepArgs& a, hipStream_t s) {
+  switch (a.collision) {
+    case LBM_COLL_REGULARIZED: return step_dispatch3<P, BUF, LBM_COLL_REGULARIZED>(forces, a, s);
+    case LBM_COLL_KBC: return step_dispatch3<P, BUF, LBM_COLL_KBC>(forces, a, s);
+    default: return step_dispatch3<P, BUF, LBM_COLL_BGK>(forces, a, s);
+  }
 }
 
 template <int P>
@@ -418,9 +429,15 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
   const bool persist = b.grid_blocks > 0 && b.grid_blocks < b.total_tiles;
   const int tiles = persist ? b.grid_blocks : b.total_tiles;
   const dim3 grid((forces ? b.nred : 0) + tiles);
-#define LBM_BATCH_GO(P, F, R) \
-  hipLaunchKernelGGL((batch_step_kernel<P, F, R>), grid, dim3(kThreads), 0, s, b.inst, \
+#define LBM_BATCH_GO3(P, F, R, K) \
+  hipLaunchKernelGGL((batch_step_kernel<P, F, R, K>), grid, dim3(kThreads), 0, s, b.inst, \
                      b.tile_inst, b.tile_local, b, parity, k)
+#define LBM_BATCH_GO(P, F, R)                                                         \
+  do {                                                                                \
+    if (b.collision == LBM_COLL_REGULARIZED) LBM_BATCH_GO3(P, F, R, LBM_COLL_REGULARIZED); \
+    else if (b.collision == LBM_COLL_KBC) LBM_BATCH_GO3(P, F, R, LBM_COLL_KBC);      \
+    else LBM_BATCH_GO3(P, F, R, LBM_COLL_BGK);                                        \
+  } while (0)
 #define LBM_BATCH_LAUNCH(P)                                          \
   if (forces) {                                                      \
     if (persist) LBM_BATCH_GO(P, true, true); else LBM_BATCH_GO(P, true, false);   \
@@ -435,6 +452,7 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
   }
 #undef LBM_BATCH_LAUNCH
 #undef LBM_BATCH_GO
+#undef LBM_BATCH_GO3
   return hipGetLastError();
 }
 

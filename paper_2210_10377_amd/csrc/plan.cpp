@@ -55,6 +55,11 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     err = "unknown precision";
     return LBM_EINVAL;
   }
+  if (g.collision != LBM_COLL_BGK && g.collision != LBM_COLL_REGULARIZED &&
+      g.collision != LBM_COLL_KBC) {
+    err = "unknown collision";
+    return LBM_EINVAL;
+  }
   if (g.max_record < 1) {
     err = "max_record must be >= 1";
     return LBM_EINVAL;

@@ -11,6 +11,8 @@ from . import _capi as C
 PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV,
               "fp32dev": C.LBM_FP32DEV}
 SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT}
+COLLISIONS = {"bgk": C.LBM_COLL_BGK, "regularized": C.LBM_COLL_REGULARIZED,
+              "kbc": C.LBM_COLL_KBC}
 
 
 def scheme_mask(schemes) -> int:
@@ -28,11 +30,13 @@ class Sim:
     mask: uint8 [ny, nx] (1 = solid).  tau: lattice relaxation time tau_lb.
     uin: inlet velocity per row (scalar or [ny]); ignored for periodic x.
     box: control-volume box (x0, x1, y0, y1) for the DRTT force, or None.
+    collision: "bgk" (Eq. CollideAdv), "regularized" or "kbc" (entropic; for tau_lb
+    close to 1/2).
     """
 
     def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, box=None, max_record=4096, rho_ref=1.0, u_ref=1.0,
-                 l_ref=1.0, rho_w=1.0, device="cuda", stream=None):
+                 l_ref=1.0, rho_w=1.0, device="cuda", stream=None, collision="bgk"):
         import torch
 
         self._lib = C.load()
@@ -47,6 +51,8 @@ class Sim:
             g.box[k] = b[k]
         g.max_record = int(max_record)
         g.rho_ref, g.u_ref, g.l_ref = float(rho_ref), float(u_ref), float(l_ref)
+        g.collision = COLLISIONS[collision]
+        self.collision = collision
         self._grid = g
         inlet = None
         if uin is not None:
@@ -203,7 +209,7 @@ class Plan:
     """A handle created but never bound: host-side classification only (no GPU)."""
 
     def __init__(self, mask, tau=0.8, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
-                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16):
+                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16, collision="bgk"):
         self._lib = C.load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         ny, nx = mask.shape
@@ -215,6 +221,7 @@ class Plan:
             g.box[k] = b[k]
         g.max_record = int(max_record)
         g.rho_ref = g.u_ref = g.l_ref = 1.0
+        g.collision = COLLISIONS[collision]
         inlet = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (ny,)))

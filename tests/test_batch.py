@@ -210,3 +210,35 @@ def test_full_256_instance_batch_bitwise_equals_singles():
     pb, fb, b = _batched(ws, calls, schedule=dict(grid_blocks=2048, graph_steps=4))
     ps, fs = _singles(ws, calls)
     _assert_same(ps, fs, pb, [fb[i] for i in range(len(ws))])
+
+
+@pytest.mark.parametrize("collision", ["regularized", "kbc"])
+def test_stabilized_collision_batch_bitwise_equals_singles(collision):
+    """A batch whose instances all use the regularized or the KBC collision."""
+    ws = MINI
+    from paper_2210_10377_amd import Sim, Batch
+    def members():
+        return [Sim(w.mask, w.tau, w.uin, precision="fp32dev", box=w.box, max_record=64,
+                    collision=collision) for w in ws]
+    sims = members()
+    _seed_states(sims, ws)
+    b = Batch(sims, max_record=64)
+    b.set_schedule(grid_blocks=0, graph_steps=4)
+    b.step(21)
+    Fb, bad = b.forces()
+    assert not bad.any()
+    ref = members()
+    _seed_states(ref, ws)
+    for i, r in enumerate(ref):
+        r.step(21)
+        np.testing.assert_array_equal(r.forces(), Fb[i])
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+
+
+def test_mixed_collision_batch_is_rejected():
+    from paper_2210_10377_amd import Sim, Batch, LbmError
+    ws = MINI[:2]
+    sims = [Sim(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=4,
+                collision=c) for w, c in zip(ws, ("bgk", "kbc"))]
+    with pytest.raises(LbmError):
+        Batch(sims)

@@ -226,3 +226,31 @@ def test_batched_instances_recipe():
     assert 100 < kinds.count("cylinder") < 156
     assert all(oracle.box_admissible(w.mask, w.box) for w in ws[:32])
     assert 12e6 < sum(w.nx * w.ny for w in ws) < 14e6
+
+
+def test_collision_code_validation_and_adjoint_bgk_only(capi):
+    """Unknown collision codes are rejected at create; the adjoint entry points refuse
+    the regularized collision before touching the device."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    mask = workloads.cylinder_mask(40, 20, 10, 9.5, 3)
+    g = capi.lbm_grid()
+    g.nx, g.ny, g.bc_x, g.bc_y, g.precision = 40, 20, 1, 0, capi.LBM_FP32
+    for k in range(4):
+        g.box[k] = -1
+    g.max_record, g.rho_ref, g.u_ref, g.l_ref = 4, 1.0, 1.0, 1.0
+    g.collision = 7
+    h = ctypes.c_void_p()
+    m = np.ascontiguousarray(mask)
+    assert L.lbm_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.6,
+                        None, ctypes.byref(h)) == capi.LBM_EINVAL
+    assert b"collision" in L.lbm_last_error(None)
+    J = ctypes.c_double()
+    reg = Plan(mask, uin=0.05, collision="regularized")
+    rc = L.lbm_adjoint_forward(reg._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_EINVAL and b"BGK" in L.lbm_last_error(reg._h)
+    bgk = Plan(mask, uin=0.05)
+    rc = L.lbm_adjoint_forward(bgk._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_ESTATE

@@ -306,3 +306,63 @@ def test_full_size_naca_one_step(precision):
              "fp32dev": np.array([1e-5, 1e-5, 1e-3])}[precision]
     print(precision, "full-size population error", err, "force errors", e)
     assert np.all(e <= tol_f), e
+
+
+@pytest.mark.parametrize("collision", ["regularized", "kbc"])
+@pytest.mark.parametrize("name", ["channel_body_box", "multi_tile_ragged", "solid_touching_inlet",
+                                  "periodic_x_body_on_seam", "channel_periodic_y"])
+def test_fp64_stabilized_collisions_small_cases(name, collision):
+    """The regularized and entropic KBC collisions (the stated variants for tau_lb near
+    1/2) at tau_lb 0.505 from a seeded random state, 80 steps, FP64: populations and all
+    forces to 1e-10 of the oracle's run with the same collision."""
+    nx, ny, bcx, bcy, mk, box, u = CASES[name]
+    mask = mk(nx, ny)
+    uin = None if bcx == BCX_PERIODIC else np.linspace(0.5, 1.0, ny) * u
+    tau = 0.505
+    S0 = workloads.near_rest_state(nx, ny, seed=3 + len(name), amp=0.05)
+    o = OracleSim(mask, tau=tau, uin=uin, bc_x=bcx, bc_y=bcy, box=box, collision=collision)
+    o.set_state(S0)
+    o.step(80)
+    g = _sim(mask=mask, tau=tau, uin=uin, precision="fp64", bc_x=bcx, bc_y=bcy, box=box,
+             max_record=100, collision=collision)
+    g.set_populations(S0)
+    g.step(80)
+    Fg, Fo = g.forces(), o.forces()
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    cols = (0, 1, 2) if box is not None else (0, 1)
+    for k in cols:
+        scale = np.abs(Fo[:, k]).max()
+        assert scale > 0
+        assert np.abs(Fg[:, k] - Fo[:, k]).max() <= TOL64 * scale
+
+
+@pytest.fixture(scope="module")
+def low_viscosity_reference():
+    """Oracle runs of the 200x80 cylinder channel at tau_lb 0.51 (Re 600 on the
+    diameter), 3000 steps from rest, per stabilized collision."""
+    w = workloads.cylinder_channel_200x80()
+    out = {}
+    for coll in ("regularized", "kbc"):
+        o = OracleSim(w.mask, tau=0.51, uin=w.uin, box=w.box, collision=coll)
+        o.step(3000)
+        out[coll] = o.forces()
+    return w, out
+
+
+@pytest.mark.parametrize("collision", ["regularized", "kbc"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_stabilized_cylinder_low_viscosity(precision, collision, low_viscosity_reference):
+    """200x80 cylinder channel at tau_lb 0.51 with the regularized or KBC collision,
+    3000 steps from rest: FP64 forces to 1e-10 of the oracle, 32-bit deviation storage
+    within 1e-3 of them (relative to the largest force)."""
+    w, ref = low_viscosity_reference
+    tau = 0.51
+    Fo = ref[collision]
+    g = _sim(mask=w.mask, tau=tau, uin=w.uin, precision=precision, box=w.box, max_record=1000,
+             collision=collision)
+    Fg = g.run(3000)
+    assert np.isfinite(Fg).all()
+    tol = TOL64 if precision == "fp64" else 1e-3
+    for k in range(3):
+        scale = np.abs(Fo[:, k]).max()
+        assert np.abs(Fg[:, k] - Fo[:, k]).max() <= tol * scale, k

@@ -134,6 +134,7 @@ class Workload:
     bc_x: int = 0  # 0 inlet/outlet, 1 periodic
     bc_y: int = 0  # 0 no-slip walls, 1 periodic
     meta: dict = field(default_factory=dict)
+    collision: str = "bgk"  # or "regularized"
 
 
 def cylinder_channel_200x80() -> Workload:
