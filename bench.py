@@ -147,8 +147,18 @@ def adjoint_bench(precision: str):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
     nodes = w.nx * w.ny
+    fluid = int(sim.info().n_fluid)
+    s = BYTES_PER_NODE[precision] // 18          # bytes per stored population
+    s_adj = 8 if precision == "fp64" else 4      # bytes per adjoint value
+    fwd_bytes = fluid * 18 * s * n               # the forward run (checkpoint copies aside)
+    bwd_bytes = fluid * (27 * s + 18 * s_adj) * n  # recompute (2Qs) + adjoint kernel (Qs + 2Q s_adj)
     print(json.dumps({
         "metric": "adjoint MLUPS", "workload": w.name, "storage": precision, "steps": n,
+        "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "forward_achieved": round(fwd_bytes / t_f / 1e9, 1),
+                     "backward_achieved": round(bwd_bytes / t_b / 1e9, 1),
+                     "backward_bytes_per_node_step": 27 * s + 18 * s_adj,
+                     "backward_frac": round(bwd_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4)},
         "checkpoint_every": every, "J_mean_drag": J, "dJ_dtau": gt,
         "dJ_duin_norm": float((gu ** 2).sum() ** 0.5),
         "forward_s": round(t_f, 4), "backward_s": round(t_b, 4), "plain_run_s": round(t_plain, 4),
