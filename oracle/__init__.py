@@ -206,16 +206,17 @@ class OracleSim:
         lib().orc_step(self._h, int(n))
 
     def records(self):
+        """[t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy] of every recorded step."""
         n = lib().orc_nrec(self._h)
-        out = np.zeros((n, 8))
+        out = np.zeros((n, 10))
         if n:
             lib().orc_records(self._h, _dp(out))
         return out
 
     def forces(self):
-        """[t, scheme (A, B, DRTT), component (x, y)] of every recorded step."""
+        """[t, scheme (A, B, DRTT, SI), component (x, y)] of every recorded step."""
         n = lib().orc_nrec(self._h)
-        out = np.zeros((n, 3, 2))
+        out = np.zeros((n, 4, 2))
         if n:
             lib().orc_forces(self._h, _dp(out))
         return out

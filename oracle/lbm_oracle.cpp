@@ -1,11 +1,12 @@
 // TEST INFRASTRUCTURE ONLY -- the oracle.
 //
 // A plain, slow reference of the D2Q9 lattice Boltzmann time step with half-way
-// bounce-back and the three per-step flow-force estimators of Kaushal, Succi &
-// Ansumali, "Flow force calculation in Lattice Boltzmann Method" (arXiv:2210.10377):
-// momentum exchange under algorithm A and algorithm B (Sec. IV, Eq. rtt4/rtt5) and the
-// discrete Reynolds-transport-theorem control-volume force DRTT (Sec. IV, second
-// Eq. rtt7; Appendix).
+// bounce-back and the per-step flow-force estimators of Kaushal, Succi & Ansumali,
+// "Flow force calculation in Lattice Boltzmann Method" (arXiv:2210.10377): momentum
+// exchange under algorithm A and algorithm B (Sec. IV, Eq. rtt4/rtt5), the discrete
+// Reynolds-transport-theorem control-volume force DRTT (Sec. IV, second Eq. rtt7;
+// Appendix), and stress integration over the staircase surface (Sec. III,
+// Eq. stress_int).
 //
 // Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark load
 // this library.  The product (the HIP library) never links, calls or reads it, and the
@@ -39,7 +40,12 @@
 //  * a population crosses a surface when its streaming link crosses it (the normal
 //    tests "c.n > 0" / "c.n <= 0" of Eq. rtt3-rtt7 read as link crossings);
 //  * the control volume V is the set of fluid nodes in the half-open box
-//    [x0, x1) x [y0, y1).
+//    [x0, x1) x [y0, y1);
+//  * stress integration: the body surface is the staircase of unit faces crossed by
+//    the axis links; the traction of a face is evaluated at the link's fluid node from
+//    its pre-collision populations; the deviatoric stress is
+//    -(1 - beta) sum f^neq c c, the sign that gives the viscous stress 2 rho nu S of
+//    the continuum limit (the printed formula is read with that sign).
 
 #include <cmath>
 #include <complex>
@@ -216,6 +222,9 @@ struct Config {
   int32_t collision;  // COLLISION_BGK, COLLISION_REGULARIZED or COLLISION_KBC
 };
 
+// Per-step record: FA(2), FB(2), J(2), Phi(2), SI(2).
+const int NREC = 10;
+
 template <class T>
 struct Sim {
   Config cfg;
@@ -225,8 +234,7 @@ struct Sim {
   std::vector<T> S;   // post-collision state of the last step, [9][ny][nx]
   std::vector<T> f;   // pulled (pre-collision) populations of the last step
   std::vector<T> Sn;  // scratch for the next state
-  // per-step records: FA(2), FB(2), J(2), Phi(2)
-  std::vector<T> rec;
+  std::vector<T> rec;  // [t][NREC]
 
   int nx() const { return cfg.nx; }
   int ny() const { return cfg.ny; }
@@ -365,16 +373,53 @@ struct Sim {
           }
         }
     }
+    // Stress integration (Sec. III, Eq. stress_int) over the staircase surface of the
+    // body: every axis link (x, i) (i = 1..4, x fluid, x + c_i solid) is a unit face
+    // whose normal out of the body is n = -c_i; the traction there is
+    // (-p I + sigma) . n with p = rho theta0 and the deviatoric stress taken as the
+    // second moment of the non-equilibrium populations (the passage following Eq.
+    // stress_int), sigma = -(1 - beta) sum_k (f_k - f_k^eq) c_k c_k, 2 beta = omega,
+    // all from the pre-collision populations f(x, t) of the fluid node of the link
+    // (f^eq of the collision; the theta0 delta / D term vanishes since sum f^neq = 0).
+    T SI[2] = {0.0, 0.0};
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        for (int i = 1; i <= 4; ++i) {
+          if (!is_link(x, y, i)) continue;
+          T fin[NQ];
+          for (int k = 0; k < NQ; ++k) fin[k] = f[idx(k, x, y)];
+          T rho = 0.0, jx = 0.0, jy = 0.0;
+          for (int k = 0; k < NQ; ++k) {
+            rho += fin[k];
+            jx += double(CX[k]) * fin[k];
+            jy += double(CY[k]) * fin[k];
+          }
+          T ux = (jx + 0.5 * cfg.gx) / rho;
+          T uy = (jy + 0.5 * cfg.gy) / rho;
+          T pxx = 0.0, pxy = 0.0, pyy = 0.0;
+          for (int k = 0; k < NQ; ++k) {
+            T neq = fin[k] - equilibrium<T>(k, rho, ux, uy);
+            pxx += double(CX[k] * CX[k]) * neq;
+            pxy += double(CX[k] * CY[k]) * neq;
+            pyy += double(CY[k] * CY[k]) * neq;
+          }
+          T visc = -(1.0 - 0.5 * omega);
+          T sxx = visc * pxx, sxy = visc * pxy, syy = visc * pyy;
+          T p = rho * THETA0;
+          double nxv = -CX[i], nyv = -CY[i];
+          SI[0] += (sxx - p) * nxv + sxy * nyv;
+          SI[1] += sxy * nxv + (syy - p) * nyv;
+        }
     S.swap(Sn);
-    const T r[8] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1], Phi[0], Phi[1]};
-    rec.insert(rec.end(), r, r + 8);
+    const T r[NREC] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1], Phi[0], Phi[1], SI[0], SI[1]};
+    rec.insert(rec.end(), r, r + NREC);
   }
 
   // Forces of every recorded step: [t][scheme A, B, DRTT][x, y].  DRTT (second
   // Eq. rtt7): F(t) = J(t) - J(t+1) + Phi(t); the J of the step after the last recorded
   // one is the control-volume momentum of the populations the next pull would give.
   void forces(T* out) const {
-    const size_t n = rec.size() / 8;
+    const size_t n = rec.size() / NREC;
     T Jlast[2] = {0.0, 0.0};
     if (cfg.box[0] >= 0) {
       std::vector<T> g(S.size(), T(0.0));
@@ -382,21 +427,23 @@ struct Sim {
       box_momentum(g, Jlast);
     }
     for (size_t t = 0; t < n; ++t) {
-      const T* r = &rec[8 * t];
-      T* o = out + 6 * t;
+      const T* r = &rec[NREC * t];
+      T* o = out + 8 * t;
       o[0] = r[0];
       o[1] = r[1];
       o[2] = r[2];
       o[3] = r[3];
       if (cfg.box[0] >= 0) {
-        T jx1 = (t + 1 < n) ? rec[8 * (t + 1) + 4] : Jlast[0];
-        T jy1 = (t + 1 < n) ? rec[8 * (t + 1) + 5] : Jlast[1];
+        T jx1 = (t + 1 < n) ? rec[NREC * (t + 1) + 4] : Jlast[0];
+        T jy1 = (t + 1 < n) ? rec[NREC * (t + 1) + 5] : Jlast[1];
         o[4] = r[4] - jx1 + r[6];
         o[5] = r[5] - jy1 + r[7];
       } else {
         o[4] = NAN;
         o[5] = NAN;
       }
+      o[6] = r[8];
+      o[7] = r[9];
     }
   }
 };
@@ -538,15 +585,15 @@ void orc_step(void* h, int32_t n) {
   for (int32_t k = 0; k < n; ++k) s->step();
 }
 
-int64_t orc_nrec(void* h) { return int64_t(static_cast<Sim<double>*>(h)->rec.size() / 8); }
+int64_t orc_nrec(void* h) { return int64_t(static_cast<Sim<double>*>(h)->rec.size() / NREC); }
 
-// Raw per-step records [t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy].
+// Raw per-step records [t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy].
 void orc_records(void* h, double* out) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   std::memcpy(out, s->rec.data(), s->rec.size() * sizeof(double));
 }
 
-// Forces [t][A, B, DRTT][x, y] of all recorded steps.
+// Forces [t][A, B, DRTT, SI][x, y] of all recorded steps.
 void orc_forces(void* h, double* out) { static_cast<Sim<double>*>(h)->forces(out); }
 
 void orc_clear_records(void* h) { static_cast<Sim<double>*>(h)->rec.clear(); }
@@ -566,7 +613,8 @@ int orc_objective_cs(const orc_cfg* c, const uint8_t* mask, double om_re, double
     s->uin[y] = Z(uin_re ? uin_re[y] : 0.0, uin_im ? uin_im[y] : 0.0);
   for (int32_t k = 0; k < nsteps; ++k) s->step();
   Z J = 0.0;
-  for (int32_t t = t0; t < t0 + T; ++t) J += wx * s->rec[8 * size_t(t) + 2] + wy * s->rec[8 * size_t(t) + 3];
+  for (int32_t t = t0; t < t0 + T; ++t)
+    J += wx * s->rec[NREC * size_t(t) + 2] + wy * s->rec[NREC * size_t(t) + 3];
   J /= double(T);
   out[0] = J.real();
   out[1] = J.imag();

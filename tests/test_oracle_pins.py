@@ -801,3 +801,107 @@ def test_kbc_keeps_an_instance_finite_where_bgk_blows_up(orc):
         s = OracleSim(w.mask, w.tau, w.uin, box=w.box, collision=coll)
         s.step(1000 if coll == "bgk" else 3000)
         assert bool(np.isfinite(s.forces()).all()) == finite, coll
+
+
+# --------------------------------------------------------------------------------------
+# Stress integration over the staircase surface (Sec. III, Eq. stress_int and the
+# non-equilibrium stress that follows it)
+# --------------------------------------------------------------------------------------
+
+def _state_pulling_to(orc, mask, f):
+    """A stored state S whose pull on a doubly periodic lattice gives exactly the
+    pre-collision field f at every fluid node: S_i(x) = f_i(x + c_i), and where x + c_i
+    is solid the bounce-back reads S_i(x) as f_opp(i)(x)."""
+    cx, cy, opp, _, _ = orc.lattice()
+    ny, nx = mask.shape
+    S = np.zeros_like(f)
+    for i in range(9):
+        S[i] = np.roll(np.roll(f[i], -int(cy[i]), axis=0), -int(cx[i]), axis=1)
+        solid_ahead = np.roll(np.roll(mask, -int(cy[i]), axis=0), -int(cx[i]), axis=1) == 1
+        S[i][solid_ahead] = f[opp[i]][solid_ahead]
+    return S
+
+
+def _spans(mask):
+    """Number of solid runs and total solid length per row and per column."""
+    def runs(rows):
+        n = length = 0
+        for r in rows:
+            d = np.diff(np.concatenate([[0], r.astype(int), [0]]))
+            n += int((d == 1).sum())
+            length += int(r.sum())
+        return n, length
+    return runs(mask), runs(mask.T)
+
+
+def test_si_pressure_part_closed_form(orc):
+    """At rest with a linear density rho = 1 + a x, the pressure tractions on the
+    staircase faces sum to F_x = -theta0 a sum_runs (len + 1) per row (each run's left
+    and right faces sample p one node outside the body), F_y = 0."""
+    cx, cy, _, w, th = orc.lattice()
+    ny, nx = 30, 40
+    mask = workloads.cylinder_mask(nx, ny, 19.5, 14.5, 6.0)
+    a = 1e-3
+    X = np.arange(nx)[None, :].repeat(ny, 0)
+    f = np.zeros((9, ny, nx))
+    for i in range(9):
+        f[i] = w[i] * (1.0 + a * (X - 20))
+    s = OracleSim(mask, tau=0.8, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    s.set_state(_state_pulling_to(orc, mask, f))
+    s.step(1)
+    np.testing.assert_allclose(s.pre()[:, mask == 0], f[:, mask == 0], rtol=0, atol=0)
+    (nruns, length), _ = _spans(mask)
+    F = s.forces()[0, 3]
+    np.testing.assert_allclose(F[0], -th * a * (length + nruns), rtol=1e-12)
+    assert abs(F[1]) <= 1e-15
+
+
+def test_si_viscous_part_closed_form(orc):
+    """At rest with a non-equilibrium part eps(x) w_i c_ix c_iy / theta0^2 (no mass, no
+    momentum, Pi^neq_xy = eps(x)), eps = e0 + b x: the shear tractions give
+    F_y = -(1 - omega/2) b sum_runs (len + 1) per row and F_x = 0; the pressure part
+    cancels on the closed surface."""
+    cx, cy, _, w, th = orc.lattice()
+    ny, nx = 30, 40
+    mask = workloads.cylinder_mask(nx, ny, 19.5, 14.5, 6.0)
+    b, e0, tau = 2e-5, 1e-4, 0.8
+    X = np.arange(nx)[None, :].repeat(ny, 0)
+    eps = e0 + b * (X - 20)
+    f = np.zeros((9, ny, nx))
+    for i in range(9):
+        f[i] = w[i] * (1.0 + eps * cx[i] * cy[i] / th ** 2)
+    s = OracleSim(mask, tau=tau, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    s.set_state(_state_pulling_to(orc, mask, f))
+    s.step(1)
+    (nruns, length), _ = _spans(mask)
+    F = s.forces()[0, 3]
+    np.testing.assert_allclose(F[1], -(1 - 0.5 / tau) * b * (length + nruns), rtol=1e-10)
+    assert abs(F[0]) <= 1e-15
+
+
+def test_si_poiseuille_walls_closed_form(orc):
+    """Body-force-driven channel whose walls are body rows (periodic x and y, solid rows
+    0 and ny-1), at the tau where half-way bounce-back Poiseuille flow is exact: the
+    staircase stress integral samples the linear shear stress half a node inside the
+    fluid, so SI_x = (H - 1)/H of the exact N g (H fluid rows), while MEA-B gives N g."""
+    for ny in (10, 18):
+        nx, g = 8, 1e-6
+        mask = np.zeros((ny, nx), np.uint8)
+        mask[0] = 1
+        mask[-1] = 1
+        s = OracleSim(mask, tau=0.5 + np.sqrt(3 / 16), bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC,
+                      g=(g, 0.0))
+        s.step(40000)
+        F = s.forces()[-1]
+        H = ny - 2
+        np.testing.assert_allclose(F[3, 0], (H - 1) / H * nx * H * g, rtol=1e-8)
+        np.testing.assert_allclose(F[1, 0], nx * H * g, rtol=1e-8)
+        assert abs(F[3, 1]) <= 1e-14
+
+
+def test_si_rest_state_zero_on_closed_body(orc):
+    """Uniform rest state: no stress, uniform pressure; the closed staircase gives zero."""
+    mask = workloads.cylinder_mask(40, 30, 19.5, 14.5, 6.0)
+    s = OracleSim(mask, tau=0.7, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
+    s.step(3)
+    assert np.abs(s.forces()[:, 3]).max() <= 1e-15
