@@ -4,10 +4,10 @@
 Workload (default): NACA0012 from the analytic 4-digit thickness law, chord 1024, angle
 of attack 4 deg, in an 8192 x 4096 channel (33.5 M nodes) with no-slip walls, uniform
 inlet 0.05 and zero-gradient outlet, Re 1e4 (tau_lb from nu = U c / Re), FP32 population
-storage, forces by momentum exchange A and B and by DRTT at every step.  Synthetic input
-(analytic geometry, flow started from rest).
+storage, forces by momentum exchange A and B, by DRTT and by stress integration at every
+step.  Synthetic input (analytic geometry, flow started from rest).
 
-One "step" is one lattice time step of the whole grid including the three force
+One "step" is one lattice time step of the whole grid including the four force
 estimators.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -55,7 +55,7 @@ def measured_traffic(workload: str, precision: str):
 
 def cpu_baseline(w, steps: int, collision: str = "bgk"):
     """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
-    `steps` full-grid time steps with all three forces."""
+    `steps` full-grid time steps with all four forces."""
     import oracle
     o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision)
     t0 = time.perf_counter()
@@ -65,7 +65,7 @@ def cpu_baseline(w, steps: int, collision: str = "bgk"):
     del o
     return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
-            "sample": f"{steps} full-grid steps of {w.nx}x{w.ny} with A, B and DRTT forces "
+            "sample": f"{steps} full-grid steps of {w.nx}x{w.ny} with A, B, DRTT and SI forces "
                       f"({dt:.1f} s, FP64, one thread)"}
 
 
@@ -102,11 +102,11 @@ def precision_study(steps: int):
             fl = w.mask == 0
             out = {"case": w.name, "steps": steps, "tau": w.tau,
                    "fp64_window_mean": {s: C64[-2000:, k].mean(0).tolist()
-                                        for k, s in enumerate(("A", "B", "DRTT"))}}
+                                        for k, s in enumerate(("A", "B", "DRTT", "SI"))}}
             for prec in ("fp32", "fp32dev", "fp16dev"):
                 C, (u, v), wall = runs[prec]
                 e = {}
-                for k, s in enumerate(("A", "B", "DRTT")):
+                for k, s in enumerate(("A", "B", "DRTT", "SI")):
                     scale = np.abs(C64[:, k]).max(0)
                     e[s] = {"step_max_rel_cd_cl": (np.abs(C[:, k] - C64[:, k]).max(0) / scale).tolist(),
                             "window_mean_rel_cd_cl": (np.abs(C[-2000:, k].mean(0) - C64[-2000:, k].mean(0))
@@ -170,7 +170,7 @@ def adjoint_bench(precision: str):
 
 def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
     """The 256-instance batch (uneven cylinder and airfoil channels, one launch per step
-    for all of them): autotuned schedule, then `steps` timed steps with all three forces.
+    for all of them): autotuned schedule, then `steps` timed steps with all four forces.
     Beside it: the same instances stepped one after another through the single-lattice
     call, and the batch in FP64 storage."""
     import numpy as np
@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--workload", default="naca8192", choices=["naca8192", "naca2048", "cyl200"])
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--aoa", type=float, default=4.0)
-    ap.add_argument("--schemes", default="A,B,DRTT")
+    ap.add_argument("--schemes", default="A,B,DRTT,SI")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "regularized", "kbc"])
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -377,9 +377,9 @@ def main():
         "force_cost_frac": round((ms / K - ms_off) / ms_off, 4),
     }
     if len(F):
-        cols = [k for k, s in enumerate(("A", "B", "DRTT")) if s in schemes]
+        cols = [k for k, s in enumerate(("A", "B", "DRTT", "SI")) if s in schemes]
         out["forces_finite"] = bool(np.all(np.isfinite(F[:, cols])))
-        out["last_coefficients"] = {s: C[-1, k].tolist() for k, s in enumerate(("A", "B", "DRTT"))
+        out["last_coefficients"] = {s: C[-1, k].tolist() for k, s in enumerate(("A", "B", "DRTT", "SI"))
                                     if s in schemes}
     del sim
     torch.cuda.empty_cache()

@@ -7,11 +7,12 @@
  * arXiv:2210.10377, Sec. II: Eq. CollideAdv, the second-order equilibrium, Table I)
  * around a body given as a solid mask on the Cartesian grid, with half-way bounce-back
  * on every fluid-solid link (Sec. II, stationary wall) and, at every step, the force of
- * the fluid on the body by three estimators:
+ * the fluid on the body by four estimators:
  *   - momentum exchange, algorithm A (Sec. IV, Eq. rtt4 "Algorithm A"),
  *   - momentum exchange, algorithm B (Sec. IV, Eq. rtt4 "Algorithm B", Eq. rtt5),
  *   - the discrete Reynolds-transport-theorem control-volume force DRTT (Sec. IV,
- *     second Eq. rtt7; Appendix).
+ *     second Eq. rtt7; Appendix),
+ *   - stress integration SI over the staircase surface (Sec. III, Eq. stress_int).
  * The paper's problem statement is a body in a channel, a relaxation time, an inlet,
  * and the force on the body at every step (Sec. V, Appendix); the calls below follow it.
  *
@@ -40,7 +41,12 @@
  *       DRTT(t) = J(t) - J(t+1) + Phi(t), J(t) the momentum of the pre-collision
  *                 populations of the control volume V (the fluid nodes of the box),
  *                 Phi(t) = sum of c_i f~_i(x,t) over populations entering V minus those
- *                 leaving V.
+ *                 leaving V,
+ *       SI(t)   = sum_{axis links (x,i), i = 1..4} (-p I + sigma)(x,t) . (-c_i): each
+ *                 axis link crosses one unit face of the staircase body surface, whose
+ *                 normal out of the body is -c_i; p = rho/3 and the deviatoric stress
+ *                 sigma = -(1 - 1/(2 tau_lb)) sum_k (f_k - f_k^eq) c_k c_k at the fluid
+ *                 node, from its pre-collision populations.
  *     A link is a fluid node x and a direction i with x + c_i a solid mask node.
  *
  * Memory: the caller owns all memory.  lbm_create copies the mask and inlet profile.
@@ -111,7 +117,8 @@ extern "C" {
 #define LBM_FORCE_MEA_A 1u
 #define LBM_FORCE_MEA_B 2u
 #define LBM_FORCE_DRTT 4u
-#define LBM_FORCE_ALL 7u
+#define LBM_FORCE_SI 8u
+#define LBM_FORCE_ALL 15u
 
 typedef struct lbm_grid {
   int32_t nx, ny;     /* grid size, each >= 3                                      */
@@ -169,20 +176,20 @@ int lbm_workspace_bytes(const lbm_t* h, size_t* bytes);
 int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream);
 
 /* Enqueue n >= 0 time steps on the bound stream.  force_scheme is a mask of
- * LBM_FORCE_*; when non-zero every step records one force row (all three estimators
+ * LBM_FORCE_*; when non-zero every step records one force row (all four estimators
  * are evaluated; rows for schemes not asked for read NaN).  Returns LBM_EOVERFLOW
  * without launching anything if the ring would overflow, LBM_ESTATE if unbound,
  * LBM_EINVAL for n < 0 or unknown scheme bits. */
 int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme);
 
-/* Copy the force rows recorded since the last call into out[k][3][2] (host; scheme
- * order A, B, DRTT; components x, y) and empty the ring.  At most cap rows are written
+/* Copy the force rows recorded since the last call into out[k][4][2] (host; scheme
+ * order A, B, DRTT, SI; components x, y) and empty the ring.  At most cap rows are written
  * (LBM_EINVAL if fewer than recorded).  Synchronises the stream.  Returns
  * LBM_ENONFINITE (after writing everything) if any requested value is not finite. */
 int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out);
 
-/* Force coefficients 2 F / (rho_ref u_ref^2 l_ref) of k force rows (Sec. V: drag and
- * lift coefficients, kept signed), host to host; in and out may alias. */
+/* Force coefficients 2 F / (rho_ref u_ref^2 l_ref) of k force rows ([k][4][2], Sec. V:
+ * drag and lift coefficients, kept signed), host to host; in and out may alias. */
 int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out);
 
 int lbm_destroy(lbm_t* h);
@@ -332,7 +339,7 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
  * force_scheme (as lbm_step).  LBM_EOVERFLOW when force rows would exceed max_record. */
 int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme);
 
-/* Drain the batch ring: out[i][t][scheme][component] (host, n_inst x cap x 3 x 2
+/* Drain the batch ring: out[i][t][scheme][component] (host, n_inst x cap x 4 x 2
  * doubles) receives instance i's forces of the t-th recorded step, as lbm_forces
  * gives them; *k_out the number of rows (also when out is NULL and nothing is
  * recorded).  nonfinite (host, n_inst bytes, may be NULL) flags instances with a

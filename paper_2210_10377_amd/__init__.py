@@ -6,5 +6,5 @@ under algorithms A and B, and the discrete Reynolds-transport-theorem force, as 
 kernels for gfx950 behind the C ABI of include/lbm.h.
 """
 from ._capi import LbmError  # noqa: F401
-from .sim import Plan, Sim, scheme_mask  # noqa: F401
+from .sim import ALL_SCHEMES, Plan, Sim, scheme_mask  # noqa: F401
 from .batch import Batch  # noqa: F401

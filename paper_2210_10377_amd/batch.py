@@ -8,7 +8,7 @@ import ctypes
 import numpy as np
 
 from . import _capi as C
-from .sim import Sim, scheme_mask
+from .sim import ALL_SCHEMES, Sim, scheme_mask
 
 
 class Batch:
@@ -67,7 +67,7 @@ class Batch:
         s = C.lbm_batch_schedule(int(grid_blocks), int(graph_steps), int(tile_order))
         C.check_batch(self._lib.lbm_batch_set_schedule(self._h, ctypes.byref(s)), self._h)
 
-    def autotune(self, steps: int = 10, schemes=("A", "B", "DRTT")):
+    def autotune(self, steps: int = 10, schemes=ALL_SCHEMES):
         """Time the candidate schedules (each advances every instance by 2 x steps) and
         keep the fastest; returns (schedule dict, milliseconds per step)."""
         best = C.lbm_batch_schedule()
@@ -83,15 +83,15 @@ class Batch:
         return inf
 
     # -- stepping ---------------------------------------------------------------------
-    def step(self, n: int, schemes=("A", "B", "DRTT")):
+    def step(self, n: int, schemes=ALL_SCHEMES):
         C.check_batch(self._lib.lbm_batch_step(self._h, int(n), scheme_mask(schemes)), self._h)
 
     def forces(self):
-        """(F [n_inst, k, 3 (A, B, DRTT), 2 (x, y)], nonfinite bool [n_inst]) of the steps
+        """(F [n_inst, k, 4 (A, B, DRTT, SI), 2 (x, y)], nonfinite bool [n_inst]) of the steps
         recorded since the last call."""
         k = self.info().n_recorded
         n = len(self.members)
-        out = np.zeros((n, max(k, 1), 3, 2))
+        out = np.zeros((n, max(k, 1), 4, 2))
         flags = np.zeros(n, np.uint8)
         got = ctypes.c_int64()
         rc = self._lib.lbm_batch_forces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -101,7 +101,7 @@ class Batch:
             C.check_batch(rc, self._h)
         return out[:, :got.value], flags.astype(bool)
 
-    def run(self, n: int, schemes=("A", "B", "DRTT")):
+    def run(self, n: int, schemes=ALL_SCHEMES):
         """n steps with forces, chunked to the ring capacity; (F, nonfinite) as ``forces``."""
         outs, bad = [], np.zeros(len(self.members), bool)
         left = int(n)
@@ -113,7 +113,7 @@ class Batch:
             bad |= nf
             left -= k
         if not outs:
-            return np.zeros((len(self.members), 0, 3, 2)), bad
+            return np.zeros((len(self.members), 0, 4, 2)), bad
         return np.concatenate(outs, axis=1), bad
 
     def coefficients(self, F: np.ndarray) -> np.ndarray:

@@ -31,7 +31,7 @@ namespace {
 #define LBM_PLANE_PAD_BYTES 512
 #endif
 
-constexpr int kRow = 10;  // FAx FAy FBx FBy Jx Jy Phix Phiy Jnext_x Jnext_y
+constexpr int kRow = kRingRow;
 constexpr uint64_t kStateMagic = 0x4c424d5332443951ull;  // "LBMS2D9Q"
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -126,7 +126,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   h->off_uin = off;
   off = align256(off + size_t(g.ny) * sizeof(double));
   h->off_part = off;
-  off = align256(off + 2 * size_t(h->plan.nslots) * 8 * sizeof(double));
+  off = align256(off + 2 * h->part_doubles() * sizeof(double));
   h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
   h->off_jpart = off;
   off = align256(off + size_t(h->njblocks) * 2 * sizeof(double));
@@ -213,7 +213,22 @@ StepArgs step_args(const lbm_t* h) {
   a.omega = h->omega;
   a.collision = h->g.collision;
   a.nslots = p.nslots;
+  a.njslots = p.njslots;
   return a;
+}
+
+bool row_forces(const double* r, uint32_t sch, bool has_box, double* o) {
+  const double v[8] = {r[0], r[1], r[2], r[3], r[4] - r[kJnext] + r[6],
+                       r[5] - r[kJnext + 1] + r[7], r[8], r[9]};
+  const bool want[4] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
+                        (sch & LBM_FORCE_DRTT) != 0 && has_box, (sch & LBM_FORCE_SI) != 0};
+  bool finite = true;
+  for (int s = 0; s < 4; ++s)
+    for (int c = 0; c < 2; ++c) {
+      o[2 * s + c] = want[s] ? v[2 * s + c] : std::nan("");
+      if (want[s] && !std::isfinite(v[2 * s + c])) finite = false;
+    }
+  return finite;
 }
 
 BoxArgs box_args(const lbm_t* h, const void* src) {
@@ -262,7 +277,7 @@ int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
     if (forces && k >= 1) {
       a.red_in = h->part((k - 1) & 1);
       a.red_row = ring + int64_t(k - 1) * kRow;
-      a.red_prev_jnext = k >= 2 ? ring + int64_t(k - 2) * kRow + 8 : nullptr;
+      a.red_prev_jnext = k >= 2 ? ring + int64_t(k - 2) * kRow + kJnext : nullptr;
     }
     hipError_t e = launch_step(h->g.precision, forces, a, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "launch step");
@@ -276,8 +291,9 @@ int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
     FinalArgs f{};
     f.red_in = h->part((n - 1) & 1);
     f.nslots = p.nslots;
+    f.njslots = p.njslots;
     f.row = ring + int64_t(n - 1) * kRow;
-    f.prev_jnext = n >= 2 ? ring + int64_t(n - 2) * kRow + 8 : nullptr;
+    f.prev_jnext = n >= 2 ? ring + int64_t(n - 2) * kRow + kJnext : nullptr;
     f.jpart = p.has_box ? reinterpret_cast<const double*>(h->ws + h->off_jpart) : nullptr;
     f.njblocks = h->njblocks;
     hipError_t e = launch_finalize(f, h->stream);
@@ -336,20 +352,9 @@ int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "forces synchronize");
   bool finite = true;
-  const double nan = std::nan("");
-  for (int64_t t = 0; t < h->nrec; ++t) {
-    const double* r = &rows[size_t(t) * kRow];
-    const uint32_t sch = h->rec_scheme[size_t(t)];
-    double* o = out + t * 6;
-    const double v[6] = {r[0], r[1], r[2], r[3], r[4] - r[8] + r[6], r[5] - r[9] + r[7]};
-    const bool want[3] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
-                          (sch & LBM_FORCE_DRTT) != 0 && h->plan.has_box};
-    for (int s = 0; s < 3; ++s)
-      for (int c = 0; c < 2; ++c) {
-        o[2 * s + c] = want[s] ? v[2 * s + c] : nan;
-        if (want[s] && !std::isfinite(v[2 * s + c])) finite = false;
-      }
-  }
+  for (int64_t t = 0; t < h->nrec; ++t)
+    finite = row_forces(&rows[size_t(t) * kRow], h->rec_scheme[size_t(t)], h->plan.has_box,
+                        out + t * 8) && finite;
   h->nrec = 0;
   h->rec_scheme.clear();
   if (!finite) return h->fail(LBM_ENONFINITE, "a recorded force is not finite");
@@ -359,7 +364,7 @@ int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
 int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out) {
   if (!h || (k > 0 && (!forces || !out)) || k < 0) return LBM_EINVAL;
   const double q = 0.5 * h->g.rho_ref * h->g.u_ref * h->g.u_ref * h->g.l_ref;
-  for (int64_t j = 0; j < k * 6; ++j) out[j] = forces[j] / q;
+  for (int64_t j = 0; j < k * 8; ++j) out[j] = forces[j] / q;
   return LBM_OK;
 }
 

@@ -466,24 +466,13 @@ int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
   if (e != hipSuccess) return b->hip_fail(e, "download force ring");
   e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return b->hip_fail(e, "forces synchronize");
-  const double nan = std::nan("");
   bool all_finite = true;
   for (size_t i = 0; i < n; ++i) {
     const bool has_box = b->m[i]->plan.has_box;
     bool finite = true;
-    for (int64_t t = 0; t < k; ++t) {
-      const double* r = &rows[(i * size_t(k) + size_t(t)) * kRingRow];
-      const uint32_t sch = b->rec_scheme[size_t(t)];
-      double* o = out + (int64_t(i) * cap + t) * 6;
-      const double v[6] = {r[0], r[1], r[2], r[3], r[4] - r[8] + r[6], r[5] - r[9] + r[7]};
-      const bool want[3] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
-                            (sch & LBM_FORCE_DRTT) != 0 && has_box};
-      for (int s = 0; s < 3; ++s)
-        for (int c = 0; c < 2; ++c) {
-          o[2 * s + c] = want[s] ? v[2 * s + c] : nan;
-          if (want[s] && !std::isfinite(v[2 * s + c])) finite = false;
-        }
-    }
+    for (int64_t t = 0; t < k; ++t)
+      finite = row_forces(&rows[(i * size_t(k) + size_t(t)) * kRingRow], b->rec_scheme[size_t(t)],
+                          has_box, out + (int64_t(i) * cap + t) * 8) && finite;
     if (!finite) {
       all_finite = false;
       if (nonfinite) nonfinite[i] = 1;

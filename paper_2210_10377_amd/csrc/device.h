@@ -290,42 +290,64 @@ __device__ __forceinline__ void block_sum8(double (&v)[8], double* out) {
   }
 }
 
-// Sum 8 doubles over the wave in a fixed (butterfly) order; lanes 0..7 store out[0..7].
-__device__ __forceinline__ void wave_sum8_store(double (&v)[8], double* out) {
+// Sum N doubles over the wave in a fixed (butterfly) order; lanes 0..N-1 store
+// out[0..N-1].
+template <int N>
+__device__ __forceinline__ void wave_sum_store(double (&v)[N], double* out) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < N; ++k)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
   const int lane = threadIdx.x & 63;
   double mine = v[0];
 #pragma unroll
-  for (int k = 1; k < 8; ++k) mine = lane == k ? v[k] : mine;
-  if (lane < 8) out[lane] = mine;
+  for (int k = 1; k < N; ++k) mine = lane == k ? v[k] : mine;
+  if (lane < N) out[lane] = mine;
 }
 
-// Fixed-order reduction of [nslots][8] partials by one 256-thread block; returns the
-// eight sums in threads 0..7.
-__device__ __forceinline__ double reduce_partials8(const double* in, int nslots) {
-  __shared__ double red[kThreads / 8][8];
-  constexpr int kG = kThreads / 8;  // slot groups
-  const int k = threadIdx.x & 7, grp = threadIdx.x >> 3;
-  // Four independent partial sums per lane keep four loads in flight; they are
-  // combined in a fixed order, so the result depends on nslots only.
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int j = grp;
-  for (; j + 3 * kG < nslots; j += 4 * kG) {
-    s0 += in[int64_t(j) * 8 + k];
-    s1 += in[int64_t(j + kG) * 8 + k];
-    s2 += in[int64_t(j + 2 * kG) * 8 + k];
-    s3 += in[int64_t(j + 3 * kG) * 8 + k];
+// Sum N doubles over the wave as wave_sum_store does and store them at out[at..at+N-1]
+// of an M-double record whose other entries are written as zero.
+template <int N, int M>
+__device__ __forceinline__ void wave_sum_store_at(double (&v)[N], int at, double* out) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int lane = threadIdx.x & 63;
+  double mine = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) mine = lane == at + k ? v[k] : mine;
+  if (lane < M) out[lane] = mine;
+}
+
+// Fixed-order reduction of [nslots][N] partials by one 256-thread block; returns the N
+// sums in threads 0..N-1.  The first G*N threads (G = 256 / N groups) read element
+// j*N + k (k = thread % N) of every G-th slot, so each keeps one component.
+template <int N>
+__device__ __forceinline__ double reduce_partials(const double* in, int nslots) {
+  constexpr int kG = kThreads / N;  // slot groups
+  __shared__ double red[kG][N];
+  const int k = threadIdx.x % N, grp = threadIdx.x / N;
+  if (grp < kG) {
+    // Eight independent partial sums per lane keep eight loads in flight (this block
+    // runs beside the step's tiles and must finish with them); they are combined in a
+    // fixed order, so the result depends on nslots only.
+    constexpr int kU = 8;
+    double acc[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+    int j = grp;
+    for (; j + (kU - 1) * kG < nslots; j += kU * kG) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) acc[u] += in[int64_t(j + u * kG) * N + k];
+    }
+    for (; j < nslots; j += kG) acc[0] += in[int64_t(j) * N + k];
+    red[grp][k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
-  for (; j < nslots; j += kG) s0 += in[int64_t(j) * 8 + k];
-  const double s = (s0 + s1) + (s2 + s3);
-  red[grp][k] = s;
   __syncthreads();
   double t = 0.0;
-  if (threadIdx.x < 8)
-    for (int gI = 0; gI < kThreads / 8; ++gI) t += red[gI][threadIdx.x];
+  if (threadIdx.x < N)
+    for (int gI = 0; gI < kG; ++gI) t += red[gI][threadIdx.x];
   return t;
 }
 

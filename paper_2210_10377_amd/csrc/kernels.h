@@ -7,6 +7,13 @@
 
 namespace lbm {
 
+// Force partial of one strip, and the per-step sums: FAx FAy FBx FBy Jx Jy Phix Phiy
+// SIx SIy.
+constexpr int kPart = 10;
+// Force-ring row: the kPart sums, then Jnext_x Jnext_y (the J of the following step).
+constexpr int kRingRow = 12;
+constexpr int kJnext = 10;
+
 // Arguments of one fused time step.
 struct StepArgs {
   const void* src;  // post-collision state of the previous step (storage type)
@@ -27,9 +34,10 @@ struct StepArgs {
   double rho_w6;               // 2 rho_w / c_s^2 = 6 rho_w
   double omega;                // 1 / tau_lb
   int32_t collision;           // LBM_COLL_*
-  double* part_out;            // [nslots][8] force partials of this step, or null
-  const double* red_in;        // [nslots][8] partials of the previous step, or null
-  int32_t nslots;
+  double* part_out;            // force partials of this step ([nslots][kPart] of the
+                               // general strips, then [njslots][2] box momenta), or null
+  const double* red_in;        // partials of the previous step (same layout), or null
+  int32_t nslots, njslots;
   double* red_row;             // ring row receiving the reduced previous step
   double* red_prev_jnext;      // Jnext slot of the row before that, or null
 };
@@ -50,16 +58,13 @@ struct BoxArgs {
 };
 
 struct FinalArgs {
-  const double* red_in;   // [nslots][8] partials of the last step
-  int32_t nslots;
+  const double* red_in;   // partials of the last step (StepArgs layout)
+  int32_t nslots, njslots;
   double* row;            // ring row of the last step
   double* prev_jnext;     // Jnext slot of the row before, or null
   const double* jpart;    // [njblocks][2], or null when there is no box
   int32_t njblocks;
 };
-
-// Force-ring row: FAx FAy FBx FBy Jx Jy Phix Phiy Jnext_x Jnext_y.
-constexpr int kRingRow = 10;
 
 // One instance of a batch, as the batched kernels read it from device memory.
 struct BatchInst {

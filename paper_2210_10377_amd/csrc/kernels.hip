@@ -106,7 +106,7 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
 // and (when `forces`) the force sums of its nodes added to acc.
 template <int P, bool BUF, int COLL>
 __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, bool forces,
-                                             double (&acc)[8]) {
+                                             double (&acc)[kPart]) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
@@ -172,15 +172,48 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
             acc[7] += kCy[i] * sv;
           }
       }
+      // Stress integration (Sec. III, Eq. stress_int): each axis link of this node is a
+      // unit face of the staircase surface with normal -c_i out of the body; the
+      // traction (-p I + sigma) . n uses p = rho/3 and sigma = -(1 - omega/2) Pi^neq of
+      // the pre-collision populations (Pi^neq = sum c c f - rho u u - rho I/3), in
+      // binary64.  Faces are linear in n, so the node adds the traction of their sum.
+      int nsx = 0, nsy = 0;
+#pragma unroll
+      for (int i = 1; i <= 4; ++i)
+        if (pull_code(w, kOpp[i]) == kBody) {
+          nsx -= kCx[i];
+          nsy -= kCy[i];
+        }
+      if (nsx != 0 || nsy != 0) {
+        double fd[kQ];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+          fd[i] = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+        const double rho = ((fd[0] + fd[1]) + (fd[2] + fd[3])) + ((fd[4] + fd[5]) + (fd[6] + fd[7])) + fd[8];
+        const double ux = ((fd[1] + fd[5] + fd[8]) - (fd[3] + fd[6] + fd[7])) / rho;
+        const double uy = ((fd[2] + fd[5] + fd[6]) - (fd[4] + fd[7] + fd[8])) / rho;
+        const double diag = (fd[5] + fd[6]) + (fd[7] + fd[8]);
+        const double p = rho * (1.0 / 3.0);
+        const double visc = -(1.0 - 0.5 * a.omega);
+        const double sxx = visc * (((fd[1] + fd[3]) + diag) - rho * ux * ux - p);
+        const double syy = visc * (((fd[2] + fd[4]) + diag) - rho * uy * uy - p);
+        const double sxy = visc * (((fd[5] + fd[7]) - (fd[6] + fd[8])) - rho * ux * uy);
+        acc[8] += (sxx - p) * nsx + sxy * nsy;
+        acc[9] += sxy * nsx + (syy - p) * nsy;
+      }
     }
   }
 }
 
 // Force row of the previous step from its partial slots (fixed order).
-__device__ __forceinline__ void reduce_row(const double* red_in, int nslots, double* row,
-                                           double* prev_jnext) {
-  const double t = reduce_partials8(red_in, nslots);
-  if (threadIdx.x < 8) {
+__device__ __forceinline__ void reduce_row(const double* red_in, int nslots, int njslots,
+                                           double* row, double* prev_jnext) {
+  // General strips, then the box momenta of the box-interior strips (added to J).
+  double t = reduce_partials<kPart>(red_in, nslots);
+  const double tj = reduce_partials<2>(red_in + int64_t(nslots) * kPart, njslots);
+  const double tj4 = __shfl(tj, threadIdx.x - 4, 64);
+  if (threadIdx.x == 4 || threadIdx.x == 5) t += tj4;
+  if (threadIdx.x < kPart) {
     row[threadIdx.x] = t;
     if (prev_jnext && (threadIdx.x == 4 || threadIdx.x == 5)) prev_jnext[threadIdx.x - 4] = t;
   }
@@ -195,21 +228,40 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
   // alone (no memory access before the first population load).
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int x0 = tx * kTileW + 64 * wave;
-  if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, x0, ty * kTileH)) {
-    if (strip_is_interior(a.nx, x0)) {
-      typename Storage<P>::T v[kTileH][kQ];
-      interior_load<P, BUF>(a, tx, ty, v);
-      interior_finish<P, BUF, COLL>(a, tx, ty, v);
-    } else {
+  const int cls = strip_class(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, a.bx0, a.bx1, a.by0,
+                              a.by1, x0, ty * kTileH);
+  if (cls != kStripGeneral) {
+    if (!strip_is_interior(a.nx, x0)) {
       edge_rows<P, BUF, COLL>(a, tx, ty);
+      return;
     }
+    typename Storage<P>::T v[kTileH][kQ];
+    interior_load<P, BUF>(a, tx, ty, v);
+    if (FORCES && cls == kStripBoxInterior) {
+      // Every node is in the control volume and streams plainly: its pre-collision
+      // populations are the loaded values; only the box momentum J is accumulated.
+      double acc[2] = {0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < kTileH; ++r)
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+          const double fi = to_f64<P>(v[r][i], i);
+          acc[0] += kCx[i] * fi;
+          acc[1] += kCy[i] * fi;
+        }
+      interior_finish<P, BUF, COLL>(a, tx, ty, v);
+      wave_sum_store<2>(acc, a.part_out + int64_t(a.nslots) * kPart +
+                                 int64_t(strip_slot[tile * kStrips + wave]) * 2);
+      return;
+    }
+    interior_finish<P, BUF, COLL>(a, tx, ty, v);
     return;
   }
   const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
-  // FA(x,y), FB(x,y), J(x,y), Phi(x,y)
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // FA(x,y), FB(x,y), J(x,y), Phi(x,y), SI(x,y)
+  double acc[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   general_rows<P, BUF, COLL>(a, tx, ty, slot >= 0, acc);
-  if (slot >= 0) wave_sum8_store(acc, a.part_out + int64_t(slot) * 8);
+  if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
 }
 
 template <int P, bool BUF, bool FORCES, int COLL>
@@ -220,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
     // Block 0 is dispatched first: it reduces the previous step's force partials while
     // the tiles stream.
     if (tile == 0) {
-      reduce_row(a.red_in, a.nslots, a.red_row, a.red_prev_jnext);
+      reduce_row(a.red_in, a.nslots, a.njslots, a.red_row, a.red_prev_jnext);
       return;
     }
     --tile;
@@ -248,8 +300,8 @@ void batch_step_kernel(
     if (k == 0 && nprev == 0) return;
     const BatchInst& I = inst[blockIdx.x];
     const int64_t r = int64_t(row_base) + k - 1;
-    reduce_row(I.part[(k - 1) & 1], I.a.nslots, I.ring + r * kRingRow,
-               k + nprev >= 2 ? I.ring + (r - 1) * kRingRow + 8 : nullptr);
+    reduce_row(I.part[(k - 1) & 1], I.a.nslots, I.a.njslots, I.ring + r * kRingRow,
+               k + nprev >= 2 ? I.ring + (r - 1) * kRingRow + kJnext : nullptr);
     return;
   }
   const int stride = PERSIST ? int(gridDim.x) - nred : b.total_tiles;
@@ -316,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void batch_box_kernel(BatchLaunch b, int3
 }
 
 __device__ __forceinline__ void finalize_body(const FinalArgs& a) {
-  reduce_row(a.red_in, a.nslots, a.row, a.prev_jnext);
+  reduce_row(a.red_in, a.nslots, a.njslots, a.row, a.prev_jnext);
   if (a.jpart) {
     __syncthreads();
     __shared__ double red[kThreads][2];
@@ -331,10 +383,10 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& a) {
     if (threadIdx.x < 2) {
       double s = 0.0;
       for (int k = 0; k < kThreads; ++k) s += red[k][threadIdx.x];
-      a.row[8 + threadIdx.x] = s;
+      a.row[kJnext + threadIdx.x] = s;
     }
   } else if (threadIdx.x < 2) {
-    a.row[8 + threadIdx.x] = __builtin_nan("");
+    a.row[kJnext + threadIdx.x] = __builtin_nan("");
   }
 }
 
@@ -349,8 +401,9 @@ __global__ __launch_bounds__(kThreads) void batch_finalize_kernel(BatchLaunch b,
   FinalArgs f{};
   f.red_in = I.part[part_parity];
   f.nslots = I.a.nslots;
+  f.njslots = I.a.njslots;
   f.row = I.ring + int64_t(row) * kRingRow;
-  f.prev_jnext = has_prev ? I.ring + (int64_t(row) - 1) * kRingRow + 8 : nullptr;
+  f.prev_jnext = has_prev ? I.ring + (int64_t(row) - 1) * kRingRow + kJnext : nullptr;
   f.jpart = I.njblocks > 0 ? I.box.jpart : nullptr;
   f.njblocks = I.njblocks;
   finalize_body(f);

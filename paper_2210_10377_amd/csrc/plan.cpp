@@ -129,14 +129,15 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         }
     }
 
-  // Rectangle of every node off the first and last rows that needs the general path.
+  // Rectangle of every node off the first and last rows whose codes need the general
+  // path.  `band`: the nodes with a control-volume term (the box and the ring around it).
   auto band = [&](int x, int y) {
     return p.has_box && x >= p.box[0] - 1 && x <= p.box[1] && y >= p.box[2] - 1 &&
            y <= p.box[3];
   };
   for (int y = 1; y < g.ny - 1; ++y)
     for (int x = 0; x < g.nx; ++x) {
-      if (p.node[size_t(y) * g.nx + x] == edge_word(g.nx, g.bc_x, x) && !band(x, y)) continue;
+      if (p.node[size_t(y) * g.nx + x] == edge_word(g.nx, g.bc_x, x)) continue;
       if (p.gx0 > p.gx1) {
         p.gx0 = p.gx1 = x;
         p.gy0 = p.gy1 = y;
@@ -147,9 +148,9 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         p.gy1 = std::max(p.gy1, y);
       }
     }
-  // Tiles and strips.  A strip outside that rectangle and off the first and last rows
-  // needs no per-node metadata; the others take the general path, and those holding a
-  // link node or a control-volume-band node own a force-partial slot.
+  // Tiles and strips (strip_class).  General strips holding a link node or a node with a
+  // control-volume term own a force-partial slot (kPart sums); box-interior strips own
+  // a slot of the box-momentum partials (2 sums).
   p.ntx = (g.nx + kTileW - 1) / kTileW;
   p.nty = (g.ny + kTileH - 1) / kTileH;
   p.ntiles = p.ntx * p.nty;
@@ -158,7 +159,16 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     for (int tx = 0; tx < p.ntx; ++tx)
       for (int w = 0; w < kStrips; ++w) {
         const int x0 = tx * kTileW + w * kStripW, y0 = ty * kTileH;
-        if (strip_is_plain(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, x0, y0)) continue;
+        const int cls = p.has_box
+                            ? strip_class(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0],
+                                          p.box[1], p.box[2], p.box[3], x0, y0)
+                            : strip_class(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, 1, 0, 1, 0,
+                                          x0, y0);
+        if (cls == kStripPlain) continue;
+        if (cls == kStripBoxInterior) {
+          p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.njslots++;
+          continue;
+        }
         ++p.ngeneral;
         bool forces = false;
         for (int y = y0; y < std::min(y0 + kTileH, g.ny); ++y)

@@ -58,10 +58,10 @@ constexpr uint32_t edge_word(int nx, int bc_x, int x) {
 
 // A strip is "plain" when it stays off the first and last rows and outside the
 // rectangle [gx0, gx1] x [gy0, gy1] that holds every node of the other rows whose pull
-// codes are not edge_word (bodies, their links, outlet bounce-backs) and every node of
-// the control-volume band: its nodes need no per-node metadata.  A plain strip is
-// "interior" when it also holds neither x = 0 nor x = nx - 1 nor any x >= nx (plain
-// streaming in every direction).  Host plan and kernels share these rules.
+// codes are not edge_word (bodies, their links, outlet bounce-backs): its nodes need no
+// per-node metadata.  A plain strip is "interior" when it also holds neither x = 0 nor
+// x = nx - 1 nor any x >= nx (plain streaming in every direction).  Host plan and
+// kernels share these rules.
 constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int x0,
                               int y0) {
   (void)nx;
@@ -70,6 +70,24 @@ constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1
 }
 constexpr bool strip_is_interior(int nx, int x0) { return x0 > 0 && x0 + kStripW < nx; }
 
+// Class of a strip for the forward step with forces, given the control volume
+// [bx0, bx1) x [by0, by1) (bx0 > bx1: none):
+//   kStripGeneral: per-node pull codes (not plain), or it touches the ring of nodes
+//     within one node of the box surface (flux terms of DRTT);
+//   kStripBoxInterior: plain and inside [bx0+1, bx1-2] x [by0+1, by1-2], where every
+//     node is in the control volume with all its neighbours: only the box momentum J
+//     is accumulated;
+//   kStripPlain: everything else (no force terms).
+enum StripClass { kStripPlain = 0, kStripBoxInterior = 1, kStripGeneral = 2 };
+constexpr int strip_class(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int bx0, int bx1,
+                          int by0, int by1, int x0, int y0) {
+  if (!strip_is_plain(nx, ny, gx0, gx1, gy0, gy1, x0, y0)) return kStripGeneral;
+  const int x1 = x0 + kStripW - 1, y1 = y0 + kTileH - 1;
+  if (bx0 > bx1 || y0 > by1 || y1 < by0 - 1 || x0 > bx1 || x1 < bx0 - 1) return kStripPlain;
+  if (x0 >= bx0 + 1 && x1 <= bx1 - 2 && y0 >= by0 + 1 && y1 <= by1 - 2) return kStripBoxInterior;
+  return kStripGeneral;
+}
+
 struct Plan {
   int nx = 0, ny = 0, bc_x = 0, bc_y = 0;
   bool has_box = false;
@@ -77,14 +95,15 @@ struct Plan {
   std::vector<uint32_t> node;     // [ny*nx] pull codes + solid bit
   std::vector<int32_t> links;     // [L][2] (y*nx + x, i), canonical order
   int ntx = 0, nty = 0, ntiles = 0;  // tiles per row / column / total
-  // Inclusive node rectangle holding every node off the first and last rows that needs
-  // the general path (a solid node, pull codes other than edge_word, a node of the
-  // control-volume band); empty when gx0 > gx1.
+  // Inclusive node rectangle holding every node off the first and last rows whose pull
+  // codes need the general path (a solid node, codes other than edge_word); empty when
+  // gx0 > gx1.  The control volume is classified separately (strip_class).
   int gx0 = 0, gx1 = -1, gy0 = 0, gy1 = -1;
   // Per strip (tile-major, kStrips per tile): the index >= 0 of its force-partial slot
   // when it holds a link node or a control-volume-band node, else -1.
   std::vector<int32_t> strip_slot;
-  int nslots = 0;                 // strips with force terms
+  int nslots = 0;                 // general strips with force terms (kPart partials each)
+  int njslots = 0;                // box-interior strips (2 partials each: J)
   int ngeneral = 0;               // strips that take the general path
   int64_t n_fluid = 0, n_box = 0;
   // tail control-volume momentum sweep: blocks of kTileW nodes along each box row

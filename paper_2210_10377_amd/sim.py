@@ -10,7 +10,9 @@ from . import _capi as C
 
 PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV,
               "fp32dev": C.LBM_FP32DEV}
-SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT}
+SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT,
+           "SI": C.LBM_FORCE_SI}
+ALL_SCHEMES = ("A", "B", "DRTT", "SI")
 COLLISIONS = {"bgk": C.LBM_COLL_BGK, "regularized": C.LBM_COLL_REGULARIZED,
               "kbc": C.LBM_COLL_KBC}
 
@@ -85,16 +87,16 @@ class Sim:
             self._h = None
 
     # -- stepping ---------------------------------------------------------------------
-    def step(self, n: int, schemes=("A", "B", "DRTT")):
+    def step(self, n: int, schemes=ALL_SCHEMES):
         """Enqueue n steps on the stream; force rows are read back with ``forces``."""
         m = scheme_mask(schemes)
         C.check(self._lib.lbm_step(self._h, int(n), m), self._h)
 
     def forces(self) -> np.ndarray:
-        """[k, 3 (A, B, DRTT), 2 (x, y)] float64 forces of the steps since the last call."""
+        """[k, 4 (A, B, DRTT, SI), 2 (x, y)] float64 forces of the steps since the last call."""
         info = self.info()
         k = info.n_recorded
-        out = np.zeros((max(k, 1), 3, 2))
+        out = np.zeros((max(k, 1), 4, 2))
         got = ctypes.c_int64()
         rc = self._lib.lbm_forces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   max(k, 1), ctypes.byref(got))
@@ -103,7 +105,7 @@ class Sim:
         self.last_nonfinite = rc == C.LBM_ENONFINITE
         return out[:got.value]
 
-    def run(self, n: int, schemes=("A", "B", "DRTT")) -> np.ndarray:
+    def run(self, n: int, schemes=ALL_SCHEMES) -> np.ndarray:
         """n steps with forces, chunked to the ring capacity."""
         outs = []
         left = int(n)
@@ -112,7 +114,7 @@ class Sim:
             self.step(k, schemes)
             outs.append(self.forces())
             left -= k
-        return np.concatenate(outs) if outs else np.zeros((0, 3, 2))
+        return np.concatenate(outs) if outs else np.zeros((0, 4, 2))
 
     def coefficients(self, forces: np.ndarray) -> np.ndarray:
         f = np.ascontiguousarray(forces, dtype=np.float64)
