@@ -195,11 +195,18 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
     ds[0] = C(0);
 #pragma unroll
     for (int i = 1; i < kQ; ++i) ds[i] = i < 5 ? (kCy[i] == 0 ? qn : -qn) : C(kCx[i] * kCy[i]) * qp;
+    // Entropic weights 1/f^eq: exact division in binary64, the hardware reciprocal
+    // (1 ulp) in binary32, where they only weigh the stabilizer.
     C sh = C(0), hh = C(0);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       const C dh = d[i] - ds[i];
-      const C wi = C(1) / (DEV ? weight<C>(i) + fe[i] : fe[i]);
+      const C fq = DEV ? weight<C>(i) + fe[i] : fe[i];
+      C wi;
+      if constexpr (sizeof(C) == 8)
+        wi = C(1) / fq;
+      else
+        wi = __builtin_amdgcn_rcpf(fq);
       sh += ds[i] * dh * wi;
       hh += dh * dh * wi;
     }
