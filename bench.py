@@ -119,6 +119,68 @@ def precision_study(steps: int):
             print(json.dumps(out), flush=True)
 
 
+def resolution_sweep(diameters, t_conv: float, precision: str):
+    """Drag of a circular cylinder at Re 100 against the grid points per diameter, for
+    the four estimators (the convergence test of Sec. V: channel 60 D x 5 D, cylinder
+    15 D from the inlet, uniform inlet 0.05, walls).  Each run lasts t_conv convective
+    times (U t / D) from rest; Cd is the mean over the last quarter.  The limit of each
+    estimator is extrapolated from the three finest grids (Richardson, with the observed
+    order); one JSON line per grid, then one summary line."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    u, re = 0.05, 100.0
+    names = ("A", "B", "DRTT", "SI")
+    rows = []
+    for d in diameters:
+        nx, ny = 60 * d, 5 * d
+        mask = workloads.cylinder_mask(nx, ny, 15 * d, (ny - 1) / 2.0, d / 2.0)
+        box = workloads.default_box(mask, max(2, d // 4))
+        tau = workloads.tau_from_re(u, d, re)
+        steps = int(round(t_conv * d / u))
+        sim = Sim(mask, tau, workloads.uniform_inlet(ny, u), precision=precision, box=box,
+                  max_record=20000, u_ref=u, l_ref=float(d))
+        t0 = time.perf_counter()
+        C = sim.coefficients(sim.run(steps))
+        wall = time.perf_counter() - t0
+        win = C[-(steps // 4):]
+        cd = {n: float(win[:, k, 0].mean()) for k, n in enumerate(names)}
+        cl_rms = {n: float(np.sqrt((win[:, k, 1] ** 2).mean())) for k, n in enumerate(names)}
+        row = {"D": d, "nx": nx, "ny": ny, "tau": tau, "steps": steps, "cd_mean": cd,
+               "cl_rms": cl_rms, "finite": bool(np.isfinite(C).all()), "wall_s": round(wall, 2)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del sim
+    summary = {"resolution_sweep": "cylinder Re 100, channel 60D x 5D", "storage": precision,
+               "convective_times": t_conv}
+    if len(rows) >= 3:
+        d1, d2, d3 = (r["D"] for r in rows[-3:])
+        ext = {}
+        for n in names:
+            c1, c2, c3 = (r["cd_mean"][n] for r in rows[-3:])
+            # c(D) = c_inf + a D^-p through the three finest grids
+            from scipy.optimize import brentq
+            f = lambda p: (c1 - c2) / (d1 ** -p - d2 ** -p) - (c2 - c3) / (d2 ** -p - d3 ** -p)
+            try:
+                p = brentq(f, 0.2, 4.0)
+                a = (c2 - c3) / (d2 ** -p - d3 ** -p)
+                cinf = c3 - a * d3 ** -p
+            except ValueError:
+                p, cinf = None, None
+            ext[n] = {"order": p, "cd_limit": cinf,
+                      "rel_err_by_D": {r["D"]: (abs(r["cd_mean"][n] - cinf) / abs(cinf)
+                                                if cinf else None) for r in rows}}
+        ref = ext["DRTT"]["cd_limit"]
+        if ref:
+            for n in names:
+                ext[n]["rel_err_vs_drtt_limit_by_D"] = {
+                    r["D"]: abs(r["cd_mean"][n] - ref) / abs(ref) for r in rows}
+        summary["extrapolated"] = ext
+    print(json.dumps(summary), flush=True)
+
+
 def adjoint_bench(precision: str):
     """Forward (checkpointed) and backward (recompute + reverse kernels) throughput of
     the adjoint workload; MLUPS = nx * ny * steps / wall time of each phase."""
@@ -270,6 +332,12 @@ def main():
                          "2000) stepped together; autotuned schedule; batched MLUPS beside "
                          "the instances stepped one by one and the FP64 batch")
     ap.add_argument("--seq-steps", type=int, default=50)
+    ap.add_argument("--resolution-sweep", action="store_true",
+                    help="cylinder at Re 100 in a 60D x 5D channel for D in --diameters: "
+                         "mean drag of A, B, DRTT and SI against points per diameter, with "
+                         "Richardson extrapolation from the three finest grids")
+    ap.add_argument("--diameters", default="10,15,20,30,40,60")
+    ap.add_argument("--convective-times", type=float, default=150.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
@@ -304,6 +372,10 @@ def main():
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
+        return
+    if args.resolution_sweep:
+        resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,
+                         args.precision if args.precision != "fp32" else "fp32dev")
         return
 
     if args.workload == "naca8192":
