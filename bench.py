@@ -345,7 +345,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the lattice is not decomposed across GPUs "
-              "(see the design notes for how it would shard).", file=sys.stderr)
+              "(it would shard into x-slabs with a three-population halo per cut).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

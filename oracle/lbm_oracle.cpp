@@ -18,8 +18,7 @@
 // std::complex<double> for complex-step derivatives.  Build with
 //   g++ -O2 -ffp-contract=off -shared -fPIC
 //
-// Readings of passages where the paper is silent or ambiguous (all documented with the
-// design notes of the repository):
+// Readings of passages where the paper is silent or ambiguous:
 //  * node (x, y) sits at the point (x, y); directions are numbered
 //      0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1);
 //  * tau is the lattice relaxation time tau_lb = tau_paper + 1/2, so that the factor

@@ -85,7 +85,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is not built; run "
-                          "`python -m paper_2210_10377_amd.build` (or __graft_entry__.build())")
+                          "`python -m paper_2210_10377_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                              ctypes.c_uint32, ctypes.POINTER(ctypes.c_double))

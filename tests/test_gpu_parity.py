@@ -308,7 +308,7 @@ def test_full_size_naca_one_step(precision):
     assert err <= tol_pop, err
     e = _force_err(Fg, Fo)
     # The DRTT force of a random field is a small difference of large box momenta; its
-    # FP32 error is set by the rounding of ~1e6 stored populations (see design notes).
+    # FP32 error is set by the rounding of ~1e6 stored populations in the control volume.
     tol_f = {"fp64": np.array([1e-10] * 4), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3]),
              "fp32dev": np.array([1e-5, 1e-5, 1e-3, 1e-4])}[precision]
     print(precision, "full-size population error", err, "force errors", e)
