@@ -36,7 +36,8 @@ class _Cfg(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_x", ctypes.c_int32),
                 ("bc_y", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
                 ("rho_w", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
-                ("collision", ctypes.c_int32)]
+                ("collision", ctypes.c_int32), ("body_u", ctypes.c_double * 2),
+                ("body_omega", ctypes.c_double), ("body_c", ctypes.c_double * 2)]
 
 COLLISIONS = {"bgk": 0, "regularized": 1, "kbc": 2}
 
@@ -85,9 +86,12 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g, collision="bgk"):
+def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g, collision="bgk", body_motion=None):
     c = _Cfg()
     c.collision = COLLISIONS[collision]
+    if body_motion is not None:
+        ux, uy, om, xc, yc = (float(v) for v in body_motion)
+        c.body_u[0], c.body_u[1], c.body_omega, c.body_c[0], c.body_c[1] = ux, uy, om, xc, yc
     c.nx, c.ny, c.bc_x, c.bc_y = int(nx), int(ny), int(bc_x), int(bc_y)
     b = (-1, -1, -1, -1) if box is None else tuple(int(v) for v in box)
     for k in range(4):
@@ -158,17 +162,19 @@ class OracleSim:
     """FP64 reference simulation.  ``tau`` is the lattice relaxation time tau_lb
     (omega = 1/tau_lb); pass ``omega`` directly for the pure-streaming fixture
     (omega = 0).  ``collision`` is "bgk" (Eq. CollideAdv), "regularized" or "kbc" (the
-    stated variants for tau_lb close to 1/2)."""
+    stated variants for tau_lb close to 1/2).  ``body_motion`` = (ux, uy, Omega, xc, yc):
+    rigid motion of the body (translation, rotation rate about (xc, yc))."""
 
     def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BCY_WALL,
-                 box=None, rho_w=1.0, g=(0.0, 0.0), omega=None, collision="bgk"):
+                 box=None, rho_w=1.0, g=(0.0, 0.0), omega=None, collision="bgk",
+                 body_motion=None):
         m, mp = _mask(mask)
         self.ny, self.nx = m.shape
         if omega is None:
             omega = 1.0 / float(tau)
         self.omega = float(omega)
         self.box = box
-        self._cfg = _cfg(self.nx, self.ny, bc_x, bc_y, box, rho_w, g, collision)
+        self._cfg = _cfg(self.nx, self.ny, bc_x, bc_y, box, rho_w, g, collision, body_motion)
         u = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),

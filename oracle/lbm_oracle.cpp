@@ -30,7 +30,8 @@
 //  * pull rules, first match wins: periodic wrap > no-slip wall > inlet > outlet >
 //    body bounce-back > plain streaming;
 //  * the inlet is the moving-wall bounce-back of Sec. II at x = -1/2 with wall
-//    velocity (u_in(y), 0) and wall density rho_w;
+//    velocity (u_in(y), 0) and wall density rho_w; a body in rigid motion takes the same
+//    rule at the half-way point of each link, with the same rho_w;
 //  * the outlet copies the post-collision populations of column nx-1 into a ghost
 //    column nx (zero gradient);
 //  * algorithm A uses the pre-collision outgoing population f_i(x,t) in the lost
@@ -219,6 +220,11 @@ struct Config {
   double rho_w;    // inlet wall density
   double gx, gy;   // body force (test fixtures only; BGK only)
   int32_t collision;  // COLLISION_BGK, COLLISION_REGULARIZED or COLLISION_KBC
+  // Rigid motion of the body (all zero: at rest): translation velocity, rotation rate
+  // about the z axis, and the centre of rotation.
+  double body_u[2];
+  double body_omega;
+  double body_c[2];
 };
 
 // Per-step record: FA(2), FB(2), J(2), Phi(2), SI(2).
@@ -271,8 +277,16 @@ struct Sim {
       if (is_solid(cfg.nx - 1, sy)) return St[idx(o, x, y)];
       return St[idx(i, cfg.nx - 1, sy)];
     }
-    // Body: stationary-wall half-way bounce-back (Sec. II).
-    if (is_solid(sx, sy)) return St[idx(o, x, y)];
+    // Body: half-way bounce-back (Sec. II).  A body in rigid motion moves the wall
+    // point half-way along the link, x - c_i/2, with u_w = U + Omega e_z x (x_w - x_c),
+    // and the moving-wall rule applies as at the inlet (zero term at rest).
+    if (is_solid(sx, sy)) {
+      const double xw = x - 0.5 * CX[i], yw = y - 0.5 * CY[i];
+      const double uwx = cfg.body_u[0] - cfg.body_omega * (yw - cfg.body_c[1]);
+      const double uwy = cfg.body_u[1] + cfg.body_omega * (xw - cfg.body_c[0]);
+      const double cu = double(CX[o]) * uwx + double(CY[o]) * uwy;
+      return St[idx(o, x, y)] - 2.0 * W[o] * cfg.rho_w * cu / THETA0;
+    }
     return St[idx(i, sx, sy)];
   }
 

@@ -905,3 +905,74 @@ def test_si_rest_state_zero_on_closed_body(orc):
     s = OracleSim(mask, tau=0.7, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC)
     s.step(3)
     assert np.abs(s.forces()[:, 3]).max() <= 1e-15
+
+
+# --------------------------------------------------------------------------------------
+# Bodies in rigid motion (moving-wall bounce-back of Sec. II on the body links; the
+# two-term momentum exchange of Eq. rtt4/rtt5 and DRTT with moving walls)
+# --------------------------------------------------------------------------------------
+
+def test_comoving_uniform_flow_is_a_fixed_point_without_force(orc):
+    """A body translating with the fluid (uniform flow f^eq(1, U), body velocity U):
+    the moving-wall rule returns exactly the equilibrium populations, so the state is a
+    fixed point and no estimator sees a force."""
+    nx, ny = 40, 30
+    mask = workloads.cylinder_mask(nx, ny, 19.5, 14.5, 6.0)
+    U = (0.04, -0.02)
+    feq = orc.equilibrium(1.0, *U)
+    S0 = np.repeat(np.repeat(feq[:, None, None], ny, 1), nx, 2)
+    s = OracleSim(mask, tau=0.7, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC, box=(6, 34, 4, 26),
+                  body_motion=(U[0], U[1], 0.0, 0.0, 0.0))
+    s.set_state(S0)
+    s.step(10)
+    fl = mask == 0
+    np.testing.assert_allclose(s.state()[:, fl], S0[:, fl], rtol=0, atol=1e-14)
+    F = s.forces()
+    assert np.abs(F[:, [0, 1, 3]]).max() <= 1e-14
+    # DRTT: a difference of box momenta of about 16 (rounding 1e-15 relative)
+    assert np.abs(F[:, 2]).max() <= 1e-12
+
+
+def test_moving_wall_rule_on_a_body_link(orc):
+    """Brute force on one link: the population entering a fluid node from a rotating
+    body is the opposite population of the node plus 2 w_i rho_w (c_i . u_w)/c_s^2, with
+    u_w the rigid-body velocity at the half-way point of the link."""
+    cx, cy, opp, w, th = orc.lattice()
+    nx, ny = 16, 12
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[6, 8] = 1
+    om, xc, yc = 0.01, 7.0, 4.0
+    s = OracleSim(mask, tau=0.8, bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC,
+                  body_motion=(0.02, 0.01, om, xc, yc))
+    S = workloads.near_rest_state(nx, ny, seed=5, amp=0.1)
+    s.set_state(S)
+    s.step(1)
+    f = s.pre()
+    for i in range(1, 9):
+        x, y = 8 + cx[i], 6 + cy[i]          # fluid node whose pull along i starts in the body
+        xw, yw = x - cx[i] / 2, y - cy[i] / 2
+        uw = np.array([0.02 - om * (yw - yc), 0.01 + om * (xw - xc)])
+        expect = S[opp[i], y, x] + 2 * w[i] * (cx[i] * uw[0] + cy[i] * uw[1]) / th
+        assert abs(f[i, y, x] - expect) <= 1e-16
+
+
+def test_rotating_cylinder_mirror_symmetry_and_magnus_sign(orc):
+    """A cylinder on the centreline of a walled channel: reversing the rotation mirrors
+    the flow, so drag is unchanged and lift changes sign; with the flow along +x, a
+    counter-clockwise rotation (Omega > 0) drives the fluid faster below the body and
+    the lift is negative (Magnus).  DRTT equals MEA-B with moving walls."""
+    nx, ny = 120, 41
+    mask = workloads.cylinder_mask(nx, ny, 30, 20, 6)
+    box = workloads.default_box(mask, 4)
+    F = {}
+    for om in (0.004, -0.004):
+        s = OracleSim(mask, tau=0.6, uin=np.full(ny, 0.04), box=box,
+                      body_motion=(0.0, 0.0, om, 30.0, 20.0))
+        s.step(1500)
+        F[om] = s.forces()
+    a, b = F[0.004], F[-0.004]
+    scale = np.abs(a[:, 1]).max()
+    np.testing.assert_allclose(a[:, :, 0], b[:, :, 0], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(a[:, :, 1], -b[:, :, 1], rtol=0, atol=1e-12 * scale)
+    assert a[-500:, 1, 1].mean() < 0
+    assert np.abs(a[:, 2] - a[:, 1]).max() <= 1e-11 * scale
