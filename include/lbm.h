@@ -225,6 +225,19 @@ int lbm_set_state(lbm_t* h, const void* blob, size_t n);
 int lbm_set_inlet(lbm_t* h, const double* ux);
 int lbm_set_tau(lbm_t* h, double tau);
 
+/* Rigid motion of the body (not in the paper's runs; the moving-wall bounce-back of
+ * Sec. II applied to the body links): translation (ux, uy) and rotation rate omega about
+ * (xc, yc), so a link whose half-way point is x_w sees the wall velocity
+ * u_w = (ux - omega (y_w - yc), uy + omega (x_w - xc)), and the population it returns
+ * gains 2 w_i rho_w (c_i . u_w) / c_s^2 (rho_w of the inlet, 1 by default).  The mask
+ * does not move (a rotating or sliding surface of fixed shape).  A and B take the
+ * returned population in their two-term form, c_i [f_out + f_back]; DRTT and SI apply
+ * unchanged.  All zero (the default) is a body at rest.  Applies from the next step of
+ * the handle (the device copy is written on the handle's stream, which is synchronised
+ * when the handle is bound) and from the next lbm_batch_step of a batch holding it;
+ * the adjoint calls refuse a moving body.  LBM_EINVAL for non-finite values. */
+int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc, double yc);
+
 /* Put every node back in the rest state w_i, zero the step counter and empty the force
  * ring.  Synchronises the stream. */
 int lbm_reset(lbm_t* h);
@@ -253,7 +266,7 @@ int lbm_reset(lbm_t* h);
  * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
  * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is
  * still valid (any step, set_* or reset since invalidates it).  The adjoint covers the
- * BGK collision only: both calls return LBM_EINVAL for the other collisions. */
+ * BGK collision and bodies at rest only: both calls return LBM_EINVAL otherwise. */
 int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes);
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J);

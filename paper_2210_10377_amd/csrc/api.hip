@@ -125,6 +125,8 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   off = align256(off + h->plan.strip_slot.size() * sizeof(int32_t));
   h->off_uin = off;
   off = align256(off + size_t(g.ny) * sizeof(double));
+  h->off_motion = off;
+  off = align256(off + sizeof(BodyMotion));
   h->off_part = off;
   off = align256(off + 2 * h->part_doubles() * sizeof(double));
   h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
@@ -161,6 +163,9 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
   e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(), h->uin.size() * sizeof(double),
                      hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload inlet");
+  e = hipMemcpyAsync(h->ws + h->off_motion, &h->motion, sizeof(BodyMotion),
+                     hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload body motion");
   for (int k = 0; k < 2; ++k) {
     e = launch_fill_rest(h->g.precision, h->buf(k), h->plane, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
@@ -210,6 +215,7 @@ StepArgs step_args(const lbm_t* h) {
   a.strip_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
   a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
   a.rho_w6 = 6.0 * h->rho_w;
+  a.motion = h->motion_dev();
   a.omega = h->omega;
   a.collision = h->g.collision;
   a.nslots = p.nslots;
@@ -248,6 +254,7 @@ BoxArgs box_args(const lbm_t* h, const void* src) {
   b.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
   b.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
   b.rho_w6 = 6.0 * h->rho_w;
+  b.motion = h->motion_dev();
   b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
   return b;
 }
@@ -541,6 +548,22 @@ int lbm_set_tau(lbm_t* h, double tau) {
   return LBM_OK;
 }
 
+int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc, double yc) {
+  if (!h) return LBM_EINVAL;
+  for (double v : {ux, uy, omega, xc, yc})
+    if (!std::isfinite(v)) return h->fail(LBM_EINVAL, "body motion must be finite");
+  h->motion = BodyMotion{ux, uy, omega, xc, yc,
+                         (ux != 0.0 || uy != 0.0 || omega != 0.0) ? 1 : 0};
+  h->adj_valid = false;
+  if (h->bound) {
+    hipError_t e = hipMemcpyAsync(h->ws + h->off_motion, &h->motion, sizeof(BodyMotion),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "upload body motion");
+  }
+  return LBM_OK;
+}
+
 int lbm_reset(lbm_t* h) {
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
@@ -611,6 +634,7 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
   if (!h) return LBM_EINVAL;
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
+  if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (!ws || !J || n_steps < 1 || every < 1 || every > n_steps || t0 < 0 || T < 1 ||
       int64_t(t0) + T > n_steps || !std::isfinite(wx) || !std::isfinite(wy))
@@ -661,6 +685,7 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   if (!h) return LBM_EINVAL;
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
+  if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
   if (!h->adj_valid)
     return h->fail(LBM_ESTATE, "no adjoint forward run matches the handle's current parameters");
   if (!grad_uin || !grad_tau || !std::isfinite(dJ)) return h->fail(LBM_EINVAL, "invalid arguments");

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <new>
@@ -53,7 +54,8 @@ struct lbm_batch_t {
   int cus = 0;
   int bpar = 0;  // buf[bpar] of every instance-table entry is the member's current state
   lbm_batch_schedule sched{0, 0, 0};
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (launches, parity, forces)
+  // (launches, parity, forces, some body in motion): the last selects the kernel variant
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
   int64_t nrec = 0, steps_done = 0;
   std::vector<uint32_t> rec_scheme;
   std::string err;
@@ -116,6 +118,21 @@ struct lbm_batch_t {
         e.box = box_args(h, nullptr);
         e.njblocks = h->njblocks;
       }
+      // The batch reads each motion from its own table, which it uploads in order on
+      // its stream, not from the member's copy (written on the member's stream).
+      const BodyMotion* mot = nullptr;
+      if (h->motion.moving) {
+        e.mot.ux = h->motion.ux;
+        e.mot.uy = h->motion.uy;
+        e.mot.omega = h->motion.omega;
+        e.mot.xc = h->motion.xc;
+        e.mot.yc = h->motion.yc;
+        e.mot.moving = 1;
+        mot = reinterpret_cast<const BodyMotion*>(ws + off_desc + i * sizeof(BatchInst) +
+                                                  offsetof(BatchInst, mot));
+      }
+      e.a.motion = mot;
+      e.box.motion = h->plan.has_box ? mot : nullptr;
     }
     return d;
   }
@@ -134,6 +151,8 @@ struct lbm_batch_t {
     L.total_box_blocks = int32_t(total_box);
     L.grid_blocks = sched.grid_blocks > 0 ? (sched.grid_blocks + 7) / 8 * 8 : 0;
     L.collision = m[0]->g.collision;
+    L.moving = 0;
+    for (const lbm_t* h : m) L.moving |= h->motion.moving;
     return L;
   }
 
@@ -173,14 +192,14 @@ struct lbm_batch_t {
 
   // Graph of `len` consecutive step launches starting at buffer parity `parity`.
   int graph(int len, int parity, bool forces, hipGraphExec_t* out) {
-    const auto key = std::make_tuple(len, parity, forces ? 1 : 0);
+    const BatchLaunch L = launch();
+    const auto key = std::make_tuple(len, parity, forces ? 1 : 0, int(L.moving));
     auto it = graphs.find(key);
     if (it != graphs.end()) {
       *out = it->second;
       return LBM_OK;
     }
     if (int(graphs.size()) >= kMaxGraphs) drop_graphs();
-    const BatchLaunch L = launch();
     hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin graph capture");
     hipError_t le = hipSuccess;

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
 
@@ -242,10 +243,21 @@ __device__ __forceinline__ int block_tile(int b, int n) {
 //   stream: S_i(x - c_i); body or wall: S_o(x) (half-way bounce-back, o = opposite);
 //   inlet: S_o(x) + 2 w_i rho_w (c_i . u_w) / c_s^2 (moving-wall bounce-back, Sec. II);
 //   outlet: S_i(nx-1, y - c_iy) (ghost column); wrap: S_i at the periodic image.
+// Moving-wall term 2 w_i rho_w (c_i . u_w) / c_s^2 of a pull along c_i that bounces
+// back from the body at the half-way point (x - c_i/2, y - c_i/2) (binary64).
+__device__ __forceinline__ double body_wall_term(const BodyMotion& m, double rho_w6, int i,
+                                                 int x, int y) {
+  const double xw = x - 0.5 * kCx[i], yw = y - 0.5 * kCy[i];
+  const double uwx = m.ux - m.omega * (yw - m.yc);
+  const double uwy = m.uy + m.omega * (xw - m.xc);
+  return rho_w6 * weight<double>(i) * (kCx[i] * uwx + kCy[i] * uwy);
+}
+
 template <int P, class A>
 __device__ __forceinline__ void pull_all(const A& src, int pitch, int nx, int ny,
                                          const double* uin, double rho_w6, uint32_t w, int x,
-                                         int y, typename Storage<P>::C (&f)[kQ]) {
+                                         int y, typename Storage<P>::C (&f)[kQ],
+                                         const BodyMotion* __restrict__ motion = nullptr) {
   using S = Storage<P>;
   using C = typename S::C;
   const int32_t own = y * pitch + x;
@@ -274,6 +286,13 @@ __device__ __forceinline__ void pull_all(const A& src, int pitch, int nx, int ny
   for (int i = 0; i < kQ; ++i) {
     f[i] = unpack<P>(v[i]);
     if (i > 0 && kCx[i] != 0 && pull_code(w, i) == kInlet) f[i] += uw * (weight<C>(i) * C(kCx[i]));
+  }
+  // A body in rigid motion: the moving-wall rule on its links (additive, as the inlet).
+  if (motion) {
+    const BodyMotion m = *motion;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+      if (pull_code(w, i) == kBody) f[i] += C(body_wall_term(m, rho_w6, i, x, y));
   }
 }
 

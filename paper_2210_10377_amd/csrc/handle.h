@@ -15,13 +15,14 @@
 struct lbm_t {
   lbm_grid g;
   double tau = 0.0, omega = 0.0, rho_w = 1.0;
+  lbm::BodyMotion motion{0.0, 0.0, 0.0, 0.0, 0.0, 0};
   std::vector<double> uin;
   lbm::Plan plan;
   // device layout
   int32_t pitch = 0;
   int64_t plane = 0;  // elements
   size_t esz = 0;
-  size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_part = 0,
+  size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_motion = 0, off_part = 0,
          off_jpart = 0, off_ring = 0, total = 0;
   int njblocks = 0;
   // binding
@@ -57,6 +58,10 @@ struct lbm_t {
     return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u;
   }
   double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
+  // The body motion as the kernels read it (device), or null for a body at rest.
+  const lbm::BodyMotion* motion_dev() const {
+    return motion.moving ? reinterpret_cast<const lbm::BodyMotion*>(ws + off_motion) : nullptr;
+  }
   // Doubles of one step's force partials: general strips, then box-interior strips.
   size_t part_doubles() const {
     return size_t(plan.nslots) * lbm::kPart + size_t(plan.njslots) * 2;

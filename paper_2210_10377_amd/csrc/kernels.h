@@ -14,6 +14,14 @@ constexpr int kPart = 10;
 constexpr int kRingRow = 12;
 constexpr int kJnext = 10;
 
+// Rigid motion of the body: velocity U + Omega e_z x (x - c) at a point x.  Kernels read
+// it from device memory, and only on body links, through a pointer that is null for a
+// body at rest.
+struct BodyMotion {
+  double ux, uy, omega, xc, yc;
+  int32_t moving;
+};
+
 // Arguments of one fused time step.
 struct StepArgs {
   const void* src;  // post-collision state of the previous step (storage type)
@@ -32,6 +40,7 @@ struct StepArgs {
   const int32_t* strip_slot;   // per 64-node strip: force partial slot, or -1
   const double* uin;           // [ny] inlet velocity
   double rho_w6;               // 2 rho_w / c_s^2 = 6 rho_w
+  const BodyMotion* motion;    // body motion (device), or null for a body at rest
   double omega;                // 1 / tau_lb
   int32_t collision;           // LBM_COLL_*
   double* part_out;            // force partials of this step ([nslots][kPart] of the
@@ -54,6 +63,7 @@ struct BoxArgs {
   const uint32_t* node;
   const double* uin;
   double rho_w6;
+  const BodyMotion* motion;   // device, or null
   double* jpart;              // [blocks][2]
 };
 
@@ -74,6 +84,7 @@ struct BatchInst {
   double* ring;             // force rows of the current chunk [rows][kRingRow]
   BoxArgs box;              // control-volume sweep (src chosen per launch)
   int32_t njblocks;         // blocks of that sweep (0 without a box)
+  BodyMotion mot;           // the member's body motion; a.motion and box.motion point here
 };
 
 struct BatchLaunch {
@@ -87,6 +98,7 @@ struct BatchLaunch {
   int32_t total_tiles, total_box_blocks;
   int32_t grid_blocks;       // tile blocks per launch (0: one block per tile)
   int32_t collision;         // LBM_COLL_* of every instance
+  int32_t moving;            // some instance has a body in motion
 };
 
 hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_t s);

@@ -104,7 +104,7 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
 
 // General path of one lane's column of the tile: boundary rules from the pull codes,
 // and (when `forces`) the force sums of its nodes added to acc.
-template <int P, bool BUF, int COLL>
+template <int P, bool BUF, int COLL, bool MOV>
 __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, bool forces,
                                              double (&acc)[kPart]) {
   using S = Storage<P>;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
     if (w & kSolidBit) continue;
     const int32_t o = y * pitch + x;
     C f[kQ];
-    pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
+    pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, MOV ? a.motion : nullptr);
     C g[kQ];
     collide<C, S::kDev, COLL>(f, C(a.omega), g);
     T s[kQ];
@@ -133,16 +133,19 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
     if (forces) {
       // Momentum exchange on the links of this node (Sec. III; Eq. rtt4): the
       // population leaving along c_i towards the body is f_i before collision (A) or
-      // f~_i after it (B); the body returns f~_i (as stored) along -c_i.
+      // f~_i after it (B); the body returns f~_i (as stored) along -c_i, less the
+      // moving-wall term of that return when the body moves.
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
         if (pull_code(w, kOpp[i]) != kBody) continue;
         const double sv = to_f64<P>(s[i], i);
-        const double fa = (S::kDev ? weight<double>(i) + double(f[i]) : double(f[i])) + sv;
+        const double back =
+            (MOV && a.motion) ? sv + body_wall_term(*a.motion, a.rho_w6, kOpp[i], x, y) : sv;
+        const double fa = (S::kDev ? weight<double>(i) + double(f[i]) : double(f[i])) + back;
         acc[0] += kCx[i] * fa;
         acc[1] += kCy[i] * fa;
-        acc[2] += kCx[i] * (sv + sv);
-        acc[3] += kCy[i] * (sv + sv);
+        acc[2] += kCx[i] * (sv + back);
+        acc[3] += kCy[i] * (sv + back);
       }
       // Control volume (second Eq. rtt7): momentum before collision, and the
       // populations crossing the box surface after collision.
@@ -220,7 +223,7 @@ __device__ __forceinline__ void reduce_row(const double* red_in, int nslots, int
 }
 
 // One 256 x kTileH tile of a step.
-template <int P, bool BUF, bool FORCES, int COLL>
+template <int P, bool BUF, bool FORCES, int COLL, bool MOV>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
                                           const int32_t* __restrict__ strip_slot) {
   const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
@@ -260,11 +263,11 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
   const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
   // FA(x,y), FB(x,y), J(x,y), Phi(x,y), SI(x,y)
   double acc[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  general_rows<P, BUF, COLL>(a, tx, ty, slot >= 0, acc);
+  general_rows<P, BUF, COLL, MOV>(a, tx, ty, slot >= 0, acc);
   if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
 }
 
-template <int P, bool BUF, bool FORCES, int COLL>
+template <int P, bool BUF, bool FORCES, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
   int tile = block_tile(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
     }
     --tile;
   }
-  step_tile<P, BUF, FORCES, COLL>(a, tile, strip_slot);
+  step_tile<P, BUF, FORCES, COLL, MOV>(a, tile, strip_slot);
 }
 
 // Batched step: every instance of a batch advances one step in one launch.  The first
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
 // tile a block takes lies on the block's own XCD in the grouping of block_tile.
 // Step k of a launch sequence writes force row ctl[0] + k; ctl[1] counts the steps of
 // the same call enqueued before the sequence (their last row is still to be reduced).
-template <int P, bool FORCES, bool PERSIST, int COLL>
+template <int P, bool FORCES, bool PERSIST, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 8)))
 void batch_step_kernel(
     const BatchInst* __restrict__ inst, const int32_t* __restrict__ tile_inst,
@@ -312,7 +315,7 @@ void batch_step_kernel(
     a.src = I.buf[parity];
     a.dst = I.buf[1 - parity];
     a.part_out = I.part[k & 1];
-    step_tile<P, true, FORCES, COLL>(a, tile_local[t], a.strip_slot);
+    step_tile<P, true, FORCES, COLL, MOV>(a, tile_local[t], a.strip_slot);
   }
 }
 
@@ -339,7 +342,7 @@ __device__ __forceinline__ void box_block(const BoxArgs& a, int blk) {
     const uint32_t w = a.node[int64_t(y) * a.nx + x];
     if (!(w & kSolidBit)) {
       C f[kQ];
-      pull_all<P>(src, a.pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
+      pull_all<P>(src, a.pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, a.motion);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
         const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
@@ -424,13 +427,24 @@ __global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t 
 
 template <int P, bool BUF, int COLL>
 hipError_t step_dispatch3(bool forces, const StepArgs& a, hipStream_t s) {
-  const int grid = a.ntiles + (a.red_in ? 1 : 0);
-  if (forces)
-    hipLaunchKernelGGL((step_kernel<P, BUF, true, COLL>), dim3(grid), dim3(kThreads), 0, s, a,
-                       a.strip_slot);
-  else
-    hipLaunchKernelGGL((step_kernel<P, BUF, false, COLL>), dim3(grid), dim3(kThreads), 0, s, a,
-                       a.strip_slot);
+  const dim3 grid(a.ntiles + (a.red_in ? 1 : 0));
+  // Bodies in motion take their own instantiation, so the moving-wall arithmetic costs
+  // the resting case no registers.
+  if (forces) {
+    if (a.motion)
+      hipLaunchKernelGGL((step_kernel<P, BUF, true, COLL, true>), grid, dim3(kThreads), 0, s, a,
+                         a.strip_slot);
+    else
+      hipLaunchKernelGGL((step_kernel<P, BUF, true, COLL, false>), grid, dim3(kThreads), 0, s, a,
+                         a.strip_slot);
+  } else {
+    if (a.motion)
+      hipLaunchKernelGGL((step_kernel<P, BUF, false, COLL, true>), grid, dim3(kThreads), 0, s, a,
+                         a.strip_slot);
+    else
+      hipLaunchKernelGGL((step_kernel<P, BUF, false, COLL, false>), grid, dim3(kThreads), 0, s,
+                         a, a.strip_slot);
+  }
   return hipGetLastError();
 }
 
@@ -482,9 +496,14 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
   const bool persist = b.grid_blocks > 0 && b.grid_blocks < b.total_tiles;
   const int tiles = persist ? b.grid_blocks : b.total_tiles;
   const dim3 grid((forces ? b.nred : 0) + tiles);
-#define LBM_BATCH_GO3(P, F, R, K) \
-  hipLaunchKernelGGL((batch_step_kernel<P, F, R, K>), grid, dim3(kThreads), 0, s, b.inst, \
+#define LBM_BATCH_GO4(P, F, R, K, M) \
+  hipLaunchKernelGGL((batch_step_kernel<P, F, R, K, M>), grid, dim3(kThreads), 0, s, b.inst, \
                      b.tile_inst, b.tile_local, b, parity, k)
+#define LBM_BATCH_GO3(P, F, R, K)                        \
+  do {                                                   \
+    if (b.moving) LBM_BATCH_GO4(P, F, R, K, true);       \
+    else LBM_BATCH_GO4(P, F, R, K, false);               \
+  } while (0)
 #define LBM_BATCH_GO(P, F, R)                                                         \
   do {                                                                                \
     if (b.collision == LBM_COLL_REGULARIZED) LBM_BATCH_GO3(P, F, R, LBM_COLL_REGULARIZED); \
@@ -506,6 +525,7 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
 #undef LBM_BATCH_LAUNCH
 #undef LBM_BATCH_GO
 #undef LBM_BATCH_GO3
+#undef LBM_BATCH_GO4
   return hipGetLastError();
 }
 

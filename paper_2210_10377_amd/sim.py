@@ -163,6 +163,13 @@ class Sim:
     def set_tau(self, tau: float) -> None:
         C.check(self._lib.lbm_set_tau(self._h, float(tau)), self._h)
 
+    def set_body_motion(self, ux: float = 0.0, uy: float = 0.0, omega: float = 0.0,
+                        xc: float = 0.0, yc: float = 0.0) -> None:
+        """Rigid motion of the body: translation (ux, uy), rotation rate omega about
+        (xc, yc); the moving-wall rule on its links from the next step."""
+        C.check(self._lib.lbm_set_body_motion(self._h, float(ux), float(uy), float(omega),
+                                              float(xc), float(yc)), self._h)
+
     def reset(self) -> None:
         C.check(self._lib.lbm_reset(self._h), self._h)
 

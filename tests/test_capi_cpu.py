@@ -254,3 +254,25 @@ def test_collision_code_validation_and_adjoint_bgk_only(capi):
     rc = L.lbm_adjoint_forward(bgk._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
                                ctypes.byref(J))
     assert rc == capi.LBM_ESTATE
+
+
+def test_body_motion_validation_and_adjoint_refusal(capi):
+    """lbm_set_body_motion rejects non-finite values (unbound handle, no device call);
+    a handle with a body in motion is refused by the adjoint before touching the
+    device, and a zero motion is a body at rest again."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    mask = workloads.cylinder_mask(40, 20, 10, 9.5, 3)
+    p = Plan(mask, uin=0.05)
+    assert L.lbm_set_body_motion(p._h, float("nan"), 0.0, 0.0, 0.0, 0.0) == capi.LBM_EINVAL
+    assert b"finite" in L.lbm_last_error(p._h)
+    assert L.lbm_set_body_motion(p._h, 0.0, 0.0, float("inf"), 0.0, 0.0) == capi.LBM_EINVAL
+    assert L.lbm_set_body_motion(p._h, 0.01, 0.0, 0.002, 10.0, 9.5) == capi.LBM_OK
+    J = ctypes.c_double()
+    rc = L.lbm_adjoint_forward(p._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_EINVAL and b"rest" in L.lbm_last_error(p._h)
+    assert L.lbm_set_body_motion(p._h, 0.0, 0.0, 0.0, 10.0, 9.5) == capi.LBM_OK
+    rc = L.lbm_adjoint_forward(p._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_ESTATE

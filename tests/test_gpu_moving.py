@@ -1,0 +1,230 @@
+"""Bodies in rigid motion on the GPU path against the oracle.
+
+The body links take the moving-wall bounce-back of Sec. II with the rigid-body velocity
+at the half-way point of each link, and the momentum-exchange forces take the wall term
+into the returning population (Eq. rtt4/rtt5).  The oracle carries the same rule; these
+tests hold the HIP path to it: FP64 populations and forces within 1e-10, 32-bit storage
+within the bounds the body-at-rest runs meet.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import BCX_INLET_OUTLET, BCX_PERIODIC, BCY_PERIODIC, BCY_WALL, OracleSim
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32_FORCE = 1e-4
+TOL16_FORCE = 5e-2
+
+
+def _sim(**kw):
+    from paper_2210_10377_amd import Sim
+    return Sim(**kw)
+
+
+def _force_err(Fg, Fo, cols=(0, 1, 2, 3)):
+    out = []
+    for k in cols:
+        scale = np.abs(Fo[:, k]).max()
+        assert scale > 0
+        out.append(np.abs(Fg[:, k] - Fo[:, k]).max() / scale)
+    return np.array(out)
+
+
+def _pop_err(Sg, So, mask):
+    fl = mask == 0
+    return (np.abs(Sg - So)[:, fl] / np.abs(So)[:, fl]).max()
+
+
+def _inlet_mask(nx, ny):
+    m = np.zeros((ny, nx), np.uint8)
+    m[6:9, 0:2] = 1
+    m[13, 1] = 1
+    m[10:12, 70:73] = 1
+    return m
+
+
+def _seam_mask(nx, ny):
+    m = np.zeros((ny, nx), np.uint8)
+    m[7:10, nx - 2:nx] = 1
+    m[7:10, 0:2] = 1
+    return m
+
+
+CASES = {
+    # name: (nx, ny, bc_x, bc_y, mask builder, box, uin)
+    "periodic_x_walls_body": (48, 20, BCX_PERIODIC, BCY_WALL,
+                              lambda nx, ny: workloads.cylinder_mask(nx, ny, 20, 9.5, 4), (10, 32, 2, 18), None),
+    "channel_body_box": (70, 30, BCX_INLET_OUTLET, BCY_WALL,
+                         lambda nx, ny: workloads.cylinder_mask(nx, ny, 22, 14, 5), (12, 34, 5, 25), 0.04),
+    "channel_periodic_y": (64, 26, BCX_INLET_OUTLET, BCY_PERIODIC,
+                           lambda nx, ny: workloads.cylinder_mask(nx, ny, 30, 12.5, 4.5), (20, 41, 4, 22), 0.03),
+    "solid_touching_inlet": (90, 22, BCX_INLET_OUTLET, BCY_WALL, _inlet_mask, None, 0.04),
+    "periodic_x_body_on_seam": (70, 18, BCX_PERIODIC, BCY_WALL, _seam_mask, None, None),
+    "multi_tile_ragged": (600, 37, BCX_INLET_OUTLET, BCY_WALL,
+                          lambda nx, ny: workloads.cylinder_mask(nx, ny, 80, 18, 8), (60, 101, 6, 31), 0.05),
+}
+
+# (ux, uy, omega, offset of the centre of rotation from the centroid of the solid nodes)
+MOTIONS = {
+    "translation": (0.03, -0.02, 0.0, (0.0, 0.0)),
+    "rotation": (0.0, 0.0, 0.004, (1.5, -2.0)),
+    "both": (-0.01, 0.015, -0.003, (-2.5, 0.5)),
+}
+
+
+def _motion(mask, name):
+    """The motion `name` for a body mask: the rotation rate is capped so that no solid
+    node turns faster than 0.03 (a wall speed far below c_s, as every stable run needs)."""
+    ux, uy, om, (dx, dy) = MOTIONS[name]
+    yc, xc = np.argwhere(mask).mean(axis=0) + (dy, dx)
+    ys, xs = np.nonzero(mask)
+    r = np.hypot(xs - xc, ys - yc).max()
+    om = np.sign(om) * min(abs(om), 0.03 / r)
+    return (ux, uy, om, xc, yc)
+
+
+@pytest.mark.parametrize("motion", list(MOTIONS))
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_moving_body_small_cases(name, motion):
+    """Every boundary rule beside a body in translation, rotation or both, from a
+    seeded random near-rest state, 60 steps, FP64: populations and every force to 1e-10
+    of the oracle with the same motion."""
+    nx, ny, bcx, bcy, mk, box, u = CASES[name]
+    mask = mk(nx, ny)
+    uin = None if bcx == BCX_PERIODIC else np.linspace(0.5, 1.0, ny) * u
+    mo = _motion(mask, motion)
+    S0 = workloads.near_rest_state(nx, ny, seed=11 + len(name), amp=0.05)
+    o = OracleSim(mask, tau=0.7, uin=uin, bc_x=bcx, bc_y=bcy, box=box, body_motion=mo)
+    o.set_state(S0)
+    o.step(60)
+    g = _sim(mask=mask, tau=0.7, uin=uin, precision="fp64", bc_x=bcx, bc_y=bcy, box=box,
+             max_record=100)
+    g.set_body_motion(*mo)
+    g.set_populations(S0)
+    g.step(60)
+    Fg, Fo = g.forces(), o.forces()
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    cols = (0, 1, 2, 3) if box is not None else (0, 1, 3)
+    e = _force_err(Fg, Fo, cols)
+    assert np.all(e <= TOL64), e
+
+
+@pytest.fixture(scope="module")
+def rotating_reference():
+    """Oracle run of the 200x80 cylinder channel (Re 20) with the cylinder turning
+    counter-clockwise about its centre at a surface speed of half the inlet speed,
+    3000 steps from rest."""
+    w = workloads.cylinder_channel_200x80()
+    mo = (0.0, 0.0, 0.5 * w.u_ref / (w.l_ref / 2), 40.0, 40.0)
+    o = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, body_motion=mo)
+    o.step(3000)
+    return w, mo, o.state(), o.forces()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32dev", "fp16dev"])
+def test_rotating_cylinder_channel(precision, rotating_reference):
+    """The rotating cylinder: FP64 populations and forces to 1e-10 of the oracle, 32-bit
+    storage forces to 1e-4 (relative to the largest force of the run), FP16 deviation
+    storage to 5e-2; the lift is negative (Magnus) on every estimator."""
+    w, mo, So, Fo = rotating_reference
+    g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision=precision, box=w.box,
+             max_record=1000)
+    g.set_body_motion(*mo)
+    Fg = g.run(3000)
+    assert np.isfinite(Fg).all()
+    e = _force_err(Fg, Fo)
+    print(precision, "rotating cylinder force errors (A, B, DRTT, SI):", e)
+    tol = {"fp64": TOL64, "fp32": TOL32_FORCE, "fp32dev": TOL32_FORCE,
+           "fp16dev": TOL16_FORCE}[precision]
+    assert np.all(e <= tol), e
+    if precision == "fp64":
+        assert _pop_err(g.populations(), So, w.mask) <= TOL64
+    assert np.all(Fg[-500:, :, 1].mean(axis=0) < 0)
+
+
+def test_comoving_uniform_flow_is_a_fixed_point():
+    """A body translating with a uniform flow: the GPU keeps the equilibrium state to
+    rounding and every momentum-exchange and stress estimator reads no force."""
+    nx, ny = 40, 30
+    mask = workloads.cylinder_mask(nx, ny, 19.5, 14.5, 6.0)
+    U = (0.04, -0.02)
+    feq = oracle.equilibrium(1.0, *U)
+    S0 = np.repeat(np.repeat(feq[:, None, None], ny, 1), nx, 2)
+    g = _sim(mask=mask, tau=0.7, precision="fp64", bc_x=BCX_PERIODIC, bc_y=BCY_PERIODIC,
+             box=(6, 34, 4, 26), max_record=20)
+    g.set_body_motion(U[0], U[1], 0.0, 0.0, 0.0)
+    g.set_populations(S0)
+    g.step(10)
+    fl = mask == 0
+    np.testing.assert_allclose(g.populations()[:, fl], S0[:, fl], rtol=0, atol=1e-14)
+    F = g.forces()
+    assert np.abs(F[:, [0, 1, 3]]).max() <= 1e-14
+    assert np.abs(F[:, 2]).max() <= 1e-12
+
+
+def test_zero_motion_is_the_resting_body_bitwise():
+    """Setting the motion to zero (after a non-zero one) gives the resting-body path:
+    populations and forces bitwise those of a simulation that never set a motion."""
+    w = workloads.cylinder_channel_200x80()
+    runs = []
+    for mo in (None, (0.01, 0.0, 0.002, 40.0, 40.0)):
+        g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision="fp32", box=w.box,
+                 max_record=200)
+        if mo is not None:
+            g.set_body_motion(*mo)
+            g.set_body_motion()
+        g.step(200)
+        runs.append((g.populations(), g.forces()))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+def test_motion_change_between_calls():
+    """The motion set between two step calls applies from the next step: two calls
+    with different rotation rates against the oracle stepped the same way (FP64)."""
+    w = workloads.cylinder_channel_200x80()
+    g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision="fp64", box=w.box, max_record=400)
+    S = None
+    F = []
+    for om in (0.002, -0.003):
+        mo = (0.0, 0.0, om, 40.0, 40.0)
+        o = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, body_motion=mo)
+        if S is not None:
+            o.set_state(S)
+        o.step(150)
+        S = o.state()
+        F.append(o.forces())
+        g.set_body_motion(*mo)
+        g.step(150)
+    Fo = np.concatenate(F)
+    Fg = g.forces()
+    assert _pop_err(g.populations(), S, w.mask) <= TOL64
+    e = _force_err(Fg, Fo)
+    assert np.all(e <= TOL64), e
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pitching_naca_full_size_two_steps(precision):
+    """The 2048x1024 NACA0012 channel in the benchmark's launch configuration with the
+    airfoil turning about its quarter chord and translating, from a seeded random state:
+    every fluid population and force row of two steps against the oracle."""
+    w = workloads.naca_2048x1024()
+    mo = (0.01, -0.005, 2e-4, float(w.meta["xq"]), float(w.meta["yq"]))
+    dt = np.float32 if precision == "fp32" else np.float64
+    S0 = workloads.near_rest_state(w.nx, w.ny, seed=91, amp=0.02, dtype=dt)
+    g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision=precision, box=w.box, max_record=4)
+    g.set_body_motion(*mo)
+    g.set_populations(S0)
+    g.step(2)
+    o = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, body_motion=mo)
+    o.set_state(S0)
+    o.step(2)
+    err = _pop_err(g.populations(), o.state(), w.mask)
+    assert err <= {"fp64": 1e-10, "fp32": 2e-6}[precision], err
+    e = _force_err(g.forces(), o.forces())
+    tol = {"fp64": np.array([1e-10] * 4), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3])}[precision]
+    assert np.all(e <= tol), e
