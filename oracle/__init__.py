@@ -73,6 +73,9 @@ def lib():
         L.orc_nrec.argtypes = [ctypes.c_void_p]
         L.orc_nrec.restype = ctypes.c_int64
         L.orc_clear_records.argtypes = [ctypes.c_void_p]
+        L.orc_set_mask.argtypes = [ctypes.c_void_p, u8, ctypes.POINTER(ctypes.c_int32), dp]
+        L.orc_set_mask.restype = ctypes.c_int
+        L.orc_set_body_motion.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 5
         L.orc_momentum_of.argtypes = [ctypes.c_void_p, dp, dp]
         L.orc_objective_cs.argtypes = [cp, u8, ctypes.c_double, ctypes.c_double, dp, dp,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -229,6 +232,30 @@ class OracleSim:
 
     def clear_records(self):
         lib().orc_clear_records(self._h)
+
+    def set_mask(self, mask, box=None):
+        """Move the body: a new mask (and control volume, if given) from the next step.
+        Uncovered nodes are refilled with f^eq(mean neighbour density, wall velocity);
+        returns the impulse handed from the fluid to the body, (2,)."""
+        m, mp = _mask(mask)
+        if m.shape != (self.ny, self.nx):
+            raise ValueError("mask shape differs from the lattice")
+        bp = None
+        if box is not None:
+            self._box_arr = (ctypes.c_int32 * 4)(*[int(v) for v in box])
+            bp = ctypes.cast(self._box_arr, ctypes.POINTER(ctypes.c_int32))
+        imp = np.zeros(2)
+        if lib().orc_set_mask(self._h, mp, bp, _dp(imp)) != 0:
+            raise ValueError("mask or control volume not admissible")
+        self._mask_keep = m
+        if box is not None:
+            self.box = tuple(int(v) for v in box)
+        return imp
+
+    def set_body_motion(self, ux=0.0, uy=0.0, omega=0.0, xc=0.0, yc=0.0):
+        """Rigid motion of the body from the next step."""
+        lib().orc_set_body_motion(self._h, float(ux), float(uy), float(omega), float(xc),
+                                  float(yc))
 
     def momentum_of(self, g):
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.shape)

@@ -240,6 +240,10 @@ struct Sim {
   std::vector<T> f;   // pulled (pre-collision) populations of the last step
   std::vector<T> Sn;  // scratch for the next state
   std::vector<T> rec;  // [t][NREC]
+  // Records whose J(t+1) was fixed when the geometry changed after them: the record
+  // index and the control-volume momentum of the pull that followed under the old mask.
+  std::vector<size_t> jfix_t;
+  std::vector<T> jfix;  // [k][2]
 
   int nx() const { return cfg.nx; }
   int ny() const { return cfg.ny; }
@@ -434,7 +438,7 @@ struct Sim {
   void forces(T* out) const {
     const size_t n = rec.size() / NREC;
     T Jlast[2] = {0.0, 0.0};
-    if (cfg.box[0] >= 0) {
+    if (cfg.box[0] >= 0 && n > 0) {
       std::vector<T> g(S.size(), T(0.0));
       stream_all(S, g);
       box_momentum(g, Jlast);
@@ -449,6 +453,11 @@ struct Sim {
       if (cfg.box[0] >= 0) {
         T jx1 = (t + 1 < n) ? rec[NREC * (t + 1) + 4] : Jlast[0];
         T jy1 = (t + 1 < n) ? rec[NREC * (t + 1) + 5] : Jlast[1];
+        for (size_t k = 0; k < jfix_t.size(); ++k)
+          if (jfix_t[k] == t) {
+            jx1 = jfix[2 * k];
+            jy1 = jfix[2 * k + 1];
+          }
         o[4] = r[4] - jx1 + r[6];
         o[5] = r[5] - jy1 + r[7];
       } else {
@@ -507,6 +516,90 @@ Sim<T>* make_sim(const Config* c, const uint8_t* mask, T omega) {
   s->f = s->S;
   s->Sn = s->S;
   return s;
+}
+
+// A body that moves through the grid: replace the mask (and optionally the control
+// volume) between two steps.  Every recorded step keeps the geometry it was taken with:
+// the J(t+1) of the last recorded step is fixed now, from the pull of the present state
+// under the old mask and box, so the momentum that changes hands with the nodes the body
+// covers or uncovers enters no estimator.  Nodes the body uncovers (solid before, fluid
+// now) are refilled with the equilibrium at the local wall velocity u_w (the rigid-body
+// velocity at the node) and the mean density of their lattice neighbours that are fluid
+// in both masks (rho_w when there is none); a neighbour across a periodic edge wraps, one
+// outside a non-periodic edge does not count.  impulse = momentum of the covered nodes
+// minus that of the refilled ones, i.e. what the fluid hands to the body in the change.
+// Returns -1 (nothing changed) when the mask or box is not admissible.
+template <class T>
+int set_mask(Sim<T>& s, const uint8_t* mask, const int32_t* box, T* impulse) {
+  Config c = s.cfg;
+  if (box) {
+    if ((box[0] >= 0) != (c.box[0] >= 0)) return -1;  // a control volume stays one
+    for (int k = 0; k < 4; ++k) c.box[k] = box[k];
+  }
+  if (!config_valid(c, mask)) return -1;
+  const int nx = c.nx, ny = c.ny;
+  const size_t n = size_t(nx) * ny;
+  const size_t nrec = s.rec.size() / NREC;
+  if (s.cfg.box[0] >= 0 && nrec > 0) {
+    std::vector<T> g(s.S.size(), T(0.0));
+    s.stream_all(s.S, g);
+    T J[2];
+    s.box_momentum(g, J);
+    s.jfix_t.push_back(nrec - 1);
+    s.jfix.push_back(J[0]);
+    s.jfix.push_back(J[1]);
+  }
+  const std::vector<uint8_t> old = s.solid;
+  auto fluid_both = [&](int x, int y) {
+    const size_t k = size_t(y) * nx + x;
+    return old[k] == 0 && mask[k] == 0;
+  };
+  T P[2] = {0.0, 0.0};
+  std::vector<T> fresh(NQ * n, T(0.0));
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const size_t k = size_t(y) * nx + x;
+      if (old[k] == 0 && mask[k] != 0) {  // covered: its momentum goes to the body
+        for (int i = 0; i < NQ; ++i) {
+          P[0] += double(CX[i]) * s.S[s.idx(i, x, y)];
+          P[1] += double(CY[i]) * s.S[s.idx(i, x, y)];
+        }
+      } else if (old[k] != 0 && mask[k] == 0) {  // uncovered: refill
+        T rsum = 0.0;
+        int cnt = 0;
+        for (int i = 1; i < NQ; ++i) {
+          int ax = x + CX[i], ay = y + CY[i];
+          if (c.bc_x == BCX_PERIODIC) ax = (ax + nx) % nx;
+          if (c.bc_y == BCY_PERIODIC) ay = (ay + ny) % ny;
+          if (ax < 0 || ax >= nx || ay < 0 || ay >= ny || !fluid_both(ax, ay)) continue;
+          T r = 0.0;
+          for (int j = 0; j < NQ; ++j) r += s.S[s.idx(j, ax, ay)];
+          rsum += r;
+          ++cnt;
+        }
+        const T rho = cnt > 0 ? rsum / double(cnt) : T(c.rho_w);
+        const T ux = c.body_u[0] - c.body_omega * (double(y) - c.body_c[1]);
+        const T uy = c.body_u[1] + c.body_omega * (double(x) - c.body_c[0]);
+        for (int i = 0; i < NQ; ++i) fresh[s.idx(i, x, y)] = equilibrium<T>(i, rho, ux, uy);
+      }
+    }
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const size_t k = size_t(y) * nx + x;
+      if (old[k] != 0 && mask[k] == 0)
+        for (int i = 0; i < NQ; ++i) {
+          s.S[s.idx(i, x, y)] = fresh[s.idx(i, x, y)];
+          P[0] -= double(CX[i]) * fresh[s.idx(i, x, y)];
+          P[1] -= double(CY[i]) * fresh[s.idx(i, x, y)];
+        }
+    }
+  s.solid.assign(mask, mask + n);
+  s.cfg = c;
+  if (impulse) {
+    impulse[0] = P[0];
+    impulse[1] = P[1];
+  }
+  return 0;
 }
 
 }  // namespace
@@ -609,7 +702,27 @@ void orc_records(void* h, double* out) {
 // Forces [t][A, B, DRTT, SI][x, y] of all recorded steps.
 void orc_forces(void* h, double* out) { static_cast<Sim<double>*>(h)->forces(out); }
 
-void orc_clear_records(void* h) { static_cast<Sim<double>*>(h)->rec.clear(); }
+void orc_clear_records(void* h) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  s->rec.clear();
+  s->jfix_t.clear();
+  s->jfix.clear();
+}
+
+// Replace the body mask, and the control volume when box is non-null (see set_mask).
+int orc_set_mask(void* h, const uint8_t* mask, const int32_t* box, double* impulse) {
+  return set_mask(*static_cast<Sim<double>*>(h), mask, box, impulse);
+}
+
+// Replace the rigid-body motion (translation, rotation rate, centre of rotation).
+void orc_set_body_motion(void* h, double ux, double uy, double omega, double xc, double yc) {
+  Config& c = static_cast<Sim<double>*>(h)->cfg;
+  c.body_u[0] = ux;
+  c.body_u[1] = uy;
+  c.body_omega = omega;
+  c.body_c[0] = xc;
+  c.body_c[1] = yc;
+}
 
 // Time-averaged momentum-exchange force of algorithm B,
 //   J = (1/T) sum_{t=t0}^{t0+T-1} (wx F_Bx(t) + wy F_By(t)),
