@@ -53,11 +53,12 @@ def measured_traffic(workload: str, precision: str):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(w, steps: int, collision: str = "bgk"):
+def cpu_baseline(w, steps: int, collision: str = "bgk", body_motion=None):
     """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
     `steps` full-grid time steps with all four forces."""
     import oracle
-    o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision)
+    o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision,
+                         body_motion=body_motion)
     t0 = time.perf_counter()
     o.step(steps)
     o.forces()
@@ -316,6 +317,10 @@ def main():
     ap.add_argument("--aoa", type=float, default=4.0)
     ap.add_argument("--schemes", default="A,B,DRTT,SI")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "regularized", "kbc"])
+    ap.add_argument("--pitch-rate", type=float, default=0.0,
+                    help="turn the body at this rate (radians per step, counter-clockwise) "
+                         "about its quarter chord (the centroid of a cylinder): the "
+                         "moving-wall rule on every body link")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
@@ -392,6 +397,14 @@ def main():
     sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box,
               max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
               device=dev, stream=stream, collision=args.collision)
+    motion = None
+    if args.pitch_rate:
+        if "xq" in w.meta:
+            xc, yc = float(w.meta["xq"]), float(w.meta["yq"])
+        else:
+            yc, xc = (float(v) for v in np.argwhere(w.mask).mean(axis=0))
+        motion = (0.0, 0.0, args.pitch_rate, xc, yc)
+        sim.set_body_motion(*motion)
     info = sim.info()
     sim.step(W, schemes)
     sim.forces()
@@ -440,7 +453,9 @@ def main():
                    "storage": args.precision, "collision": args.collision,
                    "schemes": list(schemes),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
-                   "box_nodes": int(info.n_box), **{k: v for k, v in w.meta.items()}},
+                   "box_nodes": int(info.n_box), **{k: v for k, v in w.meta.items()},
+                   **({"body_motion": {"omega": motion[2], "xc": motion[3], "yc": motion[4]}}
+                      if motion else {})},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
@@ -456,7 +471,7 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.collision)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.collision, motion)
     print(json.dumps(out), flush=True)
 
 

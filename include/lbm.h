@@ -238,6 +238,30 @@ int lbm_set_tau(lbm_t* h, double tau);
  * the adjoint calls refuse a moving body.  LBM_EINVAL for non-finite values. */
 int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc, double yc);
 
+/* A body that moves through the grid (not in the paper's runs; the bounce-back of
+ * Sec. II on the links of each mask): replace the body mask, and the control volume
+ * when `box` is non-null ([x0, x1, y0, y1] as in lbm_grid; it can be moved or resized,
+ * not added or removed), between two steps.  solid_mask: host, [ny][nx] bytes, 0 fluid
+ * / 1 solid, copied.  Every recorded step keeps the geometry it was taken with (the
+ * J(t+1) of the last step before the change was taken under the old mask and box), so
+ * the momentum that changes hands with the nodes the body covers or uncovers enters no
+ * estimator; it is returned instead in impulse[2] (host, may be NULL): the momentum of
+ * the covered nodes minus that of the refilled ones, i.e. what the fluid hands to the
+ * body in the change.  Nodes the body uncovers are refilled with the equilibrium at the
+ * rigid-body velocity of lbm_set_body_motion at the node and the mean density of their
+ * lattice neighbours that are fluid in both masks (rho_w of the inlet when none is; a
+ * neighbour across a periodic edge wraps, one outside another edge does not count).
+ * The motion's centre is not advanced by the library: a translating and turning body
+ * sets its new centre with lbm_set_body_motion at each change.  Bound handles: waits
+ * for the whole device first (no step of the handle, or of a batch holding it, may
+ * still be in flight), uses the idle state buffer as scratch, synchronises the stream.
+ * LBM_EINVAL: mask values other than 0/1, a box that is not admissible for the new
+ * mask; LBM_ENOMEM: the new mask needs more force-partial slots than twice those of
+ * the mask at create (plus 4096 doubles), or a larger box than the one at create.  On
+ * these errors nothing changes.  On LBM_EHIP the state is undefined.  The adjoint
+ * forward run held by the handle is discarded. */
+int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double* impulse);
+
 /* Put every node back in the rest state w_i, zero the step counter and empty the force
  * ring.  Synchronises the stream. */
 int lbm_reset(lbm_t* h);

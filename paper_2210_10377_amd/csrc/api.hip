@@ -127,11 +127,15 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   off = align256(off + size_t(g.ny) * sizeof(double));
   h->off_motion = off;
   off = align256(off + sizeof(BodyMotion));
+  // Force partials of two steps, with room for masks that need up to twice the slots
+  // of this one (plus 4096 doubles): a body moving through the grid keeps the layout.
+  h->part_cap = 2 * h->part_doubles() + 4096;
   h->off_part = off;
-  off = align256(off + 2 * h->part_doubles() * sizeof(double));
+  off = align256(off + 2 * h->part_cap * sizeof(double));
   h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
+  h->jcap = h->njblocks;
   h->off_jpart = off;
-  off = align256(off + size_t(h->njblocks) * 2 * sizeof(double));
+  off = align256(off + size_t(h->jcap) * 2 * sizeof(double));
   h->off_ring = off;
   off = align256(off + size_t(g.max_record) * kRow * sizeof(double));
   h->total = off;
@@ -560,6 +564,92 @@ int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc,
                                   hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "upload body motion");
+  }
+  return LBM_OK;
+}
+
+int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double* impulse) {
+  if (!h || !solid_mask) return LBM_EINVAL;
+  lbm_grid g = h->g;
+  if (box) {
+    if ((box[0] >= 0) != (g.box[0] >= 0))
+      return h->fail(LBM_EINVAL, "a control volume can be moved, not added or removed");
+    for (int k = 0; k < 4; ++k) g.box[k] = box[k];
+  }
+  Plan np;
+  std::string perr;
+  const int rc = build_plan(g, solid_mask, np, perr);
+  if (rc != LBM_OK) return h->fail(rc, perr);
+  if (size_t(np.nslots) * kPart + size_t(np.njslots) * 2 > h->part_cap)
+    return h->fail(LBM_ENOMEM, "the new mask needs more force-partial slots than reserved "
+                               "at create; create a handle for it");
+  const int nj = np.has_box ? np.box_bx * np.box_rows : 0;
+  if (nj > h->jcap)
+    return h->fail(LBM_ENOMEM, "the new control volume is larger than the one at create");
+  double P[2] = {0.0, 0.0};
+  if (h->bound) {
+    const int nx = g.nx, ny = g.ny;
+    const size_t n = size_t(nx) * ny;
+    std::vector<uint8_t> valid(n);
+    std::vector<int32_t> list;
+    for (size_t k = 0; k < n; ++k) {
+      const bool was = (h->plan.node[k] & kSolidBit) != 0, is = solid_mask[k] != 0;
+      valid[k] = (!was && !is) ? 1 : 0;
+      if (was != is) list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
+    }
+    // Scratch in the other state buffer, which the next step overwrites anyway.
+    const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
+    const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
+                 off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 16);
+    if (off_res + 16 > size_t(h->plane) * kQ * h->esz)
+      return h->fail(LBM_ENOMEM, "too many nodes change at once");
+    // Nothing in flight (on any stream, a batch holding the handle included) may still
+    // read the old node codes or the state.
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return h->hip_fail(e, "mask synchronize");
+    char* scr = static_cast<char*>(h->buf(1 - h->cur));
+    if (!list.empty()) {
+      e = hipMemcpyAsync(scr, valid.data(), n, hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(scr + off_list, list.data(), list.size() * 4, hipMemcpyHostToDevice,
+                           h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "upload mask change");
+      RemaskArgs a{};
+      a.state = h->buf(h->cur);
+      a.plane = h->plane;
+      a.pitch = h->pitch;
+      a.nx = nx;
+      a.ny = ny;
+      a.bc_x = g.bc_x;
+      a.bc_y = g.bc_y;
+      a.list = reinterpret_cast<const int32_t*>(scr + off_list);
+      a.n = int32_t(list.size());
+      a.valid = reinterpret_cast<const uint8_t*>(scr);
+      a.rho_w = h->rho_w;
+      a.motion = h->motion;
+      a.block_out = reinterpret_cast<double*>(scr + off_blk);
+      double* res = reinterpret_cast<double*>(scr + off_res);
+      e = launch_remask(g.precision, a, blocks, res, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "launch remask");
+      e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "download impulse");
+    }
+    e = hipMemcpyAsync(h->ws + h->off_node, np.node.data(), np.node.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->ws + h->off_tiles, np.strip_slot.data(),
+                         np.strip_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "upload plan");
+  }
+  h->plan = std::move(np);
+  h->g = g;
+  h->njblocks = nj;
+  h->adj_valid = false;
+  if (impulse) {
+    impulse[0] = P[0];
+    impulse[1] = P[1];
   }
   return LBM_OK;
 }

@@ -45,6 +45,7 @@ struct lbm_batch_t {
   int precision = 0;
   int64_t total_tiles = 0, total_box = 0, total_fluid = 0, total_nodes = 0;
   std::vector<int32_t> tile_inst, tile_local, box_inst, box_local;
+  std::vector<int> nj0;  // box-sweep blocks of each member at create (the lists' sizes)
   std::vector<BatchInst> desc;  // the instance table as last uploaded
   size_t off_desc = 0, off_ti = 0, off_tl = 0, off_bi = 0, off_bl = 0, off_ctl = 0,
          off_ring = 0, total = 0;
@@ -77,6 +78,14 @@ struct lbm_batch_t {
   }
 
   // Tile and box-sweep lists: instance-major, the tile list optionally shuffled.
+  // A member's box sweep may not change size after create (lbm_set_mask with a resized
+  // box): the lists and their workspace are sized for the sizes at create.
+  bool sizes_kept() const {
+    for (size_t i = 0; i < m.size(); ++i)
+      if (m[i]->njblocks != nj0[i]) return false;
+    return true;
+  }
+
   void build_lists() {
     tile_inst.clear();
     tile_local.clear();
@@ -177,6 +186,8 @@ struct lbm_batch_t {
   int refresh() {
     for (const lbm_t* h : m)
       if (!h->bound) return fail(LBM_ESTATE, "a member is no longer bound");
+    if (!sizes_kept())
+      return fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
     std::vector<BatchInst> d = make_desc();
     if (d.size() == desc.size() &&
         std::memcmp(d.data(), desc.data(), d.size() * sizeof(BatchInst)) == 0)
@@ -311,6 +322,7 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
   for (const lbm_t* h : m) {
     b->total_tiles += h->plan.ntiles;
     b->total_box += h->njblocks;
+    b->nj0.push_back(h->njblocks);
     b->total_fluid += h->plan.n_fluid;
     b->total_nodes += int64_t(h->plan.nx) * h->plan.ny;
   }
@@ -379,6 +391,8 @@ int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s) {
   if (s->grid_blocks < 0 || s->graph_steps < 0 || (s->graph_steps & 1))
     return b->fail(LBM_EINVAL, "grid_blocks and graph_steps must be >= 0, graph_steps even");
   const bool reorder = s->tile_order != b->sched.tile_order;
+  if (reorder && !b->sizes_kept())
+    return b->fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
   b->drop_graphs();
   b->sched = *s;
   if (reorder) {

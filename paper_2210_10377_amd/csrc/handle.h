@@ -25,6 +25,10 @@ struct lbm_t {
   size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_motion = 0, off_part = 0,
          off_jpart = 0, off_ring = 0, total = 0;
   int njblocks = 0;
+  // Reserved at create so that a new mask (a body moving through the grid) fits the
+  // same layout: doubles of one step's force partials, blocks of the box sweep.
+  size_t part_cap = 0;
+  int jcap = 0;
   // binding
   char* ws = nullptr;
   hipStream_t stream = nullptr;
@@ -67,7 +71,7 @@ struct lbm_t {
     return size_t(plan.nslots) * lbm::kPart + size_t(plan.njslots) * 2;
   }
   double* part(int k) const {
-    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_doubles();
+    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_cap;
   }
 };
 

@@ -101,7 +101,24 @@ struct BatchLaunch {
   int32_t moving;            // some instance has a body in motion
 };
 
+// A mask change of a body moving through the grid, over the current state buffer.
+struct RemaskArgs {
+  void* state;            // current state buffer (stored populations)
+  int64_t plane;          // elements per direction plane
+  int32_t pitch, nx, ny, bc_x, bc_y;
+  const int32_t* list;    // [n] y * nx + x; bit 31 set: uncovered (refill), clear: covered
+  int32_t n;
+  const uint8_t* valid;   // [ny * nx] 1 where the node is fluid in both masks
+  double rho_w;           // density of a refilled node without valid neighbours
+  BodyMotion motion;      // wall velocity of the refilled nodes (all zero at rest)
+  double* block_out;      // [blocks][2] covered minus refilled momentum of each block
+};
+
 hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_t s);
+// Refill the uncovered nodes and sum, in a fixed order, the momentum of the covered
+// ones minus that of the refilled ones into out[2] (block_out as scratch).
+hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double* out,
+                         hipStream_t s);
 hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, int32_t parity,
                              int32_t k, hipStream_t s);
 hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s);

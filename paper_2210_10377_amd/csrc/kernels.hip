@@ -425,6 +425,82 @@ __global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t 
   }
 }
 
+// Mask change: one thread per listed node.  A covered node contributes its momentum; an
+// uncovered one is refilled with f^eq(rho, u_w), rho the mean density of its lattice
+// neighbours that are fluid in both masks (periodic edges wrap, other edges do not
+// count; rho_w when none is) and u_w the rigid-body velocity at the node, and
+// contributes minus the momentum it now stores.  Refills read valid neighbours only, so
+// no thread reads what another writes.
+template <int P>
+__global__ __launch_bounds__(kThreads) void remask_kernel(RemaskArgs a) {
+  using S = Storage<P>;
+  using T = typename S::T;
+  using C = typename S::C;
+  T* st = static_cast<T*>(a.state);
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < a.n;
+       k += int64_t(gridDim.x) * kThreads) {
+    const uint32_t e = uint32_t(a.list[k]);
+    const int32_t node = int32_t(e & 0x7fffffffu);
+    const int y = node / a.nx, x = node - y * a.nx;
+    const int64_t at = int64_t(y) * a.pitch + x;
+    if (!(e >> 31)) {
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        const double f = to_f64<P>(st[i * a.plane + at], i);
+        v[0] += kCx[i] * f;
+        v[1] += kCy[i] * f;
+      }
+      continue;
+    }
+    double rsum = 0.0;
+    int cnt = 0;
+    for (int i = 1; i < kQ; ++i) {
+      int ax = x + kCx[i], ay = y + kCy[i];
+      if (a.bc_x == LBM_BCX_PERIODIC) ax = (ax + a.nx) % a.nx;
+      if (a.bc_y == LBM_BCY_PERIODIC) ay = (ay + a.ny) % a.ny;
+      if (ax < 0 || ax >= a.nx || ay < 0 || ay >= a.ny || !a.valid[int64_t(ay) * a.nx + ax])
+        continue;
+      const int64_t nb = int64_t(ay) * a.pitch + ax;
+      double r = 0.0;
+      for (int j = 0; j < kQ; ++j) r += to_f64<P>(st[j * a.plane + nb], j);
+      rsum += r;
+      ++cnt;
+    }
+    const double rho = cnt > 0 ? rsum / double(cnt) : a.rho_w;
+    const double ux = a.motion.ux - a.motion.omega * (double(y) - a.motion.yc);
+    const double uy = a.motion.uy + a.motion.omega * (double(x) - a.motion.xc);
+    const double uu = ux * ux + uy * uy;
+    for (int i = 0; i < kQ; ++i) {
+      const double cu = kCx[i] * ux + kCy[i] * uy;
+      const double feq = weight<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      const T q = pack<P>(C(S::kDev ? feq - weight<double>(i) : feq));
+      st[i * a.plane + at] = q;
+      const double f = to_f64<P>(q, i);
+      v[0] -= kCx[i] * f;
+      v[1] -= kCy[i] * f;
+    }
+  }
+  __shared__ double out[8];
+  block_sum8(v, out);
+  __syncthreads();
+  if (threadIdx.x < 2) a.block_out[2 * blockIdx.x + threadIdx.x] = out[threadIdx.x];
+}
+
+// Sum of the per-block momenta in a fixed order (one block).
+__global__ __launch_bounds__(kThreads) void remask_sum_kernel(const double* block_out, int nb,
+                                                              double* res) {
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    v[0] += block_out[2 * b];
+    v[1] += block_out[2 * b + 1];
+  }
+  __shared__ double out[8];
+  block_sum8(v, out);
+  __syncthreads();
+  if (threadIdx.x < 2) res[threadIdx.x] = out[threadIdx.x];
+}
+
 template <int P, bool BUF, int COLL>
 hipError_t step_dispatch3(bool forces, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.ntiles + (a.red_in ? 1 : 0));
@@ -561,6 +637,28 @@ hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity
 
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double* out,
+                         hipStream_t s) {
+  switch (precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(remask_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32:
+      hipLaunchKernelGGL(remask_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32DEV:
+      hipLaunchKernelGGL(remask_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(remask_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(remask_sum_kernel, dim3(1), dim3(kThreads), 0, s,
+                     static_cast<const double*>(a.block_out), blocks, out);
   return hipGetLastError();
 }
 

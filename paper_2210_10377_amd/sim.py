@@ -170,6 +170,23 @@ class Sim:
         C.check(self._lib.lbm_set_body_motion(self._h, float(ux), float(uy), float(omega),
                                               float(xc), float(yc)), self._h)
 
+    def set_mask(self, mask, box=None) -> np.ndarray:
+        """Move the body through the grid: a new mask (and control volume, if given)
+        from the next step.  Uncovered nodes are refilled at the wall velocity; returns
+        the impulse (2,) the fluid hands to the body in the change."""
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.shape != (self.ny, self.nx):
+            raise ValueError("mask shape differs from the lattice")
+        bp = None
+        if box is not None:
+            barr = (ctypes.c_int32 * 4)(*[int(v) for v in box])
+            bp = ctypes.cast(barr, ctypes.POINTER(ctypes.c_int32))
+        imp = np.zeros(2)
+        C.check(self._lib.lbm_set_mask(self._h, mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                       bp, imp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                self._h)
+        return imp
+
     def reset(self) -> None:
         C.check(self._lib.lbm_reset(self._h), self._h)
 

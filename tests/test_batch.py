@@ -287,3 +287,42 @@ def test_moving_members_batch_bitwise_equals_singles():
             r.step(9)
         np.testing.assert_array_equal(r.forces(), Fb[i])
         np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+
+
+def test_member_moving_through_the_grid_batch_bitwise_equals_singles():
+    """A member whose body moves one node (and its control volume with it) between two
+    batch calls: every instance bitwise equals the same member stepped alone with the
+    same calls; a member whose control volume changes size stops the batch."""
+    from paper_2210_10377_amd import Sim, Batch, LbmError
+    ws = MINI[:3]
+    k = next(i for i, w in enumerate(ws) if w.box is not None)
+    w = ws[k]
+    shifted = np.roll(w.mask, 1, axis=1)
+    x0, x1, y0, y1 = w.box
+    box1 = (x0 + 1, x1 + 1, y0, y1)
+
+    def members():
+        return [Sim(v.mask, v.tau, v.uin, precision="fp32", box=v.box, max_record=64)
+                for v in ws]
+
+    sims = members()
+    _seed_states(sims, ws)
+    b = Batch(sims, max_record=64)
+    b.set_schedule(grid_blocks=0, graph_steps=4)
+    b.step(10)
+    imp_b = sims[k].set_mask(shifted, box1)
+    b.step(10)
+    Fb, bad = b.forces()
+    assert not bad.any()
+    ref = members()
+    _seed_states(ref, ws)
+    for i, r in enumerate(ref):
+        r.step(10)
+        if i == k:
+            np.testing.assert_array_equal(r.set_mask(shifted, box1), imp_b)
+        r.step(10)
+        np.testing.assert_array_equal(r.forces(), Fb[i])
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+    sims[k].set_mask(shifted, (x0 + 1, x1 + 1, y0, y1 - 1))   # one row fewer
+    with pytest.raises(LbmError, match="changed size"):
+        b.step(1)

@@ -276,3 +276,42 @@ def test_body_motion_validation_and_adjoint_refusal(capi):
     rc = L.lbm_adjoint_forward(p._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
                                ctypes.byref(J))
     assert rc == capi.LBM_ESTATE
+
+
+def test_set_mask_validation_and_replanning(capi, orc):
+    """lbm_set_mask on an unbound handle: the link list follows the new mask (bitwise
+    the oracle's); bad mask values, a box that no longer encloses the body, adding a
+    control volume, a mask needing more force slots than reserved and a larger box are
+    refused and leave the handle as it was."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    nx, ny = 120, 40
+    m0 = workloads.cylinder_mask(nx, ny, 30, 19.5, 6)
+    m1 = workloads.cylinder_mask(nx, ny, 33, 20.5, 6)
+    p = Plan(m0, uin=0.04, box=(20, 41, 8, 32))
+    links0 = p.links()
+    imp = np.full(2, 7.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def setm(m, box=None):
+        m = np.ascontiguousarray(m, dtype=np.uint8)
+        bp = None if box is None else (ctypes.c_int32 * 4)(*box)
+        return L.lbm_set_mask(p._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                              bp if bp is None else ctypes.cast(bp, ctypes.POINTER(ctypes.c_int32)),
+                              imp.ctypes.data_as(dp))
+
+    assert setm(m1, (22, 43, 8, 32)) == capi.LBM_OK
+    assert np.all(imp == 0.0)          # unbound: no state, no impulse
+    assert np.array_equal(p.links(), orc.links(m1))
+    bad = m1.copy()
+    bad[3, 3] = 2
+    assert setm(bad) == capi.LBM_EINVAL
+    assert setm(workloads.cylinder_mask(nx, ny, 60, 20.5, 6)) == capi.LBM_EINVAL  # outside box
+    assert setm(m1, (-1, -1, -1, -1)) == capi.LBM_EINVAL and b"added or removed" in L.lbm_last_error(p._h)
+    assert setm(m1, (10, 60, 4, 36)) == capi.LBM_ENOMEM                            # larger box
+    q = Plan(np.zeros((ny, 2048), np.uint8), uin=0.04)
+    mm = np.zeros((ny, 2048), np.uint8)
+    mm[2:ny - 2, ::64] = 1
+    rc = L.lbm_set_mask(q._h, mm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None, None)
+    assert rc == capi.LBM_ENOMEM and b"slots" in L.lbm_last_error(q._h)
+    assert np.array_equal(p.links(), orc.links(m1))  # unchanged by the refusals

@@ -228,3 +228,118 @@ def test_pitching_naca_full_size_two_steps(precision):
     e = _force_err(g.forces(), o.forces())
     tol = {"fp64": np.array([1e-10] * 4), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3])}[precision]
     assert np.all(e <= tol), e
+
+
+# --------------------------------------------------------------------------------------
+# A body moving through the grid: the mask (and control volume) replaced between calls
+# --------------------------------------------------------------------------------------
+
+def _translating_run(side, moves, chunk, nx, ny, x0, yc, r, U, omega=0.0, box_every=2):
+    """On one side (a Sim or an OracleSim, which take the same calls): `moves` times
+    chunk steps, then the cylinder moved one node along x, its motion centred on the new
+    position, and the control volume moved along every `box_every`-th time; then chunk
+    more steps.  Returns the impulses and the last mask."""
+    imps = []
+    for k in range(1, moves + 1):
+        side.step(chunk)
+        m = workloads.cylinder_mask(nx, ny, x0 + k, yc, r)
+        box = None
+        if k % box_every == 0:
+            box = (int(x0 - 2 * r + k), int(x0 + 2 * r + 1 + k), int(yc - 2 * r), int(yc + 2 * r + 1))
+        imps.append(side.set_mask(m, box))
+        side.set_body_motion(U[0], U[1], omega, x0 + k, yc)
+    side.step(chunk)
+    return np.array(imps), m
+
+
+@pytest.fixture(scope="module")
+def translating_reference():
+    """Oracle run: a cylinder (radius 6) towed along a walled channel with inflow,
+    moved one node every 20 steps (velocity 0.05, turning slowly), 12 moves."""
+    nx, ny, x0, yc, r = 160, 44, 30, 21.5, 6
+    U = (0.05, 0.0)
+    m0 = workloads.cylinder_mask(nx, ny, x0, yc, r)
+    box0 = (int(x0 - 2 * r), int(x0 + 2 * r + 1), int(yc - 2 * r), int(yc + 2 * r + 1))
+    o = OracleSim(m0, tau=0.62, uin=np.full(ny, 0.03), box=box0,
+                  body_motion=(U[0], U[1], 0.002, x0, yc))
+    io, m = _translating_run(o, 12, 20, nx, ny, x0, yc, r, U, omega=0.002)
+    return (nx, ny, x0, yc, r, U, m0, box0), io, m, o.state(), o.forces()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32dev", "fp16dev"])
+def test_translating_cylinder_against_oracle(precision, translating_reference):
+    """The towed cylinder on the GPU with the same calls: FP64 populations, forces and
+    impulses to 1e-10 of the oracle; 32-bit storage forces to 1e-4 of the largest force,
+    FP16 deviations to 5e-2; DRTT equals MEA-B at every step in FP64 (each step's forces
+    use its own geometry)."""
+    (nx, ny, x0, yc, r, U, m0, box0), io, m, So, Fo = translating_reference
+    g = _sim(mask=m0, tau=0.62, uin=np.full(ny, 0.03), precision=precision, box=box0,
+             max_record=400)
+    g.set_body_motion(U[0], U[1], 0.002, x0, yc)
+    ig, _ = _translating_run(g, 12, 20, nx, ny, x0, yc, r, U, omega=0.002)
+    Fg = g.forces()
+    assert Fg.shape == Fo.shape
+    e = _force_err(Fg, Fo)
+    scale = np.abs(io).max()
+    ei = np.abs(ig - io).max() / scale
+    print(precision, "translating cylinder force errors (A, B, DRTT, SI):", e, "impulse", ei)
+    tol = {"fp64": TOL64, "fp32": TOL32_FORCE, "fp32dev": TOL32_FORCE,
+           "fp16dev": TOL16_FORCE}[precision]
+    assert np.all(e <= tol), e
+    assert ei <= {"fp64": 1e-10, "fp32": 1e-4, "fp32dev": 1e-4, "fp16dev": 5e-2}[precision], ei
+    if precision == "fp64":
+        assert _pop_err(g.populations(), So, m) <= TOL64
+        sc = np.abs(Fg[:, 1]).max()
+        assert np.abs(Fg[:, 2] - Fg[:, 1]).max() <= 1e-10 * sc
+
+
+def test_body_crossing_the_periodic_seam():
+    """A body moved across the periodic x edge from a random state (FP64): the refill
+    takes neighbours across the seam; populations, forces and impulses to 1e-10."""
+    nx, ny = 64, 24
+    S0 = workloads.near_rest_state(nx, ny, seed=31, amp=0.05)
+
+    def mask(k):
+        m = np.zeros((ny, nx), np.uint8)
+        xs = [(nx - 3 + k + j) % nx for j in range(4)]
+        m[9:14, xs] = 1
+        return m
+
+    o = OracleSim(mask(0), tau=0.7, bc_x=BCX_PERIODIC, bc_y=BCY_WALL,
+                  body_motion=(0.04, 0.0, 0.0, 0.0, 0.0))
+    g = _sim(mask=mask(0), tau=0.7, precision="fp64", bc_x=BCX_PERIODIC, bc_y=BCY_WALL,
+             max_record=200)
+    g.set_body_motion(0.04, 0.0, 0.0, 0.0, 0.0)
+    o.set_state(S0)
+    g.set_populations(S0)
+    ig, io = [], []
+    for k in range(1, 7):
+        o.step(9)
+        g.step(9)
+        io.append(o.set_mask(mask(k)))
+        ig.append(g.set_mask(mask(k)))
+    o.step(9)
+    g.step(9)
+    assert _pop_err(g.populations(), o.state(), mask(6)) <= TOL64
+    e = _force_err(g.forces(), o.forces(), (0, 1, 3))
+    assert np.all(e <= TOL64), e
+    io, ig = np.array(io), np.array(ig)
+    assert np.abs(ig - io).max() <= 1e-10 * np.abs(io).max()
+
+
+def test_set_mask_to_the_same_mask_is_bitwise_a_no_op():
+    """Re-setting the present mask and box between two calls changes nothing: state and
+    forces bitwise those of the uninterrupted run (FP32)."""
+    w = workloads.cylinder_channel_200x80()
+    runs = []
+    for call in (False, True):
+        g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision="fp32", box=w.box,
+                 max_record=200)
+        g.step(100)
+        if call:
+            imp = g.set_mask(w.mask, w.box)
+            assert np.all(imp == 0.0)
+        g.step(100)
+        runs.append((g.populations(), g.forces()))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
