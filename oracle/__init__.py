@@ -22,14 +22,24 @@ BCX_INLET_OUTLET, BCX_PERIODIC = 0, 1
 BCY_WALL, BCY_PERIODIC = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (no FMA contraction, so that it is plain IEEE)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+SRC3 = os.path.join(HERE, "lbm3d_oracle.cpp")
+LIB3 = os.path.join(HERE, "liboracle3d.so")
+
+
+def _compile(src, lib, force):
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-shared",
-                               "-fPIC", SRC, "-o", tmp])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-fPIC", src, "-o", tmp])
+        os.replace(tmp, lib)
+    return lib
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracles (two- and three-dimensional) with g++, no FMA contraction,
+    so that they are plain IEEE."""
+    _compile(SRC3, LIB3, force)
+    return _compile(SRC, LIB, force)
 
 
 class _Cfg(ctypes.Structure):

@@ -1,0 +1,269 @@
+"""Pins of the three-dimensional oracle (D3Q27) against what the mathematics fixes:
+exact weights and lattice isotropy, equilibrium moments, collision invariants, brute-force
+streaming, the exact reduction to the (separately pinned) two-dimensional oracle for
+span-invariant flows, Newton's law for the fluid, DRTT = MEA-B around a sphere, the
+exact Poiseuille profile between walls in z, and symmetry."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import d3q27 as D
+from oracle import BCX_INLET_OUTLET, BCX_PERIODIC, BCY_PERIODIC, BCY_WALL, OracleSim
+from workloads import d3
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return D.lattice()
+
+
+def test_velocity_set_and_exact_weights(lat):
+    """The 27 velocities are {-1, 0, 1}^3, each once, numbered as the population
+    arrays are laid out; the weights by shell are 8/27, 2/27, 1/54, 1/216 exactly;
+    opposite pairs are consecutive (2k-1, 2k)."""
+    cx, cy, cz, opp, w = lat
+    vel = set(zip(cx.tolist(), cy.tolist(), cz.tolist()))
+    assert len(vel) == 27 and vel == {(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1)
+                                      for c in (-1, 0, 1)}
+    assert (cx[0], cy[0], cz[0]) == (0, 0, 0)
+    faces = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    assert list(zip(cx[1:7], cy[1:7], cz[1:7])) == faces
+    shell = {0: Fraction(8, 27), 1: Fraction(2, 27), 2: Fraction(1, 54), 3: Fraction(1, 216)}
+    for i in range(27):
+        k = abs(cx[i]) + abs(cy[i]) + abs(cz[i])
+        assert w[i] == float(shell[k])
+        assert (cx[opp[i]], cy[opp[i]], cz[opp[i]]) == (-cx[i], -cy[i], -cz[i])
+        if i:
+            assert opp[i] == (i + 1 if i % 2 else i - 1)
+    assert sum(Fraction(w[i]).limit_denominator(1000) for i in range(27)) == 1
+
+
+def test_lattice_isotropy_to_fourth_order(lat):
+    """sum w = 1, sum w c_a c_b = theta0 delta_ab, odd moments vanish, and
+    sum w c_a c_b c_c c_d = theta0^2 (delta delta + delta delta + delta delta)."""
+    cx, cy, cz, _, w = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    th = 1.0 / 3.0
+    d = np.eye(3)
+    assert abs(w.sum() - 1) < 1e-15
+    np.testing.assert_allclose(np.einsum("i,ia->a", w, C), 0, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", w, C, C), th * d, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib,ic->abc", w, C, C, C), 0, atol=1e-16)
+    M4 = np.einsum("i,ia,ib,ic,id->abcd", w, C, C, C, C)
+    iso = th * th * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                     + np.einsum("ad,bc->abcd", d, d))
+    np.testing.assert_allclose(M4, iso, atol=1e-16)
+
+
+def test_equilibrium_moments(lat):
+    cx, cy, cz, _, w = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    rho, u = 1.07, np.array([0.03, -0.05, 0.02])
+    feq = D.equilibrium(rho, *u)
+    assert abs(feq.sum() - rho) < 1e-15
+    np.testing.assert_allclose(C.T @ feq, rho * u, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", feq, C, C),
+                               rho * np.outer(u, u) + rho / 3 * np.eye(3), atol=1e-15)
+    np.testing.assert_allclose(D.equilibrium(1.0, 0, 0, 0), w, atol=0)
+
+
+def test_collision_invariants_and_relaxation(lat):
+    cx, cy, cz, _, w = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    f = d3.near_rest_state3(1, 1, 1, seed=3, amp=0.2)[:, 0, 0, 0]
+    for om in (0.6, 1.0, 1.7):
+        out = D.collide_node(f, om)
+        assert abs(out.sum() - f.sum()) < 1e-15
+        np.testing.assert_allclose(C.T @ out, C.T @ f, atol=1e-16)
+    rho = f.sum()
+    u = C.T @ f / rho
+    np.testing.assert_allclose(D.collide_node(f, 1.0), D.equilibrium(rho, *u), atol=1e-16)
+    g = np.array([1e-4, -2e-4, 3e-4])
+    np.testing.assert_allclose(C.T @ D.collide_node(f, 0.8, g), C.T @ f + g, atol=1e-16)
+
+
+def test_pure_streaming_of_single_populations(lat):
+    """omega = 0 on a fully periodic 7x6x5 lattice: one marked population per direction
+    moves by c_i per step and wraps."""
+    cx, cy, cz, _, _ = lat
+    nx, ny, nz = 7, 6, 5
+    S = np.ones((27, nz, ny, nx))      # a background keeps rho > 0 at every node
+    x0, y0, z0 = 3, 2, 1
+    S[:, z0, y0, x0] = 2.0
+    s = D.OracleSim3(np.zeros((nz, ny, nx), np.uint8), omega=0.0, bc_x=BCX_PERIODIC,
+                     bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC)
+    s.set_state(S)
+    s.step(3)
+    T = s.state()
+    for i in range(27):
+        x, y, z = (x0 + 3 * cx[i]) % nx, (y0 + 3 * cy[i]) % ny, (z0 + 3 * cz[i]) % nz
+        assert T[i, z, y, x] == 2.0 and T[i].sum() == nx * ny * nz + 1
+
+
+def test_body_bounce_back_and_links_brute_force(lat):
+    """A single solid node in a periodic lattice: 26 links, one from each neighbour
+    towards it, and the population sent at it comes back reversed after one step."""
+    cx, cy, cz, opp, _ = lat
+    nx, ny, nz = 6, 6, 6
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[3, 3, 3] = 1
+    L = D.links(m, bc_x=BCX_PERIODIC, bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC)
+    expect = sorted(((((3 - cz[i]) * ny + 3 - cy[i]) * nx + 3 - cx[i]), i) for i in range(1, 27))
+    assert sorted(map(tuple, L.tolist())) == expect
+    S = np.ones((27, nz, ny, nx))
+    i = 19
+    S[i, 3 - cz[i], 3 - cy[i], 3 - cx[i]] = 2.0
+    s = D.OracleSim3(m, omega=0.0, bc_x=BCX_PERIODIC, bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC)
+    s.set_state(S)
+    s.step(1)
+    assert s.pre()[opp[i], 3 - cz[i], 3 - cy[i], 3 - cx[i]] == 2.0
+
+
+def _marginal(S3, lat):
+    """Sum over c_z of a [27, ...] field, in the two-dimensional direction order."""
+    cx, cy, cz, _, _ = lat
+    order2 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    out = np.zeros((9,) + S3.shape[1:])
+    for i in range(27):
+        out[order2.index((cx[i], cy[i]))] += S3[i]
+    return out
+
+
+@pytest.mark.parametrize("bcx", [BCX_INLET_OUTLET, BCX_PERIODIC])
+def test_span_invariant_flow_reduces_to_the_two_dimensional_oracle(lat, bcx):
+    """An extruded body in a lattice periodic across the span, started from a
+    span-invariant state: the z-marginal of the D3Q27 state equals the D2Q9 oracle's
+    state, and the x, y forces of every estimator equal nz times the two-dimensional ones
+    (DRTT with a box spanning the whole span), the z forces vanish."""
+    cx, cy, cz, _, _ = lat
+    nx, ny, nz = 60, 26, 4
+    m2 = workloads.cylinder_mask(nx, ny, 20, 12.5, 5)
+    box2 = (10, 31, 4, 22)
+    uin = None if bcx == BCX_PERIODIC else np.linspace(0.5, 1.0, ny) * 0.04
+    S2 = workloads.near_rest_state(nx, ny, seed=9, amp=0.05)
+    # a span-invariant 3-D state whose marginal is S2: split each 2-D population over
+    # c_z in fixed proportions
+    frac = {0: 2 / 3, 1: 1 / 6, -1: 1 / 6}
+    order2 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    S3 = np.zeros((27, nz, ny, nx))
+    for i in range(27):
+        S3[i] = frac[cz[i]] * S2[order2.index((cx[i], cy[i]))][None]
+    o2 = OracleSim(m2, tau=0.7, uin=uin, bc_x=bcx, bc_y=BCY_WALL, box=box2)
+    o2.set_state(S2)
+    o3 = D.OracleSim3(d3.extrude(m2, nz), tau=0.7,
+                      uin=None if uin is None else np.broadcast_to(uin, (nz, ny)),
+                      bc_x=bcx, bc_y=D.BC_WALL, bc_z=D.BC_PERIODIC,
+                      box=box2 + (0, nz))
+    o3.set_state(S3)
+    o2.step(25)
+    o3.step(25)
+    np.testing.assert_allclose(_marginal(o3.state(), lat)[:, 0], o2.state(), rtol=0, atol=1e-14)
+    F2, F3 = o2.forces(), o3.forces()
+    scale = np.abs(F2).max()
+    np.testing.assert_allclose(F3[:, :, :2], nz * F2, rtol=0, atol=1e-12 * nz * scale)
+    assert np.abs(F3[:, :, 2]).max() <= 1e-13 * nz * scale
+
+
+def test_newtons_law_for_the_fluid_pins_mea_b(lat):
+    """Fully periodic lattice with a sphere and a uniform body force g: the total fluid
+    momentum (pre-collision) obeys P(t+1) = P(t) + N g - F_B(t) at every step."""
+    cx, cy, cz, _, _ = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    nx, ny, nz = 20, 18, 16
+    m = d3.sphere_mask(nx, ny, nz, 9.5, 8.7, 7.9, 4.2)
+    g = np.array([2e-5, -1e-5, 5e-6])
+    s = D.OracleSim3(m, tau=0.8, bc_x=BCX_PERIODIC, bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC,
+                     g=g)
+    s.set_state(d3.near_rest_state3(nx, ny, nz, seed=2, amp=0.02))
+    fl = m == 0
+    N = fl.sum()
+    P = []
+    for _ in range(12):
+        s.step(1)
+        P.append(np.einsum("ia,i...->a...", C, s.pre())[:, fl].sum(1))
+    FB = s.forces()[:, 1]
+    for t in range(11):
+        np.testing.assert_allclose(P[t + 1], P[t] + N * g - FB[t], rtol=0, atol=1e-12)
+    assert np.abs(FB).max() > 1e-4
+
+
+def test_drtt_equals_mea_b_around_a_sphere_for_two_boxes(lat):
+    """Inlet/outlet duct with walls in y and z and a sphere: DRTT equals MEA-B at every
+    step for two different admissible boxes; A differs from B."""
+    w = d3.sphere_channel_64x32x32()
+    Fs, Js = [], []
+    for box in (w.box, (10, 40, 5, 27, 4, 28)):
+        s = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, box=box)
+        s.step(60)
+        Fs.append(s.forces())
+        Js.append(np.abs(s.records()[:, 6:9]).max())
+    # DRTT is a difference of box momenta of order |J| (~1e4 nodes): rounding 1e-13 |J|
+    for F, J in zip(Fs, Js):
+        scale = np.abs(F[:, 1]).max()
+        assert scale > 0
+        assert np.abs(F[:, 2] - F[:, 1]).max() <= 1e-12 * J
+        assert np.abs(F[:, 0] - F[:, 1]).max() > 1e-3 * scale
+    np.testing.assert_allclose(Fs[0][:, 2], Fs[1][:, 2], rtol=0, atol=1e-12 * max(Js))
+
+
+def test_symmetric_sphere_has_no_side_forces():
+    """A sphere centred in a square duct (mirror-symmetric in y and z) with a uniform
+    inlet: lift and side force vanish for every estimator, drag is positive."""
+    nx, ny, nz = 48, 24, 24
+    m = d3.sphere_mask(nx, ny, nz, 16, 11.5, 11.5, 4.5)
+    s = D.OracleSim3(m, tau=0.7, uin=np.full((nz, ny), 0.04), box=d3.default_box3(m, 3))
+    s.step(150)
+    F = s.forces()
+    drag = np.abs(F[:, :, 0]).max()
+    assert np.abs(F[:, :, 1:]).max() <= 1e-12 * drag
+    assert np.all(F[-20:, 1, 0] > 0)
+
+
+def test_poiseuille_between_walls_in_z_is_exact_at_the_magic_tau():
+    """Plane Poiseuille flow driven by g along x between no-slip walls at z = -1/2 and
+    nz - 1/2 (periodic x and y): at (tau - 1/2)^2 = 3/16 half-way bounce-back gives the
+    parabola u(z) = g/(2 nu) (z + 1/2)(nz - 1/2 - z) exactly at steady state."""
+    nx, ny, nz = 4, 3, 12
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    nu = (tau - 0.5) / 3.0
+    g = 1e-6
+    s = D.OracleSim3(np.zeros((nz, ny, nx), np.uint8), tau=tau, bc_x=BCX_PERIODIC,
+                     bc_y=D.BC_PERIODIC, bc_z=D.BC_WALL, g=(g, 0.0, 0.0))
+    s.step(6000)
+    S = s.pre()          # velocity from the pre-collision populations (Guo forcing)
+    cx, _, _, _, _ = D.lattice()
+    rho = S.sum(0)
+    u = (np.tensordot(cx.astype(float), S, 1) + 0.5 * g) / rho
+    z = np.arange(nz)
+    exact = g / (2 * nu) * (z + 0.5) * (nz - 0.5 - z)
+    np.testing.assert_allclose(u[:, 1, 2], exact, rtol=1e-9)
+    assert np.abs(u - u[:, :1, :1]).max() < 1e-15
+
+
+def test_uniform_flow_through_inlet_and_outlet_is_a_fixed_point():
+    """f^eq(1, (U, 0, 0)) everywhere in a duct periodic in y and z with the moving-wall
+    inlet at velocity U and the zero-gradient outlet stays exactly as it is."""
+    nx, ny, nz = 10, 5, 4
+    U = 0.05
+    feq = D.equilibrium(1.0, U, 0.0, 0.0)
+    S0 = np.broadcast_to(feq[:, None, None, None], (27, nz, ny, nx)).copy()
+    s = D.OracleSim3(np.zeros((nz, ny, nx), np.uint8), tau=0.6, uin=np.full((nz, ny), U),
+                     bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC)
+    s.set_state(S0)
+    s.step(5)
+    np.testing.assert_allclose(s.state(), S0, rtol=0, atol=2e-16)
+
+
+def test_box_admissibility_per_axis():
+    """A box may span a whole periodic axis (an extruded body through it); along a
+    bounded axis it must lie one node inside with the body strictly inside."""
+    nx, ny, nz = 40, 20, 8
+    m = d3.extrude(workloads.cylinder_mask(nx, ny, 15, 9.5, 4), nz)
+    kw = dict(bc_y=D.BC_WALL, bc_z=D.BC_PERIODIC)
+    assert D.box_admissible(m, (5, 26, 2, 18, 0, nz), **kw)
+    assert not D.box_admissible(m, (5, 26, 2, 18, 1, nz - 1), **kw)
+    assert not D.box_admissible(m, (5, 26, 2, 18, 0, nz), bc_y=D.BC_WALL, bc_z=D.BC_WALL)
+    assert not D.box_admissible(m, (0, 26, 2, 18, 0, nz), **kw)
+    assert not D.box_admissible(m, (5, 26, 6, 18, 0, nz), **kw)
