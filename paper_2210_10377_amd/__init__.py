@@ -8,3 +8,4 @@ kernels for gfx950 behind the C ABI of include/lbm.h.
 from ._capi import LbmError  # noqa: F401
 from .sim import ALL_SCHEMES, Plan, Sim, scheme_mask  # noqa: F401
 from .batch import Batch  # noqa: F401
+from .sim3 import Plan3, Sim3  # noqa: F401

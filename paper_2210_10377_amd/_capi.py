@@ -33,6 +33,11 @@ EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_for
            "lbm_batch_forces", "lbm_batch_get_info", "lbm_batch_destroy",
            "lbm_batch_last_error")
 
+# Every entry point of include/lbm3d.h.
+EXPORTS3 = ("lbm3d_create", "lbm3d_workspace_bytes", "lbm3d_bind", "lbm3d_step",
+            "lbm3d_forces", "lbm3d_get_populations", "lbm3d_set_populations",
+            "lbm3d_get_links", "lbm3d_get_info", "lbm3d_destroy", "lbm3d_last_error")
+
 
 class lbm_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
@@ -54,6 +59,20 @@ class lbm_info(ctypes.Structure):
                 ("n_recorded", ctypes.c_int64), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("plane_stride", ctypes.c_int64),
                 ("pitch", ctypes.c_int32), ("elem_bytes", ctypes.c_int32)]
+
+
+class lbm3d_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+                ("box", ctypes.c_int32 * 6), ("precision", ctypes.c_int32),
+                ("max_record", ctypes.c_int32)]
+
+
+class lbm3d_info(ctypes.Structure):
+    _fields_ = [("n_fluid", ctypes.c_int64), ("n_links", ctypes.c_int64),
+                ("n_box", ctypes.c_int64), ("steps_done", ctypes.c_int64),
+                ("n_recorded", ctypes.c_int64), ("n_general", ctypes.c_int32),
+                ("n_strips", ctypes.c_int32)]
 
 
 class lbm_batch_schedule(ctypes.Structure):
@@ -129,8 +148,22 @@ def load():
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_last_error.argtypes = [vp]
     L.lbm_batch_last_error.restype = ctypes.c_char_p
-    for name in EXPORTS:
-        if not name.endswith("last_error"):
+    L.lbm3d_create.argtypes = [ctypes.POINTER(lbm3d_grid), ctypes.POINTER(ctypes.c_uint8),
+                               ctypes.c_double, dp, ctypes.c_double, ctypes.POINTER(vp)]
+    L.lbm3d_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.lbm3d_bind.argtypes = [vp, vp, sz, vp]
+    L.lbm3d_step.argtypes = [vp, i32, u32]
+    L.lbm3d_forces.argtypes = [vp, dp, i64, ctypes.POINTER(i64)]
+    L.lbm3d_get_populations.argtypes = [vp, dp]
+    L.lbm3d_set_populations.argtypes = [vp, dp]
+    L.lbm3d_get_links.argtypes = [vp, ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
+    L.lbm3d_get_info.argtypes = [vp, ctypes.POINTER(lbm3d_info)]
+    L.lbm3d_destroy.argtypes = [vp]
+    L.lbm3d_destroy.restype = None
+    L.lbm3d_last_error.argtypes = [vp]
+    L.lbm3d_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS + EXPORTS3:
+        if not name.endswith("last_error") and name != "lbm3d_destroy":
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -139,6 +172,13 @@ def load():
 def check(rc, handle=None):
     if rc != LBM_OK:
         msg = load().lbm_last_error(handle)
+        raise LbmError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def check3(rc, handle=None):
+    if rc != LBM_OK:
+        msg = load().lbm3d_last_error(handle)
         raise LbmError(rc, msg.decode() if msg else "")
     return rc
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["api.hip", "batch.hip", "kernels.hip", "adjoint.hip", "plan.cpp"]
+SOURCES = ["api.hip", "batch.hip", "kernels.hip", "adjoint.hip", "plan.cpp", "api3.hip",
+           "kernels3.hip", "plan3.cpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,427 @@
+// C ABI of the three-dimensional (D3Q27) path (include/lbm3d.h): planning, device
+// layout, stepping with per-step forces, readout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels3.h"
+#include "lbm3d.h"
+#include "plan3.h"
+
+using namespace lbm3;
+
+struct lbm3d {
+  lbm3d_grid g;
+  double tau = 0.0, rho_w = 1.0;
+  std::vector<double> uin;  // [nz][ny]
+  Plan3 plan;
+  int32_t pitch = 0;
+  int64_t plane = 0;
+  size_t esz = 0;
+  size_t off_buf[2] = {0, 0}, off_word = 0, off_strip = 0, off_fstrip = 0, off_uin = 0, off_part = 0,
+         off_jpart = 0, off_ring = 0, total = 0;
+  int njblocks = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;
+  int64_t steps_done = 0, nrec = 0;
+  std::vector<uint32_t> rec_scheme;
+  std::string err;
+
+  int fail(int code, const std::string& m) {
+    err = m;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EHIP;
+  }
+  void* buf(int k) const { return ws + off_buf[k]; }
+  size_t part_doubles() const {
+    return size_t(plan.nslots) * kPart + size_t(plan.njslots) * 3;
+  }
+  double* part(int k) const {
+    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_doubles();
+  }
+  double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
+};
+
+namespace {
+
+std::string g_err3;
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+size_t elem_bytes(int p) { return p == LBM_FP64 ? 8 : (p == LBM_FP16DEV ? 2 : 4); }
+bool is_dev(int p) { return p == LBM_FP16DEV || p == LBM_FP32DEV; }
+double host_w27(int i) {
+  double w = 1.0;
+  w *= kCx[i] == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+  w *= kCy[i] == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+  w *= kCz[i] == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+  return w;
+}
+
+Geom3 geom(const lbm3d* h) {
+  const Plan3& p = h->plan;
+  Geom3 g{};
+  g.plane = h->plane;
+  g.pitch = h->pitch;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  g.bc_x = p.bc_x;
+  g.bc_y = p.bc_y;
+  g.bc_z = p.bc_z;
+  for (int k = 0; k < 6; ++k) g.box[k] = p.box[k];
+  for (int a = 0; a < 3; ++a) g.whole[a] = p.whole[a] ? 1 : 0;
+  g.has_box = p.has_box ? 1 : 0;
+  g.word = reinterpret_cast<const uint32_t*>(h->ws + h->off_word);
+  g.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  g.rho_w6 = 6.0 * h->rho_w;
+  return g;
+}
+
+// Enqueue n >= 1 steps on the ping-pong buffers; with a ring, step k's row is ring row k.
+int enqueue3(lbm3d* h, int32_t n, double* ring) {
+  const Plan3& p = h->plan;
+  const bool forces = ring != nullptr;
+  Step3Args a{};
+  a.g = geom(h);
+  a.ntx = p.ntx;
+  a.ntiles = p.ntiles;
+  a.strip = reinterpret_cast<const uint32_t*>(h->ws + h->off_strip);
+  a.fstrips = reinterpret_cast<const uint32_t*>(h->ws + h->off_fstrip);
+  a.omega = 1.0 / h->tau;
+  a.nslots = p.nslots;
+  a.njslots = p.njslots;
+  const int c0 = h->cur;
+  for (int32_t k = 0; k < n; ++k) {
+    const int s = (c0 + k) & 1;
+    a.src = h->buf(s);
+    a.dst = h->buf(1 - s);
+    a.part_out = forces ? h->part(k & 1) : nullptr;
+    a.red_in = nullptr;
+    a.red_row = nullptr;
+    a.red_prev_jnext = nullptr;
+    if (forces && k >= 1) {
+      a.red_in = h->part((k - 1) & 1);
+      a.red_row = ring + int64_t(k - 1) * kRow;
+      a.red_prev_jnext = k >= 2 ? ring + int64_t(k - 2) * kRow + kPart : nullptr;
+    }
+    hipError_t e = launch_step3(h->g.precision, forces, a, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "launch step");
+  }
+  const void* last = h->buf((c0 + n) & 1);
+  if (forces) {
+    if (p.has_box) {
+      Box3Args b{};
+      b.g = geom(h);
+      b.src = last;
+      b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+      hipError_t e = launch_box3(h->g.precision, b, h->njblocks, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "launch box momentum");
+    }
+    Final3Args f{};
+    f.red_in = h->part((n - 1) & 1);
+    f.nslots = p.nslots;
+    f.njslots = p.njslots;
+    f.row = ring + int64_t(n - 1) * kRow;
+    f.prev_jnext = n >= 2 ? ring + int64_t(n - 2) * kRow + kPart : nullptr;
+    f.jpart = p.has_box ? reinterpret_cast<const double*>(h->ws + h->off_jpart) : nullptr;
+    f.njblocks = h->njblocks;
+    hipError_t e = launch_final3(f, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "launch finalize");
+  }
+  h->cur = (c0 + n) & 1;
+  h->steps_done += n;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const double* uin,
+                 double rho_w, lbm3d_t** out) {
+  g_err3.clear();
+  if (!grid || !mask || !out) {
+    g_err3 = "null argument";
+    return LBM_EINVAL;
+  }
+  *out = nullptr;
+  const lbm3d_grid& g = *grid;
+  if (!std::isfinite(tau) || tau <= 0.5) {
+    g_err3 = "tau must be finite and > 1/2";
+    return LBM_EINVAL;
+  }
+  if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP32DEV &&
+      g.precision != LBM_FP16DEV) {
+    g_err3 = "unknown precision";
+    return LBM_EINVAL;
+  }
+  if (g.max_record < 1) {
+    g_err3 = "max_record must be >= 1";
+    return LBM_EINVAL;
+  }
+  lbm3d* h = new (std::nothrow) lbm3d();
+  if (!h) return LBM_ENOMEM;
+  std::string perr;
+  const int rc = build_plan3(g, mask, h->plan, perr);
+  if (rc != LBM_OK) {
+    g_err3 = perr;
+    delete h;
+    return rc;
+  }
+  h->g = g;
+  h->tau = tau;
+  h->uin.assign(size_t(g.ny) * g.nz, 0.0);
+  if (g.bc_x == LBM_BCX_INLET_OUTLET) {
+    if (!uin || !std::isfinite(rho_w) || rho_w <= 0.0) {
+      g_err3 = "an inlet plane and a wall density > 0 are required when bc_x is inlet/outlet";
+      delete h;
+      return LBM_EINVAL;
+    }
+    for (size_t k = 0; k < h->uin.size(); ++k) {
+      if (!std::isfinite(uin[k])) {
+        g_err3 = "inlet velocity is not finite";
+        delete h;
+        return LBM_EINVAL;
+      }
+      h->uin[k] = uin[k];
+    }
+    h->rho_w = rho_w;
+  }
+  // Layout: rows padded to 64 elements; planes padded so that consecutive planes do
+  // not sit a power of two apart.
+  h->esz = elem_bytes(g.precision);
+  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64);
+  const int64_t raw = int64_t(h->pitch) * g.ny * g.nz;
+  const int64_t quantum = int64_t(4096 / h->esz);
+  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(512 / h->esz);
+  if (h->plane >= (int64_t(1) << 31)) {  // in-plane offsets are 32-bit in the kernels
+    g_err3 = "grid too large: a direction plane must hold fewer than 2^31 elements";
+    delete h;
+    return LBM_ENOMEM;
+  }
+  size_t off = 0;
+  for (int k = 0; k < 2; ++k) {
+    h->off_buf[k] = off;
+    off = align256(off + size_t(h->plane) * kQ * h->esz);
+  }
+  h->off_word = off;
+  off = align256(off + h->plan.word.size() * sizeof(uint32_t));
+  h->off_strip = off;
+  off = align256(off + h->plan.strip.size() * sizeof(uint32_t));
+  h->off_fstrip = off;
+  off = align256(off + h->plan.fstrips.size() * sizeof(uint32_t));
+  h->off_uin = off;
+  off = align256(off + h->uin.size() * sizeof(double));
+  h->off_part = off;
+  off = align256(off + 2 * h->part_doubles() * sizeof(double));
+  h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
+  h->off_jpart = off;
+  off = align256(off + size_t(h->njblocks) * 3 * sizeof(double));
+  h->off_ring = off;
+  off = align256(off + size_t(g.max_record) * kRow * sizeof(double));
+  h->total = off;
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm3d_workspace_bytes(const lbm3d_t* h, size_t* bytes) {
+  if (!h || !bytes) return LBM_EINVAL;
+  *bytes = h->total;
+  return LBM_OK;
+}
+
+int lbm3d_bind(lbm3d_t* h, void* ws, size_t bytes, void* stream) {
+  if (!h) return LBM_EINVAL;
+  if (!ws) return h->fail(LBM_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return h->fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < h->total) return h->fail(LBM_ENOMEM, "workspace smaller than lbm3d_workspace_bytes");
+  h->ws = static_cast<char*>(ws);
+  h->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(h->ws + h->off_word, h->plan.word.data(),
+                                h->plan.word.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->ws + h->off_strip, h->plan.strip.data(),
+                       h->plan.strip.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && !h->plan.fstrips.empty())
+    e = hipMemcpyAsync(h->ws + h->off_fstrip, h->plan.fstrips.data(),
+                       h->plan.fstrips.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(), h->uin.size() * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload plan");
+  for (int k = 0; k < 2; ++k) {
+    e = launch_fill_rest3(h->g.precision, h->buf(k), h->plane, h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
+  }
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "bind synchronize");
+  h->bound = true;
+  h->cur = 0;
+  h->steps_done = 0;
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  return LBM_OK;
+}
+
+int lbm3d_step(lbm3d_t* h, int32_t n, uint32_t scheme) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
+  if (scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
+  const bool forces = scheme != 0;
+  if (forces && h->nrec + n > h->g.max_record)
+    return h->fail(LBM_EOVERFLOW, "force ring would overflow; read lbm3d_forces first");
+  if (n == 0) return LBM_OK;
+  const int rc = enqueue3(h, n, forces ? h->ring() + h->nrec * kRow : nullptr);
+  if (rc != LBM_OK) return rc;
+  if (forces) {
+    h->nrec += n;
+    h->rec_scheme.insert(h->rec_scheme.end(), size_t(n), scheme);
+  }
+  return LBM_OK;
+}
+
+int lbm3d_forces(lbm3d_t* h, double* out, int64_t cap, int64_t* got) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  if (got) *got = h->nrec;
+  if (h->nrec == 0) return LBM_OK;
+  if (!out || cap < h->nrec) return h->fail(LBM_EINVAL, "output holds fewer rows than recorded");
+  std::vector<double> rows(size_t(h->nrec) * kRow);
+  hipError_t e = hipMemcpyAsync(rows.data(), h->ring(), rows.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download force ring");
+  bool finite = true;
+  for (int64_t t = 0; t < h->nrec; ++t) {
+    const double* r = &rows[size_t(t) * kRow];
+    const uint32_t sch = h->rec_scheme[size_t(t)];
+    double v[12];
+    for (int c = 0; c < 3; ++c) {
+      v[c] = r[c];
+      v[3 + c] = r[3 + c];
+      v[6 + c] = r[6 + c] - r[kPart + c] + r[9 + c];
+      v[9 + c] = r[12 + c];
+    }
+    const bool want[4] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
+                          (sch & LBM_FORCE_DRTT) != 0 && h->plan.has_box,
+                          (sch & LBM_FORCE_SI) != 0};
+    double* o = out + t * 12;
+    for (int s = 0; s < 4; ++s)
+      for (int c = 0; c < 3; ++c) {
+        o[3 * s + c] = want[s] ? v[3 * s + c] : std::nan("");
+        if (want[s] && !std::isfinite(v[3 * s + c])) finite = false;
+      }
+  }
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  if (!finite) return h->fail(LBM_ENONFINITE, "a recorded force is not finite");
+  return LBM_OK;
+}
+
+int lbm3d_get_populations(lbm3d_t* h, double* out) {
+  if (!h || !out) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  std::vector<unsigned char> raw(bytes);
+  hipError_t e = hipMemcpyAsync(raw.data(), h->buf(h->cur), bytes, hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download populations");
+  const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz, prec = h->g.precision;
+  for (int i = 0; i < kQ; ++i) {
+    const double base = is_dev(prec) ? host_w27(i) : 0.0;
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const size_t k = size_t(i) * h->plane + (size_t(z) * ny + y) * h->pitch + x;
+          double v;
+          if (prec == LBM_FP64) {
+            std::memcpy(&v, &raw[k * 8], 8);
+          } else if (prec == LBM_FP16DEV) {
+            _Float16 hv;
+            std::memcpy(&hv, &raw[k * 2], 2);
+            v = double(hv);
+          } else {
+            float f;
+            std::memcpy(&f, &raw[k * 4], 4);
+            v = f;
+          }
+          out[((size_t(i) * nz + z) * ny + y) * nx + x] = base + v;
+        }
+  }
+  return LBM_OK;
+}
+
+int lbm3d_set_populations(lbm3d_t* h, const double* in) {
+  if (!h || !in) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  std::vector<unsigned char> raw(bytes, 0);
+  const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz, prec = h->g.precision;
+  for (int i = 0; i < kQ; ++i) {
+    const double base = is_dev(prec) ? host_w27(i) : 0.0;
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const size_t k = size_t(i) * h->plane + (size_t(z) * ny + y) * h->pitch + x;
+          const double v = in[((size_t(i) * nz + z) * ny + y) * nx + x] - base;
+          if (prec == LBM_FP64) {
+            std::memcpy(&raw[k * 8], &v, 8);
+          } else if (prec == LBM_FP16DEV) {
+            const _Float16 hv = _Float16(v);
+            std::memcpy(&raw[k * 2], &hv, 2);
+          } else {
+            const float f = float(v);
+            std::memcpy(&raw[k * 4], &f, 4);
+          }
+        }
+  }
+  hipError_t e = hipMemcpyAsync(h->buf(h->cur), raw.data(), bytes, hipMemcpyHostToDevice,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload populations");
+  return LBM_OK;
+}
+
+int lbm3d_get_links(const lbm3d_t* h, int64_t* out, int64_t cap, int64_t* n) {
+  if (!h || !n) return LBM_EINVAL;
+  std::vector<int64_t> L;
+  plan3_links(h->plan, L);
+  *n = int64_t(L.size() / 2);
+  const int64_t m = *n < cap ? *n : cap;
+  if (m > 0) {
+    if (!out) return LBM_EINVAL;
+    std::memcpy(out, L.data(), size_t(m) * 2 * sizeof(int64_t));
+  }
+  return LBM_OK;
+}
+
+int lbm3d_get_info(const lbm3d_t* h, lbm3d_info* info) {
+  if (!h || !info) return LBM_EINVAL;
+  info->n_fluid = h->plan.n_fluid;
+  info->n_links = h->plan.n_links;
+  info->n_box = h->plan.n_box;
+  info->steps_done = h->steps_done;
+  info->n_recorded = h->nrec;
+  info->n_general = h->plan.ngeneral;
+  info->n_strips = int32_t(h->plan.strip.size());
+  return LBM_OK;
+}
+
+void lbm3d_destroy(lbm3d_t* h) { delete h; }
+
+const char* lbm3d_last_error(const lbm3d_t* h) { return h ? h->err.c_str() : g_err3.c_str(); }
+
+}  // extern "C"

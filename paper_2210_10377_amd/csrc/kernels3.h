@@ -1,0 +1,62 @@
+// Kernel arguments and launchers of the three-dimensional (D3Q27) path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm3 {
+
+// Geometry and tables of a lattice as the kernels read them.
+struct Geom3 {
+  int64_t plane;        // elements per direction plane of a state buffer
+  int32_t pitch;        // elements per row (fixed y, z) of a plane
+  int32_t nx, ny, nz;
+  int32_t bc_x, bc_y, bc_z;
+  int32_t box[6];       // control volume (has_box)
+  int32_t whole[3];     // box spans the whole (periodic) axis
+  int32_t has_box;
+  const uint32_t* word; // [nz][ny][nx] node words
+  const double* uin;    // [nz][ny] inlet x-velocity
+  double rho_w6;        // 6 rho_w: inlet term 2 rho_w w_i (c_i . u_w) / theta0
+};
+
+struct Step3Args {
+  Geom3 g;
+  const void* src;
+  void* dst;
+  int32_t ntx;               // tiles per row
+  int64_t ntiles;
+  const uint32_t* strip;     // [ntiles * 4] strip table
+  const uint32_t* fstrips;   // [nslots] strip index of each force slot
+  double omega;
+  int32_t nslots, njslots;   // force slots (15 doubles), J slots (3 doubles)
+  double* part_out;          // partials of this step: [nslots][15] then [njslots][3]
+  // Reducer (last block of the launch): the previous step's partials into its ring row,
+  // and its J into the J(t+1) of the row before.
+  const double* red_in;
+  double* red_row;
+  double* red_prev_jnext;
+};
+
+struct Box3Args {
+  Geom3 g;
+  const void* src;
+  double* jpart;  // [blocks][3]
+};
+
+struct Final3Args {
+  const double* red_in;
+  int32_t nslots, njslots;
+  double* row;
+  double* prev_jnext;
+  const double* jpart;  // J of the pull after the last step, per box-sweep block
+  int32_t njblocks;
+};
+
+hipError_t launch_step3(int precision, bool forces, const Step3Args& a, hipStream_t s);
+hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t s);
+hipError_t launch_final3(const Final3Args& a, hipStream_t s);
+hipError_t launch_fill_rest3(int precision, void* buf, int64_t plane, hipStream_t s);
+
+}  // namespace lbm3

@@ -18,3 +18,9 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2210_10377_amd import _capi
+    return _capi

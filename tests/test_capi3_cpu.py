@@ -1,0 +1,155 @@
+"""CPU checks of the three-dimensional C ABI (include/lbm3d.h): every declared symbol is
+exported, the ctypes structs match the C layout, the planned link lists are bitwise the
+oracle's on varied geometries and boundary codes, and bad configurations are refused."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import d3q27 as D
+from workloads import d3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm3d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm3d_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(capi):
+    lib = capi.load()
+    names = _header_functions()
+    assert len(names) == 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(capi.EXPORTS3) == names
+
+
+def test_struct_layout_matches_header(capi, tmp_path):
+    structs = {"lbm3d_grid": capi.lbm3d_grid, "lbm3d_info": capi.lbm3d_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm3d.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout3.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout3"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
+
+
+def _geometries():
+    rng = np.random.default_rng(7)
+    rnd = (rng.random((9, 10, 12)) < 0.15).astype(np.uint8)
+    edge = np.zeros((8, 9, 10), np.uint8)
+    edge[2:4, 3:5, 8:10] = 1        # touches the outlet plane
+    edge[0, 4, 4] = 1               # on a z wall
+    edge[5, 0:2, 0:2] = 1           # on the inlet plane and a y wall
+    return {
+        "sphere_walls": (d3.sphere_mask(24, 16, 14, 9, 7.5, 6.5, 4), (0, 0, 0)),
+        "sphere_periodic": (d3.sphere_mask(24, 16, 14, 9, 7.5, 6.5, 4), (1, 1, 1)),
+        "extruded_periodic_z": (d3.extrude(workloads.cylinder_mask(30, 14, 10, 6.5, 3), 6),
+                                (0, 0, 1)),
+        "random_mixed": (rnd, (1, 0, 1)),
+        "random_walls": (rnd, (0, 1, 0)),
+        "edges": (edge, (0, 0, 0)),
+    }
+
+
+@pytest.mark.parametrize("name", list(_geometries()))
+def test_links_bitwise_vs_oracle(name):
+    from paper_2210_10377_amd import Plan3
+    mask, (bx, by, bz) = _geometries()[name]
+    p = Plan3(mask, bc_x=bx, bc_y=by, bc_z=bz)
+    L = p.links()
+    O = D.links(mask, bc_x=bx, bc_y=by, bc_z=bz)
+    assert L.shape == O.shape and L.shape[0] > 0
+    assert np.array_equal(L, O)
+    inf = p.info()
+    assert inf.n_links == len(O)
+    assert inf.n_fluid == int((mask == 0).sum())
+
+
+def test_box_counts_and_admissibility_agree_with_oracle(capi):
+    from paper_2210_10377_amd import Plan3
+    w = d3.sphere_channel_64x32x32()
+    p = Plan3(w.mask, box=w.box)
+    x0, x1, y0, y1, z0, z1 = w.box
+    assert p.info().n_box == int((w.mask[z0:z1, y0:y1, x0:x1] == 0).sum())
+    L = capi.load()
+    m = d3.extrude(workloads.cylinder_mask(40, 20, 15, 9.5, 4), 8)
+    cases = [((5, 26, 2, 18, 0, 8), 1), ((5, 26, 2, 18, 1, 7), 1), ((5, 26, 2, 18, 0, 8), 0),
+             ((0, 26, 2, 18, 0, 8), 1), ((5, 26, 6, 18, 0, 8), 1), ((5, 26, 2, 18, 0, 8), 1)]
+    for box, bz in cases:
+        ok = D.box_admissible(m, box, bc_y=D.BC_WALL, bc_z=bz)
+        g = capi.lbm3d_grid()
+        g.nx, g.ny, g.nz, g.bc_x, g.bc_y, g.bc_z = 40, 20, 8, 0, 0, bz
+        for k in range(6):
+            g.box[k] = box[k]
+        g.precision, g.max_record = capi.LBM_FP32, 4
+        uin = np.full((8, 20), 0.03)
+        h = ctypes.c_void_p()
+        mm = np.ascontiguousarray(m)
+        rc = L.lbm3d_create(ctypes.byref(g), mm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            0.7, uin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0,
+                            ctypes.byref(h))
+        assert (rc == capi.LBM_OK) == ok, (box, bz)
+        if rc == capi.LBM_OK:
+            L.lbm3d_destroy(h)
+
+
+@pytest.mark.parametrize("case", ["tau", "bc", "mask", "precision", "record", "inlet", "size"])
+def test_create_rejects_invalid(capi, case):
+    L = capi.load()
+    nx, ny, nz = 12, 10, 8
+    m = np.zeros((nz, ny, nx), np.uint8)
+    g = capi.lbm3d_grid()
+    g.nx, g.ny, g.nz, g.bc_x, g.bc_y, g.bc_z = nx, ny, nz, 0, 0, 0
+    for k in range(6):
+        g.box[k] = -1
+    g.precision, g.max_record = capi.LBM_FP32, 4
+    tau = 0.7
+    uin = np.full((nz, ny), 0.02)
+    up = uin.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if case == "tau":
+        tau = 0.5
+    elif case == "bc":
+        g.bc_z = 5
+    elif case == "mask":
+        m[3, 3, 3] = 2
+    elif case == "precision":
+        g.precision = 9
+    elif case == "record":
+        g.max_record = 0
+    elif case == "inlet":
+        up = None
+    elif case == "size":
+        g.nz = 1
+        m = np.zeros((1, ny, nx), np.uint8)
+    h = ctypes.c_void_p()
+    rc = L.lbm3d_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau,
+                        up, 1.0, ctypes.byref(h))
+    assert rc == capi.LBM_EINVAL
+    assert L.lbm3d_last_error(None)
+
+
+def test_workspace_accounts_for_both_buffers_and_unbound_step_is_estate(capi):
+    from paper_2210_10377_amd import Plan3
+    w = d3.sphere_channel_64x32x32()
+    for prec, esz in (("fp64", 8), ("fp32", 4), ("fp16dev", 2)):
+        p = Plan3(w.mask, box=w.box, precision=prec)
+        assert p.workspace_bytes() >= 2 * 27 * esz * w.nx * w.ny * w.nz
+    L = capi.load()
+    assert L.lbm3d_step(p._h, 1, 15) == capi.LBM_ESTATE

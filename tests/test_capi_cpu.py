@@ -13,12 +13,6 @@ import workloads
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.fixture(scope="module")
-def capi():
-    from paper_2210_10377_amd import _capi
-    return _capi
-
-
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)

@@ -1,0 +1,168 @@
+"""GPU parity of the three-dimensional (D3Q27) HIP path against the 3-D oracle, both fed
+from the same seeded inputs.  FP64: populations and every force within 1e-10 of the
+oracle (relative).  32-bit storage: forces within 1e-4 of the largest force of the run
+(DRTT of random fields: 1e-2, the rounding of the box momenta).  FP16 deviations: 5e-2."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import d3q27 as D
+from workloads import d3
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _sim3(mask, tau, uin=None, **kw):
+    from paper_2210_10377_amd import Sim3
+    return Sim3(mask, tau, uin, **kw)
+
+
+def _pop_err(Sg, So, mask):
+    fl = mask == 0
+    return (np.abs(Sg - So)[:, fl] / np.abs(So)[:, fl]).max()
+
+
+def _force_err(Fg, Fo, cols=(0, 1, 2, 3)):
+    out = []
+    for k in cols:
+        scale = np.abs(Fo[:, k]).max()
+        assert scale > 0, k
+        out.append(np.abs(Fg[:, k] - Fo[:, k]).max() / scale)
+    return np.array(out)
+
+
+def _edge_mask():
+    m = np.zeros((10, 12, 70), np.uint8)
+    m[2:4, 3:5, 66:70] = 1      # touches the outlet plane
+    m[0, 4:6, 20:23] = 1        # on a z wall
+    m[5:7, 0:2, 0:2] = 1        # on the inlet plane and a y wall
+    m[6, 6, 40] = 1             # single node
+    return m
+
+
+CASES = {
+    # name: (mask builder, bc (x, y, z), box, inlet speed)
+    "sphere_walls_box": (lambda: d3.sphere_mask(40, 24, 22, 14, 11.5, 10.5, 5),
+                         (0, 0, 0), (6, 23, 4, 20, 3, 19), 0.04),
+    "sphere_periodic_box": (lambda: d3.sphere_mask(36, 20, 18, 17, 9.5, 8.5, 4.5),
+                            (1, 1, 1), (10, 25, 3, 17, 2, 16), None),
+    "extruded_periodic_span": (lambda: d3.extrude(workloads.cylinder_mask(50, 22, 16, 10.5, 4), 6),
+                               (0, 0, 1), (8, 25, 3, 19, 0, 6), 0.04),
+    "edges_no_box": (_edge_mask, (0, 0, 0), None, 0.03),
+    "multi_tile_ragged": (lambda: d3.sphere_mask(300, 18, 14, 100, 8.5, 6.5, 4),
+                          (0, 1, 0), (90, 111, 2, 16, 1, 13), 0.05),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_small_cases_random_state(name):
+    """Every boundary rule in three dimensions, alone and together, from a seeded random
+    near-rest state, 40 steps, FP64: populations and all four forces to 1e-10."""
+    mk, (bx, by, bz), box, u = CASES[name]
+    mask = mk()
+    nz, ny, nx = mask.shape
+    uin = None if bx == 1 else np.linspace(0.5, 1.0, ny)[None, :] * np.linspace(1.0, 0.8, nz)[:, None] * u
+    S0 = d3.near_rest_state3(nx, ny, nz, seed=len(name), amp=0.05)
+    o = D.OracleSim3(mask, tau=0.7, uin=uin, bc_x=bx, bc_y=by, bc_z=bz, box=box)
+    o.set_state(S0)
+    o.step(40)
+    g = _sim3(mask, 0.7, uin, precision="fp64", bc_x=bx, bc_y=by, bc_z=bz, box=box,
+              max_record=64)
+    g.set_populations(S0)
+    g.step(40)
+    Fg, Fo = g.forces(), o.forces()
+    assert Fg.shape == Fo.shape == (40, 4, 3)
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    cols = (0, 1, 2, 3) if box is not None else (0, 1, 3)
+    e = _force_err(Fg, Fo, cols)
+    assert np.all(e <= TOL64), e
+    if box is None:
+        assert np.all(np.isnan(Fg[:, 2]))
+
+
+@pytest.fixture(scope="module")
+def sphere_reference():
+    w = d3.sphere_channel_64x32x32()
+    o = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+    o.step(w.steps)
+    return w, o.state(), o.forces()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32dev", "fp16dev"])
+def test_sphere_channel_from_rest(precision, sphere_reference):
+    """Sphere (D = 10) in a walled duct at Re 20, 300 steps from rest: FP64 populations
+    and forces to 1e-10; 32-bit storage forces to 1e-4 (DRTT 1e-3), FP16 deviations
+    5e-2; DRTT equals MEA-B in FP64; symmetric sphere: side forces vanish."""
+    w, So, Fo = sphere_reference
+    g = _sim3(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=300)
+    Fg = g.run(w.steps)
+    assert np.isfinite(Fg).all()
+    e = _force_err(Fg, Fo)
+    print(precision, "sphere force errors (A, B, DRTT, SI):", e)
+    tol = {"fp64": np.full(4, TOL64), "fp32": np.array([1e-4, 1e-4, 1e-3, 1e-4]),
+           "fp32dev": np.array([1e-4, 1e-4, 1e-3, 1e-4]),
+           "fp16dev": np.full(4, 5e-2)}[precision]
+    assert np.all(e <= tol), e
+    if precision == "fp64":
+        assert _pop_err(g.populations(), So, w.mask) <= TOL64
+        sc = np.abs(Fg[:, 1]).max()
+        assert np.abs(Fg[:, 2] - Fg[:, 1]).max() <= 1e-9 * sc
+
+
+def test_deterministic_bitwise_and_chunked_calls():
+    """Two runs give identical populations and forces; 30 steps in one call equal
+    30 steps in calls of 7, 1, 22 (the force rows included)."""
+    w = d3.sphere_channel_64x32x32()
+    outs = []
+    for calls in ((30,), (30,), (7, 1, 22)):
+        g = _sim3(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=64)
+        F = []
+        for n in calls:
+            g.step(n)
+            F.append(g.forces())
+        outs.append((g.populations(), np.concatenate(F)))
+    for p, f in outs[1:]:
+        assert np.array_equal(outs[0][0], p)
+        assert np.array_equal(outs[0][1], f, equal_nan=True)
+
+
+def test_forces_off_same_populations_and_scheme_selection():
+    w = d3.sphere_channel_64x32x32()
+    g1 = _sim3(w.mask, w.tau, w.uin, precision="fp64", box=w.box, max_record=50)
+    g2 = _sim3(w.mask, w.tau, w.uin, precision="fp64", box=w.box, max_record=50)
+    g1.step(20, schemes=())
+    g2.step(20, schemes=("B",))
+    assert np.array_equal(g1.populations(), g2.populations())
+    assert g1.forces().shape == (0, 4, 3)
+    F = g2.forces()
+    assert np.all(np.isnan(F[:, [0, 2, 3]])) and np.all(np.isfinite(F[:, 1]))
+
+
+def test_full_size_naca3d_two_steps():
+    """The benchmark's 3-D airfoil (1920 x 192 x 96, periodic span, box over the whole
+    span) in its launch configuration, FP32, from a seeded random state: every fluid
+    population and every force row of two steps against the oracle."""
+    w = d3.naca3d(24, 200.0)
+    S0 = d3.near_rest_state3(w.nx, w.ny, w.nz, seed=5, amp=0.02, dtype=np.float32)
+    g = _sim3(w.mask, w.tau, w.uin, precision="fp32", bc_z=w.bc_z, box=w.box, max_record=4)
+    g.set_populations(S0)
+    g.step(2)
+    Fg, Sg = g.forces(), g.populations()
+    del g
+    o = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, bc_z=w.bc_z, box=w.box)
+    o.set_state(S0)
+    del S0
+    o.step(2)
+    Fo = o.forces()
+    So = o.state()
+    del o
+    fl = w.mask == 0
+    err = 0.0
+    for i in range(27):
+        err = max(err, float((np.abs(Sg[i] - So[i])[fl] / So[i][fl]).max()))
+    assert err <= 2e-6, err
+    e = _force_err(Fg, Fo)
+    print("full-size 3-D population error", err, "force errors", e)
+    assert np.all(e <= np.array([1e-4, 1e-4, 1e-2, 1e-3])), e
