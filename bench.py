@@ -306,6 +306,92 @@ def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
     }), flush=True)
 
 
+def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
+                  cpu: bool):
+    """The D3Q27 path on the three-dimensional NACA0012 of the paper's Sec. V (zero
+    incidence, domain 80 x 8 x 4 chords, periodic span, control volume over the whole
+    span), all four estimators every step."""
+    import numpy as np
+    import torch
+    from workloads import d3
+    from paper_2210_10377_amd import Sim3
+
+    w = d3.naca3d(ppc, re)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sim = Sim3(w.mask, w.tau, w.uin, precision=precision, bc_z=w.bc_z, box=w.box,
+               max_record=max(steps, warmup, 1), device=dev, stream=stream)
+    info = sim.info()
+    sim.step(warmup)
+    sim.forces()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    F = sim.forces()
+    k_off = min(steps, 300)
+    e0.record(stream)
+    sim.step(k_off, ())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_off = e0.elapsed_time(e1) / k_off
+    t_step = ms / 1e3 / steps
+    nodes = w.nx * w.ny * w.nz
+    bpn = 2 * 27 * (BYTES_PER_NODE[precision] // 18)
+    achieved = info.n_fluid * bpn / t_step / 1e9
+    q = 0.5 * w.u_ref ** 2 * w.area_ref
+    out = {
+        "metric": "D3Q27 MLUPS incl. per-step force + HBM GB/s % peak",
+        "value": round(nodes / t_step / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms / steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
+                  "fp16dev": "f16 storage / f32 arithmetic"}[precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "tau": w.tau,
+                   "storage": precision, "schemes": list(ALL),
+                   "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
+                   "box_nodes": int(info.n_box), "general_strips": int(info.n_general),
+                   "strips": int(info.n_strips), **w.meta},
+        # one step = the main step kernel + the force-strip kernel; bytes are the
+        # algorithmic 2 x 27 populations per fluid node over the whole step's time
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(w.name, precision)},
+        "wall_s": round(wall, 3),
+        "forces_off_ms_per_step": round(ms_off, 5),
+        "force_cost_frac": round((ms / steps - ms_off) / ms_off, 4),
+        "forces_finite": bool(np.isfinite(F).all()) if len(F) else None,
+        "last_coefficients": {s: (F[-1, k] / q).tolist() for k, s in enumerate(ALL)}
+        if len(F) else None,
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if cpu:
+        from oracle import d3q27 as D
+        o = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, bc_z=w.bc_z, box=w.box)
+        t0 = time.perf_counter()
+        o.step(1)
+        o.forces()
+        dt = time.perf_counter() - t0
+        del o
+        out["cpu_baseline"] = {"value": round(nodes / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"1 full-grid step of {w.nx}x{w.ny}x{w.nz} with A, B, "
+                                         f"DRTT and SI forces ({dt:.1f} s, FP64, one thread)"}
+    print(json.dumps(out), flush=True)
+
+
+ALL = ("A", "B", "DRTT", "SI")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,6 +429,10 @@ def main():
                          "Richardson extrapolation from the three finest grids")
     ap.add_argument("--diameters", default="10,15,20,30,40,60")
     ap.add_argument("--convective-times", type=float, default=150.0)
+    ap.add_argument("--three-d", action="store_true",
+                    help="the D3Q27 path on the 3-D NACA0012 (80 x 8 x 4 chords, --ppc nodes "
+                         "per chord, periodic span)")
+    ap.add_argument("--ppc", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
@@ -377,6 +467,11 @@ def main():
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
+        return
+    if args.three_d:
+        three_d_bench(args.precision, args.steps if args.steps != 2000 else 500,
+                      args.warmup if args.warmup != 200 else 50, args.ppc,
+                      args.re if args.re != 1e4 else 200.0, not args.no_cpu_baseline)
         return
     if args.resolution_sweep:
         resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,

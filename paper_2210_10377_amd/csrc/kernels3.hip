@@ -10,7 +10,7 @@
 //     a periodic wrap, bounce-back (wall, body, outlet ghost of a solid node), the inlet
 //     moving-wall rule or the outlet ghost copy; strips with force terms accumulate A, B,
 //     J, Phi and SI in FP64 and reduce them over the wave into their slot.
-// The last block of a launch reduces the previous step's slots, in a fixed order, into
+// The first block of a launch reduces the previous step's slots, in a fixed order, into
 // that step's ring row.  Blocks are mapped to tiles so that runs of 4 neighbouring tiles
 // along x go to one XCD (their +-1-shifted pulls share cache lines in that L2).
 #include <hip/hip_runtime.h>
@@ -201,11 +201,30 @@ __device__ void reduce_row(const double* __restrict__ in, int nslots, int njslot
   __shared__ double red[16][16];
   const int t = threadIdx.x, c = t & 15, g = t >> 4;
   double acc = 0.0;
+  // Eight loads in flight, added in slot order.
   if (c < kPart)
-    for (int s = g; s < nslots; s += 16) acc += in[int64_t(s) * kPart + c];
+    for (int s0 = g; s0 < nslots; s0 += 16 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int s = s0 + 16 * u;
+        v[u] = s < nslots ? in[int64_t(s) * kPart + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
   if (c >= 6 && c < 9) {
     const double* jin = in + int64_t(nslots) * kPart;
-    for (int s = g; s < njslots; s += 16) acc += jin[int64_t(s) * 3 + (c - 6)];
+    for (int s0 = g; s0 < njslots; s0 += 16 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int s = s0 + 16 * u;
+        v[u] = s < njslots ? jin[int64_t(s) * 3 + (c - 6)] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
   }
   red[g][c] = acc;
   __syncthreads();
@@ -230,10 +249,15 @@ __device__ void reduce_row(const double* __restrict__ in, int nslots, int njslot
   }
 }
 
-// Tile of block b: runs of 4 consecutive tiles per XCD (blocks go to XCDs round-robin).
+// Tile of block b: runs of kXcdRun consecutive tiles per XCD (blocks go to the 8 XCDs
+// round-robin).
+#ifndef LBM3_XCD_RUN
+#define LBM3_XCD_RUN 8
+#endif
+constexpr int64_t kXcdRun = LBM3_XCD_RUN;
 __device__ __forceinline__ int64_t tile_of(int64_t b) {
   const int64_t xcd = b & 7, k = b >> 3;
-  return ((k >> 2) * 8 + xcd) * 4 + (k & 3);
+  return ((k / kXcdRun) * 8 + xcd) * kXcdRun + (k % kXcdRun);
 }
 
 // General path of one strip: the boundary-aware pull of every node, collision, store,
@@ -414,11 +438,16 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
   using S = St3<P>;
   using T = typename S::T;
   using C = typename S::C;
-  if (a.red_in && blockIdx.x == gridDim.x - 1) {
-    reduce_row(a.red_in, a.nslots, a.njslots, a.red_row, a.red_prev_jnext, nullptr, 0);
-    return;
+  // With a reducer, blocks 0-7 (one per XCD) come first: block 0 reduces while the
+  // tiles stream, and the tile blocks keep their XCD alignment.
+  int64_t b = blockIdx.x;
+  if (a.red_in) {
+    if (b == 0)
+      reduce_row(a.red_in, a.nslots, a.njslots, a.red_row, a.red_prev_jnext, nullptr, 0);
+    if (b < 8) return;
+    b -= 8;
   }
-  const int64_t tile = tile_of(blockIdx.x);
+  const int64_t tile = tile_of(b);
   if (tile >= a.ntiles) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t e = a.strip[tile * kStrips + wave];
@@ -443,12 +472,28 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
                    (int64_t(kCz[i]) * g.ny + kCy[i]) * g.pitch - kCx[i]]);
     if (FORCES && cls == kBoxJ) {
       double j[3] = {0.0, 0.0, 0.0};
+      if (P == LBM_FP16DEV) {
+        // sum c_i w_i = 0, so the node's momentum is that of its deviations; binary16
+        // deviations are summed in binary32 (the rounding stays far below theirs),
+        // and the nodes in FP64.
+        float jf[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 1; i < kQ; ++i) {
-        const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
-        if (kCx[i]) j[0] += kCx[i] * v;
-        if (kCy[i]) j[1] += kCy[i] * v;
-        if (kCz[i]) j[2] += kCz[i] * v;
+        for (int i = 1; i < kQ; ++i) {
+          if (kCx[i]) jf[0] += kCx[i] > 0 ? float(f[i]) : -float(f[i]);
+          if (kCy[i]) jf[1] += kCy[i] > 0 ? float(f[i]) : -float(f[i]);
+          if (kCz[i]) jf[2] += kCz[i] > 0 ? float(f[i]) : -float(f[i]);
+        }
+        j[0] = jf[0];
+        j[1] = jf[1];
+        j[2] = jf[2];
+      } else {
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+          const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+          if (kCx[i]) j[0] += kCx[i] * v;
+          if (kCy[i]) j[1] += kCy[i] * v;
+          if (kCz[i]) j[2] += kCz[i] * v;
+        }
       }
       wave_store<3>(j, a.part_out + int64_t(a.nslots) * kPart + int64_t(strip_slot(e)) * 3);
     }
@@ -534,8 +579,8 @@ __global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t
 
 template <int P>
 hipError_t step_p(bool forces, const Step3Args& a, hipStream_t s) {
-  const int64_t tiles = (a.ntiles + 31) / 32 * 32;
-  const dim3 grid(unsigned(tiles + (a.red_in ? 1 : 0)));
+  const int64_t tiles = (a.ntiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun);
+  const dim3 grid(unsigned(tiles + (a.red_in ? 8 : 0)));
   if (forces) {
     hipLaunchKernelGGL((step3_kernel<P, true>), grid, dim3(kThreads), 0, s, a);
     if (a.nslots > 0) {
