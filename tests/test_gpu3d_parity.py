@@ -168,3 +168,45 @@ def test_full_size_naca3d_two_steps():
     e = _force_err(Fg, Fo)
     print("full-size 3-D population error", err, "force errors", e)
     assert np.all(e <= np.array([1e-4, 1e-4, 1e-2, 1e-3])), e
+
+
+def test_ring_overflow_zero_steps_and_bad_arguments():
+    """The ring refuses steps it cannot hold (nothing enqueued), zero steps do nothing,
+    unknown scheme bits and negative counts are refused; the state is unchanged by the
+    refusals."""
+    from paper_2210_10377_amd import LbmError
+    w = d3.sphere_channel_64x32x32()
+    g = _sim3(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=8)
+    g.step(5)
+    before = g.populations()
+    with pytest.raises(LbmError, match="overflow"):
+        g.step(4)
+    g.step(0)
+    g.step(1, schemes=())  # no force row: allowed with the ring nearly full
+    assert g.info().steps_done == 6
+    L = g._lib
+    assert L.lbm3d_step(g._h, 1, 1 << 7) == -1
+    assert L.lbm3d_step(g._h, -1, 15) == -1
+    F = g.forces()
+    assert F.shape == (5, 4, 3) and np.isfinite(F).all()
+    g2 = _sim3(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=8)
+    g2.step(5)
+    g2.forces()
+    g2.step(1, schemes=())
+    assert np.array_equal(g.populations(), g2.populations())
+    del before
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN planted in the state reaches the forces: lbm3d_forces reports it
+    (LBM_ENONFINITE) and still returns the rows."""
+    w = d3.sphere_channel_64x32x32()
+    g = _sim3(w.mask, w.tau, w.uin, precision="fp64", box=w.box, max_record=8)
+    S = g.populations()
+    x0, x1, y0, y1, z0, z1 = w.box
+    S[3, (z0 + z1) // 2, y0 + 1, x0 + 1] = np.nan
+    g.set_populations(S)
+    g.step(3)
+    F = g.forces()
+    assert g.last_nonfinite and F.shape == (3, 4, 3)
+    assert not np.isfinite(F[:, 2]).all()

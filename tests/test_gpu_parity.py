@@ -373,3 +373,30 @@ def test_stabilized_cylinder_low_viscosity(precision, collision, low_viscosity_r
     for k in range(4):
         scale = np.abs(Fo[:, k]).max()
         assert np.abs(Fg[:, k] - Fo[:, k]).max() <= tol * scale, k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_naca_2048x1024_two_steps(precision):
+    """The 2048x1024 NACA0012 channel of the precision study (chord 256, AoA 4, Re 1000)
+    from a seeded random state exactly representable in the storage: every fluid
+    population and every force row of two steps against the oracle (FP64 to 1e-10)."""
+    w = workloads.naca_2048x1024()
+    if precision == "fp16dev":
+        S0 = workloads.near_rest_state_fp16dev(w.nx, w.ny, seed=13, amp=0.02)
+    else:
+        dt = np.float32 if precision == "fp32" else np.float64
+        S0 = workloads.near_rest_state(w.nx, w.ny, seed=13, amp=0.02, dtype=dt)
+    g = _sim(mask=w.mask, tau=w.tau, uin=w.uin, precision=precision, box=w.box, max_record=4)
+    g.set_populations(S0)
+    g.step(2)
+    o = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+    o.set_state(S0)
+    o.step(2)
+    err = _pop_err(g.populations(), o.state(), w.mask)
+    e = _force_err(g.forces(), o.forces())
+    print(precision, "2048x1024 population error", err, "force errors", e)
+    tol_pop = {"fp64": 1e-10, "fp32": 2e-6, "fp16dev": 2e-3}[precision]
+    tol_f = {"fp64": np.full(4, 1e-10), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3]),
+             "fp16dev": np.array([5e-2, 5e-2, 5e-1, 5e-2])}[precision]
+    assert err <= tol_pop, err
+    assert np.all(e <= tol_f), e
