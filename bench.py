@@ -246,6 +246,53 @@ def sphere_sweep(diameters, t_conv: float, precision: str, re: float):
     print(json.dumps(summary), flush=True)
 
 
+def small_grid_bench(precision: str, steps: int):
+    """The 200x80 cylinder channel (D 20, Re 20; the FP64 parity configuration): a grid
+    of 16,000 nodes is bound by launch latency, not by HBM.  Direct `lbm_step` launches
+    against the same lattice as a one-member batch replaying captured HIP graphs of 64
+    launches (bitwise the same results); all four forces every step."""
+    import torch
+    import workloads
+    from paper_2210_10377_amd import Batch, Sim
+
+    w = workloads.cylinder_channel_200x80()
+    out = {"metric": "small-grid MLUPS incl. per-step forces", "workload": w.name,
+           "storage": precision, "steps": steps}
+    sim = Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=steps + 200)
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    sim.step(200)
+    sim.forces()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_direct = e0.elapsed_time(e1) / steps
+    F_direct = sim.forces()
+    del sim
+    b = Batch([Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=1)],
+              max_record=steps + 200)
+    b.set_schedule(grid_blocks=0, graph_steps=64)
+    b.step(200)
+    b.forces()
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    F_graph, _ = b.forces()
+    nodes = w.nx * w.ny
+    out.update({"direct_us_per_step": round(ms_direct * 1e3, 3),
+                "direct_mlups": round(nodes / ms_direct / 1e3, 1),
+                "graph_us_per_step": round(ms_graph * 1e3, 3),
+                "graph_mlups": round(nodes / ms_graph / 1e3, 1),
+                "same_forces": bool((F_direct == F_graph[0]).all())})
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_bench(precision: str):
     """Forward (checkpointed) and backward (recompute + reverse kernels) throughput of
     the adjoint workload; MLUPS = nx * ny * steps / wall time of each phase."""
@@ -497,6 +544,8 @@ def main():
                     help="the D3Q27 path on the 3-D NACA0012 (80 x 8 x 4 chords, --ppc nodes "
                          "per chord, periodic span)")
     ap.add_argument("--ppc", type=int, default=24)
+    ap.add_argument("--small-grid", action="store_true",
+                    help="the 200x80 cylinder: direct launches against captured graphs")
     ap.add_argument("--sphere-sweep", action="store_true",
                     help="3-D grid-requirement study: sphere drag against points per "
                          "diameter for A, B, DRTT and SI (--sphere-diameters, --re)")
@@ -535,6 +584,10 @@ def main():
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
+        return
+    if args.small_grid:
+        small_grid_bench(args.precision if args.precision != "fp32" else "fp64",
+                         args.steps if args.steps != 2000 else 5000)
         return
     if args.sphere_sweep:
         sphere_sweep([int(v) for v in args.sphere_diameters.split(",")],
