@@ -17,7 +17,10 @@ class _Cfg3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
                 ("box", ctypes.c_int32 * 6), ("rho_w", ctypes.c_double),
-                ("g", ctypes.c_double * 3)]
+                ("g", ctypes.c_double * 3), ("collision", ctypes.c_int32)]
+
+
+COLLISIONS = {"bgk": 0, "regularized": 1}
 
 
 _lib = None
@@ -35,6 +38,7 @@ def lib():
         L.orc3_lattice.argtypes = [ip, ip, ip, ip, dp]
         L.orc3_equilibrium.argtypes = [ctypes.c_double] * 4 + [dp]
         L.orc3_collide_node.argtypes = [dp] + [ctypes.c_double] * 4 + [dp]
+        L.orc3_collide_node_regularized.argtypes = [dp, ctypes.c_double, dp]
         L.orc3_box_admissible.argtypes = [cp, u8]
         L.orc3_box_admissible.restype = ctypes.c_int
         L.orc3_links.argtypes = [cp, u8, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]
@@ -57,7 +61,7 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g):
+def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g, collision="bgk"):
     nz, ny, nx = shape
     c = _Cfg3()
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -68,6 +72,7 @@ def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g):
     c.rho_w = float(rho_w)
     for k in range(3):
         c.g[k] = float(g[k])
+    c.collision = COLLISIONS[collision]
     return c
 
 
@@ -92,11 +97,16 @@ def equilibrium(rho, ux, uy, uz):
     return out
 
 
-def collide_node(f, omega, g=(0.0, 0.0, 0.0)):
+def collide_node(f, omega, g=(0.0, 0.0, 0.0), collision="bgk"):
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros(27)
-    lib().orc3_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), float(g[2]),
-                            _dp(out))
+    if collision == "regularized":
+        if any(g):
+            raise ValueError("only the BGK collision takes a body force")
+        lib().orc3_collide_node_regularized(_dp(f), float(omega), _dp(out))
+    else:
+        lib().orc3_collide_node(_dp(f), float(omega), float(g[0]), float(g[1]), float(g[2]),
+                                _dp(out))
     return out
 
 
@@ -118,15 +128,17 @@ def links(mask, bc_x=BCX_INLET_OUTLET, bc_y=BC_WALL, bc_z=BC_WALL):
 
 class OracleSim3:
     """FP64 reference simulation on a [nz, ny, nx] lattice.  ``uin`` is the inlet
-    x-velocity, broadcast to [nz, ny]; ``box`` = (x0, x1, y0, y1, z0, z1)."""
+    x-velocity, broadcast to [nz, ny]; ``box`` = (x0, x1, y0, y1, z0, z1); ``collision``
+    "bgk" (Eq. CollideAdv) or "regularized"."""
 
     def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BC_WALL,
-                 bc_z=BC_WALL, box=None, rho_w=1.0, g=(0.0, 0.0, 0.0), omega=None):
+                 bc_z=BC_WALL, box=None, rho_w=1.0, g=(0.0, 0.0, 0.0), omega=None,
+                 collision="bgk"):
         m, mp = _mask(mask)
         self.nz, self.ny, self.nx = m.shape
         self.omega = float(omega) if omega is not None else 1.0 / float(tau)
         self.box = box
-        self._cfg = _cfg(m.shape, bc_x, bc_y, bc_z, box, rho_w, g)
+        self._cfg = _cfg(m.shape, bc_x, bc_y, bc_z, box, rho_w, g, collision)
         u = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),

@@ -38,6 +38,7 @@
 //    along a periodic axis the box may span the whole axis (then it has no surface
 //    there and neighbours wrap into it), which lets a body spanning a periodic
 //    direction (an airfoil of infinite span) have a control volume;
+//  * collision: BGK (Eq. CollideAdv) or the regularized variant (not in the paper);
 //  * stress integration: unit faces crossed by the six axis links; traction
 //    (-p I + sigma) . n, n = -c_i, at the link's fluid node from its pre-collision
 //    populations, p = rho theta0, sigma = -(1 - omega/2) sum f^neq c c.
@@ -109,11 +110,44 @@ void collide_node(const double* f, double omega, const double* g, double* out) {
   }
 }
 
+// Regularized BGK (Latt & Chopard 2006; not in the paper), as in the two-dimensional
+// oracle: the non-equilibrium part is replaced by its projection on the second-order
+// Hermite polynomials, f^(1)_i = w_i / (2 theta0^2) Q_i : Pi^neq with
+// Q_i = c_i c_i - theta0 I and Pi^neq = sum_k (f_k - f_k^eq) c_k c_k, and relaxed:
+// f~_i = f^eq_i + (1 - omega) f^(1)_i.
+void collide_node_regularized(const double* f, double omega, double* out) {
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    j[0] += CX[i] * f[i];
+    j[1] += CY[i] * f[i];
+    j[2] += CZ[i] * f[i];
+  }
+  const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  double feq[NQ], Pi[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int i = 0; i < NQ; ++i) {
+    feq[i] = equilibrium(i, rho, u[0], u[1], u[2]);
+    const int c[3] = {CX[i], CY[i], CZ[i]};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Pi[a][b] += double(c[a] * c[b]) * (f[i] - feq[i]);
+  }
+  for (int i = 0; i < NQ; ++i) {
+    const int c[3] = {CX[i], CY[i], CZ[i]};
+    double q = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) q += (double(c[a] * c[b]) - (a == b ? THETA0 : 0.0)) * Pi[a][b];
+    out[i] = feq[i] + (1.0 - omega) * weight(i) / (2.0 * THETA0 * THETA0) * q;
+  }
+}
+
+enum { COLLISION_BGK = 0, COLLISION_REGULARIZED = 1 };
+
 struct Config3 {
   int32_t nx, ny, nz, bc_x, bc_y, bc_z;
   int32_t box[6];  // x0, x1, y0, y1, z0, z1; x0 < 0: no control volume
   double rho_w;
-  double g[3];     // body force (test fixtures only)
+  double g[3];     // body force (test fixtures only; BGK only)
+  int32_t collision;  // COLLISION_BGK or COLLISION_REGULARIZED
 };
 
 // Per-step record: FA(3), FB(3), J(3), Phi(3), SI(3).
@@ -218,7 +252,10 @@ struct Sim3 {
           if (is_solid(x, y, z)) continue;
           double fin[NQ], fout[NQ];
           for (int i = 0; i < NQ; ++i) fin[i] = f[idx(i, x, y, z)];
-          collide_node(fin, omega, cfg.g, fout);
+          if (cfg.collision == COLLISION_REGULARIZED)
+            collide_node_regularized(fin, omega, fout);
+          else
+            collide_node(fin, omega, cfg.g, fout);
           for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y, z)] = fout[i];
         }
     // Momentum exchange on every link: c_i (f_i + f_o(x, t+1)) (A) and
@@ -350,6 +387,9 @@ bool config_valid(const Config3& c, const uint8_t* mask) {
   if (c.bc_x != BCX_INLET_OUTLET && c.bc_x != BCX_PERIODIC) return false;
   if (c.bc_y != BC_WALL && c.bc_y != BC_PERIODIC) return false;
   if (c.bc_z != BC_WALL && c.bc_z != BC_PERIODIC) return false;
+  if (c.collision != COLLISION_BGK && c.collision != COLLISION_REGULARIZED) return false;
+  if (c.collision != COLLISION_BGK && (c.g[0] != 0.0 || c.g[1] != 0.0 || c.g[2] != 0.0))
+    return false;
   for (size_t k = 0; k < size_t(c.nx) * c.ny * c.nz; ++k)
     if (mask[k] > 1) return false;
   return box_admissible(c, mask);
@@ -379,6 +419,10 @@ void orc3_collide_node(const double* f, double omega, double gx, double gy, doub
                        double* out) {
   const double g[3] = {gx, gy, gz};
   collide_node(f, omega, g, out);
+}
+
+void orc3_collide_node_regularized(const double* f, double omega, double* out) {
+  collide_node_regularized(f, omega, out);
 }
 
 int orc3_box_admissible(const orc3_cfg* c, const uint8_t* mask) {

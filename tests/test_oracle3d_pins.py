@@ -131,8 +131,9 @@ def _marginal(S3, lat):
     return out
 
 
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
 @pytest.mark.parametrize("bcx", [BCX_INLET_OUTLET, BCX_PERIODIC])
-def test_span_invariant_flow_reduces_to_the_two_dimensional_oracle(lat, bcx):
+def test_span_invariant_flow_reduces_to_the_two_dimensional_oracle(lat, bcx, collision):
     """An extruded body in a lattice periodic across the span, started from a
     span-invariant state: the z-marginal of the D3Q27 state equals the D2Q9 oracle's
     state, and the x, y forces of every estimator equal nz times the two-dimensional ones
@@ -150,12 +151,13 @@ def test_span_invariant_flow_reduces_to_the_two_dimensional_oracle(lat, bcx):
     S3 = np.zeros((27, nz, ny, nx))
     for i in range(27):
         S3[i] = frac[cz[i]] * S2[order2.index((cx[i], cy[i]))][None]
-    o2 = OracleSim(m2, tau=0.7, uin=uin, bc_x=bcx, bc_y=BCY_WALL, box=box2)
+    o2 = OracleSim(m2, tau=0.7, uin=uin, bc_x=bcx, bc_y=BCY_WALL, box=box2,
+                   collision=collision)
     o2.set_state(S2)
     o3 = D.OracleSim3(d3.extrude(m2, nz), tau=0.7,
                       uin=None if uin is None else np.broadcast_to(uin, (nz, ny)),
                       bc_x=bcx, bc_y=D.BC_WALL, bc_z=D.BC_PERIODIC,
-                      box=box2 + (0, nz))
+                      box=box2 + (0, nz), collision=collision)
     o3.set_state(S3)
     o2.step(25)
     o3.step(25)
@@ -267,3 +269,57 @@ def test_box_admissibility_per_axis():
     assert not D.box_admissible(m, (5, 26, 2, 18, 0, nz), bc_y=D.BC_WALL, bc_z=D.BC_WALL)
     assert not D.box_admissible(m, (0, 26, 2, 18, 0, nz), **kw)
     assert not D.box_admissible(m, (5, 26, 6, 18, 0, nz), **kw)
+
+
+# --------------------------------------------------------------------------------------
+# Regularized BGK in three dimensions (not in the paper; the stabilized variant for
+# tau_lb close to 1/2).  The span-invariant reduction above covers it as well.
+# --------------------------------------------------------------------------------------
+
+def _moments(f, C):
+    rho = f.sum()
+    u = C.T @ f / rho
+    return rho, u
+
+
+def _pi_neq(f, C):
+    rho, u = _moments(f, C)
+    neq = f - D.equilibrium(rho, *u)
+    return np.einsum("i,ia,ib->ab", neq, C, C)
+
+
+def test_regularized_conserves_and_relaxes_the_stress_exactly(lat):
+    """Mass and momentum are conserved and the non-equilibrium stress is multiplied by
+    exactly (1 - omega): the Hermite projection keeps the second moment."""
+    cx, cy, cz, _, _ = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    f = d3.near_rest_state3(1, 1, 1, seed=6, amp=0.3)[:, 0, 0, 0]
+    for om in (0.7, 1.3, 1.95):
+        out = D.collide_node(f, om, collision="regularized")
+        assert abs(out.sum() - f.sum()) < 1e-15
+        np.testing.assert_allclose(C.T @ out, C.T @ f, atol=1e-16)
+        np.testing.assert_allclose(_pi_neq(out, C), (1 - om) * _pi_neq(f, C), atol=1e-15)
+
+
+def test_regularized_equals_bgk_for_second_order_and_removes_ghosts(lat):
+    """With a non-equilibrium part that is purely second order the regularized step is
+    the BGK step; a ghost mode (no mass, momentum or stress) is removed entirely by it
+    and only relaxed by BGK."""
+    cx, cy, cz, _, w = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    rho, u = 1.02, np.array([0.03, -0.01, 0.02])
+    feq = D.equilibrium(rho, *u)
+    Pi = np.array([[2e-3, 5e-4, -3e-4], [5e-4, -1e-3, 7e-4], [-3e-4, 7e-4, -1e-3]])
+    Q = np.einsum("ia,ib->iab", C, C) - np.eye(3) / 3
+    f1 = w * 4.5 * np.einsum("iab,ab->i", Q, Pi)
+    f = feq + f1
+    np.testing.assert_allclose(D.collide_node(f, 1.4, collision="regularized"),
+                               D.collide_node(f, 1.4), rtol=0, atol=3e-16)
+    # a ghost: the product c_x c_y c_z weighted to kill every moment up to second order
+    g = w * cx * cy * cz * 1e-3
+    assert abs(g.sum()) < 1e-18 and np.abs(C.T @ g).max() < 1e-18
+    assert np.abs(np.einsum("i,ia,ib->ab", g, C, C)).max() < 1e-18
+    np.testing.assert_allclose(D.collide_node(feq + g, 1.4, collision="regularized"), feq,
+                               rtol=0, atol=3e-16)
+    np.testing.assert_allclose(D.collide_node(feq + g, 1.4), feq + (1 - 1.4) * g,
+                               rtol=0, atol=3e-16)
