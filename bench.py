@@ -418,7 +418,7 @@ def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
 
 
 def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
-                  cpu: bool):
+                  cpu: bool, collision: str = "bgk"):
     """The D3Q27 path on the three-dimensional NACA0012 of the paper's Sec. V (zero
     incidence, domain 80 x 8 x 4 chords, periodic span, control volume over the whole
     span), all four estimators every step."""
@@ -432,7 +432,8 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     sim = Sim3(w.mask, w.tau, w.uin, precision=precision, bc_z=w.bc_z, box=w.box,
-               max_record=max(steps, warmup, 1), device=dev, stream=stream)
+               max_record=max(steps, warmup, 1), device=dev, stream=stream,
+               collision=collision)
     info = sim.info()
     sim.step(warmup)
     sim.forces()
@@ -467,7 +468,7 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
                   "fp16dev": "f16 storage / f32 arithmetic"}[precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "tau": w.tau,
-                   "storage": precision, "schemes": list(ALL),
+                   "storage": precision, "collision": collision, "schemes": list(ALL),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
                    "box_nodes": int(info.n_box), "general_strips": int(info.n_general),
                    "strips": int(info.n_strips), **w.meta},
@@ -487,7 +488,8 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
     torch.cuda.empty_cache()
     if cpu:
         from oracle import d3q27 as D
-        o = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, bc_z=w.bc_z, box=w.box)
+        o = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, bc_z=w.bc_z, box=w.box,
+                         collision=collision)
         t0 = time.perf_counter()
         o.step(1)
         o.forces()
@@ -598,7 +600,8 @@ def main():
     if args.three_d:
         three_d_bench(args.precision, args.steps if args.steps != 2000 else 500,
                       args.warmup if args.warmup != 200 else 50, args.ppc,
-                      args.re if args.re != 1e4 else 200.0, not args.no_cpu_baseline)
+                      args.re if args.re != 1e4 else 200.0, not args.no_cpu_baseline,
+                      args.collision if args.collision != "kbc" else "bgk")
         return
     if args.resolution_sweep:
         resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,

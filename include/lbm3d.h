@@ -68,6 +68,8 @@ typedef struct {
   int32_t box[6];       /* x0, x1, y0, y1, z0, z1; box[0] < 0: no control volume     */
   int32_t precision;    /* LBM_FP64, LBM_FP32, LBM_FP32DEV, LBM_FP16DEV              */
   int32_t max_record;   /* rows of the force ring (>= 1)                             */
+  int32_t collision;    /* LBM_COLL_BGK or LBM_COLL_REGULARIZED (the regularized BGK of
+                           lbm.h with the D3Q27 Hermite projection; not in the paper) */
 } lbm3d_grid;
 
 typedef struct {
@@ -83,8 +85,9 @@ typedef struct {
 /* Plan a lattice: classify every node from the mask ([nz][ny][nx] bytes, 0 fluid /
  * 1 solid, copied) and the boundary codes.  tau: tau_lb > 1/2.  uin: [nz][ny] inlet
  * x-velocities (host, copied), required when bc_x is inlet/outlet, else ignored;
- * rho_w: inlet wall density (> 0).  LBM_EINVAL for a bad code, size, mask value, box
- * or tau (lbm3d_last_error(NULL) says which); LBM_ENOMEM when the grid is too large. */
+ * rho_w: inlet wall density (> 0).  LBM_EINVAL for a bad code, size, mask value, box,
+ * collision or tau (lbm3d_last_error(NULL) says which); LBM_ENOMEM when the grid is too
+ * large. */
 int lbm3d_create(const lbm3d_grid* grid, const uint8_t* solid_mask, double tau,
                  const double* uin, double rho_w, lbm3d_t** out);
 

@@ -65,7 +65,7 @@ class lbm3d_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
                 ("box", ctypes.c_int32 * 6), ("precision", ctypes.c_int32),
-                ("max_record", ctypes.c_int32)]
+                ("max_record", ctypes.c_int32), ("collision", ctypes.c_int32)]
 
 
 class lbm3d_info(ctypes.Structure):

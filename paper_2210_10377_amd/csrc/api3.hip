@@ -97,6 +97,7 @@ int enqueue3(lbm3d* h, int32_t n, double* ring) {
   a.strip = reinterpret_cast<const uint32_t*>(h->ws + h->off_strip);
   a.fstrips = reinterpret_cast<const uint32_t*>(h->ws + h->off_fstrip);
   a.omega = 1.0 / h->tau;
+  a.collision = h->g.collision;
   a.nslots = p.nslots;
   a.njslots = p.njslots;
   const int c0 = h->cur;
@@ -166,6 +167,10 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
   }
   if (g.max_record < 1) {
     g_err3 = "max_record must be >= 1";
+    return LBM_EINVAL;
+  }
+  if (g.collision != LBM_COLL_BGK && g.collision != LBM_COLL_REGULARIZED) {
+    g_err3 = "unknown collision (BGK or regularized)";
     return LBM_EINVAL;
   }
   lbm3d* h = new (std::nothrow) lbm3d();

@@ -30,6 +30,7 @@ struct Step3Args {
   const uint32_t* strip;     // [ntiles * 4] strip table
   const uint32_t* fstrips;   // [nslots] strip index of each force slot
   double omega;
+  int32_t collision;         // LBM_COLL_BGK or LBM_COLL_REGULARIZED
   int32_t nslots, njslots;   // force slots (15 doubles), J slots (3 doubles)
   double* part_out;          // partials of this step: [nslots][15] then [njslots][3]
   // Reducer (last block of the launch): the previous step's partials into its ring row,

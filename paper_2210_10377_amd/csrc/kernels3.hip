@@ -69,8 +69,11 @@ __device__ __forceinline__ void st_nt(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
-// BGK collision (Eq. CollideAdv) of one node, in place, f or deviations h = f - w.
-template <class C, bool DEV>
+// Collision of one node, in place, f or deviations h = f - w: BGK (Eq. CollideAdv), or
+// with COLL = LBM_COLL_REGULARIZED the non-equilibrium part replaced by its projection
+// w_i / (2 theta0^2) Q_i : Pi^neq on the second-order Hermite polynomials
+// (Q_i = c_i c_i - theta0 I) and relaxed: f~ = f^eq + (1 - omega) f^(1).
+template <class C, bool DEV, int COLL>
 __device__ __forceinline__ void collide27(C (&f)[kQ], C omega) {
   C r = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -84,6 +87,34 @@ __device__ __forceinline__ void collide27(C (&f)[kQ], C omega) {
   const C inv = C(1) / rho;
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+  if (COLL == LBM_COLL_REGULARIZED) {
+    C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy + C(kCz[i]) * uz;
+      const C poly = C(3) * cu + C(4.5) * cu * cu - usq;
+      const C feq = DEV ? w27<C>(i) * (r + rho * poly) : w27<C>(i) * rho * (C(1) + poly);
+      const C d = f[i] - feq;
+      if (kCx[i]) pxx += d;
+      if (kCy[i]) pyy += d;
+      if (kCz[i]) pzz += d;
+      if (kCx[i] * kCy[i]) pxy += kCx[i] * kCy[i] > 0 ? d : -d;
+      if (kCx[i] * kCz[i]) pxz += kCx[i] * kCz[i] > 0 ? d : -d;
+      if (kCy[i] * kCz[i]) pyz += kCy[i] * kCz[i] > 0 ? d : -d;
+      f[i] = feq;
+    }
+    const C tr = (pxx + pyy + pzz) / C(3);
+    const C k1 = (C(1) - omega) * C(4.5);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const C q = C(kCx[i] * kCx[i]) * pxx + C(kCy[i] * kCy[i]) * pyy +
+                  C(kCz[i] * kCz[i]) * pzz +
+                  C(2) * (C(kCx[i] * kCy[i]) * pxy + C(kCx[i] * kCz[i]) * pxz +
+                          C(kCy[i] * kCz[i]) * pyz) - tr;
+      f[i] += k1 * w27<C>(i) * q;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy + C(kCz[i]) * uz;
@@ -262,7 +293,7 @@ __device__ __forceinline__ int64_t tile_of(int64_t b) {
 
 // General path of one strip: the boundary-aware pull of every node, collision, store,
 // and with FTERMS the force terms reduced over the wave into the strip's slot.
-template <int P, bool FTERMS>
+template <int P, bool FTERMS, int COLL>
 __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, int64_t row, int x,
                                               int y, int z, int lane) {
   using S = St3<P>;
@@ -361,7 +392,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
     for (int k = 0; k < 9; ++k) mine_pre = lane == k ? pre[k] : mine_pre;
   }
   if (fluid) {
-    collide27<C, S::kDev>(f, omega);
+    collide27<C, S::kDev, COLL>(f, omega);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       const T q = T(f[i]);
@@ -433,7 +464,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
   }
 }
 
-template <int P, bool FORCES>
+template <int P, bool FORCES, int COLL>
 __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
   using S = St3<P>;
   using T = typename S::T;
@@ -497,19 +528,19 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
       }
       wave_store<3>(j, a.part_out + int64_t(a.nslots) * kPart + int64_t(strip_slot(e)) * 3);
     }
-    collide27<C, S::kDev>(f, omega);
+    collide27<C, S::kDev, COLL>(f, omega);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.plane + self, T(f[i]));
     return;
   }
   // Strips with force terms run in force3_kernel when forces are evaluated.
   if (FORCES && cls == kForce) return;
-  general_strip<P, false>(a, e, row, x, y, z, lane);
+  general_strip<P, false, COLL>(a, e, row, x, y, z, lane);
 }
 
 // The strips with force terms (one wave per slot, in slot order): the general path
 // with A, B, J, Phi and SI.
-template <int P>
+template <int P, int COLL>
 __global__ __launch_bounds__(kThreads) void force3_kernel(Step3Args a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t slot = int64_t(blockIdx.x) * kStrips + wave;
@@ -521,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void force3_kernel(Step3Args a) {
   const int64_t row = tile / a.ntx;
   const int y = int(row % a.g.ny), z = int(row / a.g.ny);
   const int x = tx * kTileW + int(si % kStrips) * kStripW + lane;
-  general_strip<P, true>(a, e, row, x, y, z, lane);
+  general_strip<P, true, COLL>(a, e, row, x, y, z, lane);
 }
 
 // J of the pull of the state src over V, per block of 256 nodes along x in a box row.
@@ -577,22 +608,28 @@ __global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t
   }
 }
 
-template <int P>
-hipError_t step_p(bool forces, const Step3Args& a, hipStream_t s) {
+template <int P, int COLL>
+hipError_t step_pc(bool forces, const Step3Args& a, hipStream_t s) {
   const int64_t tiles = (a.ntiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun);
   const dim3 grid(unsigned(tiles + (a.red_in ? 8 : 0)));
   if (forces) {
-    hipLaunchKernelGGL((step3_kernel<P, true>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step3_kernel<P, true, COLL>), grid, dim3(kThreads), 0, s, a);
     if (a.nslots > 0) {
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       const unsigned fblocks = unsigned((a.nslots + kStrips - 1) / kStrips);
-      hipLaunchKernelGGL((force3_kernel<P>), dim3(fblocks), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL((force3_kernel<P, COLL>), dim3(fblocks), dim3(kThreads), 0, s, a);
     }
   } else {
-    hipLaunchKernelGGL((step3_kernel<P, false>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step3_kernel<P, false, COLL>), grid, dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <int P>
+hipError_t step_p(bool forces, const Step3Args& a, hipStream_t s) {
+  return a.collision == LBM_COLL_REGULARIZED ? step_pc<P, LBM_COLL_REGULARIZED>(forces, a, s)
+                                             : step_pc<P, LBM_COLL_BGK>(forces, a, s);
 }
 
 }  // namespace

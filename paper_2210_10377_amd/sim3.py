@@ -7,17 +7,18 @@ import ctypes
 import numpy as np
 
 from . import _capi as C
-from .sim import ALL_SCHEMES, PRECISIONS, scheme_mask
+from .sim import ALL_SCHEMES, COLLISIONS, PRECISIONS, scheme_mask
 
 
 class Sim3:
     """mask: uint8 [nz, ny, nx] (1 = solid).  tau: tau_lb.  uin: inlet x-velocity,
     scalar or [nz, ny] (ignored for periodic x).  box: (x0, x1, y0, y1, z0, z1) or None.
-    bc_y, bc_z: C.LBM_BCY_WALL or C.LBM_BCY_PERIODIC."""
+    bc_y, bc_z: C.LBM_BCY_WALL or C.LBM_BCY_PERIODIC.  collision: "bgk" or
+    "regularized"."""
 
     def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, bc_z=C.LBM_BCY_WALL, box=None, max_record=1024,
-                 rho_w=1.0, device="cuda", stream=None):
+                 rho_w=1.0, device="cuda", stream=None, collision="bgk"):
         import torch
 
         self._lib = C.load()
@@ -32,6 +33,8 @@ class Sim3:
             g.box[k] = b[k]
         g.precision = PRECISIONS[precision]
         g.max_record = int(max_record)
+        g.collision = COLLISIONS[collision]
+        self.collision = collision
         up = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),
@@ -112,7 +115,8 @@ class Plan3:
     """A planned, unbound 3-D handle (no device needed): links and info for CPU checks."""
 
     def __init__(self, mask, tau=0.8, uin=0.0, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
-                 bc_y=C.LBM_BCY_WALL, bc_z=C.LBM_BCY_WALL, box=None, max_record=16):
+                 bc_y=C.LBM_BCY_WALL, bc_z=C.LBM_BCY_WALL, box=None, max_record=16,
+                 collision="bgk"):
         self._lib = C.load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         nz, ny, nx = mask.shape
@@ -123,6 +127,7 @@ class Plan3:
             g.box[k] = b[k]
         g.precision = PRECISIONS[precision]
         g.max_record = int(max_record)
+        g.collision = COLLISIONS[collision]
         self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (nz, ny)))
         h = ctypes.c_void_p()
         C.check3(self._lib.lbm3d_create(ctypes.byref(g),

@@ -110,7 +110,8 @@ def test_box_counts_and_admissibility_agree_with_oracle(capi):
             L.lbm3d_destroy(h)
 
 
-@pytest.mark.parametrize("case", ["tau", "bc", "mask", "precision", "record", "inlet", "size"])
+@pytest.mark.parametrize("case", ["tau", "bc", "mask", "precision", "record", "inlet", "size",
+                                  "collision"])
 def test_create_rejects_invalid(capi, case):
     L = capi.load()
     nx, ny, nz = 12, 10, 8
@@ -138,6 +139,8 @@ def test_create_rejects_invalid(capi, case):
     elif case == "size":
         g.nz = 1
         m = np.zeros((1, ny, nx), np.uint8)
+    elif case == "collision":
+        g.collision = capi.LBM_COLL_KBC   # not offered in three dimensions
     h = ctypes.c_void_p()
     rc = L.lbm3d_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tau,
                         up, 1.0, ctypes.byref(h))

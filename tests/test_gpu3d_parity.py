@@ -210,3 +210,44 @@ def test_nonfinite_state_is_reported():
     F = g.forces()
     assert g.last_nonfinite and F.shape == (3, 4, 3)
     assert not np.isfinite(F[:, 2]).all()
+
+
+@pytest.mark.parametrize("name", ["sphere_walls_box", "extruded_periodic_span", "edges_no_box"])
+def test_fp64_regularized_small_cases(name):
+    """The regularized collision (for tau_lb near 1/2) at tau_lb 0.505 from a random
+    near-rest state, 40 steps, FP64: populations and forces to 1e-10 of the oracle."""
+    mk, (bx, by, bz), box, u = CASES[name]
+    mask = mk()
+    nz, ny, nx = mask.shape
+    uin = None if bx == 1 else np.full((nz, ny), u)
+    S0 = d3.near_rest_state3(nx, ny, nz, seed=40 + len(name), amp=0.05)
+    o = D.OracleSim3(mask, tau=0.505, uin=uin, bc_x=bx, bc_y=by, bc_z=bz, box=box,
+                     collision="regularized")
+    o.set_state(S0)
+    o.step(40)
+    g = _sim3(mask, 0.505, uin, precision="fp64", bc_x=bx, bc_y=by, bc_z=bz, box=box,
+              max_record=64, collision="regularized")
+    g.set_populations(S0)
+    g.step(40)
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    cols = (0, 1, 2, 3) if box is not None else (0, 1, 3)
+    e = _force_err(g.forces(), o.forces(), cols)
+    assert np.all(e <= TOL64), e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_regularized_sphere_low_viscosity(precision):
+    """The sphere duct at tau_lb 0.506 (Re 200 on the diameter) with the regularized
+    collision, 300 steps from rest: FP64 forces to 1e-10 of the oracle, 32-bit deviation
+    storage to 1e-3 (relative to the largest force)."""
+    w = d3.sphere_channel_64x32x32()
+    tau = 0.506
+    o = D.OracleSim3(w.mask, tau=tau, uin=w.uin, box=w.box, collision="regularized")
+    o.step(300)
+    Fo = o.forces()
+    g = _sim3(w.mask, tau, w.uin, precision=precision, box=w.box, max_record=300,
+              collision="regularized")
+    Fg = g.run(300)
+    assert np.isfinite(Fg).all()
+    e = _force_err(Fg, Fo)
+    assert np.all(e <= (TOL64 if precision == "fp64" else 1e-3)), e
