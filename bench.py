@@ -30,25 +30,32 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 BATCH_WORKLOAD = "batched_256_cylinder_naca0012_64x32_to_512x256"
 
 
-def kernel_hash() -> str:
-    """sha256 over the library sources (kernel, launch layout and plan)."""
+SOURCES_3D = ("api3.hip", "kernels3.h", "kernels3.hip", "plan3.cpp", "plan3.h")
+
+
+def kernel_hash(three_d: bool = False) -> str:
+    """sha256 over the library sources of one path (kernels, launch layout and plan):
+    the three-dimensional files, or all the others; the public headers included."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    names = [n for n in sorted(os.listdir(CSRC)) if (n in SOURCES_3D) == three_d]
+    files = [os.path.join(CSRC, n) for n in names]
+    files.append(os.path.join(ROOT, "include", "lbm3d.h" if three_d else "lbm.h"))
+    for path in files:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def measured_traffic(workload: str, precision: str, three_d: bool = False):
+    """HBM bytes per step from the committed rocprofv3 counter summary, or None when the
+    path's sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     rec = t.get(f"{workload}/{precision}")
-    if not rec or rec.get("sources_sha256") != kernel_hash():
+    if not rec or rec.get("sources_sha256") != kernel_hash(three_d):
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -476,7 +483,7 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
         # algorithmic 2 x 27 populations per fluid node over the whole step's time
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(w.name, precision)},
+                     "traffic": measured_traffic(w.name, precision, three_d=True)},
         "wall_s": round(wall, 3),
         "forces_off_ms_per_step": round(ms_off, 5),
         "force_cost_frac": round((ms / steps - ms_off) / ms_off, 4),
