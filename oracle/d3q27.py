@@ -17,7 +17,9 @@ class _Cfg3(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
                 ("box", ctypes.c_int32 * 6), ("rho_w", ctypes.c_double),
-                ("g", ctypes.c_double * 3), ("collision", ctypes.c_int32)]
+                ("g", ctypes.c_double * 3), ("collision", ctypes.c_int32),
+                ("body_u", ctypes.c_double * 3), ("body_omega", ctypes.c_double * 3),
+                ("body_c", ctypes.c_double * 3)]
 
 
 COLLISIONS = {"bgk": 0, "regularized": 1}
@@ -61,7 +63,7 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g, collision="bgk"):
+def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g, collision="bgk", body_motion=None):
     nz, ny, nx = shape
     c = _Cfg3()
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
@@ -73,6 +75,10 @@ def _cfg(shape, bc_x, bc_y, bc_z, box, rho_w, g, collision="bgk"):
     for k in range(3):
         c.g[k] = float(g[k])
     c.collision = COLLISIONS[collision]
+    if body_motion is not None:
+        U, W, X = body_motion
+        for k in range(3):
+            c.body_u[k], c.body_omega[k], c.body_c[k] = float(U[k]), float(W[k]), float(X[k])
     return c
 
 
@@ -129,16 +135,17 @@ def links(mask, bc_x=BCX_INLET_OUTLET, bc_y=BC_WALL, bc_z=BC_WALL):
 class OracleSim3:
     """FP64 reference simulation on a [nz, ny, nx] lattice.  ``uin`` is the inlet
     x-velocity, broadcast to [nz, ny]; ``box`` = (x0, x1, y0, y1, z0, z1); ``collision``
-    "bgk" (Eq. CollideAdv) or "regularized"."""
+    "bgk" (Eq. CollideAdv) or "regularized"; ``body_motion`` = (U, Omega, centre), three
+    3-vectors: rigid motion of the body."""
 
     def __init__(self, mask, tau=None, uin=None, bc_x=BCX_INLET_OUTLET, bc_y=BC_WALL,
                  bc_z=BC_WALL, box=None, rho_w=1.0, g=(0.0, 0.0, 0.0), omega=None,
-                 collision="bgk"):
+                 collision="bgk", body_motion=None):
         m, mp = _mask(mask)
         self.nz, self.ny, self.nx = m.shape
         self.omega = float(omega) if omega is not None else 1.0 / float(tau)
         self.box = box
-        self._cfg = _cfg(m.shape, bc_x, bc_y, bc_z, box, rho_w, g, collision)
+        self._cfg = _cfg(m.shape, bc_x, bc_y, bc_z, box, rho_w, g, collision, body_motion)
         u = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64),

@@ -39,6 +39,8 @@
 //    there and neighbours wrap into it), which lets a body spanning a periodic
 //    direction (an airfoil of infinite span) have a control volume;
 //  * collision: BGK (Eq. CollideAdv) or the regularized variant (not in the paper);
+//  * a body in rigid motion (not in the paper's runs) takes the moving-wall rule of
+//    Sec. II on its links, with the rigid-body velocity at each link's half-way point;
 //  * stress integration: unit faces crossed by the six axis links; traction
 //    (-p I + sigma) . n, n = -c_i, at the link's fluid node from its pre-collision
 //    populations, p = rho theta0, sigma = -(1 - omega/2) sum f^neq c c.
@@ -148,6 +150,11 @@ struct Config3 {
   double rho_w;
   double g[3];     // body force (test fixtures only; BGK only)
   int32_t collision;  // COLLISION_BGK or COLLISION_REGULARIZED
+  // Rigid motion of the body (all zero: at rest): translation velocity, angular
+  // velocity and the centre of rotation.
+  double body_u[3];
+  double body_omega[3];
+  double body_c[3];
 };
 
 // Per-step record: FA(3), FB(3), J(3), Phi(3), SI(3).
@@ -200,7 +207,19 @@ struct Sim3 {
       if (is_solid(cfg.nx - 1, sy, sz)) return St[idx(o, x, y, z)];
       return St[idx(i, cfg.nx - 1, sy, sz)];
     }
-    if (is_solid(sx, sy, sz)) return St[idx(o, x, y, z)];
+    // Body: half-way bounce-back; a body in rigid motion moves the wall point half-way
+    // along the link, x_w = x - c_i/2, with u_w = U + Omega x (x_w - x_c), and the
+    // moving-wall rule of Sec. II applies as at the inlet (zero term at rest).
+    if (is_solid(sx, sy, sz)) {
+      const double r[3] = {x - 0.5 * CX[i] - cfg.body_c[0], y - 0.5 * CY[i] - cfg.body_c[1],
+                           z - 0.5 * CZ[i] - cfg.body_c[2]};
+      const double* W = cfg.body_omega;
+      const double uw[3] = {cfg.body_u[0] + W[1] * r[2] - W[2] * r[1],
+                            cfg.body_u[1] + W[2] * r[0] - W[0] * r[2],
+                            cfg.body_u[2] + W[0] * r[1] - W[1] * r[0]};
+      const double cu = CX[o] * uw[0] + CY[o] * uw[1] + CZ[o] * uw[2];
+      return St[idx(o, x, y, z)] - 2.0 * weight(o) * cfg.rho_w * cu / THETA0;
+    }
     return St[idx(i, sx, sy, sz)];
   }
 
