@@ -118,6 +118,17 @@ int lbm3d_set_populations(lbm3d_t* h, const double* in);
  * direction) order into out [cap][2]; *n = their number. */
 int lbm3d_get_links(const lbm3d_t* h, int64_t* out, int64_t cap, int64_t* n);
 
+/* Rigid motion of the body (not in the paper's runs; the moving-wall bounce-back of
+ * Sec. II on the body links): translation u[3], angular velocity omega[3] about the
+ * point centre[3] (host arrays, copied), so a link whose half-way point is x_w sees the
+ * wall velocity u_w = u + omega x (x_w - centre), and the population it returns gains
+ * 2 w_i rho_w (c_i . u_w) / c_s^2.  The mask does not move.  A and B take the returned
+ * population in their two-term form; DRTT and SI apply unchanged.  All zero (the
+ * default) is a body at rest.  Applies from the next lbm3d_step (the motion travels as
+ * a kernel argument).  LBM_EINVAL for null or non-finite vectors. */
+int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
+                          const double* centre);
+
 int lbm3d_get_info(const lbm3d_t* h, lbm3d_info* info);
 void lbm3d_destroy(lbm3d_t* h);
 /* Last error message of h, or of the last failed lbm3d_create when h is NULL. */

@@ -17,6 +17,8 @@ using namespace lbm3;
 struct lbm3d {
   lbm3d_grid g;
   double tau = 0.0, rho_w = 1.0;
+  double mu[3] = {0.0, 0.0, 0.0}, mw[3] = {0.0, 0.0, 0.0}, mc[3] = {0.0, 0.0, 0.0};
+  bool moving = false;
   std::vector<double> uin;  // [nz][ny]
   Plan3 plan;
   int32_t pitch = 0;
@@ -83,6 +85,12 @@ Geom3 geom(const lbm3d* h) {
   g.word = reinterpret_cast<const uint32_t*>(h->ws + h->off_word);
   g.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
   g.rho_w6 = 6.0 * h->rho_w;
+  for (int k = 0; k < 3; ++k) {
+    g.mu[k] = h->mu[k];
+    g.mw[k] = h->mw[k];
+    g.mc[k] = h->mc[k];
+  }
+  g.moving = h->moving ? 1 : 0;
   return g;
 }
 
@@ -422,6 +430,24 @@ int lbm3d_get_info(const lbm3d_t* h, lbm3d_info* info) {
   info->n_recorded = h->nrec;
   info->n_general = h->plan.ngeneral;
   info->n_strips = int32_t(h->plan.strip.size());
+  return LBM_OK;
+}
+
+int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
+                          const double* centre) {
+  if (!h) return LBM_EINVAL;
+  if (!u || !omega || !centre) return h->fail(LBM_EINVAL, "null motion vector");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(u[k]) || !std::isfinite(omega[k]) || !std::isfinite(centre[k]))
+      return h->fail(LBM_EINVAL, "body motion must be finite");
+  bool moving = false;
+  for (int k = 0; k < 3; ++k) {
+    h->mu[k] = u[k];
+    h->mw[k] = omega[k];
+    h->mc[k] = centre[k];
+    moving = moving || u[k] != 0.0 || omega[k] != 0.0;
+  }
+  h->moving = moving;
   return LBM_OK;
 }
 

@@ -19,6 +19,10 @@ struct Geom3 {
   const uint32_t* word; // [nz][ny][nx] node words
   const double* uin;    // [nz][ny] inlet x-velocity
   double rho_w6;        // 6 rho_w: inlet term 2 rho_w w_i (c_i . u_w) / theta0
+  // Rigid motion of the body (moving != 0): the wall velocity at a point x is
+  // mu + mw x (x - mc).
+  double mu[3], mw[3], mc[3];
+  int32_t moving;
 };
 
 struct Step3Args {

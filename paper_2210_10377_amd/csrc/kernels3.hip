@@ -161,9 +161,21 @@ __device__ __forceinline__ int32_t pull_offset(const Geom3& g, int x, int y, int
   return (sz * g.ny + sy) * g.pitch + cx;
 }
 
+// Moving-wall term of the population pulled in direction i across a body link at node
+// (x, y, z): 2 rho_w w_i (c_i . u_w) / theta0 with u_w the rigid-body velocity at the
+// half-way point x - c_i / 2.
+__device__ __forceinline__ double body_wall_term3(const Geom3& g, int i, int x, int y, int z) {
+  const double r0 = x - 0.5 * kCx[i] - g.mc[0], r1 = y - 0.5 * kCy[i] - g.mc[1],
+               r2 = z - 0.5 * kCz[i] - g.mc[2];
+  const double u0 = g.mu[0] + g.mw[1] * r2 - g.mw[2] * r1;
+  const double u1 = g.mu[1] + g.mw[2] * r0 - g.mw[0] * r2;
+  const double u2 = g.mu[2] + g.mw[0] * r1 - g.mw[1] * r0;
+  return g.rho_w6 * w27<double>(i) * (kCx[i] * u0 + kCy[i] * u1 + kCz[i] * u2);
+}
+
 // Pull of all 27 populations of a fluid node through the boundary rules; *links: bit d
-// set for a body link in direction d.
-template <int P>
+// set for a body link in direction d.  MOV: the body links carry the moving-wall term.
+template <int P, bool MOV>
 __device__ __forceinline__ void pull27(const Geom3& g, const typename St3<P>::T* __restrict__ src,
                                        int x, int y, int z, uint32_t w, int32_t self,
                                        typename St3<P>::C (&f)[kQ], uint32_t* links) {
@@ -177,6 +189,11 @@ __device__ __forceinline__ void pull27(const Geom3& g, const typename St3<P>::T*
     f[i] = C(src[int64_t(bb ? opp(i) : i) * g.plane + off]);
     if (inl) inlm |= 1u << i;
     if (body) lk |= 1u << opp(i);
+  }
+  if (MOV && lk) {
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+      if ((lk >> opp(i)) & 1u) f[i] += C(body_wall_term3(g, i, x, y, z));
   }
   if (inlm) {
     const C u = C(g.rho_w6 * g.uin[z * g.ny + y]);
@@ -293,7 +310,7 @@ __device__ __forceinline__ int64_t tile_of(int64_t b) {
 
 // General path of one strip: the boundary-aware pull of every node, collision, store,
 // and with FTERMS the force terms reduced over the wave into the strip's slot.
-template <int P, bool FTERMS, int COLL>
+template <int P, bool FTERMS, int COLL, bool MOV>
 __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, int64_t row, int x,
                                               int y, int z, int lane) {
   using S = St3<P>;
@@ -318,7 +335,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
   uint32_t lk = 0;
   bool inV = false;
   if (fluid) {
-    pull27<P>(g, src, x, y, z, w, int32_t(self), f, &lk);
+    pull27<P, MOV>(g, src, x, y, z, w, int32_t(self), f, &lk);
     if (fterms) {
       inV = g.has_box && in_box(g, x, y, z);
       if (inV)
@@ -401,17 +418,20 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
     }
     if (fterms) {
       if (lk) {
+        // The population returned along link d at t+1 is f~_d plus, for a moving body,
+        // the moving-wall term of the pull of opp(d) (half-way point x + c_d / 2).
 #pragma unroll
         for (int d = 1; d < kQ; ++d)
           if ((lk >> d) & 1u) {
             const double v = S::kDev ? w27<double>(d) + double(f[d]) : double(f[d]);
-            post[0] += kCx[d] * v;
-            post[1] += kCy[d] * v;
-            post[2] += kCz[d] * v;
+            const double back = MOV ? v + body_wall_term3(g, opp(d), x, y, z) : v;
+            post[0] += kCx[d] * back;
+            post[1] += kCy[d] * back;
+            post[2] += kCz[d] * back;
+            post[3] += kCx[d] * (v + back);
+            post[4] += kCy[d] * (v + back);
+            post[5] += kCz[d] * (v + back);
           }
-        post[3] = 2.0 * post[0];
-        post[4] = 2.0 * post[1];
-        post[5] = 2.0 * post[2];
       }
       if (g.has_box) {
         // Surface flux: populations leaving V (node inside) or entering it (outside).
@@ -464,7 +484,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
   }
 }
 
-template <int P, bool FORCES, int COLL>
+template <int P, bool FORCES, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
   using S = St3<P>;
   using T = typename S::T;
@@ -533,14 +553,15 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
     for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.plane + self, T(f[i]));
     return;
   }
-  // Strips with force terms run in force3_kernel when forces are evaluated.
+  // Strips with force terms run in force3_kernel when forces are evaluated; they hold
+  // every body link, so the edge strips left here need no moving-wall term then.
   if (FORCES && cls == kForce) return;
-  general_strip<P, false, COLL>(a, e, row, x, y, z, lane);
+  general_strip<P, false, COLL, FORCES ? false : MOV>(a, e, row, x, y, z, lane);
 }
 
 // The strips with force terms (one wave per slot, in slot order): the general path
 // with A, B, J, Phi and SI.
-template <int P, int COLL>
+template <int P, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) void force3_kernel(Step3Args a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t slot = int64_t(blockIdx.x) * kStrips + wave;
@@ -552,11 +573,11 @@ __global__ __launch_bounds__(kThreads) void force3_kernel(Step3Args a) {
   const int64_t row = tile / a.ntx;
   const int y = int(row % a.g.ny), z = int(row / a.g.ny);
   const int x = tx * kTileW + int(si % kStrips) * kStripW + lane;
-  general_strip<P, true, COLL>(a, e, row, x, y, z, lane);
+  general_strip<P, true, COLL, MOV>(a, e, row, x, y, z, lane);
 }
 
 // J of the pull of the state src over V, per block of 256 nodes along x in a box row.
-template <int P>
+template <int P, bool MOV>
 __global__ __launch_bounds__(kThreads) void box3_kernel(Box3Args a) {
   using S = St3<P>;
   using T = typename S::T;
@@ -576,7 +597,8 @@ __global__ __launch_bounds__(kThreads) void box3_kernel(Box3Args a) {
     if (!(w & kSolid)) {
       C f[kQ];
       uint32_t lk;
-      pull27<P>(g, static_cast<const T*>(a.src), x, y, z, w, int32_t(row * g.pitch + x), f, &lk);
+      pull27<P, MOV>(g, static_cast<const T*>(a.src), x, y, z, w, int32_t(row * g.pitch + x), f,
+                     &lk);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
         const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
@@ -608,22 +630,30 @@ __global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t
   }
 }
 
-template <int P, int COLL>
-hipError_t step_pc(bool forces, const Step3Args& a, hipStream_t s) {
+template <int P, int COLL, bool MOV>
+hipError_t step_pcm(bool forces, const Step3Args& a, hipStream_t s) {
   const int64_t tiles = (a.ntiles + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun);
   const dim3 grid(unsigned(tiles + (a.red_in ? 8 : 0)));
   if (forces) {
-    hipLaunchKernelGGL((step3_kernel<P, true, COLL>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step3_kernel<P, true, COLL, MOV>), grid, dim3(kThreads), 0, s, a);
     if (a.nslots > 0) {
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       const unsigned fblocks = unsigned((a.nslots + kStrips - 1) / kStrips);
-      hipLaunchKernelGGL((force3_kernel<P, COLL>), dim3(fblocks), dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL((force3_kernel<P, COLL, MOV>), dim3(fblocks), dim3(kThreads), 0, s, a);
     }
   } else {
-    hipLaunchKernelGGL((step3_kernel<P, false, COLL>), grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step3_kernel<P, false, COLL, MOV>), grid, dim3(kThreads), 0, s, a);
   }
   return hipGetLastError();
+}
+
+// Bodies in motion take their own instantiation, so the resting case keeps its
+// registers.
+template <int P, int COLL>
+hipError_t step_pc(bool forces, const Step3Args& a, hipStream_t s) {
+  return a.g.moving ? step_pcm<P, COLL, true>(forces, a, s)
+                    : step_pcm<P, COLL, false>(forces, a, s);
 }
 
 template <int P>
@@ -643,19 +673,20 @@ hipError_t launch_step3(int precision, bool forces, const Step3Args& a, hipStrea
   }
 }
 
+template <int P>
+void box_p(const Box3Args& a, int blocks, hipStream_t s) {
+  if (a.g.moving)
+    hipLaunchKernelGGL((box3_kernel<P, true>), dim3(blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((box3_kernel<P, false>), dim3(blocks), dim3(kThreads), 0, s, a);
+}
+
 hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t s) {
   switch (precision) {
-    case LBM_FP64:
-      hipLaunchKernelGGL(box3_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, a);
-      break;
-    case LBM_FP32:
-      hipLaunchKernelGGL(box3_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, a);
-      break;
-    case LBM_FP32DEV:
-      hipLaunchKernelGGL(box3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
-      break;
-    default:
-      hipLaunchKernelGGL(box3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+    case LBM_FP64: box_p<LBM_FP64>(a, blocks, s); break;
+    case LBM_FP32: box_p<LBM_FP32>(a, blocks, s); break;
+    case LBM_FP32DEV: box_p<LBM_FP32DEV>(a, blocks, s); break;
+    default: box_p<LBM_FP16DEV>(a, blocks, s);
   }
   return hipGetLastError();
 }

@@ -65,6 +65,15 @@ class Sim3:
     def step(self, n: int, schemes=ALL_SCHEMES):
         C.check3(self._lib.lbm3d_step(self._h, int(n), scheme_mask(schemes)), self._h)
 
+    def set_body_motion(self, u=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0),
+                        centre=(0.0, 0.0, 0.0)) -> None:
+        """Rigid motion of the body: translation u, angular velocity omega about centre
+        (three 3-vectors); the moving-wall rule on its links from the next step."""
+        vs = [np.ascontiguousarray(np.asarray(v, np.float64).reshape(3)) for v in (u, omega, centre)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        C.check3(self._lib.lbm3d_set_body_motion(self._h, *[v.ctypes.data_as(dp) for v in vs]),
+                 self._h)
+
     def info(self) -> C.lbm3d_info:
         inf = C.lbm3d_info()
         C.check3(self._lib.lbm3d_get_info(self._h, ctypes.byref(inf)), self._h)
