@@ -108,3 +108,24 @@ def test_zero_motion_is_the_resting_body_and_forces_off_same_state():
         g.step(40, schemes)
         pops.append(g.populations())
     np.testing.assert_array_equal(pops[0], pops[1])
+
+
+def test_moving_body_with_the_regularized_collision():
+    """A turning sphere with the regularized collision at tau_lb 0.505, FP64, against the
+    oracle: populations and forces to 1e-10."""
+    mk, (bx, by, bz), box, u = CASES["sphere_walls_box"]
+    mask = mk()
+    nz, ny, nx = mask.shape
+    mo = _motion(mask, "both")
+    S0 = d3.near_rest_state3(nx, ny, nz, seed=91, amp=0.05)
+    uin = np.full((nz, ny), u)
+    o = D.OracleSim3(mask, tau=0.505, uin=uin, box=box, body_motion=mo, collision="regularized")
+    o.set_state(S0)
+    o.step(30)
+    g = _sim3(mask, 0.505, uin, precision="fp64", box=box, max_record=64, collision="regularized")
+    g.set_body_motion(*mo)
+    g.set_populations(S0)
+    g.step(30)
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    e = _force_err(g.forces(), o.forces())
+    assert np.all(e <= TOL64), e

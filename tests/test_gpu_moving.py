@@ -343,3 +343,26 @@ def test_set_mask_to_the_same_mask_is_bitwise_a_no_op():
         runs.append((g.populations(), g.forces()))
     np.testing.assert_array_equal(runs[0][0], runs[1][0])
     np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("collision", ["regularized", "kbc"])
+def test_moving_body_with_stabilized_collisions(collision):
+    """A turning, sliding body with the regularized or KBC collision at tau_lb 0.51 from
+    a random state, FP64: populations and forces to 1e-10 of the oracle."""
+    nx, ny, bcx, bcy, mk, box, u = CASES["channel_body_box"]
+    mask = mk(nx, ny)
+    uin = np.linspace(0.5, 1.0, ny) * u
+    mo = _motion(mask, "both")
+    S0 = workloads.near_rest_state(nx, ny, seed=77, amp=0.05)
+    o = OracleSim(mask, tau=0.51, uin=uin, bc_x=bcx, bc_y=bcy, box=box, body_motion=mo,
+                  collision=collision)
+    o.set_state(S0)
+    o.step(60)
+    g = _sim(mask=mask, tau=0.51, uin=uin, precision="fp64", bc_x=bcx, bc_y=bcy, box=box,
+             max_record=100, collision=collision)
+    g.set_body_motion(*mo)
+    g.set_populations(S0)
+    g.step(60)
+    assert _pop_err(g.populations(), o.state(), mask) <= TOL64
+    e = _force_err(g.forces(), o.forces())
+    assert np.all(e <= TOL64), e
