@@ -253,6 +253,50 @@ def sphere_sweep(diameters, t_conv: float, precision: str, re: float):
     print(json.dumps(summary), flush=True)
 
 
+def precision_study3(d: int, t_conv: float, re: float):
+    """Reduced-precision storage on the D3Q27 path: the sphere duct of the sphere sweep
+    (diameter d, Re re, t_conv convective times from rest) in FP64, FP32, FP32 deviations
+    and FP16 deviations; Cd (mean over the last quarter) and the velocity field at the
+    end against the FP64 run on the same GPU."""
+    import numpy as np
+    from workloads import d3, tau_from_re
+    from paper_2210_10377_amd import Sim3
+
+    u = 0.05
+    nx, ny, nz = 16 * d, 6 * d, 6 * d
+    c = 3 * d - 0.5
+    mask = d3.sphere_mask(nx, ny, nz, 4 * d, c, c, d / 2.0)
+    box = d3.default_box3(mask, max(2, d // 4))
+    tau = tau_from_re(u, d, re)
+    steps = int(round(t_conv * d / u))
+    names = ("A", "B", "DRTT", "SI")
+    q = 0.5 * u * u * np.pi * d * d / 4.0
+    fl = mask == 0
+    cx = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1,
+                   0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1], float)
+    res, ref = {}, None
+    for prec in ("fp64", "fp32", "fp32dev", "fp16dev"):
+        sim = Sim3(mask, tau, np.full((nz, ny), u), precision=prec, box=box, max_record=4096)
+        C = sim.run(steps) / q
+        S = sim.populations()
+        del sim
+        ux = np.tensordot(cx, S, 1)[fl] / S.sum(0)[fl]
+        cd = {n: float(C[-(steps // 4):, k, 0].mean()) for k, n in enumerate(names)}
+        if ref is None:
+            ref = (cd, ux, C)
+        row = {"storage": prec, "cd_mean": cd,
+               "cd_rel_err_vs_fp64": {n: abs(cd[n] - ref[0][n]) / abs(ref[0][n]) for n in names},
+               "cd_max_step_err_vs_fp64": {n: float(np.abs(C[:, k, 0] - ref[2][:, k, 0]).max()
+                                                    / np.abs(ref[2][:, k, 0]).max())
+                                           for k, n in enumerate(names)},
+               "ux_linf_err_vs_fp64": float(np.abs(ux - ref[1]).max() / u),
+               "ux_l2_err_vs_fp64": float(np.sqrt(((ux - ref[1]) ** 2).mean()) / u)}
+        res[prec] = row
+        print(json.dumps(row), flush=True)
+    print(json.dumps({"precision_study_3d": f"sphere D {d}, Re {re:g}, duct 16D x 6D x 6D",
+                      "steps": steps, "tau": tau}), flush=True)
+
+
 def small_grid_bench(precision: str, steps: int):
     """The 200x80 cylinder channel (D 20, Re 20; the FP64 parity configuration): a grid
     of 16,000 nodes is bound by launch latency, not by HBM.  Direct `lbm_step` launches
@@ -559,6 +603,8 @@ def main():
                     help="3-D grid-requirement study: sphere drag against points per "
                          "diameter for A, B, DRTT and SI (--sphere-diameters, --re)")
     ap.add_argument("--sphere-diameters", default="8,12,16,20,24,32,40")
+    ap.add_argument("--precision-study-3d", action="store_true",
+                    help="FP64/FP32/FP32-dev/FP16-dev Cd and velocity errors on the sphere duct")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
@@ -593,6 +639,10 @@ def main():
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
+        return
+    if args.precision_study_3d:
+        precision_study3(16, args.convective_times if args.convective_times != 150.0 else 30.0,
+                         args.re if args.re != 1e4 else 50.0)
         return
     if args.small_grid:
         small_grid_bench(args.precision if args.precision != "fp32" else "fp64",
