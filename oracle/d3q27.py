@@ -55,6 +55,9 @@ def lib():
         L.orc3_nrec.argtypes = [ctypes.c_void_p]
         L.orc3_nrec.restype = ctypes.c_int64
         L.orc3_momentum_of.argtypes = [ctypes.c_void_p, dp, dp]
+        L.orc3_set_mask.argtypes = [ctypes.c_void_p, u8, ctypes.POINTER(ctypes.c_int32), dp]
+        L.orc3_set_mask.restype = ctypes.c_int
+        L.orc3_set_body_motion.argtypes = [ctypes.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -197,6 +200,27 @@ class OracleSim3:
         if n:
             lib().orc3_forces(self._h, _dp(out))
         return out
+
+    def set_mask(self, mask, box=None):
+        """Move the body through the grid: a new mask (and box, if given) from the next
+        step; uncovered nodes refilled at the wall velocity; returns the impulse (3,)."""
+        m, mp = _mask(mask)
+        if m.shape != (self.nz, self.ny, self.nx):
+            raise ValueError("mask shape differs from the lattice")
+        bp = None
+        if box is not None:
+            self._box_arr = (ctypes.c_int32 * 6)(*[int(v) for v in box])
+            bp = ctypes.cast(self._box_arr, ctypes.POINTER(ctypes.c_int32))
+        imp = np.zeros(3)
+        if lib().orc3_set_mask(self._h, mp, bp, _dp(imp)) != 0:
+            raise ValueError("mask or control volume not admissible")
+        self._mask_keep = m
+        return imp
+
+    def set_body_motion(self, u=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0), centre=(0.0, 0.0, 0.0)):
+        vs = [np.ascontiguousarray(np.asarray(v, np.float64).reshape(3)) for v in (u, omega, centre)]
+        self._motion_keep = vs
+        lib().orc3_set_body_motion(self._h, *[_dp(v) for v in vs])
 
     def momentum_of(self, g):
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.shape)

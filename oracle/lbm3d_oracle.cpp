@@ -167,6 +167,10 @@ struct Sim3 {
   double omega = 1.0;
   std::vector<double> S, f, Sn;  // [27][nz][ny][nx]
   std::vector<double> rec;
+  // Records whose J(t+1) was fixed when the geometry changed after them (set_mask): the
+  // record index and the box momentum of the pull that followed under the old mask.
+  std::vector<size_t> jfix_t;
+  std::vector<double> jfix;  // [k][3]
 
   size_t nodes() const { return size_t(cfg.nx) * cfg.ny * cfg.nz; }
   size_t node(int x, int y, int z) const {
@@ -367,7 +371,9 @@ struct Sim3 {
       for (int a = 0; a < 3; ++a) {
         o[a] = r[a];
         o[3 + a] = r[3 + a];
-        const double j1 = (t + 1 < n) ? rec[NREC * (t + 1) + 6 + a] : Jlast[a];
+        double j1 = (t + 1 < n) ? rec[NREC * (t + 1) + 6 + a] : Jlast[a];
+        for (size_t k = 0; k < jfix_t.size(); ++k)
+          if (jfix_t[k] == t) j1 = jfix[3 * k + a];
         o[6 + a] = cfg.box[0] >= 0 ? r[6 + a] - j1 + r[9 + a] : NAN;
         o[9 + a] = r[12 + a];
       }
@@ -412,6 +418,89 @@ bool config_valid(const Config3& c, const uint8_t* mask) {
   for (size_t k = 0; k < size_t(c.nx) * c.ny * c.nz; ++k)
     if (mask[k] > 1) return false;
   return box_admissible(c, mask);
+}
+
+// A body that moves through the grid: replace the mask (and optionally the control
+// volume) between two steps, as in the two-dimensional oracle.  Every recorded step
+// keeps its geometry (the J(t+1) of the last recorded step is fixed now, under the old
+// mask and box); uncovered nodes get the equilibrium at the rigid-body velocity at the
+// node and the mean density of their lattice neighbours that are fluid in both masks
+// (rho_w when there is none; periodic axes wrap, other edges do not count); impulse =
+// momentum of the covered nodes minus that of the refilled ones.  -1 (nothing changed)
+// for an inadmissible mask or box, or a box added or removed.
+int set_mask(Sim3& s, const uint8_t* mask, const int32_t* box, double* impulse) {
+  Config3 c = s.cfg;
+  if (box) {
+    if ((box[0] >= 0) != (c.box[0] >= 0)) return -1;
+    for (int k = 0; k < 6; ++k) c.box[k] = box[k];
+  }
+  if (!config_valid(c, mask)) return -1;
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const size_t n = s.nodes();
+  const size_t nrec = s.rec.size() / NREC;
+  if (s.cfg.box[0] >= 0 && nrec > 0) {
+    std::vector<double> g(s.S.size(), 0.0);
+    s.stream_all(s.S, g);
+    double J[3];
+    s.box_momentum(g, J);
+    s.jfix_t.push_back(nrec - 1);
+    for (int a = 0; a < 3; ++a) s.jfix.push_back(J[a]);
+  }
+  const std::vector<uint8_t> old = s.solid;
+  double P[3] = {0.0, 0.0, 0.0};
+  std::vector<double> fresh(NQ * n, 0.0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t k = s.node(x, y, z);
+        if (old[k] == 0 && mask[k] != 0) {  // covered
+          for (int i = 0; i < NQ; ++i) {
+            P[0] += CX[i] * s.S[s.idx(i, x, y, z)];
+            P[1] += CY[i] * s.S[s.idx(i, x, y, z)];
+            P[2] += CZ[i] * s.S[s.idx(i, x, y, z)];
+          }
+        } else if (old[k] != 0 && mask[k] == 0) {  // uncovered
+          double rsum = 0.0;
+          int cnt = 0;
+          for (int i = 1; i < NQ; ++i) {
+            int a[3];
+            s.shifted(x, y, z, CX[i], CY[i], CZ[i], a);
+            if (a[0] < 0 || a[0] >= nx || a[1] < 0 || a[1] >= ny || a[2] < 0 || a[2] >= nz)
+              continue;
+            const size_t ka = s.node(a[0], a[1], a[2]);
+            if (old[ka] != 0 || mask[ka] != 0) continue;
+            double r = 0.0;
+            for (int j = 0; j < NQ; ++j) r += s.S[s.idx(j, a[0], a[1], a[2])];
+            rsum += r;
+            ++cnt;
+          }
+          const double rho = cnt > 0 ? rsum / cnt : c.rho_w;
+          const double rr[3] = {x - c.body_c[0], y - c.body_c[1], z - c.body_c[2]};
+          const double* W = c.body_omega;
+          const double u[3] = {c.body_u[0] + W[1] * rr[2] - W[2] * rr[1],
+                               c.body_u[1] + W[2] * rr[0] - W[0] * rr[2],
+                               c.body_u[2] + W[0] * rr[1] - W[1] * rr[0]};
+          for (int i = 0; i < NQ; ++i) fresh[s.idx(i, x, y, z)] = equilibrium(i, rho, u[0], u[1], u[2]);
+        }
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t k = s.node(x, y, z);
+        if (!(old[k] != 0 && mask[k] == 0)) continue;
+        for (int i = 0; i < NQ; ++i) {
+          const double v = fresh[s.idx(i, x, y, z)];
+          s.S[s.idx(i, x, y, z)] = v;
+          P[0] -= CX[i] * v;
+          P[1] -= CY[i] * v;
+          P[2] -= CZ[i] * v;
+        }
+      }
+  s.solid.assign(mask, mask + n);
+  s.cfg = c;
+  if (impulse)
+    for (int a = 0; a < 3; ++a) impulse[a] = P[a];
+  return 0;
 }
 
 }  // namespace
@@ -488,6 +577,19 @@ void* orc3_create(const orc3_cfg* c, const uint8_t* mask, double omega, const do
 }
 
 void orc3_destroy(void* h) { delete static_cast<Sim3*>(h); }
+
+int orc3_set_mask(void* h, const uint8_t* mask, const int32_t* box, double* impulse) {
+  return set_mask(*static_cast<Sim3*>(h), mask, box, impulse);
+}
+
+void orc3_set_body_motion(void* h, const double* u, const double* w, const double* c) {
+  Config3& cfg = static_cast<Sim3*>(h)->cfg;
+  for (int a = 0; a < 3; ++a) {
+    cfg.body_u[a] = u[a];
+    cfg.body_omega[a] = w[a];
+    cfg.body_c[a] = c[a];
+  }
+}
 
 void orc3_set_state(void* h, const double* S) {
   Sim3* s = static_cast<Sim3*>(h);

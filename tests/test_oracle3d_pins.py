@@ -417,3 +417,117 @@ def test_rotating_extruded_cylinder_reduces_to_the_two_dimensional_oracle(lat):
     F2, F3 = o2.forces(), o3.forces()
     scale = np.abs(F2).max()
     np.testing.assert_allclose(F3[:, :, :2], nz * F2, rtol=0, atol=1e-12 * nz * scale)
+
+
+# --------------------------------------------------------------------------------------
+# A body moving through the grid in three dimensions (mask replaced between steps)
+# --------------------------------------------------------------------------------------
+
+def test_set_mask_same_mask_changes_nothing_3d():
+    w = d3.sphere_channel_64x32x32()
+    S0 = d3.near_rest_state3(w.nx, w.ny, w.nz, seed=3, amp=0.03)
+    runs = []
+    for call in (False, True):
+        s = D.OracleSim3(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+        s.set_state(S0)
+        s.step(6)
+        if call:
+            before = s.state()
+            assert np.all(s.set_mask(w.mask.copy()) == 0.0)
+            assert np.array_equal(s.state(), before)
+        s.step(6)
+        runs.append((s.state(), s.forces()))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_uncovered_nodes_refill_brute_force_3d(lat):
+    """A 2x2x2 cube moved one node along +x and a 3x3x3 cube removed, on a periodic
+    lattice, with a turning, sliding body: every uncovered node holds f^eq(rho, u_w),
+    rho the mean density of its neighbours fluid in both masks (1 when none: the centre
+    of the removed cube), u_w the rigid-body velocity at the node; the impulse is the
+    covered momentum minus the refilled one; no other node changes."""
+    cx, cy, cz, _, _ = lat
+    nx, ny, nz = 12, 11, 10
+    old = np.zeros((nz, ny, nx), np.uint8)
+    old[3:5, 3:5, 3:5] = 1
+    old[5:8, 5:8, 7:10] = 1
+    new = np.zeros((nz, ny, nx), np.uint8)
+    new[3:5, 3:5, 4:6] = 1
+    U, W, X = np.array([0.01, 0.02, -0.01]), np.array([0.002, 0.001, -0.003]), np.array([4.5, 4.0, 3.5])
+    S = d3.near_rest_state3(nx, ny, nz, seed=17, amp=0.1)
+    s = D.OracleSim3(old, tau=0.8, bc_x=BCX_PERIODIC, bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC,
+                     body_motion=(U, W, X))
+    s.set_state(S)
+    imp = s.set_mask(new)
+    T = s.state()
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    P = np.zeros(3)
+    for (z, y, x) in zip(*np.nonzero((old == 0) & (new == 1))):
+        P += C.T @ S[:, z, y, x]
+    changed = (old == 1) & (new == 0)
+    for (z, y, x) in zip(*np.nonzero(changed)):
+        rhos = []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if dx == dy == dz == 0:
+                        continue
+                    a, b, c = (x + dx) % nx, (y + dy) % ny, (z + dz) % nz
+                    if old[c, b, a] == 0 and new[c, b, a] == 0:
+                        rhos.append(S[:, c, b, a].sum())
+        rho = np.mean(rhos) if rhos else 1.0
+        uw = U + np.cross(W, np.array([x, y, z], float) - X)
+        np.testing.assert_allclose(T[:, z, y, x], D.equilibrium(rho, *uw), rtol=0, atol=1e-15)
+        P -= C.T @ T[:, z, y, x]
+    np.testing.assert_allclose(imp, P, rtol=0, atol=1e-14)
+    assert np.array_equal(T[:, ~changed], S[:, ~changed])
+    assert changed[6, 6, 8]  # the removed cube's centre: no neighbour fluid in both masks
+
+
+def test_comoving_translating_sphere_keeps_a_uniform_flow_3d():
+    nx, ny, nz = 32, 20, 18
+    U = (0.04, 0.0, 0.0)
+    feq = D.equilibrium(1.0, *U)
+    S0 = np.broadcast_to(feq[:, None, None, None], (27, nz, ny, nx)).copy()
+    s = D.OracleSim3(d3.sphere_mask(nx, ny, nz, 10, 9.5, 8.5, 4), tau=0.7, bc_x=BCX_PERIODIC,
+                     bc_y=D.BC_PERIODIC, bc_z=D.BC_PERIODIC, box=(3, 29, 3, 17, 2, 16),
+                     body_motion=(U, (0, 0, 0), (0, 0, 0)))
+    s.set_state(S0)
+    for k in range(1, 4):
+        s.step(25)
+        imp = s.set_mask(d3.sphere_mask(nx, ny, nz, 10 + k, 9.5, 8.5, 4))
+        assert np.abs(imp).max() <= 1e-14
+        fl = s._mask_keep == 0
+        np.testing.assert_allclose(s.state()[:, fl], S0[:, fl], rtol=0, atol=1e-14)
+    s.step(5)
+    F = s.forces()
+    assert np.abs(F[:, [0, 1, 3]]).max() <= 5e-14
+    assert np.abs(F[:, 2]).max() <= 1e-12
+
+
+def test_mask_change_bookkeeping_and_drtt_equals_b_3d(lat):
+    """Fluid momentum after a change = before - impulse, and the mass balance; DRTT
+    equals MEA-B at every step of a towed sphere whose box moves with it."""
+    cx, cy, cz, _, _ = lat
+    C = np.stack([cx, cy, cz], 1).astype(float)
+    nx, ny, nz = 48, 20, 20
+    m = lambda k: d3.sphere_mask(nx, ny, nz, 14 + k, 9.5, 9.5, 4)
+    s = D.OracleSim3(m(0), tau=0.65, uin=np.full((nz, ny), 0.04), box=(7, 22, 3, 17, 3, 17),
+                     body_motion=((0.05, 0, 0), (0, 0, 0), (0, 0, 0)))
+    for k in range(1, 6):
+        s.step(12)
+        S = s.state()
+        mo, mn = m(k - 1), m(k)
+        box = (7 + k, 22 + k, 3, 17, 3, 17) if k % 2 == 0 else None
+        imp = s.set_mask(mn, box)
+        T = s.state()
+        mom = lambda X, mk: np.einsum("ia,i...->a...", C, X)[:, mk == 0].sum(1)
+        np.testing.assert_allclose(mom(T, mn), mom(S, mo) - imp, rtol=0, atol=1e-11)
+        cov, fre = (mo == 0) & (mn == 1), (mo == 1) & (mn == 0)
+        assert abs(T.sum(0)[mn == 0].sum() - (S.sum(0)[mo == 0].sum() - S.sum(0)[cov].sum()
+                                              + T.sum(0)[fre].sum())) <= 1e-10
+    s.step(12)
+    F = s.forces()
+    J = np.abs(s.records()[:, 6:9]).max()
+    assert np.abs(F[:, 2] - F[:, 1]).max() <= 1e-12 * J
