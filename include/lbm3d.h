@@ -129,6 +129,28 @@ int lbm3d_get_links(const lbm3d_t* h, int64_t* out, int64_t cap, int64_t* n);
 int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
                           const double* centre);
 
+/* A body that moves through the grid (not in the paper's runs; the bounce-back of
+ * Sec. II on the links of each mask), as lbm_set_mask in two dimensions: replace the
+ * body mask ([nz][ny][nx] bytes, 0 fluid / 1 solid, host, copied), and the control
+ * volume when `box` is non-null (six ints as in lbm3d_grid; it can be moved or
+ * resized, not added or removed), between two steps.  Every recorded step keeps the
+ * geometry it was taken with (the J(t+1) of the last step before the change was taken
+ * under the old mask and box); the momentum that changes hands with the nodes the body
+ * covers or uncovers enters no estimator and is returned in impulse[3] (host, may be
+ * NULL): the momentum of the covered nodes minus that of the refilled ones.  Uncovered
+ * nodes are refilled with the equilibrium at the rigid-body velocity of
+ * lbm3d_set_body_motion at the node and the mean density of their lattice neighbours
+ * that are fluid in both masks (rho_w when none is; a neighbour across a periodic edge
+ * wraps, one outside another edge does not count).  The motion's centre is not
+ * advanced by the library.  Bound handles: synchronises the stream first, uses the idle
+ * state buffer as scratch and refills it with the rest state, synchronises again.
+ * LBM_EINVAL: mask values other than 0/1, a box that is not admissible for the new
+ * mask, a box added or removed; LBM_ENOMEM: the new mask needs more force slots than
+ * twice those at create (plus a margin), or a larger control-volume sweep than at
+ * create.  On these errors nothing changes.  On LBM_EHIP the state is undefined. */
+int lbm3d_set_mask(lbm3d_t* h, const uint8_t* solid_mask, const int32_t* box,
+                   double* impulse);
+
 int lbm3d_get_info(const lbm3d_t* h, lbm3d_info* info);
 void lbm3d_destroy(lbm3d_t* h);
 /* Last error message of h, or of the last failed lbm3d_create when h is NULL. */

@@ -37,7 +37,7 @@ EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_for
 EXPORTS3 = ("lbm3d_create", "lbm3d_workspace_bytes", "lbm3d_bind", "lbm3d_step",
             "lbm3d_forces", "lbm3d_get_populations", "lbm3d_set_populations",
             "lbm3d_get_links", "lbm3d_get_info", "lbm3d_destroy", "lbm3d_last_error",
-            "lbm3d_set_body_motion")
+            "lbm3d_set_body_motion", "lbm3d_set_mask")
 
 
 class lbm_grid(ctypes.Structure):
@@ -160,6 +160,7 @@ def load():
     L.lbm3d_get_links.argtypes = [vp, ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
     L.lbm3d_get_info.argtypes = [vp, ctypes.POINTER(lbm3d_info)]
     L.lbm3d_set_body_motion.argtypes = [vp, dp, dp, dp]
+    L.lbm3d_set_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(i32), dp]
     L.lbm3d_destroy.argtypes = [vp]
     L.lbm3d_destroy.restype = None
     L.lbm3d_last_error.argtypes = [vp]

@@ -2,6 +2,7 @@
 // layout, stepping with per-step forces, readout.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -27,6 +28,10 @@ struct lbm3d {
   size_t off_buf[2] = {0, 0}, off_word = 0, off_strip = 0, off_fstrip = 0, off_uin = 0, off_part = 0,
          off_jpart = 0, off_ring = 0, total = 0;
   int njblocks = 0;
+  // Reserved at create so that a mask change can re-plan in place: force slots (strip
+  // indices), doubles of one force-partial buffer, control-volume sweep blocks.
+  size_t fcap = 0, part_cap = 0;
+  int jcap = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -48,7 +53,7 @@ struct lbm3d {
     return size_t(plan.nslots) * kPart + size_t(plan.njslots) * 3;
   }
   double* part(int k) const {
-    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_doubles();
+    return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_cap;
   }
   double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }
 };
@@ -230,15 +235,18 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
   off = align256(off + h->plan.word.size() * sizeof(uint32_t));
   h->off_strip = off;
   off = align256(off + h->plan.strip.size() * sizeof(uint32_t));
+  h->fcap = 2 * h->plan.fstrips.size() + 256;
+  h->part_cap = 2 * h->part_doubles() + 4096;
+  h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
+  h->jcap = h->njblocks;
   h->off_fstrip = off;
-  off = align256(off + h->plan.fstrips.size() * sizeof(uint32_t));
+  off = align256(off + h->fcap * sizeof(uint32_t));
   h->off_uin = off;
   off = align256(off + h->uin.size() * sizeof(double));
   h->off_part = off;
-  off = align256(off + 2 * h->part_doubles() * sizeof(double));
-  h->njblocks = h->plan.has_box ? h->plan.box_bx * h->plan.box_rows : 0;
+  off = align256(off + 2 * h->part_cap * sizeof(double));
   h->off_jpart = off;
-  off = align256(off + size_t(h->njblocks) * 3 * sizeof(double));
+  off = align256(off + size_t(h->jcap) * 3 * sizeof(double));
   h->off_ring = off;
   off = align256(off + size_t(g.max_record) * kRow * sizeof(double));
   h->total = off;
@@ -448,6 +456,89 @@ int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
     moving = moving || u[k] != 0.0 || omega[k] != 0.0;
   }
   h->moving = moving;
+  return LBM_OK;
+}
+
+int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* impulse) {
+  if (!h || !mask) return LBM_EINVAL;
+  lbm3d_grid g = h->g;
+  if (box) {
+    if ((box[0] >= 0) != (g.box[0] >= 0))
+      return h->fail(LBM_EINVAL, "a control volume can be moved, not added or removed");
+    for (int k = 0; k < 6; ++k) g.box[k] = box[k];
+  }
+  Plan3 np;
+  std::string perr;
+  const int rc = build_plan3(g, mask, np, perr);
+  if (rc != LBM_OK) return h->fail(rc, perr);
+  if (np.fstrips.size() > h->fcap ||
+      size_t(np.nslots) * kPart + size_t(np.njslots) * 3 > h->part_cap)
+    return h->fail(LBM_ENOMEM, "the new mask needs more force slots than reserved at create; "
+                               "create a handle for it");
+  const int nj = np.has_box ? np.box_bx * np.box_rows : 0;
+  if (nj > h->jcap)
+    return h->fail(LBM_ENOMEM, "the new control volume is larger than the one at create");
+  double P[3] = {0.0, 0.0, 0.0};
+  if (h->bound) {
+    const size_t n = size_t(g.nx) * g.ny * g.nz;
+    std::vector<uint8_t> valid(n);
+    std::vector<int32_t> list;
+    for (size_t k = 0; k < n; ++k) {
+      const bool was = (h->plan.word[k] & kSolid) != 0, is = mask[k] != 0;
+      valid[k] = (!was && !is) ? 1 : 0;
+      if (was != is) list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
+    }
+    // Scratch in the other state buffer; it is refilled with the rest state afterwards
+    // (the next step rewrites its fluid nodes; its solid nodes then hold w_i, as after
+    // bind).
+    const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
+    const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
+                 off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 24);
+    if (off_res + 24 > size_t(h->plane) * kQ * h->esz)
+      return h->fail(LBM_ENOMEM, "too many nodes change at once");
+    // Nothing in flight may still read the old node words or the state.
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "mask synchronize");
+    char* scr = static_cast<char*>(h->buf(1 - h->cur));
+    if (!list.empty()) {
+      e = hipMemcpyAsync(scr, valid.data(), n, hipMemcpyHostToDevice, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(scr + off_list, list.data(), list.size() * 4, hipMemcpyHostToDevice,
+                           h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "upload mask change");
+      Remask3Args a{};
+      a.g = geom(h);
+      a.state = h->buf(h->cur);
+      a.list = reinterpret_cast<const int32_t*>(scr + off_list);
+      a.n = int32_t(list.size());
+      a.valid = reinterpret_cast<const uint8_t*>(scr);
+      a.rho_w = h->rho_w;
+      a.block_out = reinterpret_cast<double*>(scr + off_blk);
+      double* res = reinterpret_cast<double*>(scr + off_res);
+      e = launch_remask3(g.precision, a, blocks, res, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "launch remask");
+      e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "download impulse");
+      e = launch_fill_rest3(g.precision, scr, h->plane, h->stream);
+      if (e != hipSuccess) return h->hip_fail(e, "refill scratch buffer");
+    }
+    e = hipMemcpyAsync(h->ws + h->off_word, np.word.data(), np.word.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->ws + h->off_strip, np.strip.data(), np.strip.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && !np.fstrips.empty())
+      e = hipMemcpyAsync(h->ws + h->off_fstrip, np.fstrips.data(),
+                         np.fstrips.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "upload plan");
+  }
+  h->plan = std::move(np);
+  h->g = g;
+  h->njblocks = nj;
+  if (impulse)
+    for (int k = 0; k < 3; ++k) impulse[k] = P[k];
   return LBM_OK;
 }
 

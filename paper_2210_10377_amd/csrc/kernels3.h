@@ -59,7 +59,22 @@ struct Final3Args {
   int32_t njblocks;
 };
 
+// A mask change of a body moving through the grid, over the current state buffer.
+struct Remask3Args {
+  Geom3 g;                // geometry and the rigid motion (wall velocity of refills)
+  void* state;            // current state buffer
+  const int32_t* list;    // [n] node index (z*ny + y)*nx + x; bit 31: uncovered
+  int32_t n;
+  const uint8_t* valid;   // [nz][ny][nx] 1 where fluid in both masks
+  double rho_w;           // density of a refill without valid neighbours
+  double* block_out;      // [blocks][3] covered minus refilled momentum per block
+};
+
 hipError_t launch_step3(int precision, bool forces, const Step3Args& a, hipStream_t s);
+// Refill the uncovered nodes and sum, in a fixed order, the momentum of the covered
+// ones minus that of the refilled ones into out[3].
+hipError_t launch_remask3(int precision, const Remask3Args& a, int blocks, double* out,
+                          hipStream_t s);
 hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t s);
 hipError_t launch_final3(const Final3Args& a, hipStream_t s);
 hipError_t launch_fill_rest3(int precision, void* buf, int64_t plane, hipStream_t s);

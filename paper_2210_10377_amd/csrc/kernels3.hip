@@ -617,6 +617,82 @@ __global__ __launch_bounds__(kThreads) void final3_kernel(Final3Args a) {
   reduce_row(a.red_in, a.nslots, a.njslots, a.row, a.prev_jnext, a.jpart, a.njblocks);
 }
 
+// Mask change: one thread per listed node.  A covered node contributes its momentum; an
+// uncovered one is refilled with f^eq(rho, u_w) (rho the mean density of its lattice
+// neighbours fluid in both masks, periodic axes wrapping, rho_w when none; u_w the
+// rigid-body velocity at the node) and contributes minus what it now stores.  Refills
+// read valid neighbours only, so no thread reads what another writes.
+template <int P>
+__global__ __launch_bounds__(kThreads) void remask3_kernel(Remask3Args a) {
+  using S = St3<P>;
+  using T = typename S::T;
+  using C = typename S::C;
+  const Geom3& g = a.g;
+  T* st = static_cast<T*>(a.state);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < a.n;
+       k += int64_t(gridDim.x) * kThreads) {
+    const uint32_t e = uint32_t(a.list[k]);
+    const int32_t node = int32_t(e & 0x7fffffffu);
+    const int x = node % g.nx, y = (node / g.nx) % g.ny, z = node / (g.nx * g.ny);
+    const int64_t at = (int64_t(z) * g.ny + y) * g.pitch + x;
+    if (!(e >> 31)) {
+      for (int i = 0; i < kQ; ++i) {
+        const double f = f64<P>(st[i * g.plane + at], i);
+        v[0] += kCx[i] * f;
+        v[1] += kCy[i] * f;
+        v[2] += kCz[i] * f;
+      }
+      continue;
+    }
+    double rsum = 0.0;
+    int cnt = 0;
+    for (int i = 1; i < kQ; ++i) {
+      int ax = x + kCx[i], ay = y + kCy[i], az = z + kCz[i];
+      if (g.bc_x == LBM_BCX_PERIODIC) ax = wrapc(ax, g.nx);
+      if (g.bc_y == LBM_BCY_PERIODIC) ay = wrapc(ay, g.ny);
+      if (g.bc_z == LBM_BCY_PERIODIC) az = wrapc(az, g.nz);
+      if (ax < 0 || ax >= g.nx || ay < 0 || ay >= g.ny || az < 0 || az >= g.nz) continue;
+      if (!a.valid[(int64_t(az) * g.ny + ay) * g.nx + ax]) continue;
+      const int64_t nb = (int64_t(az) * g.ny + ay) * g.pitch + ax;
+      double r = 0.0;
+      for (int j = 0; j < kQ; ++j) r += f64<P>(st[j * g.plane + nb], j);
+      rsum += r;
+      ++cnt;
+    }
+    const double rho = cnt > 0 ? rsum / double(cnt) : a.rho_w;
+    const double r0 = x - g.mc[0], r1 = y - g.mc[1], r2 = z - g.mc[2];
+    const double u0 = g.mu[0] + g.mw[1] * r2 - g.mw[2] * r1;
+    const double u1 = g.mu[1] + g.mw[2] * r0 - g.mw[0] * r2;
+    const double u2 = g.mu[2] + g.mw[0] * r1 - g.mw[1] * r0;
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    for (int i = 0; i < kQ; ++i) {
+      const double cu = kCx[i] * u0 + kCy[i] * u1 + kCz[i] * u2;
+      const double feq = w27<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      const T q = T(C(S::kDev ? feq - w27<double>(i) : feq));
+      st[i * g.plane + at] = q;
+      const double f = f64<P>(q, i);
+      v[0] -= kCx[i] * f;
+      v[1] -= kCy[i] * f;
+      v[2] -= kCz[i] * f;
+    }
+  }
+  __shared__ double out[3];
+  block_sum<3>(v, out);
+  if (threadIdx.x < 3) a.block_out[3 * int64_t(blockIdx.x) + threadIdx.x] = out[threadIdx.x];
+}
+
+// Sum of the per-block momenta in a fixed order (one block).
+__global__ __launch_bounds__(kThreads) void remask3_sum_kernel(const double* block_out, int nb,
+                                                               double* res) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kThreads)
+    for (int k = 0; k < 3; ++k) v[k] += block_out[3 * int64_t(b) + k];
+  __shared__ double out[3];
+  block_sum<3>(v, out);
+  if (threadIdx.x < 3) res[threadIdx.x] = out[threadIdx.x];
+}
+
 template <int P>
 __global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t plane) {
   using S = St3<P>;
@@ -693,6 +769,28 @@ hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t
 
 hipError_t launch_final3(const Final3Args& a, hipStream_t s) {
   hipLaunchKernelGGL(final3_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_remask3(int precision, const Remask3Args& a, int blocks, double* out,
+                          hipStream_t s) {
+  switch (precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(remask3_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32:
+      hipLaunchKernelGGL(remask3_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32DEV:
+      hipLaunchKernelGGL(remask3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(remask3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(remask3_sum_kernel, dim3(1), dim3(kThreads), 0, s,
+                     static_cast<const double*>(a.block_out), blocks, out);
   return hipGetLastError();
 }
 

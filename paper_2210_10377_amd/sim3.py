@@ -74,6 +74,24 @@ class Sim3:
         C.check3(self._lib.lbm3d_set_body_motion(self._h, *[v.ctypes.data_as(dp) for v in vs]),
                  self._h)
 
+    def set_mask(self, mask, box=None) -> np.ndarray:
+        """Move the body through the grid: a new mask (and control volume, if given)
+        from the next step.  Uncovered nodes are refilled at the wall velocity; returns
+        the impulse (3,) the fluid hands to the body in the change."""
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.shape != (self.nz, self.ny, self.nx):
+            raise ValueError("mask shape differs from the lattice")
+        bp = None
+        if box is not None:
+            barr = (ctypes.c_int32 * 6)(*[int(v) for v in box])
+            bp = ctypes.cast(barr, ctypes.POINTER(ctypes.c_int32))
+        imp = np.zeros(3)
+        C.check3(self._lib.lbm3d_set_mask(self._h,
+                                          mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                          bp, imp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                 self._h)
+        return imp
+
     def info(self) -> C.lbm3d_info:
         inf = C.lbm3d_info()
         C.check3(self._lib.lbm3d_get_info(self._h, ctypes.byref(inf)), self._h)

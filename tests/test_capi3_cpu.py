@@ -25,7 +25,7 @@ def _header_functions():
 def test_library_exports_every_declared_symbol(capi):
     lib = capi.load()
     names = _header_functions()
-    assert len(names) == 12
+    assert len(names) == 13
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(capi.EXPORTS3) == names
@@ -156,3 +156,85 @@ def test_workspace_accounts_for_both_buffers_and_unbound_step_is_estate(capi):
         assert p.workspace_bytes() >= 2 * 27 * esz * w.nx * w.ny * w.nz
     L = capi.load()
     assert L.lbm3d_step(p._h, 1, 15) == capi.LBM_ESTATE
+
+
+def _create3(capi, mask, box, bc=(0, 0, 0)):
+    L = capi.load()
+    nz, ny, nx = mask.shape
+    g = capi.lbm3d_grid()
+    g.nx, g.ny, g.nz = nx, ny, nz
+    g.bc_x, g.bc_y, g.bc_z = bc
+    for k in range(6):
+        g.box[k] = box[k] if box is not None else -1
+    g.precision, g.max_record = capi.LBM_FP32, 4
+    uin = np.full((nz, ny), 0.03)
+    h = ctypes.c_void_p()
+    m = np.ascontiguousarray(mask, np.uint8)
+    rc = L.lbm3d_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0.7,
+                        uin.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0, ctypes.byref(h))
+    assert rc == capi.LBM_OK
+    return L, h
+
+
+def _set_mask3(capi, L, h, mask, box=None):
+    m = np.ascontiguousarray(mask, np.uint8)
+    bp = None
+    if box is not None:
+        bp = ctypes.cast((ctypes.c_int32 * 6)(*box), ctypes.POINTER(ctypes.c_int32))
+    imp = np.full(3, 7.0)
+    rc = L.lbm3d_set_mask(h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), bp,
+                          imp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return rc, imp
+
+
+def test_set_mask_validation_and_unbound_replanning(capi):
+    """lbm3d_set_mask refuses a mask value other than 0/1, a box added or removed, an
+    inadmissible box and a larger control-volume sweep than at create, changing nothing;
+    on an unbound handle it re-plans (links and box as the oracle's) and returns a zero
+    impulse."""
+    nx, ny, nz = 48, 20, 20
+    box = (7, 22, 3, 17, 3, 17)
+    m0 = d3.sphere_mask(nx, ny, nz, 14, 9.5, 9.5, 4)
+    m1 = d3.sphere_mask(nx, ny, nz, 15, 9.5, 9.5, 4)
+    L, h = _create3(capi, m0, box)
+    info = capi.lbm3d_info()
+
+    def links():
+        L.lbm3d_get_info(h, ctypes.byref(info))
+        return info.n_links, info.n_box
+
+    before = links()
+    bad = m1.copy()
+    bad[0, 0, 0] = 2
+    assert _set_mask3(capi, L, h, bad)[0] == capi.LBM_EINVAL
+    assert _set_mask3(capi, L, h, m1, (-1, 0, 0, 0, 0, 0))[0] == capi.LBM_EINVAL
+    assert _set_mask3(capi, L, h, m1, (12, 22, 3, 17, 3, 17))[0] == capi.LBM_EINVAL
+    assert _set_mask3(capi, L, h, m1, (2, 40, 2, 18, 2, 18))[0] == capi.LBM_ENOMEM
+    assert L.lbm3d_last_error(h)
+    assert links() == before
+    rc, imp = _set_mask3(capi, L, h, m1, (8, 23, 3, 17, 3, 17))
+    assert rc == capi.LBM_OK and np.all(imp == 0.0)
+    O = D.links(m1)
+    assert links() == (len(O), int((m1[3:17, 3:17, 8:23] == 0).sum()))
+    out = np.zeros((len(O), 2), np.int64)
+    n = ctypes.c_int64()
+    L.lbm3d_get_links(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(O), ctypes.byref(n))
+    assert np.array_equal(out, O)
+    L.lbm3d_destroy(h)
+
+
+def test_set_mask_refuses_more_force_slots_than_reserved(capi):
+    """A mask with far more force strips than the one at create (one solid node, then
+    solid nodes in every row) is refused with LBM_ENOMEM."""
+    nx, ny, nz = 64, 40, 40
+    m0 = np.zeros((nz, ny, nx), np.uint8)
+    m0[20, 20, 30] = 1
+    L, h = _create3(capi, m0, None, bc=(0, 1, 1))
+    m1 = np.zeros_like(m0)
+    m1[:, :, 30] = 1
+    m1[::2, ::2, 30] = 0
+    assert _set_mask3(capi, L, h, m1)[0] == capi.LBM_ENOMEM
+    m2 = m0.copy()
+    m2[10, 10, 10] = 1
+    assert _set_mask3(capi, L, h, m2)[0] == capi.LBM_OK
+    L.lbm3d_destroy(h)
