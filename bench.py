@@ -469,7 +469,7 @@ def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
 
 
 def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
-                  cpu: bool, collision: str = "bgk"):
+                  cpu: bool, collision: str = "bgk", layout: str = "auto"):
     """The D3Q27 path on the three-dimensional NACA0012 of the paper's Sec. V (zero
     incidence, domain 80 x 8 x 4 chords, periodic span, control volume over the whole
     span), all four estimators every step."""
@@ -484,7 +484,7 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
     stream = torch.cuda.current_stream(dev)
     sim = Sim3(w.mask, w.tau, w.uin, precision=precision, bc_z=w.bc_z, box=w.box,
                max_record=max(steps, warmup, 1), device=dev, stream=stream,
-               collision=collision)
+               collision=collision, layout=layout)
     info = sim.info()
     sim.step(warmup)
     sim.forces()
@@ -519,7 +519,8 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
                   "fp16dev": "f16 storage / f32 arithmetic"}[precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "tau": w.tau,
-                   "storage": precision, "collision": collision, "schemes": list(ALL),
+                   "storage": precision, "collision": collision, "layout": layout,
+                   "schemes": list(ALL),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
                    "box_nodes": int(info.n_box), "general_strips": int(info.n_general),
                    "strips": int(info.n_strips), **w.meta},
@@ -597,6 +598,8 @@ def main():
                     help="the D3Q27 path on the 3-D NACA0012 (80 x 8 x 4 chords, --ppc nodes "
                          "per chord, periodic span)")
     ap.add_argument("--ppc", type=int, default=24)
+    ap.add_argument("--layout", default="auto", choices=["auto", "rows", "planes"],
+                    help="device layout of the 3-D state buffers")
     ap.add_argument("--small-grid", action="store_true",
                     help="the 200x80 cylinder: direct launches against captured graphs")
     ap.add_argument("--sphere-sweep", action="store_true",
@@ -658,7 +661,7 @@ def main():
         three_d_bench(args.precision, args.steps if args.steps != 2000 else 500,
                       args.warmup if args.warmup != 200 else 50, args.ppc,
                       args.re if args.re != 1e4 else 200.0, not args.no_cpu_baseline,
-                      args.collision if args.collision != "kbc" else "bgk")
+                      args.collision if args.collision != "kbc" else "bgk", args.layout)
         return
     if args.resolution_sweep:
         resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,

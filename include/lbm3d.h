@@ -70,7 +70,18 @@ typedef struct {
   int32_t max_record;   /* rows of the force ring (>= 1)                             */
   int32_t collision;    /* LBM_COLL_BGK or LBM_COLL_REGULARIZED (the regularized BGK of
                            lbm.h with the D3Q27 Hermite projection; not in the paper) */
+  int32_t layout;       /* device layout of the state buffers: LBM3D_LAYOUT_AUTO (0),
+                           LBM3D_LAYOUT_ROWS or LBM3D_LAYOUT_PLANES; same results     */
 } lbm3d_grid;
+
+/* State-buffer layouts.  ROWS: [nz][ny][27][row], the 27 directions of a row side by
+ * side (fewer pages per tile: the faster one); needs 27 * ny * nz * row < 2^31 elements.
+ * PLANES: [27][nz][ny][row] (padded planes); needs a plane below 2^31 elements.  AUTO:
+ * ROWS when it fits, else PLANES.  row = nx padded to 64 (plus 64 at multiples of
+ * 1024). */
+#define LBM3D_LAYOUT_AUTO 0
+#define LBM3D_LAYOUT_ROWS 1
+#define LBM3D_LAYOUT_PLANES 2
 
 typedef struct {
   int64_t n_fluid;      /* fluid nodes                                               */
@@ -86,8 +97,8 @@ typedef struct {
  * 1 solid, copied) and the boundary codes.  tau: tau_lb > 1/2.  uin: [nz][ny] inlet
  * x-velocities (host, copied), required when bc_x is inlet/outlet, else ignored;
  * rho_w: inlet wall density (> 0).  LBM_EINVAL for a bad code, size, mask value, box,
- * collision or tau (lbm3d_last_error(NULL) says which); LBM_ENOMEM when the grid is too
- * large. */
+ * collision, layout or tau (lbm3d_last_error(NULL) says which); LBM_ENOMEM when the
+ * grid is too large for the layout. */
 int lbm3d_create(const lbm3d_grid* grid, const uint8_t* solid_mask, double tau,
                  const double* uin, double rho_w, lbm3d_t** out);
 

@@ -18,6 +18,7 @@ LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
 LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
 LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_SI, LBM_FORCE_ALL = 1, 2, 4, 8, 15
 LBM_COLL_BGK, LBM_COLL_REGULARIZED, LBM_COLL_KBC = 0, 1, 2
+LBM3D_LAYOUT_AUTO, LBM3D_LAYOUT_ROWS, LBM3D_LAYOUT_PLANES = 0, 1, 2
 
 ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
                -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EOVERFLOW"}
@@ -66,7 +67,8 @@ class lbm3d_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
                 ("box", ctypes.c_int32 * 6), ("precision", ctypes.c_int32),
-                ("max_record", ctypes.c_int32), ("collision", ctypes.c_int32)]
+                ("max_record", ctypes.c_int32), ("collision", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class lbm3d_info(ctypes.Structure):

@@ -22,8 +22,10 @@ struct lbm3d {
   bool moving = false;
   std::vector<double> uin;  // [nz][ny]
   Plan3 plan;
-  int32_t pitch = 0;
-  int64_t plane = 0;
+  // Population i of node (x, y, z) at i * dstride + (z * ny + y) * rstride + x.
+  int32_t rstride = 0;
+  int64_t dstride = 0;
+  int64_t buf_elems = 0;  // elements of one state buffer
   size_t esz = 0;
   size_t off_buf[2] = {0, 0}, off_word = 0, off_strip = 0, off_fstrip = 0, off_uin = 0, off_part = 0,
          off_jpart = 0, off_ring = 0, total = 0;
@@ -49,6 +51,7 @@ struct lbm3d {
     return LBM_EHIP;
   }
   void* buf(int k) const { return ws + off_buf[k]; }
+  size_t buf_bytes() const { return size_t(buf_elems) * esz; }
   size_t part_doubles() const {
     return size_t(plan.nslots) * kPart + size_t(plan.njslots) * 3;
   }
@@ -73,11 +76,20 @@ double host_w27(int i) {
   return w;
 }
 
+// Padded row of the row-interleaved layout, and whether that layout fits 32-bit offsets.
+int64_t rows_row(int32_t nx) {
+  const int64_t row64 = (int64_t(nx) + 63) / 64 * 64;
+  return row64 + (row64 % 1024 == 0 ? 64 : 0);
+}
+bool rows_fit(const lbm3d_grid& g) {
+  return int64_t(g.ny) * g.nz * kQ * rows_row(g.nx) < (int64_t(1) << 31);
+}
+
 Geom3 geom(const lbm3d* h) {
   const Plan3& p = h->plan;
   Geom3 g{};
-  g.plane = h->plane;
-  g.pitch = h->pitch;
+  g.dstride = h->dstride;
+  g.rstride = h->rstride;
   g.nx = p.nx;
   g.ny = p.ny;
   g.nz = p.nz;
@@ -186,6 +198,15 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     g_err3 = "unknown collision (BGK or regularized)";
     return LBM_EINVAL;
   }
+  if (g.layout != LBM3D_LAYOUT_AUTO && g.layout != LBM3D_LAYOUT_ROWS &&
+      g.layout != LBM3D_LAYOUT_PLANES) {
+    g_err3 = "unknown layout";
+    return LBM_EINVAL;
+  }
+  if (g.layout == LBM3D_LAYOUT_ROWS && g.nx >= 2 && g.ny >= 2 && g.nz >= 2 && !rows_fit(g)) {
+    g_err3 = "grid too large for the row-interleaved layout (27 ny nz row >= 2^31)";
+    return LBM_ENOMEM;
+  }
   lbm3d* h = new (std::nothrow) lbm3d();
   if (!h) return LBM_ENOMEM;
   std::string perr;
@@ -214,22 +235,36 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     }
     h->rho_w = rho_w;
   }
-  // Layout: rows padded to 64 elements; planes padded so that consecutive planes do
-  // not sit a power of two apart.
+  // Layout.  Offsets within a buffer are 32-bit in the kernels.  Row-interleaved
+  // ([nz][ny][27][row]: the 27 directions of a row side by side, so a tile touches few
+  // pages), rows padded to 64 elements, plus 64 when the padded row is a multiple of
+  // 1024 (the directions of a row then do not sit a power of two apart).  Planar
+  // ([27][nz][ny][row]), rows padded to 64, planes padded so that they do not sit a
+  // power of two apart.
   h->esz = elem_bytes(g.precision);
-  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64);
-  const int64_t raw = int64_t(h->pitch) * g.ny * g.nz;
-  const int64_t quantum = int64_t(4096 / h->esz);
-  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(512 / h->esz);
-  if (h->plane >= (int64_t(1) << 31)) {  // in-plane offsets are 32-bit in the kernels
-    g_err3 = "grid too large: a direction plane must hold fewer than 2^31 elements";
-    delete h;
-    return LBM_ENOMEM;
+  const int64_t row64 = (int64_t(g.nx) + 63) / 64 * 64;
+  const int64_t rrow = rows_row(g.nx);
+  const int64_t rows = int64_t(g.ny) * g.nz;
+  if (g.layout == LBM3D_LAYOUT_ROWS || (g.layout == LBM3D_LAYOUT_AUTO && rows_fit(g))) {
+    h->dstride = rrow;
+    h->rstride = int32_t(rrow * kQ);
+    h->buf_elems = rows * rrow * kQ;
+  } else {
+    const int64_t raw = row64 * rows;
+    const int64_t quantum = int64_t(4096 / h->esz);
+    h->rstride = int32_t(row64);
+    h->dstride = (raw + quantum - 1) / quantum * quantum + int64_t(512 / h->esz);
+    h->buf_elems = h->dstride * kQ;
+    if (h->dstride >= (int64_t(1) << 31)) {
+      g_err3 = "grid too large: a direction plane must hold fewer than 2^31 elements";
+      delete h;
+      return LBM_ENOMEM;
+    }
   }
   size_t off = 0;
   for (int k = 0; k < 2; ++k) {
     h->off_buf[k] = off;
-    off = align256(off + size_t(h->plane) * kQ * h->esz);
+    off = align256(off + h->buf_bytes());
   }
   h->off_word = off;
   off = align256(off + h->plan.word.size() * sizeof(uint32_t));
@@ -282,7 +317,7 @@ int lbm3d_bind(lbm3d_t* h, void* ws, size_t bytes, void* stream) {
                        hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload plan");
   for (int k = 0; k < 2; ++k) {
-    e = launch_fill_rest3(h->g.precision, h->buf(k), h->plane, h->stream);
+    e = launch_fill_rest3(h->g.precision, h->buf(k), h->buf_elems, h->dstride, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
   }
   e = hipStreamSynchronize(h->stream);
@@ -354,7 +389,7 @@ int lbm3d_forces(lbm3d_t* h, double* out, int64_t cap, int64_t* got) {
 int lbm3d_get_populations(lbm3d_t* h, double* out) {
   if (!h || !out) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
-  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  const size_t bytes = h->buf_bytes();
   std::vector<unsigned char> raw(bytes);
   hipError_t e = hipMemcpyAsync(raw.data(), h->buf(h->cur), bytes, hipMemcpyDeviceToHost,
                                 h->stream);
@@ -366,7 +401,7 @@ int lbm3d_get_populations(lbm3d_t* h, double* out) {
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
-          const size_t k = size_t(i) * h->plane + (size_t(z) * ny + y) * h->pitch + x;
+          const size_t k = size_t(i) * h->dstride + (size_t(z) * ny + y) * h->rstride + x;
           double v;
           if (prec == LBM_FP64) {
             std::memcpy(&v, &raw[k * 8], 8);
@@ -388,7 +423,7 @@ int lbm3d_get_populations(lbm3d_t* h, double* out) {
 int lbm3d_set_populations(lbm3d_t* h, const double* in) {
   if (!h || !in) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
-  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  const size_t bytes = h->buf_bytes();
   std::vector<unsigned char> raw(bytes, 0);
   const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz, prec = h->g.precision;
   for (int i = 0; i < kQ; ++i) {
@@ -396,7 +431,7 @@ int lbm3d_set_populations(lbm3d_t* h, const double* in) {
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
-          const size_t k = size_t(i) * h->plane + (size_t(z) * ny + y) * h->pitch + x;
+          const size_t k = size_t(i) * h->dstride + (size_t(z) * ny + y) * h->rstride + x;
           const double v = in[((size_t(i) * nz + z) * ny + y) * nx + x] - base;
           if (prec == LBM_FP64) {
             std::memcpy(&raw[k * 8], &v, 8);
@@ -494,7 +529,7 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
     const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
     const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
                  off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 24);
-    if (off_res + 24 > size_t(h->plane) * kQ * h->esz)
+    if (off_res + 24 > h->buf_bytes())
       return h->fail(LBM_ENOMEM, "too many nodes change at once");
     // Nothing in flight may still read the old node words or the state.
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -520,7 +555,7 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
       e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
       if (e != hipSuccess) return h->hip_fail(e, "download impulse");
-      e = launch_fill_rest3(g.precision, scr, h->plane, h->stream);
+      e = launch_fill_rest3(g.precision, scr, h->buf_elems, h->dstride, h->stream);
       if (e != hipSuccess) return h->hip_fail(e, "refill scratch buffer");
     }
     e = hipMemcpyAsync(h->ws + h->off_word, np.word.data(), np.word.size() * sizeof(uint32_t),

@@ -9,8 +9,11 @@ namespace lbm3 {
 
 // Geometry and tables of a lattice as the kernels read them.
 struct Geom3 {
-  int64_t plane;        // elements per direction plane of a state buffer
-  int32_t pitch;        // elements per row (fixed y, z) of a plane
+  // A state buffer holds population i of node (x, y, z) at
+  // i * dstride + (z * ny + y) * rstride + x (row-interleaved: dstride = padded row,
+  // rstride = 27 rows; planar: dstride = padded plane, rstride = padded row).
+  int64_t dstride;      // elements between directions of a node
+  int32_t rstride;      // elements between rows (fixed y, z)
   int32_t nx, ny, nz;
   int32_t bc_x, bc_y, bc_z;
   int32_t box[6];       // control volume (has_box)
@@ -77,6 +80,7 @@ hipError_t launch_remask3(int precision, const Remask3Args& a, int blocks, doubl
                           hipStream_t s);
 hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t s);
 hipError_t launch_final3(const Final3Args& a, hipStream_t s);
-hipError_t launch_fill_rest3(int precision, void* buf, int64_t plane, hipStream_t s);
+// Rest state w_i in all n elements of a buffer with direction stride dstride.
+hipError_t launch_fill_rest3(int precision, void* buf, int64_t n, int64_t dstride, hipStream_t s);
 
 }  // namespace lbm3

@@ -158,7 +158,7 @@ __device__ __forceinline__ int32_t pull_offset(const Geom3& g, int x, int y, int
   }
   *bb = false;
   const int cx = sx >= g.nx ? g.nx - 1 : sx;  // the outlet ghost copies plane nx-1
-  return (sz * g.ny + sy) * g.pitch + cx;
+  return (sz * g.ny + sy) * g.rstride + cx;
 }
 
 // Moving-wall term of the population pulled in direction i across a body link at node
@@ -186,7 +186,7 @@ __device__ __forceinline__ void pull27(const Geom3& g, const typename St3<P>::T*
   for (int i = 1; i < kQ; ++i) {
     bool bb, inl, body;
     const int32_t off = pull_offset(g, x, y, z, w, i, self, &bb, &inl, &body);
-    f[i] = C(src[int64_t(bb ? opp(i) : i) * g.plane + off]);
+    f[i] = C(src[int64_t(bb ? opp(i) : i) * g.dstride + off]);
     if (inl) inlm |= 1u << i;
     if (body) lk |= 1u << opp(i);
   }
@@ -317,7 +317,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
   using T = typename S::T;
   using C = typename S::C;
   const Geom3& g = a.g;
-  const int64_t self = row * g.pitch + x;
+  const int64_t self = row * g.rstride + x;
   const T* __restrict__ src = static_cast<const T*>(a.src);
   T* __restrict__ dst = static_cast<T*>(a.dst);
   const C omega = C(a.omega);
@@ -413,7 +413,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       const T q = T(f[i]);
-      st_nt(dst + int64_t(i) * g.plane + self, q);
+      st_nt(dst + int64_t(i) * g.dstride + self, q);
       f[i] = C(q);  // forces read the populations as stored
     }
     if (fterms) {
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
   const int64_t row = tile / a.ntx;
   const int y = int(row % g.ny), z = int(row / g.ny);
   const int x = tx * kTileW + wave * kStripW + lane;
-  const int64_t self = row * g.pitch + x;
+  const int64_t self = row * g.rstride + x;
   const T* __restrict__ src = static_cast<const T*>(a.src);
   T* __restrict__ dst = static_cast<T*>(a.dst);
   const uint32_t cls = strip_class(e);
@@ -519,8 +519,8 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
     // No boundary within reach: every source is the neighbour itself.
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      f[i] = C(src[int64_t(i) * g.plane + self -
-                   (int64_t(kCz[i]) * g.ny + kCy[i]) * g.pitch - kCx[i]]);
+      f[i] = C(src[int64_t(i) * g.dstride + self -
+                   (int64_t(kCz[i]) * g.ny + kCy[i]) * g.rstride - kCx[i]]);
     if (FORCES && cls == kBoxJ) {
       double j[3] = {0.0, 0.0, 0.0};
       if (P == LBM_FP16DEV) {
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
     }
     collide27<C, S::kDev, COLL>(f, omega);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.plane + self, T(f[i]));
+    for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.dstride + self, T(f[i]));
     return;
   }
   // Strips with force terms run in force3_kernel when forces are evaluated; they hold
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void box3_kernel(Box3Args a) {
     if (!(w & kSolid)) {
       C f[kQ];
       uint32_t lk;
-      pull27<P, MOV>(g, static_cast<const T*>(a.src), x, y, z, w, int32_t(row * g.pitch + x), f,
+      pull27<P, MOV>(g, static_cast<const T*>(a.src), x, y, z, w, int32_t(row * g.rstride + x), f,
                      &lk);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
@@ -635,10 +635,10 @@ __global__ __launch_bounds__(kThreads) void remask3_kernel(Remask3Args a) {
     const uint32_t e = uint32_t(a.list[k]);
     const int32_t node = int32_t(e & 0x7fffffffu);
     const int x = node % g.nx, y = (node / g.nx) % g.ny, z = node / (g.nx * g.ny);
-    const int64_t at = (int64_t(z) * g.ny + y) * g.pitch + x;
+    const int64_t at = (int64_t(z) * g.ny + y) * g.rstride + x;
     if (!(e >> 31)) {
       for (int i = 0; i < kQ; ++i) {
-        const double f = f64<P>(st[i * g.plane + at], i);
+        const double f = f64<P>(st[i * g.dstride + at], i);
         v[0] += kCx[i] * f;
         v[1] += kCy[i] * f;
         v[2] += kCz[i] * f;
@@ -654,9 +654,9 @@ __global__ __launch_bounds__(kThreads) void remask3_kernel(Remask3Args a) {
       if (g.bc_z == LBM_BCY_PERIODIC) az = wrapc(az, g.nz);
       if (ax < 0 || ax >= g.nx || ay < 0 || ay >= g.ny || az < 0 || az >= g.nz) continue;
       if (!a.valid[(int64_t(az) * g.ny + ay) * g.nx + ax]) continue;
-      const int64_t nb = (int64_t(az) * g.ny + ay) * g.pitch + ax;
+      const int64_t nb = (int64_t(az) * g.ny + ay) * g.rstride + ax;
       double r = 0.0;
-      for (int j = 0; j < kQ; ++j) r += f64<P>(st[j * g.plane + nb], j);
+      for (int j = 0; j < kQ; ++j) r += f64<P>(st[j * g.dstride + nb], j);
       rsum += r;
       ++cnt;
     }
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void remask3_kernel(Remask3Args a) {
       const double cu = kCx[i] * u0 + kCy[i] * u1 + kCz[i] * u2;
       const double feq = w27<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
       const T q = T(C(S::kDev ? feq - w27<double>(i) : feq));
-      st[i * g.plane + at] = q;
+      st[i * g.dstride + at] = q;
       const double f = f64<P>(q, i);
       v[0] -= kCx[i] * f;
       v[1] -= kCy[i] * f;
@@ -694,14 +694,16 @@ __global__ __launch_bounds__(kThreads) void remask3_sum_kernel(const double* blo
 }
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t plane) {
+__global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t n,
+                                                                int64_t dstride) {
   using S = St3<P>;
   using T = typename S::T;
   T* p = static_cast<T*>(buf);
-  const int64_t n = plane * kQ;
+  // Both layouts repeat the 27 directions every 27 * dstride elements.
+  const int64_t period = dstride * kQ;
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
-    const int i = int(k / plane);
+    const int i = int((k % period) / dstride);
     p[k] = S::kDev ? T(0) : T(w27<double>(i));
   }
 }
@@ -794,20 +796,24 @@ hipError_t launch_remask3(int precision, const Remask3Args& a, int blocks, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rest3(int precision, void* buf, int64_t plane, hipStream_t s) {
+hipError_t launch_fill_rest3(int precision, void* buf, int64_t n, int64_t dstride, hipStream_t s) {
   const int blocks = 2048;
   switch (precision) {
     case LBM_FP64:
-      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
+                         dstride);
       break;
     case LBM_FP32:
-      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
+                         dstride);
       break;
     case LBM_FP32DEV:
-      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
+                         dstride);
       break;
     default:
-      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
+                         dstride);
   }
   return hipGetLastError();
 }

@@ -9,16 +9,19 @@ import numpy as np
 from . import _capi as C
 from .sim import ALL_SCHEMES, COLLISIONS, PRECISIONS, scheme_mask
 
+LAYOUTS = {"auto": C.LBM3D_LAYOUT_AUTO, "rows": C.LBM3D_LAYOUT_ROWS,
+           "planes": C.LBM3D_LAYOUT_PLANES}
+
 
 class Sim3:
     """mask: uint8 [nz, ny, nx] (1 = solid).  tau: tau_lb.  uin: inlet x-velocity,
     scalar or [nz, ny] (ignored for periodic x).  box: (x0, x1, y0, y1, z0, z1) or None.
     bc_y, bc_z: C.LBM_BCY_WALL or C.LBM_BCY_PERIODIC.  collision: "bgk" or
-    "regularized"."""
+    "regularized".  layout: "auto", "rows" or "planes" (device layout of the state)."""
 
     def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, bc_z=C.LBM_BCY_WALL, box=None, max_record=1024,
-                 rho_w=1.0, device="cuda", stream=None, collision="bgk"):
+                 rho_w=1.0, device="cuda", stream=None, collision="bgk", layout="auto"):
         import torch
 
         self._lib = C.load()
@@ -34,6 +37,7 @@ class Sim3:
         g.precision = PRECISIONS[precision]
         g.max_record = int(max_record)
         g.collision = COLLISIONS[collision]
+        g.layout = LAYOUTS[layout]
         self.collision = collision
         up = None
         if uin is not None:
@@ -143,7 +147,7 @@ class Plan3:
 
     def __init__(self, mask, tau=0.8, uin=0.0, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, bc_z=C.LBM_BCY_WALL, box=None, max_record=16,
-                 collision="bgk"):
+                 collision="bgk", layout="auto"):
         self._lib = C.load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         nz, ny, nx = mask.shape
@@ -155,6 +159,7 @@ class Plan3:
         g.precision = PRECISIONS[precision]
         g.max_record = int(max_record)
         g.collision = COLLISIONS[collision]
+        g.layout = LAYOUTS[layout]
         self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (nz, ny)))
         h = ctypes.c_void_p()
         C.check3(self._lib.lbm3d_create(ctypes.byref(g),

@@ -238,3 +238,36 @@ def test_set_mask_refuses_more_force_slots_than_reserved(capi):
     m2[10, 10, 10] = 1
     assert _set_mask3(capi, L, h, m2)[0] == capi.LBM_OK
     L.lbm3d_destroy(h)
+
+
+def test_layouts_workspace_and_limits(capi):
+    """The state layouts: ROWS and PLANES both hold two buffers of 27 populations per
+    node; an unknown layout is refused; ROWS beyond 32-bit offsets is LBM_ENOMEM (the
+    mask is never read: the check comes first)."""
+    from paper_2210_10377_amd import Plan3
+    w = d3.sphere_channel_64x32x32()
+    sizes = {}
+    for lay in ("auto", "rows", "planes"):
+        sizes[lay] = Plan3(w.mask, box=w.box, precision="fp32", layout=lay).workspace_bytes()
+        assert sizes[lay] >= 2 * 27 * 4 * w.nx * w.ny * w.nz
+    assert sizes["auto"] == sizes["rows"]
+    L = capi.load()
+
+    def create(nx, ny, nz, layout):
+        g = capi.lbm3d_grid()
+        g.nx, g.ny, g.nz, g.bc_x, g.bc_y, g.bc_z = nx, ny, nz, 1, 1, 1
+        for k in range(6):
+            g.box[k] = -1
+        g.precision, g.max_record, g.layout = capi.LBM_FP32, 4, layout
+        m = np.zeros((nz, ny, nx), np.uint8)   # zero pages: never touched when refused
+        h = ctypes.c_void_p()
+        rc = L.lbm3d_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            0.7, None, 1.0, ctypes.byref(h))
+        if rc == capi.LBM_OK:
+            L.lbm3d_destroy(h)
+        return rc
+
+    assert create(12, 10, 8, 7) == capi.LBM_EINVAL
+    # 27 x 160 x 120 rows of 4160 elements (4096 padded) = 2.16e9 >= 2^31
+    assert create(4096, 160, 120, capi.LBM3D_LAYOUT_ROWS) == capi.LBM_ENOMEM
+    assert "row-interleaved" in L.lbm3d_last_error(None).decode()
