@@ -599,7 +599,7 @@ def main():
                          "per chord, periodic span)")
     ap.add_argument("--ppc", type=int, default=24)
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "planes"],
-                    help="device layout of the 3-D state buffers")
+                    help="device layout of the state buffers")
     ap.add_argument("--small-grid", action="store_true",
                     help="the 200x80 cylinder: direct launches against captured graphs")
     ap.add_argument("--sphere-sweep", action="store_true",
@@ -681,7 +681,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box,
               max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
-              device=dev, stream=stream, collision=args.collision)
+              device=dev, stream=stream, collision=args.collision, layout=args.layout)
     motion = None
     if args.pitch_rate:
         if "xq" in w.meta:
@@ -736,7 +736,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "tau": w.tau,
                    "storage": args.precision, "collision": args.collision,
-                   "schemes": list(schemes),
+                   "layout": args.layout, "schemes": list(schemes),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
                    "box_nodes": int(info.n_box), **{k: v for k, v in w.meta.items()},
                    **({"body_motion": {"omega": motion[2], "xc": motion[3], "yc": motion[4]}}

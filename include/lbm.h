@@ -132,7 +132,19 @@ typedef struct lbm_grid {
   double rho_ref, u_ref, l_ref; /* normalisation of the force coefficients (Sec. V:
                                    C = 2 F / (rho U^2 L))                           */
   int32_t collision;  /* LBM_COLL_BGK (0), LBM_COLL_REGULARIZED or LBM_COLL_KBC         */
+  int32_t layout;     /* LBM_LAYOUT_AUTO (0), LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES: device
+                         layout of the state buffers, same results                  */
 } lbm_grid;
+
+/* State-buffer layouts (both lattices).  ROWS: the populations of one grid row stored
+ * direction after direction ([ny][9][row] in 2-D, [nz][ny][27][row] in 3-D), so a tile
+ * touches few memory pages: the faster one; needs a buffer below 2^31 elements.
+ * PLANES: one plane per direction ([9][ny][row], [27][nz][ny][row]), planes padded;
+ * needs a plane below 2^31 elements.  AUTO: ROWS when it fits, else PLANES.  Rows are nx
+ * padded to 64 elements plus a pad (128 in 2-D; in 3-D 64 at multiples of 1024). */
+#define LBM_LAYOUT_AUTO 0
+#define LBM_LAYOUT_ROWS 1
+#define LBM_LAYOUT_PLANES 2
 
 typedef struct lbm_inlet {
   const double* ux; /* ny inlet velocities u_in(y) (host); ignored (may be NULL)
@@ -151,8 +163,9 @@ typedef struct lbm_info {
   int64_t steps_done;     /* steps taken since create (or the restored state)        */
   int64_t n_recorded;     /* force rows waiting in the ring                          */
   int32_t tile_w, tile_h; /* tile shape in nodes                                     */
-  int64_t plane_stride;   /* population plane stride in elements (device layout)     */
-  int32_t pitch;          /* row pitch in elements (device layout)                   */
+  int64_t plane_stride;   /* elements between the directions of a node (device layout:
+                             population i of (x, y) at i*plane_stride + y*pitch + x)  */
+  int32_t pitch;          /* elements between rows (device layout)                   */
   int32_t elem_bytes;     /* bytes per stored population                             */
 } lbm_info;
 
@@ -161,8 +174,9 @@ typedef struct lbm_info {
  * inlet may be NULL when bc_x is periodic.  Returns LBM_EINVAL for nx or ny < 3,
  * non-finite or tau <= 1/2, a mask byte outside {0,1}, a missing, non-finite inlet,
  * an inadmissible box, unknown codes (precision, boundaries, collision) or
- * max_record < 1; LBM_ENOMEM for grids whose
- * population planes exceed 2^31 elements.  Needs no GPU. */
+ * max_record < 1, or an unknown layout; LBM_ENOMEM for grids too large for the layout
+ * (a plane of 2^31 elements or more; with LBM_LAYOUT_ROWS, a buffer of 2^31 or more).
+ * Needs no GPU. */
 int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
                const lbm_inlet* inlet, lbm_t** out);
 

@@ -70,18 +70,9 @@ typedef struct {
   int32_t max_record;   /* rows of the force ring (>= 1)                             */
   int32_t collision;    /* LBM_COLL_BGK or LBM_COLL_REGULARIZED (the regularized BGK of
                            lbm.h with the D3Q27 Hermite projection; not in the paper) */
-  int32_t layout;       /* device layout of the state buffers: LBM3D_LAYOUT_AUTO (0),
-                           LBM3D_LAYOUT_ROWS or LBM3D_LAYOUT_PLANES; same results     */
+  int32_t layout;       /* device layout of the state buffers: LBM_LAYOUT_AUTO (0),
+                           LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES of lbm.h; same results */
 } lbm3d_grid;
-
-/* State-buffer layouts.  ROWS: [nz][ny][27][row], the 27 directions of a row side by
- * side (fewer pages per tile: the faster one); needs 27 * ny * nz * row < 2^31 elements.
- * PLANES: [27][nz][ny][row] (padded planes); needs a plane below 2^31 elements.  AUTO:
- * ROWS when it fits, else PLANES.  row = nx padded to 64 (plus 64 at multiples of
- * 1024). */
-#define LBM3D_LAYOUT_AUTO 0
-#define LBM3D_LAYOUT_ROWS 1
-#define LBM3D_LAYOUT_PLANES 2
 
 typedef struct {
   int64_t n_fluid;      /* fluid nodes                                               */

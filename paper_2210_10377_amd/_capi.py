@@ -18,7 +18,7 @@ LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
 LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
 LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_SI, LBM_FORCE_ALL = 1, 2, 4, 8, 15
 LBM_COLL_BGK, LBM_COLL_REGULARIZED, LBM_COLL_KBC = 0, 1, 2
-LBM3D_LAYOUT_AUTO, LBM3D_LAYOUT_ROWS, LBM3D_LAYOUT_PLANES = 0, 1, 2
+LBM_LAYOUT_AUTO, LBM_LAYOUT_ROWS, LBM_LAYOUT_PLANES = 0, 1, 2
 
 ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
                -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EOVERFLOW"}
@@ -47,7 +47,8 @@ class lbm_grid(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("box", ctypes.c_int32 * 4),
                 ("max_record", ctypes.c_int32),
                 ("rho_ref", ctypes.c_double), ("u_ref", ctypes.c_double),
-                ("l_ref", ctypes.c_double), ("collision", ctypes.c_int32)]
+                ("l_ref", ctypes.c_double), ("collision", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class lbm_inlet(ctypes.Structure):

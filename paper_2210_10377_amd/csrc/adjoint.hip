@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
-  const int tile = block_tile(blockIdx.x, a.ntiles);
+  const int tile = block_tile<kBatchGroup>(blockIdx.x, a.ntiles);
   const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const Planes<T, BUF> st(a.state, a.plane, a.state_bytes);

@@ -36,6 +36,13 @@ constexpr uint64_t kStateMagic = 0x4c424d5332443951ull;  // "LBMS2D9Q"
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Padded row of the device layout, and whether the row-interleaved layout keeps every
+// offset within a buffer below 2^31.
+int64_t padded_row(int32_t nx) { return (int64_t(nx) + 63) / 64 * 64 + LBM_PITCH_PAD; }
+bool rows_fit(const lbm_grid& g) {
+  return int64_t(g.ny) * kQ * padded_row(g.nx) < (int64_t(1) << 31);
+}
+
 size_t elem_bytes(int precision) {
   return precision == LBM_FP64 ? 8 : (precision == LBM_FP16DEV ? 2 : 4);
 }
@@ -92,6 +99,15 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
       return LBM_EINVAL;
     }
   }
+  if (g.layout != LBM_LAYOUT_AUTO && g.layout != LBM_LAYOUT_ROWS &&
+      g.layout != LBM_LAYOUT_PLANES) {
+    g_create_error = "unknown layout";
+    return LBM_EINVAL;
+  }
+  if (g.layout == LBM_LAYOUT_ROWS && g.nx >= 3 && g.ny >= 3 && !rows_fit(g)) {
+    g_create_error = "grid too large for the row-interleaved layout (9 ny row >= 2^31)";
+    return LBM_ENOMEM;
+  }
   lbm_t* h = new (std::nothrow) lbm_t();
   if (!h) return LBM_ENOMEM;
   std::string perr;
@@ -107,17 +123,32 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
   h->rho_w = rho_w;
   h->uin = uin;
   h->uin.resize(size_t(g.ny), 0.0);
-  // Device layout: rows padded to 64 elements; planes padded so that consecutive
-  // planes do not sit a power of two apart.
+  // Device layout (offsets within a buffer are 32-bit in the kernels).  Rows padded to
+  // 64 elements plus LBM_PITCH_PAD.  Row-interleaved: the nine directions of a row side
+  // by side ([ny][9][row]), so a tile touches few pages.  Planar ([9][ny][row]): planes
+  // padded so that consecutive planes do not sit a power of two apart.
   h->esz = elem_bytes(g.precision);
-  h->pitch = int32_t((int64_t(g.nx) + 63) / 64 * 64 + LBM_PITCH_PAD);
-  const int64_t raw = int64_t(h->pitch) * (g.ny + LBM_PLANE_PAD_ROWS);
-  const int64_t quantum = int64_t(4096 / h->esz);
-  h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(LBM_PLANE_PAD_BYTES / h->esz);
+  const int64_t row = padded_row(g.nx);
+  if (g.layout == LBM_LAYOUT_ROWS || (g.layout == LBM_LAYOUT_AUTO && rows_fit(g))) {
+    h->plane = row;
+    h->pitch = int32_t(row * kQ);
+    h->buf_elems = int64_t(g.ny) * row * kQ;
+  } else {
+    h->pitch = int32_t(row);
+    const int64_t raw = row * (g.ny + LBM_PLANE_PAD_ROWS);
+    const int64_t quantum = int64_t(4096 / h->esz);
+    h->plane = (raw + quantum - 1) / quantum * quantum + int64_t(LBM_PLANE_PAD_BYTES / h->esz);
+    h->buf_elems = h->plane * kQ;
+    if (h->plane >= (int64_t(1) << 31)) {
+      g_create_error = "grid too large: a direction plane must hold fewer than 2^31 elements";
+      delete h;
+      return LBM_ENOMEM;
+    }
+  }
   size_t off = 0;
   for (int k = 0; k < 2; ++k) {
     h->off_buf[k] = off;
-    off = align256(off + size_t(h->plane) * kQ * h->esz);
+    off = align256(off + h->buf_bytes());
   }
   h->off_node = off;
   off = align256(off + h->plan.node.size() * sizeof(uint32_t));
@@ -171,7 +202,7 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
                      hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload body motion");
   for (int k = 0; k < 2; ++k) {
-    e = launch_fill_rest(h->g.precision, h->buf(k), h->plane, h->stream);
+    e = launch_fill_rest(h->g.precision, h->buf(k), h->buf_elems, h->plane, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
   }
   e = hipStreamSynchronize(h->stream);
@@ -416,7 +447,7 @@ int lbm_get_info(const lbm_t* h, lbm_info* info) {
 int lbm_get_populations(lbm_t* h, double* out) {
   if (!h || !out) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
-  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  const size_t bytes = h->buf_bytes();
   std::vector<unsigned char> raw(bytes);
   hipError_t e = hipMemcpyAsync(raw.data(), h->buf(h->cur), bytes, hipMemcpyDeviceToHost, h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "download populations");
@@ -450,7 +481,7 @@ int lbm_set_populations(lbm_t* h, const double* in) {
   if (!h || !in) return LBM_EINVAL;
   h->adj_valid = false;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
-  const size_t bytes = size_t(h->plane) * kQ * h->esz;
+  const size_t bytes = h->buf_bytes();
   std::vector<unsigned char> raw(bytes, 0);
   const int nx = h->g.nx, ny = h->g.ny, prec = h->g.precision;
   for (int i = 0; i < kQ; ++i) {
@@ -479,7 +510,7 @@ int lbm_set_populations(lbm_t* h, const double* in) {
 
 int lbm_state_bytes(const lbm_t* h, size_t* bytes) {
   if (!h || !bytes) return LBM_EINVAL;
-  *bytes = sizeof(StateHeader) + size_t(h->plane) * kQ * h->esz;
+  *bytes = sizeof(StateHeader) + h->buf_bytes();
   return LBM_OK;
 }
 
@@ -601,7 +632,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
     const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
     const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
                  off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 16);
-    if (off_res + 16 > size_t(h->plane) * kQ * h->esz)
+    if (off_res + 16 > h->buf_bytes())
       return h->fail(LBM_ENOMEM, "too many nodes change at once");
     // Nothing in flight (on any stream, a batch holding the handle included) may still
     // read the old node codes or the state.
@@ -658,7 +689,7 @@ int lbm_reset(lbm_t* h) {
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   for (int k = 0; k < 2; ++k) {
-    hipError_t e = launch_fill_rest(h->g.precision, h->buf(k), h->plane, h->stream);
+    hipError_t e = launch_fill_rest(h->g.precision, h->buf(k), h->buf_elems, h->plane, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
   }
   hipError_t e = hipStreamSynchronize(h->stream);
@@ -685,8 +716,8 @@ struct AdjLayout {
 AdjLayout adj_layout(const lbm_t* h, int32_t n, int32_t every) {
   AdjLayout L;
   const size_t cbytes = h->g.precision == LBM_FP64 ? 8 : 4;
-  L.state = size_t(h->plane) * kQ * h->esz;
-  L.mu = size_t(h->plane) * kQ * cbytes;
+  L.state = h->buf_bytes();
+  L.mu = size_t(h->buf_elems) * cbytes;
   L.ncp = (n + every - 1) / every;
   size_t off = 0;
   L.off_cp = off;

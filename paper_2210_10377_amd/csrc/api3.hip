@@ -198,12 +198,12 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     g_err3 = "unknown collision (BGK or regularized)";
     return LBM_EINVAL;
   }
-  if (g.layout != LBM3D_LAYOUT_AUTO && g.layout != LBM3D_LAYOUT_ROWS &&
-      g.layout != LBM3D_LAYOUT_PLANES) {
+  if (g.layout != LBM_LAYOUT_AUTO && g.layout != LBM_LAYOUT_ROWS &&
+      g.layout != LBM_LAYOUT_PLANES) {
     g_err3 = "unknown layout";
     return LBM_EINVAL;
   }
-  if (g.layout == LBM3D_LAYOUT_ROWS && g.nx >= 2 && g.ny >= 2 && g.nz >= 2 && !rows_fit(g)) {
+  if (g.layout == LBM_LAYOUT_ROWS && g.nx >= 2 && g.ny >= 2 && g.nz >= 2 && !rows_fit(g)) {
     g_err3 = "grid too large for the row-interleaved layout (27 ny nz row >= 2^31)";
     return LBM_ENOMEM;
   }
@@ -245,7 +245,7 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
   const int64_t row64 = (int64_t(g.nx) + 63) / 64 * 64;
   const int64_t rrow = rows_row(g.nx);
   const int64_t rows = int64_t(g.ny) * g.nz;
-  if (g.layout == LBM3D_LAYOUT_ROWS || (g.layout == LBM3D_LAYOUT_AUTO && rows_fit(g))) {
+  if (g.layout == LBM_LAYOUT_ROWS || (g.layout == LBM_LAYOUT_AUTO && rows_fit(g))) {
     h->dstride = rrow;
     h->rstride = int32_t(rrow * kQ);
     h->buf_elems = rows * rrow * kQ;

@@ -100,8 +100,8 @@ struct RawBuf<_Float16> {
   }
 };
 
-// The nine population planes of one state buffer.  Offsets are element offsets
-// inside a plane (y * pitch + x); plane i starts i * plane elements into the buffer.
+// The nine populations of one state buffer: population i of the node at element offset
+// off = y * pitch + x sits at i * plane + off (row-interleaved or planar layout).
 template <class T, bool BUF>
 struct Planes;
 
@@ -225,12 +225,19 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
 // mapping hands each XCD runs of kGroup consecutive row-major tiles, so the cache
 // lines shared by horizontally adjacent tiles (the +-1-shifted pulls) meet in one L2,
 // while the XCDs together still sweep one region of memory at a time.  The tail that
-// does not fill a whole round keeps the identity mapping.
+// does not fill a whole round keeps the identity mapping.  Runs of 32 tiles for the
+// single-lattice step (measured best on the row-interleaved layout of a wide grid),
+// of 4 for the batch (instances of 1-2 tiles per row) and the adjoint.
 #ifndef LBM_XCD_GROUP
-#define LBM_XCD_GROUP 4
+#define LBM_XCD_GROUP 32
 #endif
+#ifndef LBM_XCD_GROUP_BATCH
+#define LBM_XCD_GROUP_BATCH 4
+#endif
+constexpr int kStepGroup = LBM_XCD_GROUP, kBatchGroup = LBM_XCD_GROUP_BATCH;
+template <int kGroup>
 __device__ __forceinline__ int block_tile(int b, int n) {
-  constexpr int kGroup = LBM_XCD_GROUP, kRound = 8 * kGroup;
+  constexpr int kRound = 8 * kGroup;
   if (kGroup == 1 || b >= n / kRound * kRound) return b;
   const int xcd = b & 7, k = b >> 3;
   return ((k / kGroup) * 8 + xcd) * kGroup + (k % kGroup);

@@ -19,8 +19,11 @@ struct lbm_t {
   std::vector<double> uin;
   lbm::Plan plan;
   // device layout
+  // Population i of node (x, y) at i * plane + y * pitch + x (elements): row-interleaved
+  // (plane = padded row, pitch = 9 rows) or planar (plane = padded plane, pitch = row).
   int32_t pitch = 0;
-  int64_t plane = 0;  // elements
+  int64_t plane = 0;
+  int64_t buf_elems = 0;  // elements of one state buffer
   size_t esz = 0;
   size_t off_buf[2] = {0, 0}, off_node = 0, off_tiles = 0, off_uin = 0, off_motion = 0, off_part = 0,
          off_jpart = 0, off_ring = 0, total = 0;
@@ -55,10 +58,11 @@ struct lbm_t {
     return LBM_EHIP;
   }
   void* buf(int k) const { return ws + off_buf[k]; }
+  size_t buf_bytes() const { return size_t(buf_elems) * esz; }
   // Size of one state buffer for buffer-resource addressing, or 0 when it needs 64-bit
   // addresses.
   uint32_t buf_bytes32() const {
-    const uint64_t b = uint64_t(plane) * lbm::kQ * esz;
+    const uint64_t b = buf_bytes();
     return b < (uint64_t(1) << 32) - 4096 ? uint32_t(b) : 0u;
   }
   double* ring() const { return reinterpret_cast<double*>(ws + off_ring); }

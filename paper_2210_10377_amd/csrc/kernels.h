@@ -26,10 +26,10 @@ struct BodyMotion {
 struct StepArgs {
   const void* src;  // post-collision state of the previous step (storage type)
   void* dst;        // post-collision state of this step
-  int64_t plane;    // population plane stride, elements
+  int64_t plane;    // elements between the directions of a node (i * plane + y * pitch + x)
   uint32_t buf_bytes;  // bytes of one state buffer when below 4 GiB (buffer-resource
                        // addressing), 0 for 64-bit global addressing
-  int32_t pitch;    // row pitch, elements
+  int32_t pitch;    // elements between rows
   int32_t nx, ny;
   int32_t bc_x;     // LBM_BCX_*
   int32_t ntx, nty, ntiles;
@@ -104,7 +104,7 @@ struct BatchLaunch {
 // A mask change of a body moving through the grid, over the current state buffer.
 struct RemaskArgs {
   void* state;            // current state buffer (stored populations)
-  int64_t plane;          // elements per direction plane
+  int64_t plane;          // elements between the directions of a node
   int32_t pitch, nx, ny, bc_x, bc_y;
   const int32_t* list;    // [n] y * nx + x; bit 31 set: uncovered (refill), clear: covered
   int32_t n;
@@ -129,6 +129,8 @@ hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity
 hipError_t launch_box_momentum(int precision, const BoxArgs& a, int blocks, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 // Rest state w_i in every element of a population buffer (padding included).
-hipError_t launch_fill_rest(int precision, void* buf, int64_t plane, hipStream_t s);
+// Rest state w_i in all n elements of a state buffer whose directions sit plane elements
+// apart.
+hipError_t launch_fill_rest(int precision, void* buf, int64_t n, int64_t plane, hipStream_t s);
 
 }  // namespace lbm

@@ -270,7 +270,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
 template <int P, bool BUF, bool FORCES, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
-  int tile = block_tile(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
+  int tile = block_tile<kStepGroup>(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
   if (a.red_in) {
     // Block 0 is dispatched first: it reduces the previous step's force partials while
     // the tiles stream.
@@ -309,7 +309,7 @@ void batch_step_kernel(
   }
   const int stride = PERSIST ? int(gridDim.x) - nred : b.total_tiles;
   for (int v = int(blockIdx.x) - nred; v < b.total_tiles; v += stride) {
-    const int t = block_tile(v, b.total_tiles);
+    const int t = block_tile<kBatchGroup>(v, b.total_tiles);
     const BatchInst& I = inst[tile_inst[t]];
     StepArgs a = I.a;
     a.src = I.buf[parity];
@@ -413,14 +413,16 @@ __global__ __launch_bounds__(kThreads) void batch_finalize_kernel(BatchLaunch b,
 }
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t plane) {
+__global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t n,
+                                                               int64_t plane) {
   using S = Storage<P>;
   using T = typename S::T;
   T* p = static_cast<T*>(buf);
-  const int64_t n = plane * kQ;
+  // Both layouts repeat the nine directions every 9 * plane elements.
+  const int64_t period = plane * kQ;
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
-    const int i = int(k / plane);
+    const int i = int((k % period) / plane);
     p[k] = S::kDev ? T(0) : T(weight<typename S::C>(i));
   }
 }
@@ -662,20 +664,20 @@ hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double*
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rest(int precision, void* buf, int64_t plane, hipStream_t s) {
+hipError_t launch_fill_rest(int precision, void* buf, int64_t n, int64_t plane, hipStream_t s) {
   const int blocks = 2048;
   switch (precision) {
     case LBM_FP64:
-      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP64>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
       break;
     case LBM_FP32:
-      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
       break;
     case LBM_FP32DEV:
-      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
       break;
     default:
-      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, plane);
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
   }
   return hipGetLastError();
 }

@@ -15,6 +15,8 @@ SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_D
 ALL_SCHEMES = ("A", "B", "DRTT", "SI")
 COLLISIONS = {"bgk": C.LBM_COLL_BGK, "regularized": C.LBM_COLL_REGULARIZED,
               "kbc": C.LBM_COLL_KBC}
+LAYOUTS = {"auto": C.LBM_LAYOUT_AUTO, "rows": C.LBM_LAYOUT_ROWS,
+           "planes": C.LBM_LAYOUT_PLANES}
 
 
 def scheme_mask(schemes) -> int:
@@ -33,12 +35,13 @@ class Sim:
     uin: inlet velocity per row (scalar or [ny]); ignored for periodic x.
     box: control-volume box (x0, x1, y0, y1) for the DRTT force, or None.
     collision: "bgk" (Eq. CollideAdv), "regularized" or "kbc" (entropic; for tau_lb
-    close to 1/2).
+    close to 1/2).  layout: "auto", "rows" or "planes" (device layout of the state).
     """
 
     def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, box=None, max_record=4096, rho_ref=1.0, u_ref=1.0,
-                 l_ref=1.0, rho_w=1.0, device="cuda", stream=None, collision="bgk"):
+                 l_ref=1.0, rho_w=1.0, device="cuda", stream=None, collision="bgk",
+                 layout="auto"):
         import torch
 
         self._lib = C.load()
@@ -54,6 +57,7 @@ class Sim:
         g.max_record = int(max_record)
         g.rho_ref, g.u_ref, g.l_ref = float(rho_ref), float(u_ref), float(l_ref)
         g.collision = COLLISIONS[collision]
+        g.layout = LAYOUTS[layout]
         self.collision = collision
         self._grid = g
         inlet = None
@@ -235,7 +239,7 @@ class Plan:
     """A handle created but never bound: host-side classification only (no GPU)."""
 
     def __init__(self, mask, tau=0.8, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
-                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16, collision="bgk"):
+                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16, collision="bgk", layout="auto"):
         self._lib = C.load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         ny, nx = mask.shape
@@ -248,6 +252,7 @@ class Plan:
         g.max_record = int(max_record)
         g.rho_ref = g.u_ref = g.l_ref = 1.0
         g.collision = COLLISIONS[collision]
+        g.layout = LAYOUTS[layout]
         inlet = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (ny,)))

@@ -7,10 +7,7 @@ import ctypes
 import numpy as np
 
 from . import _capi as C
-from .sim import ALL_SCHEMES, COLLISIONS, PRECISIONS, scheme_mask
-
-LAYOUTS = {"auto": C.LBM3D_LAYOUT_AUTO, "rows": C.LBM3D_LAYOUT_ROWS,
-           "planes": C.LBM3D_LAYOUT_PLANES}
+from .sim import ALL_SCHEMES, COLLISIONS, LAYOUTS, PRECISIONS, scheme_mask
 
 
 class Sim3:

@@ -158,3 +158,21 @@ def test_adjoint_naca_1024x512_against_fp64_central_differences():
         errs.append(abs(gu @ v - d_v) / abs(d_v))
     print("naca 1024x512 adjoint rel errors (tau, v1, v2):", errs, "J", J0, "dJ/dtau", d_tau)
     assert max(errs) <= 1e-4, errs
+
+
+def test_adjoint_same_in_both_layouts(mini_refs):
+    """The adjoint runs the same arithmetic in the row-interleaved and planar layouts:
+    objective and gradients bitwise equal (FP32 deviations)."""
+    from paper_2210_10377_amd import Sim
+    r = mini_refs["naca_walls"]
+    n, every, t0, T, w, bcy = r["cfg"]
+    out = []
+    for layout in ("rows", "planes"):
+        g = Sim(r["mask"], r["tau"], r["uin"], precision="fp32dev", bc_y=bcy, max_record=8,
+                layout=layout)
+        J = g.adjoint_forward(n, every, t0, T, w)
+        gu, gt = g.adjoint_backward(1.0)
+        out.append((J, gu, gt))
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]

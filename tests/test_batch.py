@@ -326,3 +326,26 @@ def test_member_moving_through_the_grid_batch_bitwise_equals_singles():
     sims[k].set_mask(shifted, (x0 + 1, x1 + 1, y0, y1 - 1))   # one row fewer
     with pytest.raises(LbmError, match="changed size"):
         b.step(1)
+
+
+def test_batch_mixing_state_layouts_bitwise_equals_singles():
+    """Members in the row-interleaved and the planar layout, alternating, in one batch:
+    every member bitwise equal to the same member stepped alone."""
+    ws = MINI
+    from paper_2210_10377_amd import Sim, Batch
+    def members():
+        return [Sim(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=64,
+                    layout=("rows", "planes")[i % 2]) for i, w in enumerate(ws)]
+    sims = members()
+    _seed_states(sims, ws)
+    b = Batch(sims, max_record=64)
+    b.set_schedule(grid_blocks=24, graph_steps=4)
+    b.step(21)
+    Fb, bad = b.forces()
+    assert not bad.any()
+    ref = members()
+    _seed_states(ref, ws)
+    for i, r in enumerate(ref):
+        r.step(21)
+        np.testing.assert_array_equal(r.forces(), Fb[i])
+        np.testing.assert_array_equal(r.populations(), b.members[i].populations())

@@ -269,5 +269,5 @@ def test_layouts_workspace_and_limits(capi):
 
     assert create(12, 10, 8, 7) == capi.LBM_EINVAL
     # 27 x 160 x 120 rows of 4160 elements (4096 padded) = 2.16e9 >= 2^31
-    assert create(4096, 160, 120, capi.LBM3D_LAYOUT_ROWS) == capi.LBM_ENOMEM
+    assert create(4096, 160, 120, capi.LBM_LAYOUT_ROWS) == capi.LBM_ENOMEM
     assert "row-interleaved" in L.lbm3d_last_error(None).decode()

@@ -181,14 +181,52 @@ def test_step_unbound_is_estate(capi):
 
 
 def test_workspace_size_accounts_for_buffers(capi):
+    """Both state layouts hold two buffers of nine populations per node: row-interleaved
+    (the default: directions a padded row apart, rows nine padded rows apart) and
+    planar (rows a padded row apart, directions a padded plane apart)."""
     from paper_2210_10377_amd import Plan
     for prec, s in (("fp64", 8), ("fp32", 4), ("fp16dev", 2), ("fp32dev", 4)):
-        p = Plan(np.zeros((100, 300), np.uint8), 0.8, np.full(100, 0.01), precision=prec)
+        m = np.zeros((100, 300), np.uint8)
+        p = Plan(m, 0.8, np.full(100, 0.01), precision=prec)
         inf = p.info()
         assert inf.elem_bytes == s
+        assert inf.plane_stride >= 300 and inf.plane_stride % 64 == 0
+        assert inf.pitch == 9 * inf.plane_stride
+        assert p.workspace_bytes() >= 2 * inf.pitch * 100 * s + 300 * 100 * 4
+        q = Plan(m, 0.8, np.full(100, 0.01), precision=prec, layout="planes")
+        inf = q.info()
         assert inf.pitch >= 300 and inf.pitch % 64 == 0
         assert inf.plane_stride >= inf.pitch * 100
-        assert p.workspace_bytes() >= 2 * 9 * inf.plane_stride * s + 300 * 100 * 4
+        assert q.workspace_bytes() >= 2 * 9 * inf.plane_stride * s + 300 * 100 * 4
+
+
+def test_layout_validation(capi):
+    """An unknown layout is refused; the row-interleaved layout beyond 32-bit offsets is
+    LBM_ENOMEM before the mask is read."""
+    L = capi.load()
+
+    def create(nx, ny, layout):
+        g = capi.lbm_grid()
+        g.nx, g.ny, g.bc_x, g.bc_y = nx, ny, capi.LBM_BCX_PERIODIC, capi.LBM_BCY_PERIODIC
+        for k in range(4):
+            g.box[k] = -1
+        g.precision, g.max_record, g.layout = capi.LBM_FP16DEV, 4, layout
+        g.rho_ref = g.u_ref = g.l_ref = 1.0
+        m = np.zeros((ny, nx), np.uint8)   # zero pages: never touched when refused
+        h = ctypes.c_void_p()
+        rc = L.lbm_create(ctypes.byref(g), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          0.8, None, ctypes.byref(h))
+        info = capi.lbm_info()
+        if rc == capi.LBM_OK:
+            L.lbm_get_info(h, ctypes.byref(info))
+            L.lbm_destroy(h)
+        return rc, info
+
+    assert create(16, 16, 7)[0] == capi.LBM_EINVAL
+    # 9 x 16384 rows of 32896 elements (32768 + 128) = 4.85e9 >= 2^31
+    rc, _ = create(32768, 16384, capi.LBM_LAYOUT_ROWS)
+    assert rc == capi.LBM_ENOMEM
+    assert "row-interleaved" in L.lbm_last_error(None).decode()
 
 
 def test_batch_create_rejects_bad_members(capi):
