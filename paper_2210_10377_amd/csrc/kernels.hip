@@ -270,7 +270,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
 template <int P, bool BUF, bool FORCES, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
                                                         const int32_t* __restrict__ strip_slot) {
-  int tile = block_tile<kStepGroup>(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
+  constexpr int kGroup = kStepGroup * 4 / int(sizeof(typename Storage<P>::T));
+  int tile = block_tile<kGroup>(blockIdx.x, a.ntiles + (a.red_in ? 1 : 0));
   if (a.red_in) {
     // Block 0 is dispatched first: it reduces the previous step's force partials while
     // the tiles stream.
