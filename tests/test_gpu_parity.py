@@ -339,6 +339,39 @@ def test_full_size_naca_one_step(precision):
     assert np.all(e <= tol_f), e
 
 
+def test_state_buffers_beyond_4gib_take_64bit_addressing():
+    """An 8192 x 8192 FP64 channel: each state buffer holds more than 4 GiB, so the step
+    addresses it with 64-bit pointers instead of buffer resources.  Two steps from a
+    seeded random state: every fluid population to 1e-10 of the oracle, all four forces
+    to 1e-10."""
+    nx = ny = 8192
+    mask = workloads.cylinder_mask(nx, ny, 2000, 4095.5, 300)
+    box = (1500, 2700, 3500, 4700)
+    uin = np.full(ny, 0.03)
+    g = _sim(mask=mask, tau=0.6, uin=uin, precision="fp64", box=box, max_record=4)
+    inf = g.info()
+    assert inf.pitch * ny * inf.elem_bytes > 4 << 30
+    S0 = workloads.near_rest_state(nx, ny, seed=81, amp=0.02)
+    g.set_populations(S0)
+    g.step(2)
+    Fg = g.forces()
+    Sg = g.populations()
+    del g
+    o = OracleSim(mask, tau=0.6, uin=uin, box=box)
+    o.set_state(S0)
+    del S0
+    o.step(2)
+    Fo = o.forces()
+    So = o.state()
+    del o
+    fl = mask == 0
+    err = 0.0
+    for i in range(9):
+        err = max(err, float((np.abs(Sg[i] - So[i])[fl] / So[i][fl]).max()))
+    assert err <= 1e-10, err
+    assert np.all(_force_err(Fg, Fo) <= 1e-10)
+
+
 @pytest.mark.parametrize("collision", ["regularized", "kbc"])
 @pytest.mark.parametrize("name", ["channel_body_box", "multi_tile_ragged", "solid_touching_inlet",
                                   "periodic_x_body_on_seam", "channel_periodic_y"])
