@@ -297,6 +297,47 @@ def precision_study3(d: int, t_conv: float, re: float):
                       "steps": steps, "tau": tau}), flush=True)
 
 
+def slab_bench(precision: str, steps: int, warmup: int, k: int = 2, parts: int = 8):
+    """One GPU's share of the benchmark airfoil split into `parts` x-slabs (the
+    decomposition the path would use on several GPUs): columns [k W, (k+1) W) of the
+    8192 x 4096 channel with the airfoil part they hold, at that real shape.  Periodic
+    x stands in for the halo columns the neighbouring slabs would provide, so every
+    column streams as in the interior of the full run; A, B and SI every step (the
+    control volume of the full run spans several slabs: no DRTT here)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2210_10377_amd import Sim, _capi as C
+
+    w = workloads.naca_8192x4096()
+    W = w.nx // parts
+    mask = np.ascontiguousarray(w.mask[:, k * W:(k + 1) * W])
+    sim = Sim(mask, w.tau, None, precision=precision, bc_x=C.LBM_BCX_PERIODIC,
+              max_record=max(steps, warmup, 1))
+    info = sim.info()
+    schemes = ("A", "B", "SI")
+    sim.step(warmup, schemes)
+    sim.forces()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps, schemes)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bpn = BYTES_PER_NODE[precision]
+    achieved = info.n_fluid * bpn / (ms / 1e3) / 1e9
+    print(json.dumps({
+        "metric": "slab MLUPS incl. per-step forces", "workload": f"{w.name}_slab{k}of{parts}",
+        "nx": W, "ny": w.ny, "storage": precision, "steps": steps,
+        "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
+        "us_per_step": round(ms * 1e3, 3), "mlups": round(W * w.ny / ms / 1e3, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)},
+        "halo_bytes_per_cut_each_way": 3 * w.ny * (bpn // 18)}), flush=True)
+
+
 def small_grid_bench(precision: str, steps: int):
     """The 200x80 cylinder channel (D 20, Re 20; the FP64 parity configuration): a grid
     of 16,000 nodes is bound by launch latency, not by HBM.  Direct `lbm_step` launches
@@ -598,6 +639,9 @@ def main():
                     help="the D3Q27 path on the 3-D NACA0012 (80 x 8 x 4 chords, --ppc nodes "
                          "per chord, periodic span)")
     ap.add_argument("--ppc", type=int, default=24)
+    ap.add_argument("--slab", action="store_true",
+                    help="one GPU's share of the benchmark airfoil in an 8-way x-slab "
+                         "decomposition (1024 x 4096, periodic x for the halo)")
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "planes"],
                     help="device layout of the state buffers")
     ap.add_argument("--small-grid", action="store_true",
@@ -646,6 +690,9 @@ def main():
     if args.precision_study_3d:
         precision_study3(16, args.convective_times if args.convective_times != 150.0 else 30.0,
                          args.re if args.re != 1e4 else 50.0)
+        return
+    if args.slab:
+        slab_bench(args.precision, args.steps, args.warmup)
         return
     if args.small_grid:
         small_grid_bench(args.precision if args.precision != "fp32" else "fp64",
