@@ -271,3 +271,14 @@ def test_layouts_workspace_and_limits(capi):
     # 27 x 160 x 120 rows of 4160 elements (4096 padded) = 2.16e9 >= 2^31
     assert create(4096, 160, 120, capi.LBM_LAYOUT_ROWS) == capi.LBM_ENOMEM
     assert "row-interleaved" in L.lbm3d_last_error(None).decode()
+
+
+def test_auto_layout_falls_back_to_planes_beyond_32bit_offsets():
+    """2048 x 256 x 160 (84 M nodes): the row-interleaved buffer would pass 2^31
+    elements, so AUTO takes the planar layout (same workspace as PLANES)."""
+    from paper_2210_10377_amd import Plan3
+    m = np.zeros((160, 256, 2048), np.uint8)
+    m[70:90, 118:138, 500:520] = 1
+    sizes = {lay: Plan3(m, bc_x=1, bc_y=1, bc_z=1, precision="fp16dev",
+                        layout=lay).workspace_bytes() for lay in ("auto", "planes")}
+    assert sizes["auto"] == sizes["planes"] >= 2 * 27 * 2 * m.size

@@ -347,3 +347,14 @@ def test_set_mask_validation_and_replanning(capi, orc):
     rc = L.lbm_set_mask(q._h, mm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None, None)
     assert rc == capi.LBM_ENOMEM and b"slots" in L.lbm_last_error(q._h)
     assert np.array_equal(p.links(), orc.links(m1))  # unchanged by the refusals
+
+
+def test_auto_layout_falls_back_to_planes_beyond_32bit_offsets():
+    """30000 x 8000 (240 M nodes): the row-interleaved buffer would pass 2^31 elements,
+    so AUTO takes the planar layout (rows a padded row apart)."""
+    from paper_2210_10377_amd import Plan
+    m = np.zeros((8000, 30000), np.uint8)
+    m[3900:4100, 5000:5200] = 1
+    p = Plan(m, 0.8, np.full(8000, 0.01), precision="fp16dev")
+    inf = p.info()
+    assert inf.pitch == 30016 + 128 and inf.plane_stride >= inf.pitch * 8000
