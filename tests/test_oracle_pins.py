@@ -5,6 +5,7 @@ None of these compares the oracle with itself: they use exact rationals, closed 
 conservation laws, brute-force tracking of single populations, Newton's law for the
 whole fluid, and the worked one-dimensional example of the introduction.
 """
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -18,18 +19,33 @@ from oracle import BCX_INLET_OUTLET, BCX_PERIODIC, BCY_PERIODIC, BCY_WALL, Oracl
 # Lattice and equilibrium (Sec. II, Table I and the moment conditions)
 # --------------------------------------------------------------------------------------
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _table_d2q9():
+    """tests/golden/d2q9_shells.txt: the paper's D2Q9 table (Sec. II, Table tabD2Q9)."""
+    theta0, rows = None, []
+    for line in open(os.path.join(GOLDEN, "d2q9_shells.txt")):
+        t = line.split("#")[0].split()
+        if not t:
+            continue
+        if t[0] == "theta0":
+            theta0 = Fraction(t[1])
+        else:
+            rows.append((int(t[1]), int(t[2]), Fraction(t[3])))
+    return theta0, rows
+
+
 def test_lattice_matches_table_I(orc):
+    """The oracle's velocities, weights and theta0 are exactly the printed table's; the
+    opposite of each direction is its negative."""
     cx, cy, opp, w, th = orc.lattice()
-    shells = {}
-    for i in range(9):
-        shells.setdefault(int(cx[i] ** 2 + cy[i] ** 2), []).append((int(cx[i]), int(cy[i]), w[i]))
-    assert sorted((a, b) for a, b, _ in shells[0]) == [(0, 0)]
-    assert sorted((a, b) for a, b, _ in shells[1]) == sorted([(1, 0), (-1, 0), (0, 1), (0, -1)])
-    assert sorted((a, b) for a, b, _ in shells[2]) == sorted([(1, 1), (1, -1), (-1, 1), (-1, -1)])
-    for s, wt in ((0, Fraction(16, 36)), (1, Fraction(4, 36)), (2, Fraction(1, 36))):
-        for _, _, wi in shells[s]:
-            assert wi == float(wt)
-    assert th == float(Fraction(1, 3))
+    theta0, rows = _table_d2q9()
+    assert len(rows) == 9
+    got = sorted((int(cx[i]), int(cy[i]), w[i]) for i in range(9))
+    want = sorted((a, b, float(wt)) for a, b, wt in rows)
+    assert got == want
+    assert th == float(theta0)
     for i in range(9):
         assert cx[opp[i]] == -cx[i] and cy[opp[i]] == -cy[i]
 
