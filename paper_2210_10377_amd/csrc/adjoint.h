@@ -10,9 +10,9 @@ namespace lbm {
 // One reverse step t: mu(t) from mu(t+1) and the stored state S(t-1).
 struct AdjArgs {
   const void* state;     // S(t-1), storage type, state layout
-  const void* mu_in;     // mu(t+1), arithmetic type, same plane layout (zero at the end)
+  const void* mu_in;     // mu(t+1), arithmetic type, same layout (zero at the end)
   void* mu_out;          // mu(t)
-  int64_t plane;         // plane stride, elements (state and adjoint share it)
+  int64_t plane;         // elements between directions (state and adjoint share it)
   uint32_t state_bytes;  // bytes of a state buffer below 4 GiB (buffer addressing), else 0
   uint32_t mu_bytes;     // bytes of an adjoint buffer below 4 GiB, else 0
   int32_t pitch, nx, ny, ntx, ntiles;

@@ -245,8 +245,8 @@ __device__ __forceinline__ int block_tile(int b, int n) {
 }
 
 // Populations arriving at fluid node (x, y) (streaming of Eq. CollideAdv with the
-// boundary rules), from the node's pull codes.  The source plane and offset of every
-// direction are selected first and the nine loads issued together, so a node costs one
+// boundary rules), from the node's pull codes.  The source direction and offset of
+// every direction are selected first and the nine loads issued together, so a node costs one
 // memory latency whatever its boundary rules:
 //   stream: S_i(x - c_i); body or wall: S_o(x) (half-way bounce-back, o = opposite);
 //   inlet: S_o(x) + 2 w_i rho_w (c_i . u_w) / c_s^2 (moving-wall bounce-back, Sec. II);

@@ -6,9 +6,11 @@
 // bounce-back (Sec. II), the momentum exchange of Sec. III with the two operator
 // orders of Eq. rtt4, and the control-volume balance of the second Eq. rtt7.
 //
-// Data layout (HBM): structure of arrays, one plane per direction, x fastest; plane
-// stride and row pitch come from the host.  Every node is updated by one thread of a
-// 256-thread block; a block covers a 256 x kTileH tile, each wave a 64 x kTileH strip.
+// Data layout (HBM): structure of arrays, x fastest; population i of node (x, y) sits at
+// i * plane + y * pitch + x, with the strides from the host (row-interleaved: the nine
+// directions of a row side by side; or one plane per direction).  Every node is updated
+// by one thread of a 256-thread block; a block covers a 256 x kTileH tile, each wave a
+// 64 x kTileH strip.
 // Strips of plain fluid (all pulls plain streaming, away from the control-volume band)
 // take a branch-free path that reads no per-node metadata; the other strips read a
 // 32-bit word of pull codes per node, apply the boundary rules, and accumulate the
@@ -18,7 +20,7 @@
 // the finalize kernel, so every force is deterministic.
 //
 // Addressing: when a state buffer is below 4 GiB its populations are read and written
-// through buffer resources (one descriptor per buffer, the plane offsets in scalar
+// through buffer resources (one descriptor per buffer, the direction offsets in scalar
 // registers, 32-bit per-lane offsets); out-of-range offsets read zero and drop writes.
 // Larger buffers use 64-bit global addresses.
 #include <hip/hip_runtime.h>

@@ -133,8 +133,8 @@ __device__ __forceinline__ bool in_box(const Geom3& g, int x, int y, int z) {
 }
 
 // Source of the pull of direction i at fluid node (x, y, z) with node word w: the
-// element offset inside a direction plane, and whether it is read from plane opp(i) of
-// the node itself (bounce-back: wall, body, outlet ghost of a solid node; the inlet's
+// element offset of the source node ((z ny + y) rstride + x), and whether direction
+// opp(i) of the node itself is read (bounce-back: wall, body, outlet ghost of a solid node; the inlet's
 // moving-wall rule).  *inl: the inlet term applies; *body: a force-bearing body link in
 // direction opp(i).
 __device__ __forceinline__ int32_t pull_offset(const Geom3& g, int x, int y, int z, uint32_t w,
