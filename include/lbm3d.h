@@ -153,6 +153,24 @@ int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
 int lbm3d_set_mask(lbm3d_t* h, const uint8_t* solid_mask, const int32_t* box,
                    double* impulse);
 
+/* Checkpoint as in lbm.h: the exact stored state (raw storage bytes plus the step
+ * counter) as an opaque host blob of lbm3d_state_bytes bytes; lbm3d_set_state accepts a
+ * blob of a handle with the same grid size, precision and layout (else LBM_EINVAL).
+ * Both synchronise the stream; LBM_ESTATE before bind. */
+int lbm3d_state_bytes(const lbm3d_t* h, size_t* bytes);
+int lbm3d_get_state(lbm3d_t* h, void* blob, size_t cap);
+int lbm3d_set_state(lbm3d_t* h, const void* blob, size_t n);
+
+/* Put every node back in the rest state w_i, zero the step counter and empty the force
+ * ring.  Synchronises the stream. */
+int lbm3d_reset(lbm3d_t* h);
+
+/* Replace the relaxation time tau_lb (> 1/2, finite) or the inlet plane ([nz][ny] host
+ * values, copied; only with an inlet) of a handle; later steps use the new values.
+ * lbm3d_set_inlet synchronises the stream when the handle is bound. */
+int lbm3d_set_tau(lbm3d_t* h, double tau);
+int lbm3d_set_inlet(lbm3d_t* h, const double* uin);
+
 int lbm3d_get_info(const lbm3d_t* h, lbm3d_info* info);
 void lbm3d_destroy(lbm3d_t* h);
 /* Last error message of h, or of the last failed lbm3d_create when h is NULL. */

@@ -38,7 +38,9 @@ EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_for
 EXPORTS3 = ("lbm3d_create", "lbm3d_workspace_bytes", "lbm3d_bind", "lbm3d_step",
             "lbm3d_forces", "lbm3d_get_populations", "lbm3d_set_populations",
             "lbm3d_get_links", "lbm3d_get_info", "lbm3d_destroy", "lbm3d_last_error",
-            "lbm3d_set_body_motion", "lbm3d_set_mask")
+            "lbm3d_set_body_motion", "lbm3d_set_mask", "lbm3d_state_bytes",
+            "lbm3d_get_state", "lbm3d_set_state", "lbm3d_reset", "lbm3d_set_tau",
+            "lbm3d_set_inlet")
 
 
 class lbm_grid(ctypes.Structure):
@@ -164,6 +166,12 @@ def load():
     L.lbm3d_get_info.argtypes = [vp, ctypes.POINTER(lbm3d_info)]
     L.lbm3d_set_body_motion.argtypes = [vp, dp, dp, dp]
     L.lbm3d_set_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(i32), dp]
+    L.lbm3d_state_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    L.lbm3d_get_state.argtypes = [vp, vp, sz]
+    L.lbm3d_set_state.argtypes = [vp, vp, sz]
+    L.lbm3d_reset.argtypes = [vp]
+    L.lbm3d_set_tau.argtypes = [vp, ctypes.c_double]
+    L.lbm3d_set_inlet.argtypes = [vp, dp]
     L.lbm3d_destroy.argtypes = [vp]
     L.lbm3d_destroy.restype = None
     L.lbm3d_last_error.argtypes = [vp]

@@ -65,6 +65,17 @@ namespace {
 
 std::string g_err3;
 
+constexpr uint64_t kState3Magic = 0x4c424d5333443237ull;  // "LBMS3D27"
+
+// Header of a checkpoint blob; the raw state buffer follows.
+struct State3Header {
+  uint64_t magic;
+  int32_t nx, ny, nz, precision;
+  int64_t dstride;
+  int32_t rstride, pad;
+  int64_t steps_done;
+};
+
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 size_t elem_bytes(int p) { return p == LBM_FP64 ? 8 : (p == LBM_FP16DEV ? 2 : 4); }
 bool is_dev(int p) { return p == LBM_FP16DEV || p == LBM_FP32DEV; }
@@ -574,6 +585,95 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
   h->njblocks = nj;
   if (impulse)
     for (int k = 0; k < 3; ++k) impulse[k] = P[k];
+  return LBM_OK;
+}
+
+int lbm3d_state_bytes(const lbm3d_t* h, size_t* bytes) {
+  if (!h || !bytes) return LBM_EINVAL;
+  *bytes = sizeof(State3Header) + h->buf_bytes();
+  return LBM_OK;
+}
+
+int lbm3d_get_state(lbm3d_t* h, void* blob, size_t cap) {
+  if (!h || !blob) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  size_t need = 0;
+  lbm3d_state_bytes(h, &need);
+  if (cap < need) return h->fail(LBM_EINVAL, "state buffer too small");
+  State3Header hd{};
+  hd.magic = kState3Magic;
+  hd.nx = h->g.nx;
+  hd.ny = h->g.ny;
+  hd.nz = h->g.nz;
+  hd.precision = h->g.precision;
+  hd.dstride = h->dstride;
+  hd.rstride = h->rstride;
+  hd.steps_done = h->steps_done;
+  std::memcpy(blob, &hd, sizeof hd);
+  hipError_t e = hipMemcpyAsync(static_cast<char*>(blob) + sizeof hd, h->buf(h->cur),
+                                need - sizeof hd, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "download state");
+  return LBM_OK;
+}
+
+int lbm3d_set_state(lbm3d_t* h, const void* blob, size_t n) {
+  if (!h || !blob) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  size_t need = 0;
+  lbm3d_state_bytes(h, &need);
+  State3Header hd{};
+  if (n < sizeof hd) return h->fail(LBM_EINVAL, "state blob too small");
+  std::memcpy(&hd, blob, sizeof hd);
+  if (hd.magic != kState3Magic || hd.nx != h->g.nx || hd.ny != h->g.ny || hd.nz != h->g.nz ||
+      hd.precision != h->g.precision || hd.dstride != h->dstride ||
+      hd.rstride != h->rstride || n != need)
+    return h->fail(LBM_EINVAL, "state blob does not match this handle");
+  hipError_t e = hipMemcpyAsync(h->buf(h->cur), static_cast<const char*>(blob) + sizeof hd,
+                                need - sizeof hd, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "upload state");
+  h->steps_done = hd.steps_done;
+  return LBM_OK;
+}
+
+int lbm3d_reset(lbm3d_t* h) {
+  if (!h) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = launch_fill_rest3(h->g.precision, h->buf(k), h->buf_elems, h->dstride,
+                                     h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "fill rest state");
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "reset synchronize");
+  h->cur = 0;
+  h->steps_done = 0;
+  h->nrec = 0;
+  h->rec_scheme.clear();
+  return LBM_OK;
+}
+
+int lbm3d_set_tau(lbm3d_t* h, double tau) {
+  if (!h) return LBM_EINVAL;
+  if (!std::isfinite(tau) || tau <= 0.5) return h->fail(LBM_EINVAL, "tau must be finite and > 1/2");
+  h->tau = tau;
+  return LBM_OK;
+}
+
+int lbm3d_set_inlet(lbm3d_t* h, const double* uin) {
+  if (!h || !uin) return LBM_EINVAL;
+  if (h->g.bc_x != LBM_BCX_INLET_OUTLET) return h->fail(LBM_EINVAL, "the lattice has no inlet");
+  for (size_t k = 0; k < h->uin.size(); ++k)
+    if (!std::isfinite(uin[k])) return h->fail(LBM_EINVAL, "inlet velocity is not finite");
+  h->uin.assign(uin, uin + h->uin.size());
+  if (h->bound) {
+    hipError_t e = hipMemcpyAsync(h->ws + h->off_uin, h->uin.data(),
+                                  h->uin.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return h->hip_fail(e, "upload inlet");
+  }
   return LBM_OK;
 }
 

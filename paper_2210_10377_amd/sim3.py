@@ -93,6 +93,29 @@ class Sim3:
                  self._h)
         return imp
 
+    def get_state(self) -> bytes:
+        """Checkpoint: the exact stored state and step counter as an opaque blob."""
+        n = ctypes.c_size_t()
+        C.check3(self._lib.lbm3d_state_bytes(self._h, ctypes.byref(n)), self._h)
+        buf = ctypes.create_string_buffer(n.value)
+        C.check3(self._lib.lbm3d_get_state(self._h, buf, n.value), self._h)
+        return buf.raw
+
+    def set_state(self, blob: bytes) -> None:
+        C.check3(self._lib.lbm3d_set_state(self._h, blob, len(blob)), self._h)
+
+    def reset(self) -> None:
+        C.check3(self._lib.lbm3d_reset(self._h), self._h)
+
+    def set_tau(self, tau: float) -> None:
+        C.check3(self._lib.lbm3d_set_tau(self._h, float(tau)), self._h)
+
+    def set_inlet(self, uin) -> None:
+        """Inlet x-velocity, scalar or [nz, ny]."""
+        u = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (self.nz, self.ny)))
+        C.check3(self._lib.lbm3d_set_inlet(self._h, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                 self._h)
+
     def info(self) -> C.lbm3d_info:
         inf = C.lbm3d_info()
         C.check3(self._lib.lbm3d_get_info(self._h, ctypes.byref(inf)), self._h)

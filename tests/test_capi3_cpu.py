@@ -25,7 +25,7 @@ def _header_functions():
 def test_library_exports_every_declared_symbol(capi):
     lib = capi.load()
     names = _header_functions()
-    assert len(names) == 13
+    assert len(names) == 19
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(capi.EXPORTS3) == names
@@ -282,3 +282,31 @@ def test_auto_layout_falls_back_to_planes_beyond_32bit_offsets():
     sizes = {lay: Plan3(m, bc_x=1, bc_y=1, bc_z=1, precision="fp16dev",
                         layout=lay).workspace_bytes() for lay in ("auto", "planes")}
     assert sizes["auto"] == sizes["planes"] >= 2 * 27 * 2 * m.size
+
+
+def test_parameter_and_state_calls_validate_without_a_gpu(capi):
+    """lbm3d_set_tau refuses tau <= 1/2 and non-finite values; lbm3d_set_inlet refuses
+    non-finite values and a lattice without an inlet; the state calls need a bound
+    handle (LBM_ESTATE); lbm3d_state_bytes holds the header and one state buffer."""
+    from paper_2210_10377_amd import Plan3
+    w = d3.sphere_channel_64x32x32()
+    L = capi.load()
+    p = Plan3(w.mask, box=w.box)
+    h = p._h
+    assert L.lbm3d_set_tau(h, 0.5) == capi.LBM_EINVAL
+    assert L.lbm3d_set_tau(h, float("nan")) == capi.LBM_EINVAL
+    assert L.lbm3d_set_tau(h, 0.8) == capi.LBM_OK
+    bad = np.full((w.nz, w.ny), np.inf)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert L.lbm3d_set_inlet(h, bad.ctypes.data_as(dp)) == capi.LBM_EINVAL
+    ok = np.full((w.nz, w.ny), 0.02)
+    assert L.lbm3d_set_inlet(h, ok.ctypes.data_as(dp)) == capi.LBM_OK
+    q = Plan3(w.mask, bc_x=1, box=w.box)
+    assert L.lbm3d_set_inlet(q._h, ok.ctypes.data_as(dp)) == capi.LBM_EINVAL
+    n = ctypes.c_size_t()
+    assert L.lbm3d_state_bytes(h, ctypes.byref(n)) == capi.LBM_OK
+    assert n.value >= 27 * 4 * w.nx * w.ny * w.nz
+    buf = ctypes.create_string_buffer(n.value)
+    assert L.lbm3d_get_state(h, buf, n.value) == capi.LBM_ESTATE
+    assert L.lbm3d_set_state(h, buf, n.value) == capi.LBM_ESTATE
+    assert L.lbm3d_reset(h) == capi.LBM_ESTATE

@@ -276,3 +276,45 @@ def test_row_interleaved_and_planar_layouts_agree_bitwise(precision, name):
         runs.append((g.populations(), g.forces()))
     np.testing.assert_array_equal(runs[0][0], runs[1][0])
     np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+def test_checkpoint_reset_and_parameter_changes_3d():
+    """2n steps equal n steps, a checkpoint, a new handle restoring it, n steps (bitwise,
+    populations and forces); a checkpoint of the other layout is refused; reset equals a
+    fresh handle; set_tau and set_inlet between calls equal a handle created with the new
+    values and restored from the checkpoint (FP32 sphere duct)."""
+    from paper_2210_10377_amd import LbmError
+    w = d3.sphere_channel_64x32x32()
+    mk = lambda tau=w.tau, uin=w.uin, layout="auto": _sim3(
+        w.mask, tau, uin, precision="fp32", box=w.box, max_record=64, layout=layout)
+    a = mk()
+    a.step(40)
+    Fa = a.forces()
+    b = mk()
+    b.step(20)
+    Fb = b.forces()
+    blob = b.get_state()
+    c = mk()
+    c.set_state(blob)
+    c.step(20)
+    assert np.array_equal(a.populations(), c.populations())
+    assert np.array_equal(Fa, np.concatenate([Fb, c.forces()]))
+    assert c.info().steps_done == 40
+    with pytest.raises(LbmError):
+        mk(layout="planes").set_state(blob)
+    c.reset()
+    c.step(20)
+    f = mk()
+    f.step(20)
+    assert np.array_equal(c.populations(), f.populations())
+    assert np.array_equal(c.forces(), f.forces())
+    # parameter changes between calls
+    tau2, uin2 = w.tau * 1.1, np.asarray(w.uin) * 0.8
+    b.set_tau(tau2)
+    b.set_inlet(uin2)
+    b.step(20)
+    d = mk(tau=tau2, uin=uin2)
+    d.set_state(blob)
+    d.step(20)
+    assert np.array_equal(b.populations(), d.populations())
+    assert np.array_equal(b.forces(), d.forces())
