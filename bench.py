@@ -338,6 +338,60 @@ def slab_bench(precision: str, steps: int, warmup: int, k: int = 2, parts: int =
         "halo_bytes_per_cut_each_way": 3 * w.ny * (bpn // 18)}), flush=True)
 
 
+def remask_bench(precision: str, moves: int = 8, chunk: int = 20):
+    """Cost of moving a body through the grid: the benchmark airfoil (8192 x 4096) and the
+    3-D airfoil (1920 x 192 x 96), each translated one node along x `moves` times with
+    its control volume, `chunk` steps with all forces between moves.  Reports the wall
+    time of one mask change (host re-plan, changed-node refill, plan upload; the call
+    synchronises) against the time of one step."""
+    import numpy as np
+    import torch
+    import workloads
+    from workloads import d3
+    from paper_2210_10377_amd import Sim, Sim3
+
+    out = {"metric": "mask change cost (a body moving through the grid)", "storage": precision,
+           "moves": moves, "steps_between": chunk}
+    w = workloads.naca_8192x4096()
+    w3 = d3.naca3d(24, 200.0)
+    for key, ww, make in (
+            ("2d", w, lambda: Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box,
+                                  max_record=moves * chunk + chunk)),
+            ("3d", w3, lambda: Sim3(w3.mask, w3.tau, w3.uin, precision=precision, bc_z=w3.bc_z,
+                                    box=w3.box, max_record=moves * chunk + chunk))):
+        sim = make()
+        box = list(ww.box)
+        t_mask, n_changed = 0.0, 0
+        t0 = time.perf_counter()
+        for k in range(1, moves + 1):
+            sim.step(chunk)
+            torch.cuda.synchronize()
+            m = np.roll(ww.mask, k, axis=-1)
+            box[0] += 1
+            box[1] += 1
+            n_changed += int((m != np.roll(ww.mask, k - 1, axis=-1)).sum())
+            t1 = time.perf_counter()
+            sim.set_mask(m, tuple(box))
+            t_mask += time.perf_counter() - t1
+        sim.step(chunk)
+        sim.forces()
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(chunk)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        out[key] = {"workload": ww.name, "ms_per_mask_change": round(t_mask / moves * 1e3, 2),
+                    "changed_nodes_per_move": n_changed // moves,
+                    "ms_per_step": round(e0.elapsed_time(e1) / chunk, 4),
+                    "wall_s": round(total, 2)}
+        del sim
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def small_grid_bench(precision: str, steps: int):
     """The 200x80 cylinder channel (D 20, Re 20; the FP64 parity configuration): a grid
     of 16,000 nodes is bound by launch latency, not by HBM.  Direct `lbm_step` launches
@@ -639,6 +693,9 @@ def main():
                     help="the D3Q27 path on the 3-D NACA0012 (80 x 8 x 4 chords, --ppc nodes "
                          "per chord, periodic span)")
     ap.add_argument("--ppc", type=int, default=24)
+    ap.add_argument("--remask", action="store_true",
+                    help="cost of a mask change (a body moving through the grid) on the "
+                         "2-D and 3-D benchmark airfoils")
     ap.add_argument("--slab", action="store_true",
                     help="one GPU's share of the benchmark airfoil in an 8-way x-slab "
                          "decomposition (1024 x 4096, periodic x for the halo)")
@@ -693,6 +750,9 @@ def main():
         return
     if args.slab:
         slab_bench(args.precision, args.steps, args.warmup)
+        return
+    if args.remask:
+        remask_bench(args.precision)
         return
     if args.small_grid:
         small_grid_bench(args.precision if args.precision != "fp32" else "fp64",

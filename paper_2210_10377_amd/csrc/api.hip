@@ -607,44 +607,57 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
       return h->fail(LBM_EINVAL, "a control volume can be moved, not added or removed");
     for (int k = 0; k < 4; ++k) g.box[k] = box[k];
   }
+  // Nodes that swap between fluid and solid (bit 31 of a list entry: uncovered), and
+  // the nodes fluid in both masks (read by the refill).
+  const int nx = g.nx, ny = g.ny;
+  const size_t n = size_t(nx) * ny;
+  std::vector<int32_t> changed, list;
+  std::vector<uint8_t> valid(h->bound ? n : 0);
+  for (size_t k = 0; k < n; ++k) {
+    const bool was = (h->plan.node[k] & kSolidBit) != 0, is = solid_mask[k] != 0;
+    if (h->bound) valid[k] = (!was && !is) ? 1 : 0;
+    if (was != is) {
+      changed.push_back(int32_t(k));
+      list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
+    }
+  }
+  // Scratch in the other state buffer, which the next step overwrites anyway.
+  const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
+  const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
+               off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 16);
+  if (h->bound && off_res + 16 > h->buf_bytes())
+    return h->fail(LBM_ENOMEM, "too many nodes change at once");
+  // Re-classify only around the changed nodes; the new plan takes the old node words.
   Plan np;
+  PlanDelta d;
   std::string perr;
-  const int rc = build_plan(g, solid_mask, np, perr);
+  const int rc = replan(g, solid_mask, changed, h->plan, np, d, perr);
   if (rc != LBM_OK) return h->fail(rc, perr);
-  if (size_t(np.nslots) * kPart + size_t(np.njslots) * 2 > h->part_cap)
-    return h->fail(LBM_ENOMEM, "the new mask needs more force-partial slots than reserved "
-                               "at create; create a handle for it");
   const int nj = np.has_box ? np.box_bx * np.box_rows : 0;
-  if (nj > h->jcap)
-    return h->fail(LBM_ENOMEM, "the new control volume is larger than the one at create");
+  if (size_t(np.nslots) * kPart + size_t(np.njslots) * 2 > h->part_cap || nj > h->jcap) {
+    undo_replan(h->plan, np, d);
+    return h->fail(LBM_ENOMEM, nj > h->jcap
+                                   ? "the new control volume is larger than the one at create"
+                                   : "the new mask needs more force-partial slots than "
+                                     "reserved at create; create a handle for it");
+  }
+  auto commit = [&]() {
+    h->plan = std::move(np);
+    h->g = g;
+    h->njblocks = nj;
+    h->adj_valid = false;
+  };
   double P[2] = {0.0, 0.0};
   if (h->bound) {
-    const int nx = g.nx, ny = g.ny;
-    const size_t n = size_t(nx) * ny;
-    std::vector<uint8_t> valid(n);
-    std::vector<int32_t> list;
-    for (size_t k = 0; k < n; ++k) {
-      const bool was = (h->plan.node[k] & kSolidBit) != 0, is = solid_mask[k] != 0;
-      valid[k] = (!was && !is) ? 1 : 0;
-      if (was != is) list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
-    }
-    // Scratch in the other state buffer, which the next step overwrites anyway.
-    const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
-    const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
-                 off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 16);
-    if (off_res + 16 > h->buf_bytes())
-      return h->fail(LBM_ENOMEM, "too many nodes change at once");
     // Nothing in flight (on any stream, a batch holding the handle included) may still
     // read the old node codes or the state.
     hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return h->hip_fail(e, "mask synchronize");
     char* scr = static_cast<char*>(h->buf(1 - h->cur));
-    if (!list.empty()) {
+    if (e == hipSuccess && !list.empty()) {
       e = hipMemcpyAsync(scr, valid.data(), n, hipMemcpyHostToDevice, h->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(scr + off_list, list.data(), list.size() * 4, hipMemcpyHostToDevice,
                            h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "upload mask change");
       RemaskArgs a{};
       a.state = h->buf(h->cur);
       a.plane = h->plane;
@@ -660,24 +673,27 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
       a.motion = h->motion;
       a.block_out = reinterpret_cast<double*>(scr + off_blk);
       double* res = reinterpret_cast<double*>(scr + off_res);
-      e = launch_remask(g.precision, a, blocks, res, h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "launch remask");
-      e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "download impulse");
+      if (e == hipSuccess) e = launch_remask(g.precision, a, blocks, res, h->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
     }
-    e = hipMemcpyAsync(h->ws + h->off_node, np.node.data(), np.node.size() * sizeof(uint32_t),
-                       hipMemcpyHostToDevice, h->stream);
+    // Upload the rewritten node words (one contiguous index range) and the strip slots.
+    if (e == hipSuccess && !d.idx.empty()) {
+      const size_t lo = size_t(d.idx.front()), cnt = size_t(d.idx.back()) - lo + 1;
+      e = hipMemcpyAsync(h->ws + h->off_node + lo * sizeof(uint32_t), np.node.data() + lo,
+                         cnt * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    }
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->ws + h->off_tiles, np.strip_slot.data(),
                          np.strip_slot.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                          h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return h->hip_fail(e, "upload plan");
+    if (e != hipSuccess) {
+      commit();  // the state is undefined; the plan is the new mask's
+      return h->hip_fail(e, "mask change");
+    }
   }
-  h->plan = std::move(np);
-  h->g = g;
-  h->njblocks = nj;
-  h->adj_valid = false;
+  commit();
   if (impulse) {
     impulse[0] = P[0];
     impulse[1] = P[1];

@@ -34,9 +34,9 @@ uint32_t classify(const Plan& p, const uint8_t* mask, int x, int y, int i) {
   return wrapped ? kWrap : kStream;
 }
 
-}  // namespace
-
-int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err) {
+// Checks of a grid and mask that need no plan: codes, sizes, mask bytes, and the
+// control volume (one node inside the domain, every solid node strictly inside it).
+int validate(const lbm_grid& g, const uint8_t* mask, std::string& err) {
   char buf[256];
   if (g.nx < 3 || g.ny < 3) {
     err = "nx and ny must be >= 3";
@@ -70,64 +70,81 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     err = "grid too large";
     return LBM_ENOMEM;
   }
-  const size_t n = size_t(g.nx) * size_t(g.ny);
-  for (size_t k = 0; k < n; ++k)
-    if (mask[k] > 1) {
-      std::snprintf(buf, sizeof buf, "mask byte %zu is %d (must be 0 or 1)", k, int(mask[k]));
+  // Mask bytes, and the bounding box of the solid nodes (the control volume holds every
+  // solid node strictly inside it exactly when it holds their bounding box).
+  int sx0 = g.nx, sx1 = -1, sy0 = g.ny, sy1 = -1, fx = 0, fy = 0;
+  for (int y = 0; y < g.ny; ++y) {
+    const uint8_t* row = mask + size_t(y) * g.nx;
+    for (int x = 0; x < g.nx; ++x) {
+      if (row[x] == 0) continue;
+      if (row[x] > 1) {
+        std::snprintf(buf, sizeof buf, "mask byte %zu is %d (must be 0 or 1)",
+                      size_t(y) * g.nx + x, int(row[x]));
+        err = buf;
+        return LBM_EINVAL;
+      }
+      if (sx1 < 0) {
+        fx = x;
+        fy = y;
+      }
+      sx0 = std::min(sx0, x);
+      sx1 = std::max(sx1, x);
+      sy0 = std::min(sy0, y);
+      sy1 = std::max(sy1, y);
+    }
+  }
+  if (g.box[0] >= 0) {
+    const int x0 = g.box[0], x1 = g.box[1], y0 = g.box[2], y1 = g.box[3];
+    if (x0 < 1 || y0 < 1 || x1 > g.nx - 1 || y1 > g.ny - 1 || x1 - x0 < 3 || y1 - y0 < 3) {
+      err = "control-volume box must lie one node inside the domain and span >= 3 nodes";
+      return LBM_EINVAL;
+    }
+    if (sx1 >= 0 && !(sx0 >= x0 + 1 && sx1 < x1 - 1 && sy0 >= y0 + 1 && sy1 < y1 - 1)) {
+      // Name one offending node.
+      for (int y = sy0; y <= sy1; ++y)
+        for (int x = sx0; x <= sx1; ++x)
+          if (mask[size_t(y) * g.nx + x] &&
+              !(x >= x0 + 1 && x < x1 - 1 && y >= y0 + 1 && y < y1 - 1)) {
+            fx = x;
+            fy = y;
+            y = sy1 + 1;
+            break;
+          }
+      std::snprintf(buf, sizeof buf,
+                    "solid node (%d,%d) is not strictly inside the control-volume box", fx, fy);
       err = buf;
       return LBM_EINVAL;
     }
-  p = Plan();
+  }
+  return LBM_OK;
+}
+
+void set_geometry(Plan& p, const lbm_grid& g) {
   p.nx = g.nx;
   p.ny = g.ny;
   p.bc_x = g.bc_x;
   p.bc_y = g.bc_y;
   p.has_box = g.box[0] >= 0;
   for (int k = 0; k < 4; ++k) p.box[k] = g.box[k];
-  if (p.has_box) {
-    const int x0 = g.box[0], x1 = g.box[1], y0 = g.box[2], y1 = g.box[3];
-    if (x0 < 1 || y0 < 1 || x1 > g.nx - 1 || y1 > g.ny - 1 || x1 - x0 < 3 || y1 - y0 < 3) {
-      err = "control-volume box must lie one node inside the domain and span >= 3 nodes";
-      return LBM_EINVAL;
-    }
-    for (int y = 0; y < g.ny; ++y)
-      for (int x = 0; x < g.nx; ++x)
-        if (mask[size_t(y) * g.nx + x] && !(x >= x0 + 1 && x < x1 - 1 && y >= y0 + 1 && y < y1 - 1)) {
-          std::snprintf(buf, sizeof buf,
-                        "solid node (%d,%d) is not strictly inside the control-volume box", x, y);
-          err = buf;
-          return LBM_EINVAL;
-        }
-  }
+}
 
-  // Per-node pull codes.
-  p.node.assign(n, 0u);
-  for (int y = 0; y < g.ny; ++y)
-    for (int x = 0; x < g.nx; ++x) {
-      const size_t k = size_t(y) * g.nx + x;
-      if (mask[k]) {
-        p.node[k] = kSolidBit;
-        continue;
-      }
-      ++p.n_fluid;
-      if (in_box(p, x, y)) ++p.n_box;
-      uint32_t w = 0;
-      for (int i = 1; i < kQ; ++i) w |= classify(p, mask, x, y, i) << (3 * (i - 1));
-      p.node[k] = w;
-    }
+uint32_t node_word(const Plan& p, const uint8_t* mask, int x, int y) {
+  if (mask[size_t(y) * p.nx + x]) return kSolidBit;
+  uint32_t w = 0;
+  for (int i = 1; i < kQ; ++i) w |= classify(p, mask, x, y, i) << (3 * (i - 1));
+  return w;
+}
 
-  // Canonical link list: (x, i) with x + c_i a solid mask node, i.e. the pull of the
-  // opposite direction bounces back from the body.
-  for (int y = 0; y < g.ny; ++y)
-    for (int x = 0; x < g.nx; ++x) {
-      const size_t k = size_t(y) * g.nx + x;
-      if (p.node[k] & kSolidBit) continue;
-      for (int i = 1; i < kQ; ++i)
-        if (pull_code(p.node[k], kOpp[i]) == kBody) {
-          p.links.push_back(int32_t(k));
-          p.links.push_back(i);
-        }
-    }
+// Everything the plan derives from its node words and geometry: node counts, the
+// general rectangle, the canonical link list, strip classes and slots, the box sweep.
+void derive(Plan& p) {
+  const int nx = p.nx, ny = p.ny;
+  p.n_fluid = p.n_box = 0;
+  for (size_t k = 0; k < p.node.size(); ++k) p.n_fluid += (p.node[k] & kSolidBit) ? 0 : 1;
+  if (p.has_box)
+    for (int y = p.box[2]; y < p.box[3]; ++y)
+      for (int x = p.box[0]; x < p.box[1]; ++x)
+        p.n_box += (p.node[size_t(y) * nx + x] & kSolidBit) ? 0 : 1;
 
   // Rectangle of every node off the first and last rows whose codes need the general
   // path.  `band`: the nodes with a control-volume term (the box and the ring around it).
@@ -135,34 +152,74 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
     return p.has_box && x >= p.box[0] - 1 && x <= p.box[1] && y >= p.box[2] - 1 &&
            y <= p.box[3];
   };
-  for (int y = 1; y < g.ny - 1; ++y)
-    for (int x = 0; x < g.nx; ++x) {
-      if (p.node[size_t(y) * g.nx + x] == edge_word(g.nx, g.bc_x, x)) continue;
-      if (p.gx0 > p.gx1) {
-        p.gx0 = p.gx1 = x;
-        p.gy0 = p.gy1 = y;
-      } else {
-        p.gx0 = std::min(p.gx0, x);
-        p.gx1 = std::max(p.gx1, x);
-        p.gy0 = std::min(p.gy0, y);
-        p.gy1 = std::max(p.gy1, y);
+  p.gx0 = 0;
+  p.gx1 = -1;
+  p.gy0 = 0;
+  p.gy1 = -1;
+  const uint32_t e0 = edge_word(nx, p.bc_x, 0), e1 = edge_word(nx, p.bc_x, nx - 1);
+  for (int y = 1; y < ny - 1; ++y) {
+    const uint32_t* row = p.node.data() + size_t(y) * nx;
+    int lo = -1, hi = -1;
+    if (row[0] != e0) lo = hi = 0;
+    for (int x = 1; x < nx - 1; ++x)
+      if (row[x] != 0) {
+        if (lo < 0) lo = x;
+        hi = x;
       }
+    if (row[nx - 1] != e1) {
+      if (lo < 0) lo = nx - 1;
+      hi = nx - 1;
     }
+    if (lo < 0) continue;
+    if (p.gx0 > p.gx1) {
+      p.gx0 = lo;
+      p.gx1 = hi;
+      p.gy0 = p.gy1 = y;
+    } else {
+      p.gx0 = std::min(p.gx0, lo);
+      p.gx1 = std::max(p.gx1, hi);
+      p.gy1 = y;
+    }
+  }
+
+  // Canonical link list: (x, i) with x + c_i a solid mask node, i.e. the pull of the
+  // opposite direction bounces back from the body.  Off the first and last rows such
+  // nodes lie in the general rectangle.
+  p.links.clear();
+  auto scan_links = [&](int y, int xa, int xb) {
+    for (int x = xa; x <= xb; ++x) {
+      const size_t k = size_t(y) * nx + x;
+      if (p.node[k] & kSolidBit) continue;
+      for (int i = 1; i < kQ; ++i)
+        if (pull_code(p.node[k], kOpp[i]) == kBody) {
+          p.links.push_back(int32_t(k));
+          p.links.push_back(i);
+        }
+    }
+  };
+  for (int y = 0; y < ny; ++y) {
+    if (y == 0 || y == ny - 1)
+      scan_links(y, 0, nx - 1);
+    else if (p.gx0 <= p.gx1 && y >= p.gy0 && y <= p.gy1)
+      scan_links(y, p.gx0, p.gx1);
+  }
+
   // Tiles and strips (strip_class).  General strips holding a link node or a node with a
   // control-volume term own a force-partial slot (kPart sums); box-interior strips own
   // a slot of the box-momentum partials (2 sums).
-  p.ntx = (g.nx + kTileW - 1) / kTileW;
-  p.nty = (g.ny + kTileH - 1) / kTileH;
+  p.ntx = (nx + kTileW - 1) / kTileW;
+  p.nty = (ny + kTileH - 1) / kTileH;
   p.ntiles = p.ntx * p.nty;
   p.strip_slot.assign(size_t(p.ntiles) * kStrips, -1);
+  p.nslots = p.njslots = p.ngeneral = 0;
   for (int ty = 0; ty < p.nty; ++ty)
     for (int tx = 0; tx < p.ntx; ++tx)
       for (int w = 0; w < kStrips; ++w) {
         const int x0 = tx * kTileW + w * kStripW, y0 = ty * kTileH;
         const int cls = p.has_box
-                            ? strip_class(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0],
+                            ? strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0],
                                           p.box[1], p.box[2], p.box[3], x0, y0)
-                            : strip_class(g.nx, g.ny, p.gx0, p.gx1, p.gy0, p.gy1, 1, 0, 1, 0,
+                            : strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, 1, 0, 1, 0,
                                           x0, y0);
         if (cls == kStripPlain) continue;
         if (cls == kStripBoxInterior) {
@@ -171,9 +228,9 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
         }
         ++p.ngeneral;
         bool forces = false;
-        for (int y = y0; y < std::min(y0 + kTileH, g.ny); ++y)
-          for (int x = x0; x < std::min(x0 + kStripW, g.nx); ++x) {
-            const uint32_t wd = p.node[size_t(y) * g.nx + x];
+        for (int y = y0; y < std::min(y0 + kTileH, ny); ++y)
+          for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {
+            const uint32_t wd = p.node[size_t(y) * nx + x];
             bool link = false;
             if (!(wd & kSolidBit))
               for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
@@ -181,11 +238,75 @@ int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err
           }
         if (forces) p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.nslots++;
       }
+  p.box_bx = p.box_rows = 0;
   if (p.has_box) {
     p.box_bx = (p.box[1] - p.box[0] + kTileW - 1) / kTileW;
     p.box_rows = p.box[3] - p.box[2];
   }
+}
+
+}  // namespace
+
+int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err) {
+  const int rc = validate(g, mask, err);
+  if (rc != LBM_OK) return rc;
+  p = Plan();
+  set_geometry(p, g);
+  p.node.assign(size_t(g.nx) * size_t(g.ny), 0u);
+  for (int y = 0; y < g.ny; ++y)
+    for (int x = 0; x < g.nx; ++x) p.node[size_t(y) * g.nx + x] = node_word(p, mask, x, y);
+  derive(p);
   return LBM_OK;
+}
+
+int replan(const lbm_grid& g, const uint8_t* mask, const std::vector<int32_t>& changed,
+           Plan& p, Plan& np, PlanDelta& d, std::string& err) {
+  const int rc = validate(g, mask, err);
+  if (rc != LBM_OK) return rc;
+  // Node words that can change: those of the changed nodes and of their lattice
+  // neighbours (a pull reads its source node, and the outlet rule the last column of
+  // the neighbouring rows).
+  Plan geo;
+  set_geometry(geo, g);
+  std::vector<int64_t> idx;
+  idx.reserve(changed.size() * kQ);
+  for (int32_t c : changed) {
+    const int x = c % g.nx, y = c / g.nx;
+    for (int i = 0; i < kQ; ++i) {
+      int ax = x + kCx[i], ay = y + kCy[i];
+      if (g.bc_x == LBM_BCX_PERIODIC) ax = (ax + g.nx) % g.nx;
+      if (g.bc_y == LBM_BCY_PERIODIC) ay = (ay + g.ny) % g.ny;
+      if (ax < 0 || ax >= g.nx || ay < 0 || ay >= g.ny) continue;
+      idx.push_back(int64_t(ay) * g.nx + ax);
+    }
+  }
+  std::sort(idx.begin(), idx.end());
+  idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+  d = PlanDelta();
+  for (int64_t k : idx) {
+    const uint32_t w = node_word(geo, mask, int(k % g.nx), int(k / g.nx));
+    if (w == p.node[size_t(k)]) continue;
+    d.idx.push_back(k);
+    d.old_w.push_back(p.node[size_t(k)]);
+    d.new_w.push_back(w);
+  }
+  // The new plan takes p's words (no copy) with the delta applied.
+  apply_delta(p, d, true);
+  np = Plan();
+  set_geometry(np, g);
+  np.node.swap(p.node);
+  derive(np);
+  return LBM_OK;
+}
+
+void apply_delta(Plan& p, const PlanDelta& d, bool forward) {
+  for (size_t j = 0; j < d.idx.size(); ++j)
+    p.node[size_t(d.idx[j])] = forward ? d.new_w[j] : d.old_w[j];
+}
+
+void undo_replan(Plan& p, Plan& np, const PlanDelta& d) {
+  p.node.swap(np.node);
+  apply_delta(p, d, false);
 }
 
 void build_adjoint_codes(const Plan& p, std::vector<uint32_t>& adj) {

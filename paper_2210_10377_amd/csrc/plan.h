@@ -113,6 +113,23 @@ struct Plan {
 // Validate and classify.  Returns LBM_OK or an error code with a message in err.
 int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err);
 
+// Node words a mask change rewrites (index, old word, new word), in index order.
+struct PlanDelta {
+  std::vector<int64_t> idx;
+  std::vector<uint32_t> old_w, new_w;
+};
+
+// The plan of a changed mask (and grid g, e.g. a moved control volume) built from the
+// plan p of the old mask without re-classifying every node: only the changed nodes
+// (`changed`: node indices where solid and fluid swap) and their lattice neighbours are
+// re-classified; np receives the same plan build_plan would give, taking p's node words
+// (p.node is left empty).  On an error nothing changes.  undo_replan gives p its plan
+// back (for a change the caller then refuses).
+int replan(const lbm_grid& g, const uint8_t* mask, const std::vector<int32_t>& changed,
+           Plan& p, Plan& np, PlanDelta& d, std::string& err);
+void apply_delta(Plan& p, const PlanDelta& d, bool forward);
+void undo_replan(Plan& p, Plan& np, const PlanDelta& d);
+
 // Adjoint codes: for a fluid node s and direction k (three bits at 3*(k-1)), which
 // pulls read S_k(s) apart from the bounce-back of s itself: the node s + c_k streams it
 // (kAdjStream), through a periodic wrap (kAdjWrap), or the outlet node

@@ -109,19 +109,27 @@ int build_plan3(const lbm3d_grid& g, const uint8_t* mask, Plan3& p, std::string&
   // Counts, band (fluid nodes with a neighbour across the box surface), V.
   std::vector<uint8_t> band;
   if (p.has_box) band.assign(size_t(N), 0);
+  // Rows (y, z) more than one node from the box in y or z hold no node of V or of its
+  // band.
+  auto row_near = [&](int y, int z) {
+    return p.has_box && (p.whole[1] || (y >= p.box[2] - 1 && y <= p.box[3])) &&
+           (p.whole[2] || (z >= p.box[4] - 1 && z <= p.box[5]));
+  };
   for (int z = 0; z < g.nz; ++z)
-    for (int y = 0; y < g.ny; ++y)
+    for (int y = 0; y < g.ny; ++y) {
+      const bool rnear = row_near(y, z);
       for (int x = 0; x < g.nx; ++x) {
         const int64_t k = (int64_t(z) * g.ny + y) * g.nx + x;
         if (mask[k]) continue;
         ++p.n_fluid;
         const uint32_t w = p.word[k];
-        for (int i = 1; i < kQ; ++i)
-          if ((w >> i) & 1u) {
-            int s[3] = {x - kCx[i], y - kCy[i], z - kCz[i]};
-            if (geo.wrap(s)) ++p.n_links;
-          }
-        if (!p.has_box) continue;
+        if (w)  // most nodes pull plainly in every direction
+          for (int i = 1; i < kQ; ++i)
+            if ((w >> i) & 1u) {
+              int s[3] = {x - kCx[i], y - kCy[i], z - kCz[i]};
+              if (geo.wrap(s)) ++p.n_links;
+            }
+        if (!rnear) continue;
         const int q[3] = {x, y, z};
         const bool in = in_box(q);
         if (in) ++p.n_box;
@@ -139,6 +147,7 @@ int build_plan3(const lbm3d_grid& g, const uint8_t* mask, Plan3& p, std::string&
           }
         }
       }
+    }
   // Strips.
   p.ntx = (g.nx + kTileW - 1) / kTileW;
   p.ntiles = int64_t(p.ntx) * g.ny * g.nz;
@@ -153,11 +162,12 @@ int build_plan3(const lbm3d_grid& g, const uint8_t* mask, Plan3& p, std::string&
           bool general = x0 == 0 || x1 == g.nx || y == 0 || y == g.ny - 1 || z == 0 ||
                          z == g.nz - 1;
           bool force = false, inV = false;
+          const bool rnear = row_near(y, z);
           for (int x = x0; x < x1; ++x) {
             const int64_t k = (int64_t(z) * g.ny + y) * g.nx + x;
             if (p.word[k]) general = force = true;
-            if (p.has_box && band[size_t(k)]) general = force = true;
-            if (p.has_box && !mask[k]) {
+            if (rnear && band[size_t(k)]) general = force = true;
+            if (rnear && !mask[k]) {
               const int q[3] = {x, y, z};
               if (in_box(q)) inV = true;
             }
