@@ -118,6 +118,7 @@ int lbm_create(const lbm_grid* grid, const uint8_t* solid_mask, double tau,
     return rc;
   }
   h->g = g;
+  h->mask.assign(solid_mask, solid_mask + size_t(g.nx) * size_t(g.ny));
   h->tau = tau;
   h->omega = 1.0 / tau;
   h->rho_w = rho_w;
@@ -609,18 +610,27 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
   }
   // Nodes that swap between fluid and solid (bit 31 of a list entry: uncovered), and
   // the nodes fluid in both masks (read by the refill).
+  // Compared with the mask of the plan eight bytes at a time (bytes other than 0/1 are
+  // refused by replan before anything changes).
   const int nx = g.nx, ny = g.ny;
   const size_t n = size_t(nx) * ny;
   std::vector<int32_t> changed, list;
-  std::vector<uint8_t> valid(h->bound ? n : 0);
-  for (size_t k = 0; k < n; ++k) {
-    const bool was = (h->plan.node[k] & kSolidBit) != 0, is = solid_mask[k] != 0;
-    if (h->bound) valid[k] = (!was && !is) ? 1 : 0;
-    if (was != is) {
-      changed.push_back(int32_t(k));
-      list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
-    }
+  const uint8_t* old = h->mask.data();
+  size_t k = 0;
+  for (; k + 8 <= n; k += 8) {
+    uint64_t a, b;
+    std::memcpy(&a, old + k, 8);
+    std::memcpy(&b, solid_mask + k, 8);
+    if (a == b) continue;
+    for (size_t j = k; j < k + 8; ++j)
+      if ((old[j] != 0) != (solid_mask[j] != 0)) changed.push_back(int32_t(j));
   }
+  for (; k < n; ++k)
+    if ((old[k] != 0) != (solid_mask[k] != 0)) changed.push_back(int32_t(k));
+  list.reserve(changed.size());
+  for (int32_t c : changed) list.push_back(int32_t(uint32_t(c) | (old[c] ? 0x80000000u : 0u)));
+  std::vector<uint8_t> valid(h->bound && !list.empty() ? n : 0);
+  for (size_t j = 0; j < valid.size(); ++j) valid[j] = (old[j] | solid_mask[j]) == 0;
   // Scratch in the other state buffer, which the next step overwrites anyway.
   const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
   const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
@@ -643,6 +653,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
   }
   auto commit = [&]() {
     h->plan = std::move(np);
+    std::memcpy(h->mask.data(), solid_mask, n);
     h->g = g;
     h->njblocks = nj;
     h->adj_valid = false;

@@ -18,6 +18,7 @@ struct lbm_t {
   lbm::BodyMotion motion{0.0, 0.0, 0.0, 0.0, 0.0, 0};
   std::vector<double> uin;
   lbm::Plan plan;
+  std::vector<uint8_t> mask;  // the body mask of the plan ([ny][nx], 0/1)
   // device layout
   // Population i of node (x, y) at i * plane + y * pitch + x (elements): row-interleaved
   // (plane = padded row, pitch = 9 rows) or planar (plane = padded plane, pitch = row).
