@@ -22,6 +22,7 @@ struct lbm3d {
   bool moving = false;
   std::vector<double> uin;  // [nz][ny]
   Plan3 plan;
+  std::vector<uint8_t> mask;  // the body mask of the plan ([nz][ny][nx], 0/1)
   // Population i of node (x, y, z) at i * dstride + (z * ny + y) * rstride + x.
   int32_t rstride = 0;
   int64_t dstride = 0;
@@ -228,6 +229,7 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     return rc;
   }
   h->g = g;
+  h->mask.assign(mask, mask + size_t(g.nx) * g.ny * g.nz);
   h->tau = tau;
   h->uin.assign(size_t(g.ny) * g.nz, 0.0);
   if (g.bc_x == LBM_BCX_INLET_OUTLET) {
@@ -513,45 +515,64 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
       return h->fail(LBM_EINVAL, "a control volume can be moved, not added or removed");
     for (int k = 0; k < 6; ++k) g.box[k] = box[k];
   }
+  // Nodes that swap between fluid and solid, from the mask of the plan compared eight
+  // bytes at a time (bytes other than 0/1 are refused by replan3 before anything
+  // changes); bit 31 of a list entry: uncovered.
+  const size_t n = size_t(g.nx) * g.ny * g.nz;
+  const uint8_t* old = h->mask.data();
+  std::vector<int32_t> changed, list;
+  size_t k = 0;
+  for (; k + 8 <= n; k += 8) {
+    uint64_t a, b;
+    std::memcpy(&a, old + k, 8);
+    std::memcpy(&b, mask + k, 8);
+    if (a == b) continue;
+    for (size_t j = k; j < k + 8; ++j)
+      if ((old[j] != 0) != (mask[j] != 0)) changed.push_back(int32_t(j));
+  }
+  for (; k < n; ++k)
+    if ((old[k] != 0) != (mask[k] != 0)) changed.push_back(int32_t(k));
+  list.reserve(changed.size());
+  for (int32_t c : changed) list.push_back(int32_t(uint32_t(c) | (old[c] ? 0x80000000u : 0u)));
+  // Scratch in the other state buffer, which the next step overwrites anyway.
+  const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
+  const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
+               off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 24);
+  if (h->bound && off_res + 24 > h->buf_bytes())
+    return h->fail(LBM_ENOMEM, "too many nodes change at once");
+  // Re-classify around the changed nodes; the new plan takes the old words.
   Plan3 np;
+  Plan3Delta d;
   std::string perr;
-  const int rc = build_plan3(g, mask, np, perr);
+  const int rc = replan3(g, mask, changed, h->plan, np, d, perr);
   if (rc != LBM_OK) return h->fail(rc, perr);
-  if (np.fstrips.size() > h->fcap ||
-      size_t(np.nslots) * kPart + size_t(np.njslots) * 3 > h->part_cap)
-    return h->fail(LBM_ENOMEM, "the new mask needs more force slots than reserved at create; "
-                               "create a handle for it");
   const int nj = np.has_box ? np.box_bx * np.box_rows : 0;
-  if (nj > h->jcap)
-    return h->fail(LBM_ENOMEM, "the new control volume is larger than the one at create");
+  if (np.fstrips.size() > h->fcap ||
+      size_t(np.nslots) * kPart + size_t(np.njslots) * 3 > h->part_cap || nj > h->jcap) {
+    undo_replan3(h->plan, np, d);
+    return h->fail(LBM_ENOMEM, nj > h->jcap
+                                   ? "the new control volume is larger than the one at create"
+                                   : "the new mask needs more force slots than reserved at "
+                                     "create; create a handle for it");
+  }
+  auto commit = [&]() {
+    h->plan = std::move(np);
+    std::memcpy(h->mask.data(), mask, n);
+    h->g = g;
+    h->njblocks = nj;
+  };
   double P[3] = {0.0, 0.0, 0.0};
   if (h->bound) {
-    const size_t n = size_t(g.nx) * g.ny * g.nz;
-    std::vector<uint8_t> valid(n);
-    std::vector<int32_t> list;
-    for (size_t k = 0; k < n; ++k) {
-      const bool was = (h->plan.word[k] & kSolid) != 0, is = mask[k] != 0;
-      valid[k] = (!was && !is) ? 1 : 0;
-      if (was != is) list.push_back(int32_t(uint32_t(k) | (was ? 0x80000000u : 0u)));
-    }
-    // Scratch in the other state buffer; it is refilled with the rest state afterwards
-    // (the next step rewrites its fluid nodes; its solid nodes then hold w_i, as after
-    // bind).
-    const int blocks = int(std::min<size_t>((list.size() + 255) / 256, 1024));
-    const size_t off_list = align256(n), off_blk = align256(off_list + list.size() * 4),
-                 off_res = align256(off_blk + size_t(std::max(blocks, 1)) * 24);
-    if (off_res + 24 > h->buf_bytes())
-      return h->fail(LBM_ENOMEM, "too many nodes change at once");
     // Nothing in flight may still read the old node words or the state.
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return h->hip_fail(e, "mask synchronize");
     char* scr = static_cast<char*>(h->buf(1 - h->cur));
-    if (!list.empty()) {
+    if (e == hipSuccess && !list.empty()) {
+      std::vector<uint8_t> valid(n);  // fluid in both masks
+      for (size_t j = 0; j < n; ++j) valid[j] = (old[j] | mask[j]) == 0;
       e = hipMemcpyAsync(scr, valid.data(), n, hipMemcpyHostToDevice, h->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(scr + off_list, list.data(), list.size() * 4, hipMemcpyHostToDevice,
                            h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "upload mask change");
       Remask3Args a{};
       a.g = geom(h);
       a.state = h->buf(h->cur);
@@ -561,16 +582,19 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
       a.rho_w = h->rho_w;
       a.block_out = reinterpret_cast<double*>(scr + off_blk);
       double* res = reinterpret_cast<double*>(scr + off_res);
-      e = launch_remask3(g.precision, a, blocks, res, h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "launch remask");
-      e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = launch_remask3(g.precision, a, blocks, res, h->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(P, res, sizeof(P), hipMemcpyDeviceToHost, h->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "download impulse");
-      e = launch_fill_rest3(g.precision, scr, h->buf_elems, h->dstride, h->stream);
-      if (e != hipSuccess) return h->hip_fail(e, "refill scratch buffer");
+      // The scratch buffer back to the rest state (its solid nodes are never written).
+      if (e == hipSuccess) e = launch_fill_rest3(g.precision, scr, h->buf_elems, h->dstride, h->stream);
     }
-    e = hipMemcpyAsync(h->ws + h->off_word, np.word.data(), np.word.size() * sizeof(uint32_t),
-                       hipMemcpyHostToDevice, h->stream);
+    // The rewritten node words (one contiguous index range), the strip table and the
+    // force-strip list.
+    if (e == hipSuccess && !d.idx.empty()) {
+      const size_t lo = size_t(d.idx.front()), cnt = size_t(d.idx.back()) - lo + 1;
+      e = hipMemcpyAsync(h->ws + h->off_word + lo * sizeof(uint32_t), np.word.data() + lo,
+                         cnt * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    }
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->ws + h->off_strip, np.strip.data(), np.strip.size() * sizeof(uint32_t),
                          hipMemcpyHostToDevice, h->stream);
@@ -578,13 +602,14 @@ int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* 
       e = hipMemcpyAsync(h->ws + h->off_fstrip, np.fstrips.data(),
                          np.fstrips.size() * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return h->hip_fail(e, "upload plan");
+    if (e != hipSuccess) {
+      commit();  // the state is undefined; the plan is the new mask's
+      return h->hip_fail(e, "mask change");
+    }
   }
-  h->plan = std::move(np);
-  h->g = g;
-  h->njblocks = nj;
+  commit();
   if (impulse)
-    for (int k = 0; k < 3; ++k) impulse[k] = P[k];
+    for (int c = 0; c < 3; ++c) impulse[c] = P[c];
   return LBM_OK;
 }
 

@@ -61,6 +61,23 @@ struct Plan3 {
 };
 
 int build_plan3(const lbm3d_grid& g, const uint8_t* mask, Plan3& p, std::string& err);
+
+// Node words a mask change rewrites (index, old word, new word), in index order.
+struct Plan3Delta {
+  std::vector<int64_t> idx;
+  std::vector<uint32_t> old_w, new_w;
+};
+
+// The plan of a changed mask (and grid g, e.g. a moved control volume) from the plan p
+// of the old mask: the changed nodes (`changed`: node indices where solid and fluid
+// swap), the nodes that pull from them and the strips around them are re-classified, the
+// strips around the old and new control volume when it moved, and the slots renumbered;
+// np receives the plan build_plan3 would give, taking p's words (p.word is left empty).
+// On an error nothing changes; undo_replan3 gives p its plan back.
+int replan3(const lbm3d_grid& g, const uint8_t* mask, const std::vector<int32_t>& changed,
+            Plan3& p, Plan3& np, Plan3Delta& d, std::string& err);
+void apply_delta3(Plan3& p, const Plan3Delta& d, bool forward);
+void undo_replan3(Plan3& p, Plan3& np, const Plan3Delta& d);
 // Body links (node, direction) in (z, y, x, direction) order.
 void plan3_links(const Plan3& p, std::vector<int64_t>& out);
 
