@@ -72,7 +72,10 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
-  const int tile = block_tile<kBatchGroup>(blockIdx.x, a.ntiles);
+  // Tiles reach the XCDs in runs of the single-lattice step's length (the same bytes per
+  // run: 32 tiles at 4-byte adjoint values, 16 at 8-byte).
+  constexpr int kGroup = kStepGroup * 4 / int(sizeof(C));
+  const int tile = block_tile<kGroup>(blockIdx.x, a.ntiles);
   const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const Planes<T, BUF> st(a.state, a.plane, a.state_bytes);

@@ -227,8 +227,9 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
 // while the XCDs together still sweep one region of memory at a time.  The tail that
 // does not fill a whole round keeps the identity mapping.  The single-lattice step takes
 // runs of 32 tiles at 4-byte storage and the same bytes per run at the others (16 tiles
-// in FP64, 64 in FP16; measured best on the row-interleaved layout of a wide grid); the
-// batch (instances of 1-2 tiles per row) and the adjoint take runs of 4.
+// in FP64, 64 in FP16; measured best on the row-interleaved layout of a wide grid), as
+// does the adjoint (keyed on its adjoint values); the batch (instances of 1-2 tiles per
+// row) takes runs of 4.
 #ifndef LBM_XCD_GROUP
 #define LBM_XCD_GROUP 32
 #endif
