@@ -176,3 +176,30 @@ def test_adjoint_same_in_both_layouts(mini_refs):
     assert out[0][0] == out[1][0]
     np.testing.assert_array_equal(out[0][1], out[1][1])
     assert out[0][2] == out[1][2]
+
+
+def test_adjoint_whole_tile_rounds_and_tail(orc):
+    """A 512x130 cylinder channel: 2 tiles per row, 260 tiles.  The reverse kernel hands
+    tiles to the XCDs in runs (32 tiles at 4-byte adjoint values, 16 at 8-byte), over
+    whole rounds of 8 runs, and the last 4 tiles (the tail) keep the identity mapping; the
+    objective and gradients must not depend on which block takes which tile.  FP64 and
+    FP32-deviation adjoints against complex-step derivatives through the oracle."""
+    nx, ny = 512, 130
+    mask = workloads.cylinder_mask(nx, ny, 120, 64.5, 13)
+    y = np.arange(ny)
+    uin = 0.03 + 0.02 * np.sin(np.pi * (y + 0.5) / ny)
+    tau, n, every, t0, T, w = 0.75, 400, 100, 200, 200, (1.0, 0.3)
+    h = 1e-30
+    v = np.random.default_rng(130).normal(size=ny)
+    J_ref = orc.objective(mask, 1 / tau, uin, n, t0, T, w=w).real
+    d_tau = orc.objective(mask, 1 / complex(tau, h), uin, n, t0, T, w=w).imag / h
+    d_v = orc.objective(mask, 1 / tau, uin + 1j * h * v, n, t0, T, w=w).imag / h
+    for precision, tol in (("fp64", 1e-9), ("fp32dev", 2e-4)):
+        g = _sim(mask, tau, uin, precision)
+        J = g.adjoint_forward(n, every, t0, T, w)
+        gu, gt = g.adjoint_backward(1.0)
+        e_tau = abs(gt - d_tau) / abs(d_tau)
+        e_v = abs(gu @ v - d_v) / abs(d_v)
+        print("512x130", precision, "J", J, J_ref, "rel errors tau", e_tau, "direction", e_v)
+        assert abs(J - J_ref) <= (1e-12 if precision == "fp64" else 1e-4) * abs(J_ref)
+        assert e_tau <= tol and e_v <= tol
