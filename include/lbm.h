@@ -304,7 +304,10 @@ int lbm_reset(lbm_t* h);
  * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
  * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is
  * still valid (any step, set_* or reset since invalidates it).  The adjoint covers the
- * BGK collision and bodies at rest only: both calls return LBM_EINVAL otherwise. */
+ * BGK collision, bodies at rest and the LBM_FP64, LBM_FP32 and LBM_FP32DEV storages
+ * only: both calls return LBM_EINVAL otherwise (LBM_FP16DEV included, checked before
+ * anything else, so an unbound handle gets it too).  After lbm_set_mask the adjoint
+ * follows the new mask. */
 int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes);
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J);

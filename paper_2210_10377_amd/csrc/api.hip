@@ -657,6 +657,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
     h->g = g;
     h->njblocks = nj;
     h->adj_valid = false;
+    h->adj_codes.clear();  // the adjoint codes invert the pull codes of the old mask
   };
   double P[2] = {0.0, 0.0};
   if (h->bound) {
@@ -780,6 +781,8 @@ int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* by
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J) {
   if (!h) return LBM_EINVAL;
+  if (h->g.precision == LBM_FP16DEV)
+    return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
@@ -831,6 +834,8 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
 
 int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
   if (!h) return LBM_EINVAL;
+  if (h->g.precision == LBM_FP16DEV)
+    return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
@@ -844,11 +849,12 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   void* mu[2] = {aws + L.off_mu, aws + L.off_mu + align256(L.mu)};
   double* dom = reinterpret_cast<double*>(aws + L.off_dom);
   double* duin = reinterpret_cast<double*>(aws + L.off_duin);
-  hipError_t e;
-  if (cbytes == 8)
-    e = launch_zero_f64(static_cast<double*>(mu[0]), int64_t(L.mu / 8), h->stream);
-  else
-    e = launch_zero_f32(static_cast<float*>(mu[0]), int64_t(L.mu / 4), h->stream);
+  hipError_t e = hipSuccess;
+  // Both adjoint fields start at zero: mu(n) = 0, and no entry of a solid node is ever
+  // written, so neither buffer keeps values of an earlier run or geometry.
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = cbytes == 8 ? launch_zero_f64(static_cast<double*>(mu[k]), int64_t(L.mu / 8), h->stream)
+                    : launch_zero_f32(static_cast<float*>(mu[k]), int64_t(L.mu / 4), h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "zero adjoint");
   if ((e = launch_zero_f64(dom, int64_t(p.ntiles) * kStrips, h->stream)) != hipSuccess)
     return h->hip_fail(e, "zero adjoint sums");

@@ -209,6 +209,8 @@ class Sim:
                 self.adjoint_workspace = torch.empty(int(nb.value), dtype=torch.uint8,
                                                      device=self.device)
         J = ctypes.c_double()
+        # Every forward run replaces the one the handle holds for the backward sweep.
+        self.adjoint_runs = getattr(self, "adjoint_runs", 0) + 1
         C.check(self._lib.lbm_adjoint_forward(
             self._h, ctypes.c_void_p(self.adjoint_workspace.data_ptr()),
             int(self.adjoint_workspace.numel()), int(n_steps), int(every), int(t0), int(T),

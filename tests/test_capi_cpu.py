@@ -286,6 +286,17 @@ def test_collision_code_validation_and_adjoint_bgk_only(capi):
     rc = L.lbm_adjoint_forward(bgk._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
                                ctypes.byref(J))
     assert rc == capi.LBM_ESTATE
+    # The adjoint covers the FP64, FP32 and FP32-deviation storages; binary16 deviations
+    # are refused by both calls before anything else.
+    h16 = Plan(mask, uin=0.05, precision="fp16dev")
+    rc = L.lbm_adjoint_forward(h16._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_EINVAL and b"storages" in L.lbm_last_error(h16._h)
+    gu = np.zeros(20)
+    gt = ctypes.c_double()
+    rc = L.lbm_adjoint_backward(h16._h, 1.0, gu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.byref(gt))
+    assert rc == capi.LBM_EINVAL
 
 
 def test_body_motion_validation_and_adjoint_refusal(capi):
