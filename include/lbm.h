@@ -42,6 +42,13 @@
  *                 populations of the control volume V (the fluid nodes of the box),
  *                 Phi(t) = sum of c_i f~_i(x,t) over populations entering V minus those
  *                 leaving V,
+ *       DRTT-post(t) = J~(t) - J(t+1) + Phi(t), J~(t) the momentum of the stored
+ *                 (post-collision) populations of V: the box balance over the
+ *                 streaming half of the step.  A momentum-conserving collision makes
+ *                 J~(t) = J(t) in exact arithmetic (Appendix: J is sampled before the
+ *                 collision); with rounded storage only DRTT-post stays equal to B up
+ *                 to the rounding of the FP64 sums, since every term then reads the
+ *                 same stored values,
  *       SI(t)   = sum_{axis links (x,i), i = 1..4} (-p I + sigma)(x,t) . (-c_i): each
  *                 axis link crosses one unit face of the staircase body surface, whose
  *                 normal out of the body is -c_i; p = rho/3 and the deviatoric stress
@@ -118,7 +125,8 @@ extern "C" {
 #define LBM_FORCE_MEA_B 2u
 #define LBM_FORCE_DRTT 4u
 #define LBM_FORCE_SI 8u
-#define LBM_FORCE_ALL 15u
+#define LBM_FORCE_DRTT_POST 16u /* DRTT with J(t) taken after the collision (below)   */
+#define LBM_FORCE_ALL 31u
 
 typedef struct lbm_grid {
   int32_t nx, ny;     /* grid size, each >= 3                                      */
@@ -196,13 +204,13 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream);
  * LBM_EINVAL for n < 0 or unknown scheme bits. */
 int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme);
 
-/* Copy the force rows recorded since the last call into out[k][4][2] (host; scheme
- * order A, B, DRTT, SI; components x, y) and empty the ring.  At most cap rows are written
+/* Copy the force rows recorded since the last call into out[k][5][2] (host; scheme
+ * order A, B, DRTT, SI, DRTT-post; components x, y) and empty the ring.  At most cap rows are written
  * (LBM_EINVAL if fewer than recorded).  Synchronises the stream.  Returns
  * LBM_ENONFINITE (after writing everything) if any requested value is not finite. */
 int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out);
 
-/* Force coefficients 2 F / (rho_ref u_ref^2 l_ref) of k force rows ([k][4][2], Sec. V:
+/* Force coefficients 2 F / (rho_ref u_ref^2 l_ref) of k force rows ([k][5][2], Sec. V:
  * drag and lift coefficients, kept signed), host to host; in and out may alias. */
 int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out);
 
@@ -393,7 +401,7 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
  * force_scheme (as lbm_step).  LBM_EOVERFLOW when force rows would exceed max_record. */
 int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme);
 
-/* Drain the batch ring: out[i][t][scheme][component] (host, n_inst x cap x 4 x 2
+/* Drain the batch ring: out[i][t][scheme][component] (host, n_inst x cap x 5 x 2
  * doubles) receives instance i's forces of the t-th recorded step, as lbm_forces
  * gives them; *k_out the number of rows (also when out is NULL and nothing is
  * recorded).  nonfinite (host, n_inst bytes, may be NULL) flags instances with a

@@ -101,6 +101,10 @@ int lbm3d_workspace_bytes(const lbm3d_t* h, size_t* bytes);
  * stream (NULL: the default stream); fills the rest state w_i.  Synchronises. */
 int lbm3d_bind(lbm3d_t* h, void* device_workspace, size_t bytes, void* hip_stream);
 
+/* Force schemes of the three-dimensional lattice: LBM_FORCE_MEA_A, LBM_FORCE_MEA_B,
+ * LBM_FORCE_DRTT and LBM_FORCE_SI of lbm.h (DRTT-post is two-dimensional only). */
+#define LBM3D_FORCE_ALL 15u
+
 /* Enqueue n >= 0 steps.  force_scheme: LBM_FORCE_* bits; with any bit set every step
  * appends one row to the ring (LBM_EOVERFLOW, nothing enqueued, when it cannot hold
  * them: read the rows first). */

@@ -225,17 +225,19 @@ class OracleSim:
         lib().orc_step(self._h, int(n))
 
     def records(self):
-        """[t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy] of every recorded step."""
+        """[t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy, Jpostx, Jposty] of every
+        recorded step (J before collision, Jpost after it)."""
         n = lib().orc_nrec(self._h)
-        out = np.zeros((n, 10))
+        out = np.zeros((n, 12))
         if n:
             lib().orc_records(self._h, _dp(out))
         return out
 
     def forces(self):
-        """[t, scheme (A, B, DRTT, SI), component (x, y)] of every recorded step."""
+        """[t, scheme (A, B, DRTT, SI, DRTT-post), component (x, y)] of every recorded
+        step; DRTT-post takes the control-volume momentum J(t) after the collision."""
         n = lib().orc_nrec(self._h)
-        out = np.zeros((n, 4, 2))
+        out = np.zeros((n, 5, 2))
         if n:
             lib().orc_forces(self._h, _dp(out))
         return out

@@ -227,8 +227,11 @@ struct Config {
   double body_c[2];
 };
 
-// Per-step record: FA(2), FB(2), J(2), Phi(2), SI(2).
-const int NREC = 10;
+// Per-step record: FA(2), FB(2), J(2), Phi(2), SI(2), Jpost(2).
+const int NREC = 12;
+// Estimators reported per step: A, B, DRTT, SI, DRTT with the post-collision box
+// momentum; two components each.
+const int NSCHEME = 5;
 
 template <class T>
 struct Sim {
@@ -353,6 +356,10 @@ struct Sim {
           collide_node<T>(fin, omega, cfg.gx, cfg.gy, fout);
         for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y)] = fout[i];
       }
+    // Control-volume momentum after collision, of the populations as stored (the
+    // momentum J(t) of Eq. rtt1 sampled on the other side of the collision).
+    T Jpost[2];
+    box_momentum(Sn, Jpost);
     // Momentum exchange on every fluid-solid link (Sec. III; Eq. rtt4, rtt5):
     // lost momentum c_i f_i (A: pre-collision) or c_i f~_i (B: post-collision) plus
     // the momentum -c_o f_o(x, t+1) = c_i f_o(x, t+1) returned by the boundary.
@@ -428,13 +435,18 @@ struct Sim {
           SI[1] += sxy * nxv + (syy - p) * nyv;
         }
     S.swap(Sn);
-    const T r[NREC] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1], Phi[0], Phi[1], SI[0], SI[1]};
+    const T r[NREC] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1],
+                       Phi[0], Phi[1], SI[0], SI[1], Jpost[0], Jpost[1]};
     rec.insert(rec.end(), r, r + NREC);
   }
 
-  // Forces of every recorded step: [t][scheme A, B, DRTT][x, y].  DRTT (second
-  // Eq. rtt7): F(t) = J(t) - J(t+1) + Phi(t); the J of the step after the last recorded
-  // one is the control-volume momentum of the populations the next pull would give.
+  // Forces of every recorded step: [t][scheme A, B, DRTT, SI, DRTT-post][x, y].
+  // DRTT (second Eq. rtt7): F(t) = J(t) - J(t+1) + Phi(t), both J before collision
+  // (Appendix); the J of the step after the last recorded one is the control-volume
+  // momentum of the populations the next pull would give.  DRTT-post takes J(t) after
+  // the collision instead: F(t) = J^post(t) - J(t+1) + Phi(t), the momentum balance of
+  // the box over the streaming half of the step alone.  A collision that conserves
+  // momentum makes the two equal.
   void forces(T* out) const {
     const size_t n = rec.size() / NREC;
     T Jlast[2] = {0.0, 0.0};
@@ -445,7 +457,7 @@ struct Sim {
     }
     for (size_t t = 0; t < n; ++t) {
       const T* r = &rec[NREC * t];
-      T* o = out + 8 * t;
+      T* o = out + 2 * NSCHEME * t;
       o[0] = r[0];
       o[1] = r[1];
       o[2] = r[2];
@@ -460,9 +472,13 @@ struct Sim {
           }
         o[4] = r[4] - jx1 + r[6];
         o[5] = r[5] - jy1 + r[7];
+        o[8] = r[10] - jx1 + r[6];
+        o[9] = r[11] - jy1 + r[7];
       } else {
         o[4] = NAN;
         o[5] = NAN;
+        o[8] = NAN;
+        o[9] = NAN;
       }
       o[6] = r[8];
       o[7] = r[9];
@@ -693,13 +709,14 @@ void orc_step(void* h, int32_t n) {
 
 int64_t orc_nrec(void* h) { return int64_t(static_cast<Sim<double>*>(h)->rec.size() / NREC); }
 
-// Raw per-step records [t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy].
+// Raw per-step records [t][FAx, FAy, FBx, FBy, Jx, Jy, Phix, Phiy, SIx, SIy, Jpostx,
+// Jposty].
 void orc_records(void* h, double* out) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   std::memcpy(out, s->rec.data(), s->rec.size() * sizeof(double));
 }
 
-// Forces [t][A, B, DRTT, SI][x, y] of all recorded steps.
+// Forces [t][A, B, DRTT, SI, DRTT-post][x, y] of all recorded steps.
 void orc_forces(void* h, double* out) { static_cast<Sim<double>*>(h)->forces(out); }
 
 void orc_clear_records(void* h) {

@@ -16,7 +16,9 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE, LBM_EOVERF
 LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_FP32DEV = 0, 1, 2, 3
 LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
 LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
-LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_SI, LBM_FORCE_ALL = 1, 2, 4, 8, 15
+LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_SI = 1, 2, 4, 8
+LBM_FORCE_DRTT_POST, LBM_FORCE_ALL = 16, 31
+LBM3D_FORCE_ALL = 15
 LBM_COLL_BGK, LBM_COLL_REGULARIZED, LBM_COLL_KBC = 0, 1, 2
 LBM_LAYOUT_AUTO, LBM_LAYOUT_ROWS, LBM_LAYOUT_PLANES = 0, 1, 2
 

@@ -8,7 +8,7 @@ import ctypes
 import numpy as np
 
 from . import _capi as C
-from .sim import ALL_SCHEMES, Sim, scheme_mask
+from .sim import ALL_SCHEMES, NSCHEMES, Sim, scheme_mask
 
 
 class Batch:
@@ -91,7 +91,7 @@ class Batch:
         recorded since the last call."""
         k = self.info().n_recorded
         n = len(self.members)
-        out = np.zeros((n, max(k, 1), 4, 2))
+        out = np.zeros((n, max(k, 1), NSCHEMES, 2))
         flags = np.zeros(n, np.uint8)
         got = ctypes.c_int64()
         rc = self._lib.lbm_batch_forces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -113,7 +113,7 @@ class Batch:
             bad |= nf
             left -= k
         if not outs:
-            return np.zeros((len(self.members), 0, 4, 2)), bad
+            return np.zeros((len(self.members), 0, NSCHEMES, 2)), bad
         return np.concatenate(outs, axis=1), bad
 
     def coefficients(self, F: np.ndarray) -> np.ndarray:

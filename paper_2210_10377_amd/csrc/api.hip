@@ -260,12 +260,16 @@ StepArgs step_args(const lbm_t* h) {
 }
 
 bool row_forces(const double* r, uint32_t sch, bool has_box, double* o) {
-  const double v[8] = {r[0], r[1], r[2], r[3], r[4] - r[kJnext] + r[6],
-                       r[5] - r[kJnext + 1] + r[7], r[8], r[9]};
-  const bool want[4] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
-                        (sch & LBM_FORCE_DRTT) != 0 && has_box, (sch & LBM_FORCE_SI) != 0};
+  // DRTT: J(t) - J(t+1) + Phi(t) with J(t) before collision; DRTT-post: the same with
+  // J(t) after collision (the stored populations).
+  const double v[2 * kSchemes] = {r[0], r[1], r[2], r[3], r[4] - r[kJnext] + r[6],
+                                  r[5] - r[kJnext + 1] + r[7], r[8], r[9],
+                                  r[kJpost] - r[kJnext] + r[6], r[kJpost + 1] - r[kJnext + 1] + r[7]};
+  const bool want[kSchemes] = {(sch & LBM_FORCE_MEA_A) != 0, (sch & LBM_FORCE_MEA_B) != 0,
+                               (sch & LBM_FORCE_DRTT) != 0 && has_box, (sch & LBM_FORCE_SI) != 0,
+                               (sch & LBM_FORCE_DRTT_POST) != 0 && has_box};
   bool finite = true;
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < kSchemes; ++s)
     for (int c = 0; c < 2; ++c) {
       o[2 * s + c] = want[s] ? v[2 * s + c] : std::nan("");
       if (want[s] && !std::isfinite(v[2 * s + c])) finite = false;
@@ -397,7 +401,7 @@ int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
   bool finite = true;
   for (int64_t t = 0; t < h->nrec; ++t)
     finite = row_forces(&rows[size_t(t) * kRow], h->rec_scheme[size_t(t)], h->plan.has_box,
-                        out + t * 8) && finite;
+                        out + t * 2 * kSchemes) && finite;
   h->nrec = 0;
   h->rec_scheme.clear();
   if (!finite) return h->fail(LBM_ENONFINITE, "a recorded force is not finite");
@@ -407,7 +411,7 @@ int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
 int lbm_coefficients(const lbm_t* h, const double* forces, int64_t k, double* out) {
   if (!h || (k > 0 && (!forces || !out)) || k < 0) return LBM_EINVAL;
   const double q = 0.5 * h->g.rho_ref * h->g.u_ref * h->g.u_ref * h->g.l_ref;
-  for (int64_t j = 0; j < k * 8; ++j) out[j] = forces[j] / q;
+  for (int64_t j = 0; j < k * 2 * kSchemes; ++j) out[j] = forces[j] / q;
   return LBM_OK;
 }
 
@@ -644,7 +648,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
   const int rc = replan(g, solid_mask, changed, h->plan, np, d, perr);
   if (rc != LBM_OK) return h->fail(rc, perr);
   const int nj = np.has_box ? np.box_bx * np.box_rows : 0;
-  if (size_t(np.nslots) * kPart + size_t(np.njslots) * 2 > h->part_cap || nj > h->jcap) {
+  if (size_t(np.nslots) * kPart + size_t(np.njslots) * kBoxPart > h->part_cap || nj > h->jcap) {
     undo_replan(h->plan, np, d);
     return h->fail(LBM_ENOMEM, nj > h->jcap
                                    ? "the new control volume is larger than the one at create"

@@ -347,7 +347,7 @@ int lbm3d_step(lbm3d_t* h, int32_t n, uint32_t scheme) {
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
-  if (scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
+  if (scheme & ~LBM3D_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
   const bool forces = scheme != 0;
   if (forces && h->nrec + n > h->g.max_record)
     return h->fail(LBM_EOVERFLOW, "force ring would overflow; read lbm3d_forces first");

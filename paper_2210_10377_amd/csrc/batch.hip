@@ -505,7 +505,7 @@ int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
     bool finite = true;
     for (int64_t t = 0; t < k; ++t)
       finite = row_forces(&rows[(i * size_t(k) + size_t(t)) * kRingRow], b->rec_scheme[size_t(t)],
-                          has_box, out + (int64_t(i) * cap + t) * 8) && finite;
+                          has_box, out + (int64_t(i) * cap + t) * 2 * kSchemes) && finite;
     if (!finite) {
       all_finite = false;
       if (nonfinite) nonfinite[i] = 1;

@@ -73,7 +73,7 @@ struct lbm_t {
   }
   // Doubles of one step's force partials: general strips, then box-interior strips.
   size_t part_doubles() const {
-    return size_t(plan.nslots) * lbm::kPart + size_t(plan.njslots) * 2;
+    return size_t(plan.nslots) * lbm::kPart + size_t(plan.njslots) * lbm::kBoxPart;
   }
   double* part(int k) const {
     return reinterpret_cast<double*>(ws + off_part) + size_t(k) * part_cap;
@@ -86,8 +86,9 @@ namespace lbm {
 StepArgs step_args(const lbm_t* h);
 // Control-volume sweep arguments of the handle over the state `src`.
 BoxArgs box_args(const lbm_t* h, const void* src);
-// One ring row -> forces [A, B, DRTT, SI][x, y] (NaN for schemes not recorded, and for
-// DRTT without a control volume); returns false if a recorded force is not finite.
+// One ring row -> forces [A, B, DRTT, SI, DRTT-post][x, y] (NaN for schemes not
+// recorded, and for the DRTT forms without a control volume); returns false if a
+// recorded force is not finite.
 bool row_forces(const double* row, uint32_t scheme, bool has_box, double* out);
 
 }  // namespace lbm

@@ -8,11 +8,16 @@
 namespace lbm {
 
 // Force partial of one strip, and the per-step sums: FAx FAy FBx FBy Jx Jy Phix Phiy
-// SIx SIy.
-constexpr int kPart = 10;
+// SIx SIy Jpx Jpy (J before collision, Jp after it, both over the control volume).
+constexpr int kPart = 12;
+constexpr int kJpost = 10;
+// Partial of a box-interior strip: Jx Jy Jpx Jpy.
+constexpr int kBoxPart = 4;
 // Force-ring row: the kPart sums, then Jnext_x Jnext_y (the J of the following step).
-constexpr int kRingRow = 12;
-constexpr int kJnext = 10;
+constexpr int kRingRow = 14;
+constexpr int kJnext = 12;
+// Estimators of a force row as lbm_forces reports them: A, B, DRTT, SI, DRTT-post.
+constexpr int kSchemes = 5;
 
 // Rigid motion of the body: velocity U + Omega e_z x (x - c) at a point x.  Kernels read
 // it from device memory, and only on body links, through a pointer that is null for a
@@ -44,7 +49,8 @@ struct StepArgs {
   double omega;                // 1 / tau_lb
   int32_t collision;           // LBM_COLL_*
   double* part_out;            // force partials of this step ([nslots][kPart] of the
-                               // general strips, then [njslots][2] box momenta), or null
+                               // general strips, then [njslots][kBoxPart] box momenta),
+                               // or null
   const double* red_in;        // partials of the previous step (same layout), or null
   int32_t nslots, njslots;
   double* red_row;             // ring row receiving the reduced previous step

@@ -57,9 +57,12 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, int tx, int ty,
     for (int i = 0; i < kQ; ++i) v[r][i] = src.ld(i, o0 + (r - kCy[i]) * pitch - kCx[i]);
 }
 
-template <int P, bool BUF, int COLL>
+// Collision and store of an interior tile; with JP the momentum of the stored
+// (post-collision) populations is added to jp (binary64).
+template <int P, bool BUF, int COLL, bool JP = false>
 __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int ty,
-                                                const typename Storage<P>::T (&v)[kTileH][kQ]) {
+                                                const typename Storage<P>::T (&v)[kTileH][kQ],
+                                                double* jp = nullptr) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
@@ -74,7 +77,17 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
     C g[kQ];
     collide<C, S::kDev, COLL>(f, C(a.omega), g);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) dst.st(i, o0 + r * pitch, pack<P>(g[i]));
+    for (int i = 0; i < kQ; ++i) {
+      const T q = pack<P>(g[i]);
+      dst.st(i, o0 + r * pitch, q);
+      if constexpr (JP) {
+        if (i > 0) {
+          const double fi = to_f64<P>(q, i);
+          jp[0] += kCx[i] * fi;
+          jp[1] += kCy[i] * fi;
+        }
+      }
+    }
   }
 }
 
@@ -149,18 +162,23 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
         acc[2] += kCx[i] * (sv + back);
         acc[3] += kCy[i] * (sv + back);
       }
-      // Control volume (second Eq. rtt7): momentum before collision, and the
-      // populations crossing the box surface after collision.
+      // Control volume (second Eq. rtt7): momentum before collision (and after it, as
+      // stored), and the populations crossing the box surface after collision.
       if (in_box(a, x, y)) {
-        double jx = 0.0, jy = 0.0;
+        double jx = 0.0, jy = 0.0, px = 0.0, py = 0.0;
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
           const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
           jx += kCx[i] * fi;
           jy += kCy[i] * fi;
+          const double sv = to_f64<P>(s[i], i);
+          px += kCx[i] * sv;
+          py += kCy[i] * sv;
         }
         acc[4] += jx;
         acc[5] += jy;
+        acc[kJpost] += px;
+        acc[kJpost + 1] += py;
 #pragma unroll
         for (int i = 1; i < kQ; ++i)
           if (!in_box(a, x + kCx[i], y + kCy[i])) {
@@ -213,11 +231,14 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
 // Force row of the previous step from its partial slots (fixed order).
 __device__ __forceinline__ void reduce_row(const double* red_in, int nslots, int njslots,
                                            double* row, double* prev_jnext) {
-  // General strips, then the box momenta of the box-interior strips (added to J).
+  // General strips, then the box momenta of the box-interior strips (J before and after
+  // collision, added to the two J sums).
   double t = reduce_partials<kPart>(red_in, nslots);
-  const double tj = reduce_partials<2>(red_in + int64_t(nslots) * kPart, njslots);
-  const double tj4 = __shfl(tj, threadIdx.x - 4, 64);
-  if (threadIdx.x == 4 || threadIdx.x == 5) t += tj4;
+  const double tj = reduce_partials<kBoxPart>(red_in + int64_t(nslots) * kPart, njslots);
+  const int tid = int(threadIdx.x);
+  const bool pre = tid == 4 || tid == 5, post = tid == kJpost || tid == kJpost + 1;
+  const double tjs = __shfl(tj, pre ? tid - 4 : (post ? tid - kJpost + 2 : 0), 64);
+  if (pre || post) t += tjs;
   if (threadIdx.x < kPart) {
     row[threadIdx.x] = t;
     if (prev_jnext && (threadIdx.x == 4 || threadIdx.x == 5)) prev_jnext[threadIdx.x - 4] = t;
@@ -244,8 +265,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
     interior_load<P, BUF>(a, tx, ty, v);
     if (FORCES && cls == kStripBoxInterior) {
       // Every node is in the control volume and streams plainly: its pre-collision
-      // populations are the loaded values; only the box momentum J is accumulated.
-      double acc[2] = {0.0, 0.0};
+      // populations are the loaded values; only the box momentum J is accumulated,
+      // before collision and after it (of the stored values).
+      double acc[kBoxPart] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int r = 0; r < kTileH; ++r)
 #pragma unroll
@@ -254,17 +276,17 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
           acc[0] += kCx[i] * fi;
           acc[1] += kCy[i] * fi;
         }
-      interior_finish<P, BUF, COLL>(a, tx, ty, v);
-      wave_sum_store<2>(acc, a.part_out + int64_t(a.nslots) * kPart +
-                                 int64_t(strip_slot[tile * kStrips + wave]) * 2);
+      interior_finish<P, BUF, COLL, true>(a, tx, ty, v, acc + 2);
+      wave_sum_store<kBoxPart>(acc, a.part_out + int64_t(a.nslots) * kPart +
+                                        int64_t(strip_slot[tile * kStrips + wave]) * kBoxPart);
       return;
     }
     interior_finish<P, BUF, COLL>(a, tx, ty, v);
     return;
   }
   const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
-  // FA(x,y), FB(x,y), J(x,y), Phi(x,y), SI(x,y)
-  double acc[kPart] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // FA(x,y), FB(x,y), J(x,y), Phi(x,y), SI(x,y), Jpost(x,y)
+  double acc[kPart] = {};
   general_rows<P, BUF, COLL, MOV>(a, tx, ty, slot >= 0, acc);
   if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
 }

@@ -11,8 +11,10 @@ from . import _capi as C
 PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV,
               "fp32dev": C.LBM_FP32DEV}
 SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT,
-           "SI": C.LBM_FORCE_SI}
-ALL_SCHEMES = ("A", "B", "DRTT", "SI")
+           "SI": C.LBM_FORCE_SI, "DRTT_POST": C.LBM_FORCE_DRTT_POST}
+ALL_SCHEMES = ("A", "B", "DRTT", "SI", "DRTT_POST")
+# Number of estimators in a force row: A, B, DRTT, SI, DRTT-post.
+NSCHEMES = 5
 COLLISIONS = {"bgk": C.LBM_COLL_BGK, "regularized": C.LBM_COLL_REGULARIZED,
               "kbc": C.LBM_COLL_KBC}
 LAYOUTS = {"auto": C.LBM_LAYOUT_AUTO, "rows": C.LBM_LAYOUT_ROWS,
@@ -97,10 +99,11 @@ class Sim:
         C.check(self._lib.lbm_step(self._h, int(n), m), self._h)
 
     def forces(self) -> np.ndarray:
-        """[k, 4 (A, B, DRTT, SI), 2 (x, y)] float64 forces of the steps since the last call."""
+        """[k, 5 (A, B, DRTT, SI, DRTT_POST), 2 (x, y)] float64 forces of the steps since
+        the last call."""
         info = self.info()
         k = info.n_recorded
-        out = np.zeros((max(k, 1), 4, 2))
+        out = np.zeros((max(k, 1), NSCHEMES, 2))
         got = ctypes.c_int64()
         rc = self._lib.lbm_forces(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   max(k, 1), ctypes.byref(got))
@@ -118,7 +121,7 @@ class Sim:
             self.step(k, schemes)
             outs.append(self.forces())
             left -= k
-        return np.concatenate(outs) if outs else np.zeros((0, 4, 2))
+        return np.concatenate(outs) if outs else np.zeros((0, NSCHEMES, 2))
 
     def coefficients(self, forces: np.ndarray) -> np.ndarray:
         f = np.ascontiguousarray(forces, dtype=np.float64)

@@ -7,7 +7,10 @@ import ctypes
 import numpy as np
 
 from . import _capi as C
-from .sim import ALL_SCHEMES, COLLISIONS, LAYOUTS, PRECISIONS, scheme_mask
+from .sim import COLLISIONS, LAYOUTS, PRECISIONS, scheme_mask
+
+# The estimators of the three-dimensional lattice.
+ALL_SCHEMES = ("A", "B", "DRTT", "SI")
 
 
 class Sim3:

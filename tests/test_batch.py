@@ -165,7 +165,7 @@ def test_steps_without_forces_and_ring_overflow():
     with pytest.raises(LbmError):
         b.step(1)
     F, _ = b.forces()
-    assert F.shape == (3, 10, 4, 2)
+    assert F.shape == (3, 10, 5, 2)
 
 
 def test_nonfinite_instance_is_flagged_alone():

@@ -53,7 +53,7 @@ def test_degenerate_2d_against_oracle(name):
     o.step(25)
     assert _close(g.populations(), o.state(), mask) <= TOL
     Fg, Fo = g.forces(), o.forces()
-    assert Fg.shape == (25, 4, 2)
+    assert Fg.shape == (25, 5, 2)
     if mask.any():
         assert g.info().n_links == 8
         _forces_close(Fg, Fo, (0, 1, 3))
@@ -74,7 +74,7 @@ def test_no_fluid_node_2d():
     g.step(4)
     np.testing.assert_array_equal(g.populations(), S0)
     F = g.forces()
-    assert F.shape == (4, 4, 2)
+    assert F.shape == (4, 5, 2)
     assert np.all(F[:, [0, 1, 3]] == 0.0) and np.all(np.isnan(F[:, 2]))
 
 

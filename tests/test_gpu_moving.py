@@ -25,7 +25,7 @@ def _sim(**kw):
     return Sim(**kw)
 
 
-def _force_err(Fg, Fo, cols=(0, 1, 2, 3)):
+def _force_err(Fg, Fo, cols=(0, 1, 2, 3, 4)):
     out = []
     for k in cols:
         scale = np.abs(Fo[:, k]).max()
@@ -108,7 +108,7 @@ def test_fp64_moving_body_small_cases(name, motion):
     g.step(60)
     Fg, Fo = g.forces(), o.forces()
     assert _pop_err(g.populations(), o.state(), mask) <= TOL64
-    cols = (0, 1, 2, 3) if box is not None else (0, 1, 3)
+    cols = (0, 1, 2, 3, 4) if box is not None else (0, 1, 3)
     e = _force_err(Fg, Fo, cols)
     assert np.all(e <= TOL64), e
 
@@ -137,7 +137,7 @@ def test_rotating_cylinder_channel(precision, rotating_reference):
     Fg = g.run(3000)
     assert np.isfinite(Fg).all()
     e = _force_err(Fg, Fo)
-    print(precision, "rotating cylinder force errors (A, B, DRTT, SI):", e)
+    print(precision, "rotating cylinder force errors (A, B, DRTT, SI, DRTT-post):", e)
     tol = {"fp64": TOL64, "fp32": TOL32_FORCE, "fp32dev": TOL32_FORCE,
            "fp16dev": TOL16_FORCE}[precision]
     assert np.all(e <= tol), e
@@ -226,7 +226,8 @@ def test_pitching_naca_full_size_two_steps(precision):
     err = _pop_err(g.populations(), o.state(), w.mask)
     assert err <= {"fp64": 1e-10, "fp32": 2e-6}[precision], err
     e = _force_err(g.forces(), o.forces())
-    tol = {"fp64": np.array([1e-10] * 4), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3])}[precision]
+    # DRTT-post reads the stored values as B does: B's tolerance.
+    tol = {"fp64": np.array([1e-10] * 5), "fp32": np.array([1e-4, 1e-4, 1e-2, 1e-3, 1e-4])}[precision]
     assert np.all(e <= tol), e
 
 

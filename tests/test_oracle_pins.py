@@ -517,6 +517,58 @@ def test_drtt_empty_box_is_zero(orc):
     assert np.abs(F[:, 2]).max() <= 1e-12
 
 
+def test_drtt_post_equals_mea_b_and_drtt(orc):
+    """DRTT with the control-volume momentum taken after the collision (J^post(t), the
+    stored populations of V) in place of J(t) (second Eq. rtt7; the Appendix samples J
+    before the collision): every term then reads the stored populations, so
+    J^post(t) - J(t+1) + Phi(t) is the momentum balance of the box over streaming and
+    bounce-back alone and equals MEA-B; BGK conserves momentum node by node, so it also
+    equals DRTT.  Three boxes; an empty box gives zero."""
+    w = workloads.cylinder_channel_200x80()
+    for box in ((10, 70, 10, 70), (25, 56, 24, 57), (5, 120, 3, 77)):
+        s = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=box)
+        s.step(300)
+        F = s.forces()
+        assert F.shape == (300, 5, 2)
+        # The three sums run over the n_V nodes of the box with |c_i f_i| adding to at
+        # most 0.7 per node: rounding of at most 64 units each, 1.5e-14 per node.
+        nv = int((w.mask[box[2]:box[3], box[0]:box[1]] == 0).sum())
+        tol = 1.5e-14 * nv
+        assert np.abs(F[:, 4] - F[:, 1]).max() <= tol
+        assert np.abs(F[:, 4] - F[:, 2]).max() <= tol
+        assert np.abs(F[:, 1]).max() > 1e3 * tol
+    nx, ny = 60, 30
+    s = OracleSim(np.zeros((ny, nx), np.uint8), tau=0.7, uin=np.full(ny, 0.05),
+                  box=(10, 40, 5, 25))
+    s.set_state(workloads.near_rest_state(nx, ny, seed=9, amp=0.05))
+    s.step(50)
+    assert np.abs(s.forces()[:, 4]).max() <= 1e-12
+
+
+def test_drtt_post_separates_momentum_added_by_the_collision(orc):
+    """A collision that adds momentum (the Guo body force g on each node, a test-only
+    extension) separates the two samplings of the box momentum: J^post(t) = J(t) + N_V g
+    for the N_V fluid nodes of the box, so DRTT = MEA-B - N_V g at every step (the closed
+    form), while DRTT-post = MEA-B (the box balance over streaming only).  A reading that
+    sampled both J at the same side of the collision would fail one of the two."""
+    nx, ny = 40, 24
+    mask = workloads.cylinder_mask(nx, ny, 19.5, 11.5, 4.0)
+    g = (3e-6, -2e-6)
+    box = (8, 32, 4, 20)
+    s = OracleSim(mask, tau=0.8, bc_x=BCX_PERIODIC, bc_y=BCY_WALL, box=box, g=g)
+    s.set_state(workloads.near_rest_state(nx, ny, seed=5, amp=0.02))
+    s.step(200)
+    F = s.forces()
+    R = s.records()
+    nv = int((mask[box[2]:box[3], box[0]:box[1]] == 0).sum())
+    np.testing.assert_allclose(R[:, 10:12] - R[:, 4:6], np.broadcast_to(nv * np.array(g), (200, 2)),
+                               rtol=0, atol=1e-12 * nv)
+    np.testing.assert_allclose(F[:, 2], F[:, 1] - nv * np.array(g), rtol=0, atol=1.5e-14 * nv)
+    np.testing.assert_allclose(F[:, 4], F[:, 1], rtol=0, atol=1.5e-14 * nv)
+    # the separated term N_V g is far above the rounding bound
+    assert nv * min(abs(g[0]), abs(g[1])) > 1e6 * 1.5e-14 * nv
+
+
 def test_a_minus_b_is_the_collision_of_the_outgoing_populations(orc):
     """Eq. rtt4: algorithm A takes the outgoing population before collision, B after, with
     the same returned populations, so F_A - F_B = 2 beta sum_L c_i (f_i - f_i^eq) -- the
