@@ -284,6 +284,23 @@ int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc,
  * forward run held by the handle is discarded. */
 int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double* impulse);
 
+/* Pressure coefficient at the boundary fluid nodes (Sec. V, the C_p equation: computed
+ * over the boundary fluid nodes, without extrapolation):
+ *   C_p = (p - p_inf) / (rho_ref u_ref^2 / 2),  p = rho theta0 = rho / 3,
+ * rho the density of the current stored state at the node (sum of its populations in
+ * binary64; the collision conserves it), p_inf the same at the far-upstream reference
+ * node (x_inf, y_inf), or rho_ref / 3 when x_inf < 0; rho_ref and u_ref of lbm_grid.  A
+ * boundary fluid node is a fluid node with at least one fluid-solid link; the nodes come
+ * in row-major order (the node order of lbm_get_links).  Writes the n values to cp (host,
+ * cap >= n) and, when nodes is non-null, their indices y * nx + x (host, n entries);
+ * *n = n (also when n is 0 and cp is NULL).  Computed by a kernel from the current
+ * state; synchronises the stream and uses the idle state buffer as scratch (no work of
+ * the handle, or of a batch holding it, may be in flight on another stream).
+ * LBM_EINVAL for a reference node outside the grid or solid, cap < n, or rho_ref or
+ * u_ref zero or non-finite; LBM_ESTATE if unbound. */
+int lbm_boundary_cp(lbm_t* h, int32_t x_inf, int32_t y_inf, double* cp, int32_t* nodes,
+                    int64_t cap, int64_t* n);
+
 /* Put every node back in the rest state w_i, zero the step counter and empty the force
  * ring.  Synchronises the stream. */
 int lbm_reset(lbm_t* h);

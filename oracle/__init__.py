@@ -29,8 +29,8 @@ LIB3 = os.path.join(HERE, "liboracle3d.so")
 def _compile(src, lib, force):
     if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
         tmp = lib + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-shared",
-                               "-fPIC", src, "-o", tmp])
+        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-fopenmp",
+                               "-shared", "-fPIC", src, "-o", tmp])
         os.replace(tmp, lib)
     return lib
 
@@ -91,12 +91,24 @@ def lib():
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_double, dp]
         L.orc_objective_cs.restype = ctypes.c_int
+        L.orc_boundary_cp.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_double, ip, dp, ctypes.c_int64]
+        L.orc_boundary_cp.restype = ctypes.c_int64
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_set_threads.restype = ctypes.c_int32
         _lib = L
     return _lib
 
 
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the two-dimensional oracle's row loops (1: serial, the default).  Every
+    sum keeps its serial order, so results are bitwise the same for any count.  Returns
+    the previous count."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _cfg(nx, ny, bc_x, bc_y, box, rho_w, g, collision="bgk", body_motion=None):
@@ -268,6 +280,22 @@ class OracleSim:
         """Rigid motion of the body from the next step."""
         lib().orc_set_body_motion(self._h, float(ux), float(uy), float(omega), float(xc),
                                   float(yc))
+
+    def boundary_cp(self, ref=None, rho_ref=1.0, u_ref=1.0):
+        """Pressure coefficient (p - p_inf) / (rho_ref u_ref^2 / 2) at every boundary fluid
+        node (row-major order), p = rho theta0 of the stored state; p_inf at the
+        reference node ref = (x, y), or rho_ref theta0 when ref is None.  Returns
+        (node indices y*nx + x as int32 [n], C_p float64 [n])."""
+        x, y = (-1, -1) if ref is None else (int(ref[0]), int(ref[1]))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        n = lib().orc_boundary_cp(self._h, x, y, float(rho_ref), float(u_ref), None, None, 0)
+        if n < 0:
+            raise ValueError("reference node outside the grid or solid")
+        nodes = np.zeros(max(n, 1), np.int32)
+        cp = np.zeros(max(n, 1))
+        lib().orc_boundary_cp(self._h, x, y, float(rho_ref), float(u_ref),
+                              nodes.ctypes.data_as(ip), _dp(cp), n)
+        return nodes[:n], cp[:n]
 
     def momentum_of(self, g):
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.shape)

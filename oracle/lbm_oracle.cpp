@@ -47,6 +47,7 @@
 //    -(1 - beta) sum f^neq c c, the sign that gives the viscous stress 2 rho nu S of
 //    the continuum limit (the printed formula is read with that sign).
 
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -54,6 +55,26 @@
 #include <vector>
 
 namespace {
+
+// Threads of the row loops (1: serial).  The node loops over rows are independent.
+// Every sum over nodes is formed from per-row lists of its terms that are added
+// afterwards, one term at a time in the serial (y, x, i) order, so every result is
+// bitwise the same for any thread count.
+int g_threads = 1;
+
+// Terms of K sums, row by row: rows may be filled in parallel; fold() adds them to
+// acc[0..K-1] in row order and, within a row, in the order they were pushed.
+template <class T, int K>
+struct RowTerms {
+  std::vector<std::vector<std::array<T, K>>> rows;
+  explicit RowTerms(int ny) : rows(size_t(ny)) {}
+  void push(int y, const std::array<T, K>& t) { rows[size_t(y)].push_back(t); }
+  void fold(T* acc) const {
+    for (const auto& r : rows)
+      for (const auto& t : r)
+        for (int k = 0; k < K; ++k) acc[k] += t[k];
+  }
+};
 
 // ---------------------------------------------------------------------------------
 // Lattice: D2Q9 velocity set and weights (Sec. II, Table I), theta0 = 1/3.
@@ -314,17 +335,19 @@ struct Sim {
   void box_momentum(const std::vector<T>& g, T* J) const {
     J[0] = 0.0;
     J[1] = 0.0;
+    RowTerms<T, 2> terms(cfg.ny);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < cfg.ny; ++y)
       for (int x = 0; x < cfg.nx; ++x) {
         if (!in_V(x, y)) continue;
-        for (int i = 0; i < NQ; ++i) {
-          J[0] += double(CX[i]) * g[idx(i, x, y)];
-          J[1] += double(CY[i]) * g[idx(i, x, y)];
-        }
+        for (int i = 0; i < NQ; ++i)
+          terms.push(y, {double(CX[i]) * g[idx(i, x, y)], double(CY[i]) * g[idx(i, x, y)]});
       }
+    terms.fold(J);
   }
 
   void stream_all(const std::vector<T>& St, std::vector<T>& out) const {
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < cfg.ny; ++y)
       for (int x = 0; x < cfg.nx; ++x) {
         if (is_solid(x, y)) continue;
@@ -342,10 +365,13 @@ struct Sim {
     T J[2];
     box_momentum(f, J);
     // Collision of the entire fluid domain (Eq. CollideAdv, first line).
-    Sn = S;  // body nodes keep whatever they hold; it is never read
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
-        if (is_solid(x, y)) continue;
+        if (is_solid(x, y)) {  // body nodes keep what they hold; it is never read
+          for (int i = 0; i < NQ; ++i) Sn[idx(i, x, y)] = S[idx(i, x, y)];
+          continue;
+        }
         T fin[NQ], fout[NQ];
         for (int i = 0; i < NQ; ++i) fin[i] = f[idx(i, x, y)];
         if (cfg.collision == COLLISION_REGULARIZED)
@@ -363,39 +389,44 @@ struct Sim {
     // Momentum exchange on every fluid-solid link (Sec. III; Eq. rtt4, rtt5):
     // lost momentum c_i f_i (A: pre-collision) or c_i f~_i (B: post-collision) plus
     // the momentum -c_o f_o(x, t+1) = c_i f_o(x, t+1) returned by the boundary.
-    T FA[2] = {0.0, 0.0}, FB[2] = {0.0, 0.0};
+    // Terms [FAx, FAy, FBx, FBy] per link.
+    T F4[4] = {0.0, 0.0, 0.0, 0.0};
+    RowTerms<T, 4> mea(ny);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x)
         for (int i = 1; i < NQ; ++i) {
           if (!is_link(x, y, i)) continue;
           const int o = opposite(i);
           T back = pull(Sn, x, y, o);  // f_o(x, t+1)
-          FA[0] += double(CX[i]) * (f[idx(i, x, y)] + back);
-          FA[1] += double(CY[i]) * (f[idx(i, x, y)] + back);
-          FB[0] += double(CX[i]) * (Sn[idx(i, x, y)] + back);
-          FB[1] += double(CY[i]) * (Sn[idx(i, x, y)] + back);
+          mea.push(y, {double(CX[i]) * (f[idx(i, x, y)] + back),
+                       double(CY[i]) * (f[idx(i, x, y)] + back),
+                       double(CX[i]) * (Sn[idx(i, x, y)] + back),
+                       double(CY[i]) * (Sn[idx(i, x, y)] + back)});
         }
+    mea.fold(F4);
+    const T FA[2] = {F4[0], F4[1]}, FB[2] = {F4[2], F4[3]};
     // DRTT surface terms on the outer surface of the control volume (second Eq. rtt7):
     //  + populations f~_i(x - c_i, t) entering a node x of V from outside V,
     //  - populations f~_i(x, t) leaving a node x of V for a node outside V.
+    // (A leaving population is added negated: a - b is a + (-b) in IEEE arithmetic.)
     T Phi[2] = {0.0, 0.0};
     if (cfg.box[0] >= 0) {
+      RowTerms<T, 2> flux(ny);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
           if (!in_V(x, y)) continue;
           for (int i = 1; i < NQ; ++i) {
             int ux = x - CX[i], uy = y - CY[i];  // upstream node
-            if (!in_box(ux, uy)) {
-              Phi[0] += double(CX[i]) * Sn[idx(i, ux, uy)];
-              Phi[1] += double(CY[i]) * Sn[idx(i, ux, uy)];
-            }
+            if (!in_box(ux, uy))
+              flux.push(y, {double(CX[i]) * Sn[idx(i, ux, uy)], double(CY[i]) * Sn[idx(i, ux, uy)]});
             int dx = x + CX[i], dy = y + CY[i];  // downstream node
-            if (!in_box(dx, dy)) {
-              Phi[0] -= double(CX[i]) * Sn[idx(i, x, y)];
-              Phi[1] -= double(CY[i]) * Sn[idx(i, x, y)];
-            }
+            if (!in_box(dx, dy))
+              flux.push(y, {-(double(CX[i]) * Sn[idx(i, x, y)]), -(double(CY[i]) * Sn[idx(i, x, y)])});
           }
         }
+      flux.fold(Phi);
     }
     // Stress integration (Sec. III, Eq. stress_int) over the staircase surface of the
     // body: every axis link (x, i) (i = 1..4, x fluid, x + c_i solid) is a unit face
@@ -406,6 +437,8 @@ struct Sim {
     // all from the pre-collision populations f(x, t) of the fluid node of the link
     // (f^eq of the collision; the theta0 delta / D term vanishes since sum f^neq = 0).
     T SI[2] = {0.0, 0.0};
+    RowTerms<T, 2> traction(ny);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x)
         for (int i = 1; i <= 4; ++i) {
@@ -431,9 +464,9 @@ struct Sim {
           T sxx = visc * pxx, sxy = visc * pxy, syy = visc * pyy;
           T p = rho * THETA0;
           double nxv = -CX[i], nyv = -CY[i];
-          SI[0] += (sxx - p) * nxv + sxy * nyv;
-          SI[1] += sxy * nxv + (syy - p) * nyv;
+          traction.push(y, {(sxx - p) * nxv + sxy * nyv, sxy * nxv + (syy - p) * nyv});
         }
+    traction.fold(SI);
     S.swap(Sn);
     const T r[NREC] = {FA[0], FA[1], FB[0], FB[1], J[0], J[1],
                        Phi[0], Phi[1], SI[0], SI[1], Jpost[0], Jpost[1]};
@@ -624,6 +657,14 @@ extern "C" {
 
 typedef Config orc_cfg;
 
+// Threads of the oracle's row loops (values below 1 mean 1); results do not depend on
+// it.  Returns the previous value.
+int32_t orc_set_threads(int32_t n) {
+  const int32_t old = g_threads;
+  g_threads = n < 1 ? 1 : n;
+  return old;
+}
+
 // Lattice tables of the oracle (for pins against the paper's Table I).
 void orc_lattice(int32_t* cx, int32_t* cy, int32_t* opp, double* w, double* theta0) {
   for (int i = 0; i < NQ; ++i) {
@@ -763,6 +804,43 @@ int orc_objective_cs(const orc_cfg* c, const uint8_t* mask, double om_re, double
   out[1] = J.imag();
   delete s;
   return 0;
+}
+
+// Pressure coefficient at the boundary fluid nodes (Sec. V, the C_p equation: computed
+// over the boundary fluid nodes, no extrapolation): C_p = (p - p_inf) / (rho_ref U^2 / 2)
+// with p = rho theta0 (rho = sum_i f_i of the stored state) and p_inf the pressure at the
+// far-upstream reference node (x_inf, y_inf), or rho_ref theta0 when x_inf < 0.  A
+// boundary fluid node is a fluid node with at least one fluid-solid link.  Nodes in
+// row-major order; writes at most cap (node index y*nx + x, C_p) pairs and returns their
+// number, or -1 when the reference node is outside the grid or solid.
+int64_t orc_boundary_cp(void* h, int32_t x_inf, int32_t y_inf, double rho_ref, double u_ref,
+                        int32_t* nodes, double* cp, int64_t cap) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  const int nx = s->cfg.nx, ny = s->cfg.ny;
+  auto density = [&](int x, int y) {
+    double rho = 0.0;
+    for (int i = 0; i < NQ; ++i) rho += s->S[s->idx(i, x, y)];
+    return rho;
+  };
+  double p_inf = rho_ref * THETA0;
+  if (x_inf >= 0) {
+    if (x_inf >= nx || y_inf < 0 || y_inf >= ny || s->is_solid(x_inf, y_inf)) return -1;
+    p_inf = density(x_inf, y_inf) * THETA0;
+  }
+  const double q = 0.5 * rho_ref * u_ref * u_ref;
+  int64_t n = 0;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      bool boundary = false;
+      for (int i = 1; i < NQ; ++i) boundary = boundary || s->is_link(x, y, i);
+      if (!boundary) continue;
+      if (n < cap) {
+        nodes[n] = int32_t(y * nx + x);
+        cp[n] = (density(x, y) * THETA0 - p_inf) / q;
+      }
+      ++n;
+    }
+  return n;
 }
 
 // Control-volume momentum of an arbitrary population field g (Eq. rtt1).

@@ -717,6 +717,55 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
   return LBM_OK;
 }
 
+int lbm_boundary_cp(lbm_t* h, int32_t x_inf, int32_t y_inf, double* cp, int32_t* nodes,
+                    int64_t cap, int64_t* n) {
+  if (!h || !n) return LBM_EINVAL;
+  if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
+  const int nx = h->g.nx, ny = h->g.ny;
+  int32_t ref = -1;
+  if (x_inf >= 0) {
+    if (x_inf >= nx || y_inf < 0 || y_inf >= ny || h->mask[size_t(y_inf) * nx + x_inf])
+      return h->fail(LBM_EINVAL, "the reference node must be a fluid node of the grid");
+    ref = y_inf * nx + x_inf;
+  }
+  if (!std::isfinite(h->g.rho_ref) || !std::isfinite(h->g.u_ref) || h->g.rho_ref * h->g.u_ref == 0.0)
+    return h->fail(LBM_EINVAL, "rho_ref and u_ref must be finite and non-zero");
+  // The boundary fluid nodes: the distinct nodes of the canonical link list (sorted by
+  // node, so row-major).
+  std::vector<int32_t> list;
+  const std::vector<int32_t>& L = h->plan.links;
+  for (size_t k = 0; k < L.size(); k += 2)
+    if (list.empty() || list.back() != L[k]) list.push_back(L[k]);
+  *n = int64_t(list.size());
+  if (list.empty()) return LBM_OK;
+  if (!cp || cap < *n) return h->fail(LBM_EINVAL, "output holds fewer values than boundary nodes");
+  if (nodes) std::memcpy(nodes, list.data(), list.size() * sizeof(int32_t));
+  // Scratch in the idle state buffer, which the next step overwrites anyway.
+  const size_t off_out = align256(list.size() * sizeof(int32_t));
+  if (off_out + list.size() * sizeof(double) > h->buf_bytes())
+    return h->fail(LBM_ENOMEM, "boundary node list larger than the scratch buffer");
+  char* scr = static_cast<char*>(h->buf(1 - h->cur));
+  hipError_t e = hipMemcpyAsync(scr, list.data(), list.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, h->stream);
+  CpArgs a{};
+  a.state = h->buf(h->cur);
+  a.plane = h->plane;
+  a.pitch = h->pitch;
+  a.nx = nx;
+  a.nodes = reinterpret_cast<const int32_t*>(scr);
+  a.n = int32_t(list.size());
+  a.ref_node = ref;
+  a.p_ref = h->g.rho_ref * (1.0 / 3.0);
+  a.q = 0.5 * h->g.rho_ref * h->g.u_ref * h->g.u_ref;
+  a.out = reinterpret_cast<double*>(scr + off_out);
+  if (e == hipSuccess) e = launch_boundary_cp(h->g.precision, a, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cp, a.out, list.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return h->hip_fail(e, "boundary pressure coefficient");
+  return LBM_OK;
+}
+
 int lbm_reset(lbm_t* h) {
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");

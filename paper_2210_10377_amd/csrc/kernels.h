@@ -120,7 +120,23 @@ struct RemaskArgs {
   double* block_out;      // [blocks][2] covered minus refilled momentum of each block
 };
 
+// Pressure coefficient at listed nodes of a state buffer (see launch_boundary_cp).
+struct CpArgs {
+  const void* state;      // current state buffer (stored populations)
+  int64_t plane;          // elements between the directions of a node
+  int32_t pitch, nx;
+  const int32_t* nodes;   // [n] y * nx + x
+  int32_t n;
+  int32_t ref_node;       // y * nx + x of the reference node, or -1
+  double p_ref;           // reference pressure when ref_node < 0
+  double q;               // dynamic pressure rho_ref u_ref^2 / 2
+  double* out;            // [n]
+};
+
 hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_t s);
+// C_p = (rho/3 - p_inf) / q at every listed node, rho the sum of the node's stored
+// populations in binary64, p_inf = rho/3 of the reference node (or p_ref).
+hipError_t launch_boundary_cp(int precision, const CpArgs& a, hipStream_t s);
 // Refill the uncovered nodes and sum, in a fixed order, the momentum of the covered
 // ones minus that of the refilled ones into out[2] (block_out as scratch).
 hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double* out,

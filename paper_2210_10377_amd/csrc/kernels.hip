@@ -528,6 +528,27 @@ __global__ __launch_bounds__(kThreads) void remask_sum_kernel(const double* bloc
   if (threadIdx.x < 2) res[threadIdx.x] = out[threadIdx.x];
 }
 
+// Boundary pressure coefficient (Sec. V, the C_p equation: over the boundary fluid
+// nodes, no extrapolation), one thread per listed node: p = rho theta0 with rho the sum
+// of the stored populations (binary64), p_inf the same at the reference node.
+template <int P>
+__global__ __launch_bounds__(kThreads) void boundary_cp_kernel(CpArgs a) {
+  using T = typename Storage<P>::T;
+  const T* st = static_cast<const T*>(a.state);
+  auto density = [&](int32_t node) {
+    const int y = node / a.nx, x = node - y * a.nx;
+    const int64_t at = int64_t(y) * a.pitch + x;
+    double rho = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) rho += to_f64<P>(st[i * a.plane + at], i);
+    return rho;
+  };
+  const int k = int(blockIdx.x) * kThreads + int(threadIdx.x);
+  if (k >= a.n) return;
+  const double p_inf = a.ref_node >= 0 ? density(a.ref_node) * (1.0 / 3.0) : a.p_ref;
+  a.out[k] = (density(a.nodes[k]) * (1.0 / 3.0) - p_inf) / a.q;
+}
+
 template <int P, bool BUF, int COLL>
 hipError_t step_dispatch3(bool forces, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.ntiles + (a.red_in ? 1 : 0));
@@ -686,6 +707,24 @@ hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double*
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(remask_sum_kernel, dim3(1), dim3(kThreads), 0, s,
                      static_cast<const double*>(a.block_out), blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary_cp(int precision, const CpArgs& a, hipStream_t s) {
+  const dim3 grid((a.n + kThreads - 1) / kThreads);
+  switch (precision) {
+    case LBM_FP64:
+      hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP64>, grid, dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32:
+      hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP32>, grid, dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP32DEV:
+      hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP32DEV>, grid, dim3(kThreads), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP16DEV>, grid, dim3(kThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -197,6 +197,22 @@ class Sim:
     def reset(self) -> None:
         C.check(self._lib.lbm_reset(self._h), self._h)
 
+    def boundary_cp(self, ref=None):
+        """Pressure coefficient (p - p_inf) / (rho_ref u_ref^2 / 2) at every boundary fluid
+        node of the current state, p = rho/3; p_inf at the reference node ref = (x, y)
+        (far upstream), or rho_ref/3 when ref is None.  Returns (node indices y*nx + x
+        as int32 [n], C_p float64 [n]), nodes in row-major order."""
+        x, y = (-1, -1) if ref is None else (int(ref[0]), int(ref[1]))
+        n = ctypes.c_int64()
+        ip = ctypes.POINTER(ctypes.c_int32)
+        k = self.info().n_links  # every boundary node has a link: an upper bound
+        cp = np.zeros(max(k, 1))
+        nodes = np.zeros(max(k, 1), np.int32)
+        C.check(self._lib.lbm_boundary_cp(self._h, x, y, cp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          nodes.ctypes.data_as(ip), max(k, 1), ctypes.byref(n)),
+                self._h)
+        return nodes[:n.value], cp[:n.value]
+
     # -- adjoint ----------------------------------------------------------------------
     def adjoint_forward(self, n_steps: int, every: int, t0: int, T: int, w=(1.0, 0.0)) -> float:
         """Run n_steps from the current state with checkpoints every `every` steps and

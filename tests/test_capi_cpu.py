@@ -369,3 +369,16 @@ def test_auto_layout_falls_back_to_planes_beyond_32bit_offsets():
     p = Plan(m, 0.8, np.full(8000, 0.01), precision="fp16dev")
     inf = p.info()
     assert inf.pitch == 30016 + 128 and inf.plane_stride >= inf.pitch * 8000
+
+
+def test_boundary_cp_validation(capi):
+    """lbm_boundary_cp refuses an unbound handle (no device work) before anything else."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    mask = workloads.cylinder_mask(40, 20, 10, 9.5, 3)
+    p = Plan(mask, uin=0.05)
+    n = ctypes.c_int64(-7)
+    cp = np.zeros(64)
+    rc = L.lbm_boundary_cp(p._h, 1, 9, cp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
+                           64, ctypes.byref(n))
+    assert rc == capi.LBM_ESTATE and b"bound" in L.lbm_last_error(p._h)

@@ -367,6 +367,17 @@ def test_full_size_naca_one_step(precision):
              "fp32dev": np.array([1e-5, 1e-5, 1e-3, 1e-4, 1e-5])}[precision]
     print(precision, "full-size population error", err, "force errors", e)
     assert np.all(e <= tol_f), e
+    # Boundary pressure coefficient (Sec. V) over every boundary fluid node, p_inf far
+    # upstream (q = 1/2 here): FP64 to 1e-10 of the largest value; otherwise C_p differs
+    # by the density errors of the node and of the reference node, each at most
+    # tol_pop rho (rho < 1.1), scaled by 1 / (3 q).
+    ref = (100, w.ny // 2)
+    ng, cg = g.boundary_cp(ref)
+    no, co = o.boundary_cp(ref, rho_ref=1.0, u_ref=1.0)
+    assert np.array_equal(ng, no) and len(ng) > 1000
+    tol_cp = 1e-10 * np.abs(co).max() if precision == "fp64" else 2 * tol_pop * 1.1 / 3 / 0.5
+    print(precision, "full-size C_p max abs error", np.abs(cg - co).max(), "bound", tol_cp)
+    assert np.abs(cg - co).max() <= tol_cp
 
 
 def test_state_buffers_beyond_4gib_take_64bit_addressing():

@@ -1265,3 +1265,118 @@ def test_drtt_equals_mea_b_with_a_translating_body(orc):
     # the fluid ahead of the body is pushed: the fluid hands momentum to the body
     # (covered fluid moves slower than the refilled wake) with a nonzero impulse
     assert all(np.abs(i).max() > 0 for i in imps)
+
+
+@pytest.mark.parametrize("threads", [2, 5])
+def test_row_parallel_oracle_is_bitwise_serial(orc, threads):
+    """The oracle's row loops may run on several threads; every force sum is still
+    formed in the serial order, so states, records and forces are bitwise the same as
+    with one thread (cylinder channel with inlet, outlet, walls and a box; complex
+    arithmetic too)."""
+    w = workloads.cylinder_channel_200x80()
+    outs = []
+    for n in (1, threads):
+        old = orc.set_threads(n)
+        try:
+            s = OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box)
+            s.set_state(workloads.near_rest_state(w.nx, w.ny, seed=4, amp=0.03))
+            s.step(30)
+            J = orc.objective(w.mask, 1 / complex(w.tau, 1e-30), w.uin, 20, 10, 10, w=(1.0, 0.5))
+            outs.append((s.state(), s.records(), s.forces(), J))
+        finally:
+            orc.set_threads(old)
+    a, b = outs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2], equal_nan=True) and a[3] == b[3]
+
+
+# --------------------------------------------------------------------------------------
+# Boundary pressure coefficient (Sec. V, the C_p equation)
+# --------------------------------------------------------------------------------------
+
+def _brute_boundary_nodes(mask, periodic_x=False, periodic_y=False):
+    """Fluid nodes with a solid node among their eight lattice neighbours (a wrapped
+    neighbour across a periodic edge counts), row-major."""
+    ny, nx = mask.shape
+    out = []
+    for y in range(ny):
+        for x in range(nx):
+            if mask[y, x]:
+                continue
+            hit = False
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if dx == 0 and dy == 0:
+                        continue
+                    tx, ty = x + dx, y + dy
+                    if periodic_x:
+                        tx %= nx
+                    if periodic_y:
+                        ty %= ny
+                    if 0 <= tx < nx and 0 <= ty < ny and mask[ty, tx]:
+                        hit = True
+            if hit:
+                out.append(y * nx + x)
+    return out
+
+
+def test_boundary_cp_rest_state_is_zero(orc):
+    """At rest (f = w_i, p = theta0 everywhere) C_p vanishes at every boundary fluid node,
+    with p_inf sampled at a reference node or taken as rho_ref theta0."""
+    w = workloads.cylinder_channel_200x80()
+    s = OracleSim(w.mask, tau=w.tau, uin=w.uin)
+    for ref in ((5, 40), None):
+        nodes, cp = s.boundary_cp(ref, rho_ref=1.0, u_ref=0.05)
+        assert nodes.tolist() == _brute_boundary_nodes(w.mask)
+        if ref is not None:
+            assert np.all(cp == 0.0)   # the same sum of w_i on both sides
+        else:
+            # sum w_i = 1 up to its rounding (9 terms): |C_p| <= theta0 9 2^-53 / (U^2/2)
+            assert np.abs(cp).max() <= 9 * 2.0 ** -53 / 3 / (0.5 * 0.05 ** 2)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_boundary_cp_linear_density_closed_form(orc, periodic):
+    """A linear density field rho = 1 + a x + b y at rest (f = w_i rho): at a boundary
+    fluid node C_p = theta0 (a (x - x_inf) + b (y - y_inf)) / (rho_ref U^2 / 2); the
+    boundary nodes are the fluid nodes next to the body (brute-force enumeration)."""
+    nx, ny = 48, 30
+    mask = workloads.cylinder_mask(nx, ny, 23.5, 14.0, 6.0)
+    mask[0:3, 40:44] = 1          # a second body on the first rows: wraps when periodic
+    bc = BCX_PERIODIC if periodic else BCX_INLET_OUTLET
+    bcy = BCY_PERIODIC if periodic else BCY_WALL
+    s = OracleSim(mask, tau=0.8, uin=None if periodic else np.full(ny, 0.02), bc_x=bc, bc_y=bcy)
+    _, _, _, wts, th = orc.lattice()
+    a, b = 3e-4, -2e-4
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    rho = 1.0 + a * xx + b * yy
+    s.set_state(wts[:, None, None] * rho[None])
+    rho_ref, U, ref = 1.2, 0.04, (2, 20)
+    nodes, cp = s.boundary_cp(ref, rho_ref=rho_ref, u_ref=U)
+    assert nodes.tolist() == _brute_boundary_nodes(mask, periodic, periodic)
+    y, x = nodes // nx, nodes % nx
+    want = th * (a * (x - ref[0]) + b * (y - ref[1])) / (0.5 * rho_ref * U * U)
+    np.testing.assert_allclose(cp, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    nodes2, cp2 = s.boundary_cp(None, rho_ref=rho_ref, u_ref=U)
+    want2 = th * (rho[y, x] - rho_ref) / (0.5 * rho_ref * U * U)
+    np.testing.assert_allclose(cp2, want2, rtol=0, atol=1e-12 * np.abs(want2).max())
+    with pytest.raises(ValueError):
+        s.boundary_cp((23, 14), rho_ref=1.0, u_ref=U)   # solid reference node
+
+
+def test_boundary_cp_symmetric_cylinder_is_mirror_symmetric(orc):
+    """A cylinder on the centreline of a walled channel with a uniform inlet: the flow is
+    mirror symmetric about the centreline, so C_p(x, y) = C_p(x, ny - 1 - y); the front
+    stagnation node carries the largest C_p, positive, and the flanks negative values."""
+    nx, ny = 120, 41
+    mask = workloads.cylinder_mask(nx, ny, 30, 20, 6)
+    s = OracleSim(mask, tau=0.8, uin=np.full(ny, 0.04))
+    s.step(600)
+    nodes, cp = s.boundary_cp((3, 20), rho_ref=1.0, u_ref=0.04)
+    y, x = nodes // nx, nodes % nx
+    val = dict(zip(zip(x.tolist(), y.tolist()), cp.tolist()))
+    for (xi, yi), c in val.items():
+        assert abs(c - val[(xi, ny - 1 - yi)]) <= 1e-10 * np.abs(cp).max()
+    front = val[(23, 20)]
+    assert front == max(val.values()) and front > 0.5
+    assert val[(30, 13)] < 0 and val[(30, 27)] < 0
