@@ -174,6 +174,64 @@ def resolution_sweep(diameters, t_conv: float, precision: str):
     print(json.dumps(summary), flush=True)
 
 
+def cp_cylinder(d: int, t_conv: float, window: float, precision: str):
+    """Pressure coefficient around a circular cylinder at Re 100 (Sec. V, the C_p
+    equation and Fig. cp_cylinder (a): over the boundary fluid nodes, no extrapolation),
+    channel 60 D x 5 D, cylinder 15 D from the inlet, uniform inlet 0.05, walls.  After
+    t_conv convective times from rest, C_p is sampled every 50 steps over the last
+    `window` convective times and averaged; p_inf is sampled far upstream, on the
+    centreline 10 D ahead of the cylinder.  theta is the angle from the front
+    stagnation point (upstream), counted towards the upper side.  One JSON line per
+    15-degree bin (upper and lower halves folded), then a summary."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    u, re = 0.05, 100.0
+    nx, ny = 60 * d, 5 * d
+    xc, yc = 15 * d, (ny - 1) / 2.0
+    mask = workloads.cylinder_mask(nx, ny, xc, yc, d / 2.0)
+    tau = workloads.tau_from_re(u, d, re)
+    steps = int(round(t_conv * d / u))
+    nwin = int(round(window * d / u)) // 50 * 50
+    sim = Sim(mask, tau, workloads.uniform_inlet(ny, u), precision=precision, max_record=8,
+              u_ref=u, l_ref=float(d))
+    ref = (5 * d, ny // 2)
+    sim.step(steps - nwin, schemes=())
+    acc, k = None, 0
+    lo = hi = None
+    for _ in range(nwin // 50):
+        sim.step(50, schemes=())
+        nodes, cp = sim.boundary_cp(ref)
+        acc = cp.copy() if acc is None else acc + cp
+        lo = cp.copy() if lo is None else np.minimum(lo, cp)
+        hi = cp.copy() if hi is None else np.maximum(hi, cp)
+        k += 1
+    cp_mean = acc / k
+    y, x = nodes // nx, nodes % nx
+    theta = np.degrees(np.arctan2(np.abs(y - yc), -(x - xc)))
+    rows = []
+    for b0 in range(0, 180, 15):
+        sel = (theta >= b0) & (theta < b0 + 15) if b0 < 165 else (theta >= b0)
+        if not sel.any():
+            continue
+        row = {"theta_deg": [b0, b0 + 15], "nodes": int(sel.sum()),
+               "cp_mean": round(float(cp_mean[sel].mean()), 4),
+               "cp_min": round(float(lo[sel].min()), 4), "cp_max": round(float(hi[sel].max()), 4)}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    front = int(np.argmin(theta))
+    print(json.dumps({"cp_cylinder": f"Re 100, D = {d}, channel {nx}x{ny}", "storage": precision,
+                      "tau": tau, "steps": steps, "window_steps": nwin, "samples": k,
+                      "boundary_nodes": int(len(nodes)), "p_inf_node": list(ref),
+                      "cp_front_stagnation": round(float(cp_mean[front]), 4),
+                      "cp_min_mean": round(float(cp_mean.min()), 4),
+                      "theta_of_cp_min_deg": round(float(theta[np.argmin(cp_mean)]), 1),
+                      "cp_base_mean": round(float(cp_mean[theta >= 170].mean()), 4)}),
+          flush=True)
+
+
 def _richardson(rows, names, key="cd_mean"):
     """c(D) = c_inf + a D^-p through the three finest grids, per estimator; each grid's
     relative error against that limit."""
@@ -702,6 +760,13 @@ def main():
                          "2000) stepped together; autotuned schedule; batched MLUPS beside "
                          "the instances stepped one by one and the FP64 batch")
     ap.add_argument("--seq-steps", type=int, default=50)
+    ap.add_argument("--cp-cylinder", action="store_true",
+                    help="time-averaged C_p around a cylinder at Re 100 (D = --cp-diameter, "
+                         "channel 60D x 5D), binned by the angle from the front stagnation "
+                         "point")
+    ap.add_argument("--cp-diameter", type=int, default=15)
+    ap.add_argument("--cp-window", type=float, default=40.0,
+                    help="convective times averaged at the end of the --convective-times run")
     ap.add_argument("--resolution-sweep", action="store_true",
                     help="cylinder at Re 100 in a 60D x 5D channel for D in --diameters: "
                          "mean drag of A, B, DRTT and SI against points per diameter, with "
@@ -789,6 +854,9 @@ def main():
                       args.warmup if args.warmup != 200 else 50, args.ppc,
                       args.re if args.re != 1e4 else 200.0, not args.no_cpu_baseline,
                       args.collision if args.collision != "kbc" else "bgk", args.layout)
+        return
+    if args.cp_cylinder:
+        cp_cylinder(args.cp_diameter, args.convective_times, args.cp_window, args.precision)
         return
     if args.resolution_sweep:
         resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,
