@@ -204,6 +204,34 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream);
  * LBM_EINVAL for n < 0 or unknown scheme bits. */
 int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_step on two caller-owned state
+ * buffers, with every other device buffer the step needs (pull codes, strip slots,
+ * inlet profile, body motion, force partials, force rows) in a static device array of
+ * the library, LBM_STATIC_SCRATCH_BYTES per GPU, held by each GPU from the first call on
+ * it until the process ends.  The call allocates no device memory.
+ *   buf0, buf1: distinct 256-byte aligned device buffers of buf_bytes >= one state of the
+ *     handle each (the state layout of the handle's workspace, see lbm_info: population
+ *     i of (x, y) at i * plane_stride + y * pitch + x, elem_bytes each, in a buffer of
+ *     max(9 plane_stride, ny pitch) elements).  buf0 holds the current state on entry;
+ *     step k reads one buffer and writes the other, so after the call the state is in
+ *     buf0 when n is even and in buf1 when n is odd.
+ *   n >= 0 steps, force_scheme as lbm_step; with any scheme bit set and n > 0 the force
+ *     rows of the n steps are written to forces[n][5][2] (host, cap >= n rows) as
+ *     lbm_forces gives them.
+ *   hip_stream: the stream the work is enqueued on (NULL: the null stream); the call
+ *     synchronises it when forces are asked for.
+ * The handle needs no binding; its own state, step count, force ring and adjoint run
+ * are not touched (its geometry, tau, inlet and body motion are used).  Every call on a
+ * GPU shares that GPU's array, which keeps the last call's contents (each call writes
+ * what it reads first); calls that overlap on one GPU race.  LBM_ENOMEM when the grid's
+ * tables and n force rows do not fit the array (about 4 bytes per node plus 112 bytes per
+ * step with forces) or the buffers are smaller than a state; LBM_EINVAL for bad
+ * arguments; LBM_ENONFINITE as lbm_forces. */
+#define LBM_STATIC_SCRATCH_BYTES (32u << 20)
+int lbm_step_static(lbm_t* h, void* buf0, void* buf1, size_t buf_bytes, int32_t n,
+                    uint32_t force_scheme, double* forces, int64_t cap, void* hip_stream);
+
 /* Copy the force rows recorded since the last call into out[k][5][2] (host; scheme
  * order A, B, DRTT, SI, DRTT-post; components x, y) and empty the ring.  At most cap rows are written
  * (LBM_EINVAL if fewer than recorded).  Synchronises the stream.  Returns

@@ -31,7 +31,8 @@ EXPORTS = ("lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_step", "lbm_for
            "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_last_error", "lbm_set_inlet", "lbm_set_tau", "lbm_reset",
            "lbm_adjoint_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
-           "lbm_set_body_motion", "lbm_set_mask", "lbm_boundary_cp", "lbm_batch_create", "lbm_batch_workspace_bytes", "lbm_batch_bind",
+           "lbm_set_body_motion", "lbm_set_mask", "lbm_boundary_cp", "lbm_step_static",
+           "lbm_batch_create", "lbm_batch_workspace_bytes", "lbm_batch_bind",
            "lbm_batch_set_schedule", "lbm_batch_autotune", "lbm_batch_step",
            "lbm_batch_forces", "lbm_batch_get_info", "lbm_batch_destroy",
            "lbm_batch_last_error")
@@ -136,6 +137,7 @@ def load():
     L.lbm_set_tau.argtypes = [vp, ctypes.c_double]
     L.lbm_reset.argtypes = [vp]
     L.lbm_boundary_cp.argtypes = [vp, i32, i32, dp, ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    L.lbm_step_static.argtypes = [vp, vp, vp, sz, i32, u32, dp, i64, vp]
     L.lbm_set_body_motion.argtypes = [vp] + [ctypes.c_double] * 5
     L.lbm_set_mask.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(i32), dp]
     L.lbm_adjoint_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["api.hip", "batch.hip", "kernels.hip", "adjoint.hip", "plan.cpp", "api3.hip",
-           "kernels3.hip", "plan3.cpp"]
+           "kernels3.hip", "plan3.cpp", "noalloc.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -220,7 +220,21 @@ int lbm_bind(lbm_t* h, void* device_workspace, size_t bytes, void* hip_stream) {
 
 namespace lbm {
 
-StepArgs step_args(const lbm_t* h) {
+DevTables ws_tables(const lbm_t* h) {
+  DevTables t{};
+  t.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
+  t.strip_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
+  t.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  t.motion = h->motion_dev();
+  t.part[0] = h->part(0);
+  t.part[1] = h->part(1);
+  t.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+  return t;
+}
+
+StepArgs step_args(const lbm_t* h) { return step_args(h, ws_tables(h)); }
+
+StepArgs step_args(const lbm_t* h, const DevTables& t) {
   const Plan& p = h->plan;
   StepArgs a{};
   a.plane = h->plane;
@@ -247,11 +261,11 @@ StepArgs step_args(const lbm_t* h) {
     a.by0 = 1;
     a.by1 = 0;
   }
-  a.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
-  a.strip_slot = reinterpret_cast<const int32_t*>(h->ws + h->off_tiles);
-  a.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  a.node = t.node;
+  a.strip_slot = t.strip_slot;
+  a.uin = t.uin;
   a.rho_w6 = 6.0 * h->rho_w;
-  a.motion = h->motion_dev();
+  a.motion = t.motion;
   a.omega = h->omega;
   a.collision = h->g.collision;
   a.nslots = p.nslots;
@@ -277,7 +291,9 @@ bool row_forces(const double* r, uint32_t sch, bool has_box, double* o) {
   return finite;
 }
 
-BoxArgs box_args(const lbm_t* h, const void* src) {
+BoxArgs box_args(const lbm_t* h, const void* src) { return box_args(h, src, ws_tables(h)); }
+
+BoxArgs box_args(const lbm_t* h, const void* src, const DevTables& t) {
   const Plan& p = h->plan;
   BoxArgs b{};
   b.src = src;
@@ -291,11 +307,11 @@ BoxArgs box_args(const lbm_t* h, const void* src) {
   b.by0 = p.box[2];
   b.by1 = p.box[3];
   b.box_bx = p.box_bx;
-  b.node = reinterpret_cast<const uint32_t*>(h->ws + h->off_node);
-  b.uin = reinterpret_cast<const double*>(h->ws + h->off_uin);
+  b.node = t.node;
+  b.uin = t.uin;
   b.rho_w6 = 6.0 * h->rho_w;
-  b.motion = h->motion_dev();
-  b.jpart = reinterpret_cast<double*>(h->ws + h->off_jpart);
+  b.motion = t.motion;
+  b.jpart = t.jpart;
   return b;
 }
 
@@ -307,43 +323,44 @@ namespace {
 // non-null ring, the force row of step k goes to ring row k (rows are self-contained:
 // the J of the following step, or of the pull after the last one, is stored with it).
 template <class IO>
-int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
+int enqueue_steps(lbm_t* h, const DevTables& t, hipStream_t stream, int32_t n, double* ring,
+                  IO&& io) {
   const Plan& p = h->plan;
   const bool forces = ring != nullptr;
-  StepArgs a = step_args(h);
+  StepArgs a = step_args(h, t);
   const void* last = nullptr;
   for (int32_t k = 0; k < n; ++k) {
     const auto sd = io(k);
     a.src = sd.first;
     a.dst = sd.second;
     last = sd.second;
-    a.part_out = forces ? h->part(k & 1) : nullptr;
+    a.part_out = forces ? t.part[k & 1] : nullptr;
     a.red_in = nullptr;
     a.red_row = nullptr;
     a.red_prev_jnext = nullptr;
     if (forces && k >= 1) {
-      a.red_in = h->part((k - 1) & 1);
+      a.red_in = t.part[(k - 1) & 1];
       a.red_row = ring + int64_t(k - 1) * kRow;
       a.red_prev_jnext = k >= 2 ? ring + int64_t(k - 2) * kRow + kJnext : nullptr;
     }
-    hipError_t e = launch_step(h->g.precision, forces, a, h->stream);
+    hipError_t e = launch_step(h->g.precision, forces, a, stream);
     if (e != hipSuccess) return h->hip_fail(e, "launch step");
   }
   if (forces) {
     if (p.has_box) {
-      const BoxArgs b = box_args(h, last);
-      hipError_t e = launch_box_momentum(h->g.precision, b, h->njblocks, h->stream);
+      const BoxArgs b = box_args(h, last, t);
+      hipError_t e = launch_box_momentum(h->g.precision, b, h->njblocks, stream);
       if (e != hipSuccess) return h->hip_fail(e, "launch box momentum");
     }
     FinalArgs f{};
-    f.red_in = h->part((n - 1) & 1);
+    f.red_in = t.part[(n - 1) & 1];
     f.nslots = p.nslots;
     f.njslots = p.njslots;
     f.row = ring + int64_t(n - 1) * kRow;
     f.prev_jnext = n >= 2 ? ring + int64_t(n - 2) * kRow + kJnext : nullptr;
-    f.jpart = p.has_box ? reinterpret_cast<const double*>(h->ws + h->off_jpart) : nullptr;
+    f.jpart = p.has_box ? t.jpart : nullptr;
     f.njblocks = h->njblocks;
-    hipError_t e = launch_finalize(f, h->stream);
+    hipError_t e = launch_finalize(f, stream);
     if (e != hipSuccess) return h->hip_fail(e, "launch finalize");
   }
   return LBM_OK;
@@ -352,7 +369,7 @@ int enqueue_steps(lbm_t* h, int32_t n, double* ring, IO&& io) {
 // n steps on the handle's own ping-pong state buffers.
 int enqueue_own_steps(lbm_t* h, int32_t n, double* ring) {
   const int c0 = h->cur;
-  const int rc = enqueue_steps(h, n, ring, [&](int32_t k) {
+  const int rc = enqueue_steps(h, ws_tables(h), h->stream, n, ring, [&](int32_t k) {
     const int s = (c0 + k) & 1;
     return std::pair<const void*, void*>(h->buf(s), h->buf(1 - s));
   });
@@ -364,6 +381,17 @@ int enqueue_own_steps(lbm_t* h, int32_t n, double* ring) {
 }
 
 }  // namespace
+
+namespace lbm {
+
+int enqueue_pingpong(lbm_t* h, const DevTables& t, void* b0, void* b1, hipStream_t stream,
+                     int32_t n, double* ring) {
+  return enqueue_steps(h, t, stream, n, ring, [&](int32_t k) {
+    return (k & 1) ? std::pair<const void*, void*>(b1, b0) : std::pair<const void*, void*>(b0, b1);
+  });
+}
+
+}  // namespace lbm
 
 extern "C" {
 
@@ -943,7 +971,7 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
                     : static_cast<void*>(aws + L.off_seg + size_t(j - 1) * align256(L.state));
     };
     if (len > 1) {
-      const int rc = enqueue_steps(h, len - 1, nullptr, [&](int32_t k) {
+      const int rc = enqueue_steps(h, ws_tables(h), h->stream, len - 1, nullptr, [&](int32_t k) {
         return std::pair<const void*, void*>(seg(k), seg(k + 1));
       });
       if (rc != LBM_OK) return rc;

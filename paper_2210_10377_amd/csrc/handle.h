@@ -82,10 +82,30 @@ struct lbm_t {
 
 namespace lbm {
 
+// Device tables a step reads besides the state buffers, and the force scratch it writes:
+// in the handle's workspace (ws_tables), or elsewhere (the static scratch of the
+// allocation-free entry point).
+struct DevTables {
+  const uint32_t* node;        // per-node pull codes
+  const int32_t* strip_slot;   // per-strip force slots
+  const double* uin;           // [ny] inlet profile
+  const BodyMotion* motion;    // body motion (device), or null at rest
+  double* part[2];             // force partials of alternate steps
+  double* jpart;               // box-sweep partials
+};
+DevTables ws_tables(const lbm_t* h);
+
 // Kernel arguments of the handle's step (src, dst and the force buffers unset).
 StepArgs step_args(const lbm_t* h);
+StepArgs step_args(const lbm_t* h, const DevTables& t);
 // Control-volume sweep arguments of the handle over the state `src`.
 BoxArgs box_args(const lbm_t* h, const void* src);
+BoxArgs box_args(const lbm_t* h, const void* src, const DevTables& t);
+// Enqueue n >= 1 steps alternating between two state buffers (step k reads b[k & 1]
+// and writes the other) with the tables t; with a non-null ring, step k's force row
+// goes to ring row k.  Leaves the handle's own buffers and counters alone.
+int enqueue_pingpong(lbm_t* h, const DevTables& t, void* b0, void* b1, hipStream_t stream,
+                     int32_t n, double* ring);
 // One ring row -> forces [A, B, DRTT, SI, DRTT-post][x, y] (NaN for schemes not
 // recorded, and for the DRTT forms without a control volume); returns false if a
 // recorded force is not finite.

@@ -382,3 +382,25 @@ def test_boundary_cp_validation(capi):
     rc = L.lbm_boundary_cp(p._h, 1, 9, cp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
                            64, ctypes.byref(n))
     assert rc == capi.LBM_ESTATE and b"bound" in L.lbm_last_error(p._h)
+
+
+def test_static_step_validation_without_device(capi):
+    """lbm_step_static checks its arguments and the size of the static scratch before any
+    device call: a grid whose pull codes alone exceed LBM_STATIC_SCRATCH_BYTES is
+    refused with LBM_ENOMEM, bad buffers and a short force output with LBM_EINVAL."""
+    from paper_2210_10377_amd import Plan
+    L = capi.load()
+    big = Plan(np.zeros((2048, 4096), np.uint8), bc_x=capi.LBM_BCX_PERIODIC,
+               bc_y=capi.LBM_BCY_PERIODIC)
+    F = np.zeros((4, 5, 2))
+    fp = F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    vp = ctypes.c_void_p
+    rc = L.lbm_step_static(big._h, vp(256), vp(512), 1 << 40, 1, 0, None, 0, None)
+    assert rc == capi.LBM_ENOMEM and b"static scratch" in L.lbm_last_error(big._h)
+    small = Plan(workloads.cylinder_mask(40, 20, 10, 9.5, 3), uin=0.05)
+    assert L.lbm_step_static(small._h, vp(256), vp(256), 1 << 20, 1, 0, None, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_step_static(small._h, vp(256), vp(300), 1 << 20, 1, 0, None, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_step_static(small._h, vp(256), vp(512), 16, 1, 0, None, 0, None) == capi.LBM_ENOMEM
+    assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, 5, 2, fp, 4, None) == capi.LBM_EINVAL
+    assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, -1, 0, None, 0, None) == capi.LBM_EINVAL
+    assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, 0, 2, None, 0, None) == capi.LBM_OK
