@@ -60,21 +60,67 @@ def measured_traffic(workload: str, precision: str, three_d: bool = False):
     return rec["hbm_bytes_per_launch"]
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use: the CPUs this process may run on, at most 16 (the
+    host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(w, steps: int, collision: str = "bgk", body_motion=None):
-    """The oracle (plain FP64 C++, one thread) on a bounded sample of the same workload:
-    `steps` full-grid time steps with all four forces."""
+    """The oracle (plain FP64 C++) on a bounded sample of the same workload: `steps`
+    full-grid time steps with all five force estimators, from the same initial state,
+    once on one thread and once on every available host thread (row loops in parallel;
+    the sums keep their serial order, so both give bitwise the same numbers).  `value` is
+    the all-thread rate; the one-thread rate is reported beside it."""
     import oracle
-    o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision,
-                         body_motion=body_motion)
-    t0 = time.perf_counter()
-    o.step(steps)
-    o.forces()
-    dt = time.perf_counter() - t0
-    del o
-    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} full-grid steps of {w.nx}x{w.ny} with A, B, DRTT and SI forces "
-                      f"({dt:.1f} s, FP64, one thread)"}
+
+    def run(threads):
+        oracle.set_threads(threads)
+        o = oracle.OracleSim(w.mask, tau=w.tau, uin=w.uin, box=w.box, collision=collision,
+                             body_motion=body_motion)
+        t0 = time.perf_counter()
+        o.step(steps)
+        o.forces()
+        dt = time.perf_counter() - t0
+        del o
+        return dt
+
+    n = host_threads()
+    dt1 = run(1)
+    dtn = run(n) if n > 1 else dt1
+    oracle.set_threads(1)
+    rate = lambda dt: round(w.nx * w.ny * steps / dt / 1e6, 3)
+    return {"value": rate(dtn), "unit": "MLUPS", "cores": n, "kind": "oracle",
+            "one_core_value": rate(dt1), "cpu_model": host_cpu_model(),
+            "sample": f"{steps} full-grid steps of {w.nx}x{w.ny} from rest with the A, B, "
+                      f"DRTT, SI and DRTT-post forces, FP64 ({dtn:.1f} s on {n} threads, "
+                      f"{dt1:.1f} s on one)"}
+
+
+def uniform_flow_state(w):
+    """[9, ny, nx] equilibrium populations of density 1 and velocity (u_in(y), 0) at every
+    node (the second-order equilibrium with weights 4/9, 1/9, 1/36)."""
+    import numpy as np
+    wts = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+    u = np.asarray(w.uin, np.float64)[None, :]
+    cu = cx[:, None] * u
+    feq_y = wts[:, None] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u * u)   # [9, ny]
+    return np.ascontiguousarray(np.broadcast_to(feq_y[:, :, None], (9, w.ny, w.nx)))
 
 
 def precision_study(steps: int):
@@ -544,14 +590,17 @@ def adjoint_bench(precision: str, large: bool = False):
     s = BYTES_PER_NODE[precision] // 18          # bytes per stored population
     s_adj = 8 if precision == "fp64" else 4      # bytes per adjoint value
     fwd_bytes = fluid * 18 * s * n               # the forward run (checkpoint copies aside)
-    bwd_bytes = fluid * (27 * s + 18 * s_adj) * n  # recompute (2Qs) + adjoint kernel (Qs + 2Q s_adj)
+    # Backward: each segment of len steps recomputes len - 1 of them (2 Q s per node),
+    # n - ceil(n / every) in all; the reverse kernel runs every step (Q s + 2 Q s_adj).
+    recomputed = n - (n + every - 1) // every
+    bwd_bytes = fluid * (18 * s * recomputed + (9 * s + 18 * s_adj) * n)
     print(json.dumps({
         "metric": "adjoint MLUPS", "workload": w.name, "storage": precision, "steps": n,
         "developed_steps": develop,
         "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "forward_achieved": round(fwd_bytes / t_f / 1e9, 1),
                      "backward_achieved": round(bwd_bytes / t_b / 1e9, 1),
-                     "backward_bytes_per_node_step": 27 * s + 18 * s_adj,
+                     "backward_bytes_per_node_step": round(bwd_bytes / fluid / n, 2),
                      "backward_frac": round(bwd_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4)},
         "checkpoint_every": every, "J_mean_drag": J, "dJ_dtau": gt,
         "dJ_duin_norm": float((gu ** 2).sum() ** 0.5),
@@ -735,13 +784,15 @@ def main():
     ap.add_argument("--workload", default="naca8192", choices=["naca8192", "naca2048", "cyl200"])
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--aoa", type=float, default=4.0)
-    ap.add_argument("--schemes", default="A,B,DRTT,SI")
+    ap.add_argument("--schemes", default="A,B,DRTT,SI,DRTT_POST")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "regularized", "kbc"])
     ap.add_argument("--pitch-rate", type=float, default=0.0,
                     help="turn the body at this rate (radians per step, counter-clockwise) "
                          "about its quarter chord (the centroid of a cylinder): the "
                          "moving-wall rule on every body link")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--from-rest", action="store_true",
+                    help="start the timed workload from rest (default: the uniform inlet flow)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32 and FP16-deviation storage against FP64 on the NACA0012 "
@@ -886,6 +937,10 @@ def main():
         motion = (0.0, 0.0, args.pitch_rate, xc, yc)
         sim.set_body_motion(*motion)
     info = sim.info()
+    if not args.from_rest:
+        # Impulsive start: every node at the equilibrium of the inlet flow (rho = 1,
+        # u = (u_in, 0)), so the body carries a physical force from the first step.
+        sim.set_populations(uniform_flow_state(w))
     sim.step(W, schemes)
     sim.forces()
     torch.cuda.synchronize()
@@ -944,9 +999,11 @@ def main():
         "force_cost_frac": round((ms / K - ms_off) / ms_off, 4),
     }
     if len(F):
-        cols = [k for k, s in enumerate(("A", "B", "DRTT", "SI")) if s in schemes]
+        names = ("A", "B", "DRTT", "SI", "DRTT_POST")
+        cols = [k for k, s in enumerate(names) if s in schemes]
         out["forces_finite"] = bool(np.all(np.isfinite(F[:, cols])))
-        out["last_coefficients"] = {s: C[-1, k].tolist() for k, s in enumerate(("A", "B", "DRTT", "SI"))
+        out["initial_state"] = "rest" if args.from_rest else "uniform inlet flow (impulsive start)"
+        out["last_coefficients"] = {s: C[-1, k].tolist() for k, s in enumerate(names)
                                     if s in schemes}
     del sim
     torch.cuda.empty_cache()

@@ -11,8 +11,9 @@
 //     moving-wall rule or the outlet ghost copy; strips with force terms accumulate A, B,
 //     J, Phi and SI in FP64 and reduce them over the wave into their slot.
 // The first block of a launch reduces the previous step's slots, in a fixed order, into
-// that step's ring row.  Blocks are mapped to tiles so that runs of 4 neighbouring tiles
-// along x go to one XCD (their +-1-shifted pulls share cache lines in that L2).
+// that step's ring row.  Blocks are mapped to tiles so that runs of kXcdRun (8)
+// neighbouring tiles along x go to one XCD (their +-1-shifted pulls share cache lines in
+// that L2).
 #include <hip/hip_runtime.h>
 
 #include "kernels3.h"
