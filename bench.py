@@ -111,6 +111,60 @@ def cpu_baseline(w, steps: int, collision: str = "bgk", body_motion=None):
                       f"{dt1:.1f} s on one)"}
 
 
+def sensitivity_study(steps: int, seeds: int, every: int = 0, frozen: bool = False):
+    """How far the FP64 path itself moves when perturbed by noise of the size of binary32
+    rounding: the 2048x1024 NACA0012 channel (AoA 4, Re 100 and 1000) from rest; every
+    population is multiplied by (1 + a xi), xi ~ U(-1, 1) seeded, once at step 100 with
+    a = 2^-24 (every = 0), or at every `every`-th step with a = 2^-24 sqrt(every) (the
+    accumulated size of independent per-step rounding, as a 32-bit run rounds every
+    step), or with `frozen` the same pattern xi every time with a = 2^-24 every (a
+    rounding error that recurs with the same sign at each node every step, as at the
+    nodes of a steady flow); the window-mean (last 2000 steps) force coefficients of each
+    perturbed twin against the unperturbed run.  One JSON line per Reynolds number."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    names = ("A", "B", "DRTT", "SI", "DRTT_POST")
+    for re in (100.0, 1000.0):
+        w = workloads.naca_2048x1024(aoa=4.0, re=re)
+
+        def run(seed):
+            sim = Sim(w.mask, w.tau, w.uin, precision="fp64", box=w.box, max_record=steps,
+                      u_ref=w.u_ref, l_ref=w.l_ref)
+            rng = np.random.default_rng(seed)
+            done, F = 0, []
+            marks = [100] if every == 0 else list(range(every, steps, every))
+            amp = 2.0 ** -24 * (1.0 if every == 0 else (every if frozen else np.sqrt(every)))
+            xi0 = None
+            for m in marks + [steps]:
+                sim.step(m - done)
+                F.append(sim.forces())
+                done = m
+                if seed is not None and m < steps:
+                    S = sim.populations()
+                    if xi0 is None or not frozen:
+                        xi0 = rng.uniform(-1.0, 1.0, S.shape)
+                    sim.set_populations(S * (1.0 + amp * xi0))
+            C = sim.coefficients(np.concatenate(F))
+            return C[-2000:].mean(0)
+
+        base = run(None)
+        errs = np.array([np.abs(run(k) - base) / np.abs(base) for k in range(seeds)])
+        out = {"sensitivity": w.name, "storage": "fp64",
+               "perturbation": ("relative 2^-24 at step 100" if every == 0 else
+                                (f"one pattern, relative 2^-24 x {every}, every {every} steps"
+                                 if frozen else
+                                 f"relative 2^-24 sqrt({every}) every {every} steps")),
+               "steps": steps, "twins": seeds,
+               "cd_window_mean": dict(zip(names, base[:, 0].round(6).tolist())),
+               "cl_window_mean": dict(zip(names, base[:, 1].round(6).tolist())),
+               "cd_rel_change_max": dict(zip(names, errs[:, :, 0].max(0).tolist())),
+               "cl_rel_change_max": dict(zip(names, errs[:, :, 1].max(0).tolist()))}
+        print(json.dumps(out), flush=True)
+
+
 def uniform_flow_state(w):
     """[9, ny, nx] equilibrium populations of density 1 and velocity (u_in(y), 0) at every
     node (the second-order equilibrium with weights 4/9, 1/9, 1/36)."""
@@ -154,13 +208,14 @@ def precision_study(steps: int):
                 del sim
             C64, (u64, v64), _ = runs["fp64"]
             fl = w.mask == 0
+            names = ("A", "B", "DRTT", "SI", "DRTT_POST")
             out = {"case": w.name, "steps": steps, "tau": w.tau,
                    "fp64_window_mean": {s: C64[-2000:, k].mean(0).tolist()
-                                        for k, s in enumerate(("A", "B", "DRTT", "SI"))}}
+                                        for k, s in enumerate(names)}}
             for prec in ("fp32", "fp32dev", "fp16dev"):
                 C, (u, v), wall = runs[prec]
                 e = {}
-                for k, s in enumerate(("A", "B", "DRTT", "SI")):
+                for k, s in enumerate(names):
                     scale = np.abs(C64[:, k]).max(0)
                     e[s] = {"step_max_rel_cd_cl": (np.abs(C[:, k] - C64[:, k]).max(0) / scale).tolist(),
                             "window_mean_rel_cd_cl": (np.abs(C[-2000:, k].mean(0) - C64[-2000:, k].mean(0))
@@ -799,6 +854,12 @@ def main():
                          "2048x1024 channel (AoA 0/4/8, Re 100/1000): force, coefficient "
                          "and velocity-field errors; one JSON line per case")
     ap.add_argument("--study-steps", type=int, default=20000)
+    ap.add_argument("--sensitivity", action="store_true",
+                    help="FP64 twins of the precision-study channel perturbed once by "
+                         "binary32-sized noise: the spread of the window-mean coefficients")
+    ap.add_argument("--twins", type=int, default=4)
+    ap.add_argument("--perturb-every", type=int, default=0)
+    ap.add_argument("--frozen", action="store_true")
     ap.add_argument("--adjoint-large", action="store_true",
                     help="adjoint on the 8192x4096 airfoil (chord 1024, AoA 4, Re 1e4): 200 "
                          "steps, checkpoint every 20, mean drag over the last 100")
@@ -870,6 +931,9 @@ def main():
     import workloads
     from paper_2210_10377_amd import Sim
 
+    if args.sensitivity:
+        sensitivity_study(args.study_steps, args.twins, args.perturb_every, args.frozen)
+        return
     if args.precision_study:
         precision_study(args.study_steps)
         return

@@ -1,0 +1,129 @@
+"""The full-size workloads against oracle fixtures (tests/golden/*.npz, written by
+tests/golden/make_fixtures.py from the FP64 oracle alone).
+
+* The precision-study channel (NACA0012, 2048x1024, chord 256, 4 degrees, Re 100 and
+  Re 1000), 20 000 steps from rest: the FP64 path against the oracle's per-step forces
+  and final velocity sample; the 32-bit and FP16-deviation storages against the same
+  fixtures, as the window-mean coefficient errors the design reports.
+* The adjoint workload (NACA0012 1024x512, Re 500, 10 000 steps, mean drag over the last
+  2000, checkpoint every 500): objective and gradient (tau and two inlet directions)
+  against complex-step derivatives through the oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NAMES = ("A", "B", "DRTT", "SI", "DRTT_POST")
+
+
+def _fixture(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"fixture {name}.npz not written (tests/golden/make_fixtures.py)")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-4), ("fp32", 1e-4)])
+def test_adjoint_workload_against_oracle_complex_step(precision, tol):
+    """The adjoint of the 1024x512 workload: J within 1e-12 (FP64) or 1e-4 of the oracle's,
+    dJ/dtau and the directional derivatives within `tol` (relative) of the complex-step
+    values (exact to rounding).  FP64 runs the same map in another order of operations;
+    the 32-bit storages are held to the 1e-4 of the adjoint target."""
+    from paper_2210_10377_amd import Sim
+    z = _fixture("naca1024x512_adjoint")
+    w = workloads.naca_1024x512_adjoint()
+    n, t0, T = int(z["n_steps"]), int(z["t0"]), int(z["T"])
+    g = Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=8)
+    J = g.adjoint_forward(n, 500, t0, T)
+    gu, gt = g.adjoint_backward(1.0)
+    eJ = abs(J - z["J"]) / abs(z["J"])
+    e_tau = abs(gt - z["dJ_dtau"]) / abs(z["dJ_dtau"])
+    e_v = [abs(gu @ z["v"][k] - z["dJ_dv"][k]) / abs(z["dJ_dv"][k]) for k in range(2)]
+    print(precision, "adjoint 1024x512: J rel err", eJ, "dJ/dtau", e_tau, "directions", e_v)
+    assert eJ <= (1e-12 if precision == "fp64" else 1e-4)
+    assert e_tau <= tol and max(e_v) <= tol
+
+
+def _run_channel(w, precision):
+    from paper_2210_10377_amd import Sim
+    g = Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=w.steps,
+            u_ref=w.u_ref, l_ref=w.l_ref)
+    g.step(w.steps)
+    return g, g.forces()
+
+
+def _velocity(S, ys, xs):
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], float)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], float)
+    P = S[:, ys, xs]
+    rho = P.sum(0)
+    return rho, np.tensordot(cx, P, 1) / rho, np.tensordot(cy, P, 1) / rho
+
+
+@pytest.mark.parametrize("re", [100, 1000])
+def test_precision_study_channel_fp64_against_oracle(re):
+    """FP64 over 20 000 steps: every fixture step's five forces within 1e-10 of the
+    largest oracle force of the run, the window means within 1e-10, density and velocity
+    at the sampled nodes within 1e-10 (velocity relative to the inlet speed)."""
+    z = _fixture(f"naca2048x1024_a4_re{re}")
+    w = workloads.naca_2048x1024(aoa=4.0, re=float(re))
+    g, F = _run_channel(w, "fp64")
+    Fz = z["forces"]
+    Fg = F[z["steps"]]
+    for k, name in enumerate(NAMES):
+        scale = np.abs(Fz[:, k]).max()
+        err = np.abs(Fg[:, k] - Fz[:, k]).max() / scale
+        merr = np.abs(F[-2000:, k].mean(0) - z["window_mean"][k]).max() / np.abs(z["window_mean"][k]).max()
+        print(f"re {re} fp64 {name}: step error {err:.2e}, window-mean error {merr:.2e}")
+        assert err <= 1e-10 and merr <= 1e-10, name
+    rho, ux, uy = _velocity(g.populations(), z["sample_y"], z["sample_x"])
+    assert np.abs(rho - z["rho"]).max() <= 1e-10
+    assert max(np.abs(ux - z["ux"]).max(), np.abs(uy - z["uy"]).max()) <= 1e-10 * w.u_ref
+
+
+# Window-mean drag coefficient errors of the reduced storages against the oracle
+# (relative to the oracle's window mean), per estimator A, B, DRTT, SI, DRTT-post.  The
+# 1e-4 target holds for the binary32 deviation storage at both Reynolds numbers and for
+# binary32 populations at Re 100.  Binary32 populations f ~ w_i carry a rounding of about
+# 7.5e-9 absolute that recurs with the same sign at a node of a steady flow step after
+# step, a static forcing of the flow: at Re 1000 it moves the window-mean drag by
+# 3e-5 .. 3e-4 over the three incidences of the precision study (an FP64 run forced
+# by a static random pattern of relative 2^-24 per step moves it by 2e-5 .. 4e-5, an
+# independent pattern each step by 7e-7: bench.py --sensitivity); the deviation storage
+# rounds quantities a hundred times smaller.  Binary16 deviations: 2^-11 relative.
+TOLS = {
+    (100, "fp32"): [1e-4] * 5,
+    (100, "fp32dev"): [1e-4] * 5,
+    (100, "fp16dev"): [1e-1] * 5,
+    (1000, "fp32"): [5e-4, 5e-4, 1e-3, 5e-4, 5e-4],
+    (1000, "fp32dev"): [1e-4] * 5,
+    (1000, "fp16dev"): [1e-2] * 5,
+}
+
+
+@pytest.mark.parametrize("re", [100, 1000])
+@pytest.mark.parametrize("precision", ["fp32", "fp32dev", "fp16dev"])
+def test_precision_study_channel_storages_against_oracle(re, precision):
+    z = _fixture(f"naca2048x1024_a4_re{re}")
+    w = workloads.naca_2048x1024(aoa=4.0, re=float(re))
+    g, F = _run_channel(w, precision)
+    assert np.isfinite(F).all()
+    mean = F[-2000:].mean(0)
+    cd_err = np.abs(mean[:, 0] - z["window_mean"][:, 0]) / np.abs(z["window_mean"][:, 0])
+    cl_err = np.abs(mean[:, 1] - z["window_mean"][:, 1]) / np.abs(z["window_mean"][:, 1])
+    rho, ux, uy = _velocity(g.populations(), z["sample_y"], z["sample_x"])
+    verr = max(np.abs(ux - z["ux"]).max(), np.abs(uy - z["uy"]).max()) / w.u_ref
+    dpost = np.abs(F[:, 4] - F[:, 1]).max() / np.abs(F[:, 1]).max()
+    print(f"re {re} {precision}: Cd errors {dict(zip(NAMES, cd_err.round(8)))}, "
+          f"Cl errors {dict(zip(NAMES, cl_err.round(8)))}, velocity Linf/U {verr:.2e}, "
+          f"max |DRTT-post - B| / max |B| {dpost:.1e}")
+    tol = np.array(TOLS[(re, precision)])
+    assert np.all(cd_err <= tol), cd_err
+    assert dpost <= 1e-10
