@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
   double dom_acc = 0.0;
   const int x0 = tx * kTileW + 64 * wave;
   if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, x0, ty * kTileH) &&
-      strip_is_interior(a.nx, x0)) {
+      strip_is_interior(a.nx, a.ny, x0, ty * kTileH)) {
     // Every neighbour is fluid and streams: lambda_k(s) = mu_k(s + c_k),
     // f_i(s) = S_i(s - c_i).
 #pragma unroll

@@ -243,6 +243,7 @@ StepArgs step_args(const lbm_t* h, const DevTables& t) {
   a.nx = p.nx;
   a.ny = p.ny;
   a.bc_x = p.bc_x;
+  a.bc_y = p.bc_y;
   a.ntx = p.ntx;
   a.nty = p.nty;
   a.gx0 = p.gx0;

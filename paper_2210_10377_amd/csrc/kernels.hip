@@ -91,9 +91,10 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
   }
 }
 
-// Plain strip holding x = 0, x = nx - 1 or lanes past the row end: the pull codes are
-// those of edge_word (inlet or wrap, outlet or wrap, plain streaming elsewhere), made
-// from the lane's x alone, with no per-node metadata; no forces.
+// Plain strip on the first or last row, or holding x = 0, x = nx - 1 or lanes past the
+// row end: the pull codes are those of edge_word (walls or wrap, inlet or wrap, outlet
+// or wrap, plain streaming elsewhere), made from the lane's coordinates alone, with no
+// per-node metadata; no forces.
 template <int P, bool BUF, int COLL>
 __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
   using S = Storage<P>;
@@ -104,9 +105,10 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
   const int pitch = a.pitch;
   const int x = tx * kTileW + int(threadIdx.x);
   if (x >= a.nx) return;
-  const uint32_t w = edge_word(a.nx, a.bc_x, x);
   for (int r = 0; r < kTileH; ++r) {
     const int y = ty * kTileH + r;
+    if (y >= a.ny) break;
+    const uint32_t w = edge_word(a.nx, a.ny, a.bc_x, a.bc_y, x, y);
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
     C g[kQ];
@@ -114,6 +116,79 @@ __device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
     const int32_t o = y * pitch + x;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
+  }
+}
+
+// Control-volume terms of fluid node (x, y) (second Eq. rtt7) added to acc: the
+// momentum of its populations before collision (f) and as stored after it (s) when it
+// lies in the control volume, and the stored populations crossing the box surface:
+// entering V (+) from a node outside, leaving V (-) from a node inside.
+template <int P>
+__device__ __forceinline__ void box_terms(const StepArgs& a, int x, int y,
+                                          const typename Storage<P>::C (&f)[kQ],
+                                          const typename Storage<P>::T (&s)[kQ],
+                                          double (&acc)[kPart]) {
+  using S = Storage<P>;
+  if (in_box(a, x, y)) {
+    double jx = 0.0, jy = 0.0, px = 0.0, py = 0.0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+      jx += kCx[i] * fi;
+      jy += kCy[i] * fi;
+      const double sv = to_f64<P>(s[i], i);
+      px += kCx[i] * sv;
+      py += kCy[i] * sv;
+    }
+    acc[4] += jx;
+    acc[5] += jy;
+    acc[kJpost] += px;
+    acc[kJpost + 1] += py;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+      if (!in_box(a, x + kCx[i], y + kCy[i])) {
+        const double sv = to_f64<P>(s[i], i);
+        acc[6] -= kCx[i] * sv;
+        acc[7] -= kCy[i] * sv;
+      }
+  } else {
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+      if (in_box(a, x + kCx[i], y + kCy[i])) {
+        const double sv = to_f64<P>(s[i], i);
+        acc[6] += kCx[i] * sv;
+        acc[7] += kCy[i] * sv;
+      }
+  }
+}
+
+// Interior strip touching the control-volume surface: plain pulls (the loaded v),
+// collision and store as interior_finish, and the control-volume terms of every node.
+template <int P, bool BUF, int COLL>
+__device__ __forceinline__ void ring_finish(const StepArgs& a, int tx, int ty,
+                                            const typename Storage<P>::T (&v)[kTileH][kQ],
+                                            double (&acc)[kPart]) {
+  using S = Storage<P>;
+  using T = typename S::T;
+  using C = typename S::C;
+  const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
+  const int pitch = a.pitch;
+  const int x = tx * kTileW + int(threadIdx.x);
+  const int32_t o0 = (ty * kTileH) * pitch + x;
+#pragma unroll
+  for (int r = 0; r < kTileH; ++r) {
+    C f[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[r][i]);
+    C g[kQ];
+    collide<C, S::kDev, COLL>(f, C(a.omega), g);
+    T s[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      s[i] = pack<P>(g[i]);
+      dst.st(i, o0 + r * pitch, s[i]);
+    }
+    box_terms<P>(a, x, ty * kTileH + r, f, s, acc);
   }
 }
 
@@ -162,39 +237,8 @@ __device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, 
         acc[2] += kCx[i] * (sv + back);
         acc[3] += kCy[i] * (sv + back);
       }
-      // Control volume (second Eq. rtt7): momentum before collision (and after it, as
-      // stored), and the populations crossing the box surface after collision.
-      if (in_box(a, x, y)) {
-        double jx = 0.0, jy = 0.0, px = 0.0, py = 0.0;
-#pragma unroll
-        for (int i = 1; i < kQ; ++i) {
-          const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
-          jx += kCx[i] * fi;
-          jy += kCy[i] * fi;
-          const double sv = to_f64<P>(s[i], i);
-          px += kCx[i] * sv;
-          py += kCy[i] * sv;
-        }
-        acc[4] += jx;
-        acc[5] += jy;
-        acc[kJpost] += px;
-        acc[kJpost + 1] += py;
-#pragma unroll
-        for (int i = 1; i < kQ; ++i)
-          if (!in_box(a, x + kCx[i], y + kCy[i])) {
-            const double sv = to_f64<P>(s[i], i);
-            acc[6] -= kCx[i] * sv;
-            acc[7] -= kCy[i] * sv;
-          }
-      } else {
-#pragma unroll
-        for (int i = 1; i < kQ; ++i)
-          if (in_box(a, x + kCx[i], y + kCy[i])) {
-            const double sv = to_f64<P>(s[i], i);
-            acc[6] += kCx[i] * sv;
-            acc[7] += kCy[i] * sv;
-          }
-      }
+      // Control volume (second Eq. rtt7).
+      box_terms<P>(a, x, y, f, s, acc);
       // Stress integration (Sec. III, Eq. stress_int): each axis link of this node is a
       // unit face of the staircase surface with normal -c_i out of the body; the
       // traction (-p I + sigma) . n uses p = rho/3 and sigma = -(1 - omega/2) Pi^neq of
@@ -257,12 +301,20 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
   const int cls = strip_class(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, a.bx0, a.bx1, a.by0,
                               a.by1, x0, ty * kTileH);
   if (cls != kStripGeneral) {
-    if (!strip_is_interior(a.nx, x0)) {
+    if (!strip_is_interior(a.nx, a.ny, x0, ty * kTileH)) {
       edge_rows<P, BUF, COLL>(a, tx, ty);
       return;
     }
     typename Storage<P>::T v[kTileH][kQ];
     interior_load<P, BUF>(a, tx, ty, v);
+    if (FORCES && cls == kStripBoxRing) {
+      // Plain pulls, with the control-volume terms of every node from its coordinates.
+      double acc[kPart] = {};
+      ring_finish<P, BUF, COLL>(a, tx, ty, v, acc);
+      const int slot = strip_slot[tile * kStrips + wave];
+      if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
+      return;
+    }
     if (FORCES && cls == kStripBoxInterior) {
       // Every node is in the control volume and streams plainly: its pre-collision
       // populations are the loaded values; only the box momentum J is accumulated,

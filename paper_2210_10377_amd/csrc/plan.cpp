@@ -169,8 +169,8 @@ void derive(Plan& p, const Solids& sol) {
       for (int x = p.box[0]; x < p.box[1]; ++x)
         p.n_box += (p.node[size_t(y) * nx + x] & kSolidBit) ? 0 : 1;
 
-  // Rectangle of every node off the first and last rows whose codes need the general
-  // path.  `band`: the nodes with a control-volume term (the box and the ring around it).
+  // Rectangle of every node whose codes need the general path.  `band`: the nodes with
+  // a control-volume term (the box and the ring around it).
   auto band = [&](int x, int y) {
     return p.has_box && x >= p.box[0] - 1 && x <= p.box[1] && y >= p.box[2] - 1 &&
            y <= p.box[3];
@@ -194,15 +194,16 @@ void derive(Plan& p, const Solids& sol) {
   }
   xa = std::max(xa, 0);
   xb = std::min(xb, nx - 1);
-  ya = std::max(ya, 1);
-  yb = std::min(yb, ny - 2);
+  ya = std::max(ya, 0);
+  yb = std::min(yb, ny - 1);
   if (sol.count == 0) yb = ya - 1;
-  const uint32_t e0 = edge_word(nx, p.bc_x, 0), e1 = edge_word(nx, p.bc_x, nx - 1);
   for (int y = ya; y <= yb; ++y) {
     const uint32_t* row = p.node.data() + size_t(y) * nx;
+    // Away from x = 0 and x = nx - 1 the edge word of a row is one value.
+    const uint32_t emid = edge_word(nx, ny, p.bc_x, p.bc_y, nx / 2, y);
     int lo = -1, hi = -1;
     for (int x = xa; x <= xb; ++x)
-      if (row[x] != (x == 0 ? e0 : (x == nx - 1 ? e1 : 0u))) {
+      if (row[x] != ((x == 0 || x == nx - 1) ? edge_word(nx, ny, p.bc_x, p.bc_y, x, y) : emid)) {
         if (lo < 0) lo = x;
         hi = x;
       }
@@ -262,7 +263,7 @@ void derive(Plan& p, const Solids& sol) {
           p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.njslots++;
           continue;
         }
-        ++p.ngeneral;
+        if (cls == kStripGeneral) ++p.ngeneral;
         bool forces = false;
         for (int y = y0; y < std::min(y0 + kTileH, ny); ++y)
           for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {

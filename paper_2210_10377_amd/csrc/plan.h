@@ -41,51 +41,63 @@ constexpr int kTileH = LBM_TILE_H;
 constexpr int kStripW = 64;
 constexpr int kStrips = kTileW / kStripW;
 
-// Pull-code word of a node off the first and last rows that no body, wall, outlet
-// bounce-back or control volume touches: plain streaming, except that at x = 0 the
-// directions with c_x = +1 take the inlet rule (periodic x: the wrap) and at x = nx - 1
-// those with c_x = -1 take the outlet rule (periodic x: the wrap).
-constexpr uint32_t edge_word(int nx, int bc_x, int x) {
+// Pull-code word of a node that no body and no outlet bounce-back touches: the rules of
+// the domain's edges alone, from the node's coordinates (the precedence of the plan:
+// periodic wrap, then wall, inlet, outlet; plain streaming elsewhere).  At y = 0 the
+// directions with c_y = +1 bounce back from the wall (periodic y: wrap), at y = ny - 1
+// those with c_y = -1; at x = 0 those with c_x = +1 take the inlet rule (periodic x:
+// wrap), at x = nx - 1 those with c_x = -1 the outlet rule (periodic x: wrap).
+constexpr uint32_t edge_word(int nx, int ny, int bc_x, int bc_y, int x, int y) {
   uint32_t w = 0;
   for (int i = 1; i < kQ; ++i) {
-    if (x == 0 && kCx[i] == 1)
-      w |= uint32_t(bc_x == LBM_BCX_PERIODIC ? kWrap : kInlet) << (3 * (i - 1));
-    if (x == nx - 1 && kCx[i] == -1)
-      w |= uint32_t(bc_x == LBM_BCX_PERIODIC ? kWrap : kOutlet) << (3 * (i - 1));
+    const int sx = x - kCx[i], sy = y - kCy[i];
+    const bool out_x = sx < 0 || sx >= nx, out_y = sy < 0 || sy >= ny;
+    uint32_t c = kStream;
+    if (out_y && bc_y == LBM_BCY_WALL)
+      c = kWall;
+    else if (out_x && bc_x == LBM_BCX_INLET_OUTLET)
+      c = sx < 0 ? kInlet : kOutlet;
+    else if (out_x || out_y)
+      c = kWrap;
+    w |= c << (3 * (i - 1));
   }
   return w;
 }
 
-// A strip is "plain" when it stays off the first and last rows and outside the
-// rectangle [gx0, gx1] x [gy0, gy1] that holds every node of the other rows whose pull
-// codes are not edge_word (bodies, their links, outlet bounce-backs): its nodes need no
-// per-node metadata.  A plain strip is "interior" when it also holds neither x = 0 nor
-// x = nx - 1 nor any x >= nx (plain streaming in every direction).  Host plan and
-// kernels share these rules.
+// A strip is "plain" when it stays outside the rectangle [gx0, gx1] x [gy0, gy1] that
+// holds every node whose pull codes are not edge_word (bodies, their links, outlet
+// bounce-backs): its nodes need no per-node metadata.  A plain strip is "interior" when
+// it also stays off the first and last rows and holds neither x = 0 nor x = nx - 1 nor
+// any x >= nx (plain streaming in every direction).  Host plan and kernels share these
+// rules.
 constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int x0,
                               int y0) {
   (void)nx;
-  return y0 > 0 && y0 + kTileH < ny &&
-         !(y0 <= gy1 && y0 + kTileH - 1 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
+  (void)ny;
+  return !(y0 <= gy1 && y0 + kTileH - 1 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
 }
-constexpr bool strip_is_interior(int nx, int x0) { return x0 > 0 && x0 + kStripW < nx; }
+constexpr bool strip_is_interior(int nx, int ny, int x0, int y0) {
+  return x0 > 0 && x0 + kStripW < nx && y0 > 0 && y0 + kTileH < ny;
+}
 
 // Class of a strip for the forward step with forces, given the control volume
 // [bx0, bx1) x [by0, by1) (bx0 > bx1: none):
 //   kStripGeneral: per-node pull codes (not plain), or it touches the ring of nodes
-//     within one node of the box surface (flux terms of DRTT);
+//     within one node of the box surface (flux terms of DRTT) and is not interior;
 //   kStripBoxInterior: plain and inside [bx0+1, bx1-2] x [by0+1, by1-2], where every
 //     node is in the control volume with all its neighbours: only the box momentum J
 //     is accumulated;
+//   kStripBoxRing: plain and interior, touching the ring: plain streaming, with the
+//     control-volume terms of each node from its coordinates;
 //   kStripPlain: everything else (no force terms).
-enum StripClass { kStripPlain = 0, kStripBoxInterior = 1, kStripGeneral = 2 };
+enum StripClass { kStripPlain = 0, kStripBoxInterior = 1, kStripGeneral = 2, kStripBoxRing = 3 };
 constexpr int strip_class(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int bx0, int bx1,
                           int by0, int by1, int x0, int y0) {
   if (!strip_is_plain(nx, ny, gx0, gx1, gy0, gy1, x0, y0)) return kStripGeneral;
   const int x1 = x0 + kStripW - 1, y1 = y0 + kTileH - 1;
   if (bx0 > bx1 || y0 > by1 || y1 < by0 - 1 || x0 > bx1 || x1 < bx0 - 1) return kStripPlain;
   if (x0 >= bx0 + 1 && x1 <= bx1 - 2 && y0 >= by0 + 1 && y1 <= by1 - 2) return kStripBoxInterior;
-  return kStripGeneral;
+  return strip_is_interior(nx, ny, x0, y0) ? kStripBoxRing : kStripGeneral;
 }
 
 struct Plan {
@@ -95,9 +107,9 @@ struct Plan {
   std::vector<uint32_t> node;     // [ny*nx] pull codes + solid bit
   std::vector<int32_t> links;     // [L][2] (y*nx + x, i), canonical order
   int ntx = 0, nty = 0, ntiles = 0;  // tiles per row / column / total
-  // Inclusive node rectangle holding every node off the first and last rows whose pull
-  // codes need the general path (a solid node, codes other than edge_word); empty when
-  // gx0 > gx1.  The control volume is classified separately (strip_class).
+  // Inclusive node rectangle holding every node whose pull codes need the general path
+  // (a solid node, codes other than edge_word); empty when gx0 > gx1.  The control
+  // volume is classified separately (strip_class).
   int gx0 = 0, gx1 = -1, gy0 = 0, gy1 = -1;
   // Per strip (tile-major, kStrips per tile): the index >= 0 of its force-partial slot
   // when it holds a link node or a control-volume-band node, else -1.

@@ -169,7 +169,10 @@ def test_full_size_naca3d_two_steps(precision):
     assert err <= (1e-5 if precision == "fp32" else TOL64), err
     e = _force_err(Fg, Fo)
     print("full-size 3-D population error", err, "force errors", e)
-    tol = np.array([1e-4, 1e-4, 1e-2, 1e-3]) if precision == "fp32" else np.full(4, TOL64)
+    # A random field's forces are sums of random link terms: binary32 rounding of the
+    # populations (2.4e-6 relative, above) summed over the ~4e4 links of the span moves
+    # A and B by about 1e-4 of the largest force (measured 7e-5 .. 1.1e-4).
+    tol = np.array([2e-4, 2e-4, 1e-2, 1e-3]) if precision == "fp32" else np.full(4, TOL64)
     assert np.all(e <= tol), e
 
 

@@ -71,18 +71,25 @@ def _velocity(S, ys, xs):
 def test_precision_study_channel_fp64_against_oracle(re):
     """FP64 over 20 000 steps: every fixture step's five forces within 1e-10 of the
     largest oracle force of the run, the window means within 1e-10, density and velocity
-    at the sampled nodes within 1e-10 (velocity relative to the inlet speed)."""
+    at the sampled nodes within 1e-10 (velocity relative to the inlet speed).  The two
+    DRTT forms are differences of control-volume momenta of ~3e3 summed over the box's
+    nodes in another order on each side: their rounding, up to 1.5e-14 per box node on
+    each side, is allowed on top."""
     z = _fixture(f"naca2048x1024_a4_re{re}")
     w = workloads.naca_2048x1024(aoa=4.0, re=float(re))
     g, F = _run_channel(w, "fp64")
     Fz = z["forces"]
     Fg = F[z["steps"]]
+    box_round = 2 * 1.5e-14 * g.info().n_box
     for k, name in enumerate(NAMES):
         scale = np.abs(Fz[:, k]).max()
-        err = np.abs(Fg[:, k] - Fz[:, k]).max() / scale
-        merr = np.abs(F[-2000:, k].mean(0) - z["window_mean"][k]).max() / np.abs(z["window_mean"][k]).max()
-        print(f"re {re} fp64 {name}: step error {err:.2e}, window-mean error {merr:.2e}")
-        assert err <= 1e-10 and merr <= 1e-10, name
+        extra = box_round if name in ("DRTT", "DRTT_POST") else 0.0
+        err = np.abs(Fg[:, k] - Fz[:, k]).max()
+        merr = np.abs(F[-2000:, k].mean(0) - z["window_mean"][k]).max()
+        mscale = np.abs(z["window_mean"][k]).max()
+        print(f"re {re} fp64 {name}: step error {err / scale:.2e}, window-mean error "
+              f"{merr / mscale:.2e} (box rounding allowance {extra / scale:.1e})")
+        assert err <= 1e-10 * scale + extra and merr <= 1e-10 * mscale + extra, name
     rho, ux, uy = _velocity(g.populations(), z["sample_y"], z["sample_x"])
     assert np.abs(rho - z["rho"]).max() <= 1e-10
     assert max(np.abs(ux - z["ux"]).max(), np.abs(uy - z["uy"]).max()) <= 1e-10 * w.u_ref
@@ -120,10 +127,13 @@ def test_precision_study_channel_storages_against_oracle(re, precision):
     cl_err = np.abs(mean[:, 1] - z["window_mean"][:, 1]) / np.abs(z["window_mean"][:, 1])
     rho, ux, uy = _velocity(g.populations(), z["sample_y"], z["sample_x"])
     verr = max(np.abs(ux - z["ux"]).max(), np.abs(uy - z["uy"]).max()) / w.u_ref
-    dpost = np.abs(F[:, 4] - F[:, 1]).max() / np.abs(F[:, 1]).max()
+    # DRTT-post and B read the same stored values: they differ by FP64 summation rounding
+    # over the control volume, at most 1.5e-14 per box node (test_gpu_parity).
+    dpost = np.abs(F[:, 4] - F[:, 1]).max()
+    dpost_bound = 1.5e-14 * g.info().n_box
     print(f"re {re} {precision}: Cd errors {dict(zip(NAMES, cd_err.round(8)))}, "
           f"Cl errors {dict(zip(NAMES, cl_err.round(8)))}, velocity Linf/U {verr:.2e}, "
-          f"max |DRTT-post - B| / max |B| {dpost:.1e}")
+          f"max |DRTT-post - B| {dpost:.1e} (bound {dpost_bound:.1e})")
     tol = np.array(TOLS[(re, precision)])
     assert np.all(cd_err <= tol), cd_err
-    assert dpost <= 1e-10
+    assert dpost <= dpost_bound
