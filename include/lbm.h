@@ -142,7 +142,17 @@ typedef struct lbm_grid {
   int32_t collision;  /* LBM_COLL_BGK (0), LBM_COLL_REGULARIZED or LBM_COLL_KBC         */
   int32_t layout;     /* LBM_LAYOUT_AUTO (0), LBM_LAYOUT_ROWS or LBM_LAYOUT_PLANES: device
                          layout of the state buffers, same results                  */
+  int32_t tile;       /* LBM_TILE_AUTO (0), LBM_TILE_WIDE or LBM_TILE_NARROW: shape of
+                         the step kernel's tiles, same results                       */
 } lbm_grid;
+
+/* Tiles of the step kernel (one 256-thread workgroup of four 64-node strips).  WIDE:
+ * the strips side by side along a row (256 x 1).  NARROW: one above the other (64 x 4),
+ * fewer idle lanes on grids whose rows end in a partial wide tile.  AUTO: NARROW when
+ * nx <= 1024 and a wide tile would leave at least 64 idle lanes at the end of a row. */
+#define LBM_TILE_AUTO 0
+#define LBM_TILE_WIDE 1
+#define LBM_TILE_NARROW 2
 
 /* State-buffer layouts (both lattices).  ROWS: the populations of one grid row stored
  * direction after direction ([ny][9][row] in 2-D, [nz][ny][27][row] in 3-D), so a tile

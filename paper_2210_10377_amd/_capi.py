@@ -21,6 +21,7 @@ LBM_FORCE_DRTT_POST, LBM_FORCE_ALL = 16, 31
 LBM3D_FORCE_ALL = 15
 LBM_COLL_BGK, LBM_COLL_REGULARIZED, LBM_COLL_KBC = 0, 1, 2
 LBM_LAYOUT_AUTO, LBM_LAYOUT_ROWS, LBM_LAYOUT_PLANES = 0, 1, 2
+LBM_TILE_AUTO, LBM_TILE_WIDE, LBM_TILE_NARROW = 0, 1, 2
 
 ERROR_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP",
                -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EOVERFLOW"}
@@ -53,7 +54,7 @@ class lbm_grid(ctypes.Structure):
                 ("max_record", ctypes.c_int32),
                 ("rho_ref", ctypes.c_double), ("u_ref", ctypes.c_double),
                 ("l_ref", ctypes.c_double), ("collision", ctypes.c_int32),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class lbm_inlet(ctypes.Structure):

@@ -43,13 +43,13 @@ class Batch:
 
     @classmethod
     def from_workloads(cls, workloads, precision: str = "fp32", max_record: int = 1024,
-                       device="cuda", stream=None, collision=None) -> "Batch":
+                       device="cuda", stream=None, collision=None, tile="auto") -> "Batch":
         """Members built from ``workloads.Workload`` descriptions (walled channels with an
         inlet, the body mask, tau, inlet profile and control volume of each); `collision`
-        overrides each workload's collision operator."""
+        overrides each workload's collision operator; `tile` is every member's tile shape."""
         members = [Sim(w.mask, w.tau, w.uin, precision=precision, bc_x=w.bc_x, bc_y=w.bc_y,
                        box=w.box, max_record=1, u_ref=w.u_ref, l_ref=w.l_ref, device=device,
-                       stream=stream, collision=collision or w.collision)
+                       stream=stream, collision=collision or w.collision, tile=tile)
                    for w in workloads]
         return cls(members, max_record=max_record, stream=stream)
 

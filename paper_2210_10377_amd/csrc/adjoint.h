@@ -16,6 +16,7 @@ struct AdjArgs {
   uint32_t state_bytes;  // bytes of a state buffer below 4 GiB (buffer addressing), else 0
   uint32_t mu_bytes;     // bytes of an adjoint buffer below 4 GiB, else 0
   int32_t pitch, nx, ny, ntx, ntiles;
+  int32_t tile_rows;           // rows of a tile: 1 (256 x 1) or 4 (64 x 4)
   int32_t gx0, gx1, gy0, gy1;  // node rectangle of the general path (as the step kernel)
   const uint32_t* node;        // forward pull codes
   const uint32_t* adj;         // adjoint codes (readers of each population)

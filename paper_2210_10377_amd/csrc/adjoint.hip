@@ -76,23 +76,25 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
   // run: 32 tiles at 4-byte adjoint values, 16 at 8-byte).
   constexpr int kGroup = kStepGroup * 4 / int(sizeof(C));
   const int tile = block_tile<kGroup>(blockIdx.x, a.ntiles);
-  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  // The wave's strip (the step kernel's tiles): 64 nodes of row y0 from x0.
+  int x0 = 0, y0 = 0;
+  strip_origin(tile, wave, a.ntx, a.tile_rows, x0, y0);
   const Planes<T, BUF> st(a.state, a.plane, a.state_bytes);
   const Planes<C, BUF> min(a.mu_in, a.plane, a.mu_bytes);
   const Planes<C, BUF> mout(a.mu_out, a.plane, a.mu_bytes);
   const int pitch = a.pitch;
-  const int x = tx * kTileW + int(threadIdx.x);
+  const int x = x0 + (int(threadIdx.x) & 63);
   const C om = C(a.omega);
   double dom_acc = 0.0;
-  const int x0 = tx * kTileW + 64 * wave;
-  if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, x0, ty * kTileH) &&
-      strip_is_interior(a.nx, a.ny, x0, ty * kTileH)) {
+  if (y0 >= a.ny) {
+    // a narrow tile's strip below the last row: nothing to do
+  } else if (strip_is_plain(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, x0, y0) &&
+             strip_is_interior(a.nx, a.ny, x0, y0)) {
     // Every neighbour is fluid and streams: lambda_k(s) = mu_k(s + c_k),
     // f_i(s) = S_i(s - c_i).
-#pragma unroll
-    for (int r = 0; r < kTileH; ++r) {
-      const int32_t o = (ty * kTileH + r) * pitch + x;
+    {
+      const int32_t o = y0 * pitch + x;
       C lam[kQ], f[kQ];
 #pragma unroll
       for (int k = 0; k < kQ; ++k) lam[k] = min.ld(k, o + kCy[k] * pitch + kCx[k]);
@@ -104,11 +106,11 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
       for (int k = 0; k < kQ; ++k) mout.st(k, o, mu[k]);
     }
   } else {
-    for (int r = 0; r < kTileH; ++r) {
-      const int y = ty * kTileH + r;
-      if (x >= a.nx || y >= a.ny) continue;
+    do {
+      const int y = y0;
+      if (x >= a.nx) break;
       const uint32_t w = a.node[int64_t(y) * a.nx + x];
-      if (w & kSolidBit) continue;
+      if (w & kSolidBit) break;
       const uint32_t aw = a.adj[int64_t(y) * a.nx + x];
       const int32_t o = y * pitch + x;
       // Transposed pull: the readers of S_k(s) return their adjoints.
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
             g += double(mu[i]) * a.rho_w6 * weight<double>(i) * kCx[i];
         a.duin[y] += g;
       }
-    }
+    } while (false);
   }
   // dJ/domega: one running sum per wave, updated in launch order (deterministic).
 #pragma unroll

@@ -244,6 +244,7 @@ StepArgs step_args(const lbm_t* h, const DevTables& t) {
   a.ny = p.ny;
   a.bc_x = p.bc_x;
   a.bc_y = p.bc_y;
+  a.tile_rows = p.tile_rows;
   a.ntx = p.ntx;
   a.nty = p.nty;
   a.gx0 = p.gx0;
@@ -470,8 +471,8 @@ int lbm_get_info(const lbm_t* h, lbm_info* info) {
   info->n_box = h->plan.n_box;
   info->steps_done = h->steps_done;
   info->n_recorded = h->nrec;
-  info->tile_w = kTileW;
-  info->tile_h = kTileH;
+  info->tile_w = kTileW / h->plan.tile_rows;
+  info->tile_h = h->plan.tile_rows;
   info->plane_stride = h->plane;
   info->pitch = h->pitch;
   info->elem_bytes = int32_t(h->esz);
@@ -950,6 +951,7 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   a.nx = p.nx;
   a.ny = p.ny;
   a.ntx = p.ntx;
+  a.tile_rows = p.tile_rows;
   a.ntiles = p.ntiles;
   a.gx0 = p.gx0;
   a.gx1 = p.gx1;

@@ -37,6 +37,7 @@ struct StepArgs {
   int32_t pitch;    // elements between rows
   int32_t nx, ny;
   int32_t bc_x, bc_y;  // LBM_BCX_*, LBM_BCY_*
+  int32_t tile_rows;   // rows of a tile: 1 (256 x 1) or 4 (64 x 4)
   int32_t ntx, nty, ntiles;
   int32_t gx0, gx1, gy0, gy1;  // node rectangle (inclusive) of every non-border node that
                                // needs the general path; empty when gx0 > gx1

@@ -9,8 +9,9 @@
 // Data layout (HBM): structure of arrays, x fastest; population i of node (x, y) sits at
 // i * plane + y * pitch + x, with the strides from the host (row-interleaved: the nine
 // directions of a row side by side; or one plane per direction).  Every node is updated
-// by one thread of a 256-thread block; a block covers a 256 x kTileH tile, each wave a
-// 64 x kTileH strip.
+// by one thread of a 256-thread block; each wave of a block covers a strip of 64 nodes
+// of one row, the four strips of a block side by side (256 x 1 tiles) or one above the
+// other (64 x 4 tiles, for grids with short rows).
 // Strips of plain fluid (all pulls plain streaming, away from the control-volume band)
 // take a branch-free path that reads no per-node metadata; the other strips read a
 // 32-bit word of pull codes per node, apply the boundary rules, and accumulate the
@@ -41,51 +42,46 @@ __device__ __forceinline__ bool in_box(const StepArgs& a, int x, int y) {
   return x >= a.bx0 && x < a.bx1 && y >= a.by0 && y < a.by1;
 }
 
-// Interior tile: plain pull streaming in every direction, no metadata.  All rows of
-// the tile are loaded before any is collided, so each lane keeps 9 * kTileH loads in
-// flight.
+__device__ __forceinline__ int lane_id() { return int(threadIdx.x) & 63; }
+
+// Interior strip at (x0, y0): plain pull streaming in every direction, no metadata; the
+// nine loads are issued together.
 template <int P, bool BUF>
-__device__ __forceinline__ void interior_load(const StepArgs& a, int tx, int ty,
-                                              typename Storage<P>::T (&v)[kTileH][kQ]) {
+__device__ __forceinline__ void interior_load(const StepArgs& a, int x0, int y0,
+                                              typename Storage<P>::T (&v)[kQ]) {
   using T = typename Storage<P>::T;
   const Planes<T, BUF> src(a.src, a.plane, a.buf_bytes);
   const int pitch = a.pitch;
-  const int32_t o0 = (ty * kTileH) * pitch + tx * kTileW + int(threadIdx.x);
+  const int32_t o0 = y0 * pitch + x0 + lane_id();
 #pragma unroll
-  for (int r = 0; r < kTileH; ++r)
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) v[r][i] = src.ld(i, o0 + (r - kCy[i]) * pitch - kCx[i]);
+  for (int i = 0; i < kQ; ++i) v[i] = src.ld(i, o0 - kCy[i] * pitch - kCx[i]);
 }
 
-// Collision and store of an interior tile; with JP the momentum of the stored
+// Collision and store of an interior strip; with JP the momentum of the stored
 // (post-collision) populations is added to jp (binary64).
 template <int P, bool BUF, int COLL, bool JP = false>
-__device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int ty,
-                                                const typename Storage<P>::T (&v)[kTileH][kQ],
+__device__ __forceinline__ void interior_finish(const StepArgs& a, int x0, int y0,
+                                                const typename Storage<P>::T (&v)[kQ],
                                                 double* jp = nullptr) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
   const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
-  const int pitch = a.pitch;
-  const int32_t o0 = (ty * kTileH) * pitch + tx * kTileW + int(threadIdx.x);
+  const int32_t o = y0 * a.pitch + x0 + lane_id();
+  C f[kQ];
 #pragma unroll
-  for (int r = 0; r < kTileH; ++r) {
-    C f[kQ];
+  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
+  C g[kQ];
+  collide<C, S::kDev, COLL>(f, C(a.omega), g);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[r][i]);
-    C g[kQ];
-    collide<C, S::kDev, COLL>(f, C(a.omega), g);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const T q = pack<P>(g[i]);
-      dst.st(i, o0 + r * pitch, q);
-      if constexpr (JP) {
-        if (i > 0) {
-          const double fi = to_f64<P>(q, i);
-          jp[0] += kCx[i] * fi;
-          jp[1] += kCy[i] * fi;
-        }
+  for (int i = 0; i < kQ; ++i) {
+    const T q = pack<P>(g[i]);
+    dst.st(i, o, q);
+    if constexpr (JP) {
+      if (i > 0) {
+        const double fi = to_f64<P>(q, i);
+        jp[0] += kCx[i] * fi;
+        jp[1] += kCy[i] * fi;
       }
     }
   }
@@ -96,27 +92,23 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int tx, int t
 // or wrap, plain streaming elsewhere), made from the lane's coordinates alone, with no
 // per-node metadata; no forces.
 template <int P, bool BUF, int COLL>
-__device__ __forceinline__ void edge_rows(const StepArgs& a, int tx, int ty) {
+__device__ __forceinline__ void edge_strip(const StepArgs& a, int x0, int y) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
   const Planes<T, BUF> src(a.src, a.plane, a.buf_bytes);
   const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
   const int pitch = a.pitch;
-  const int x = tx * kTileW + int(threadIdx.x);
+  const int x = x0 + lane_id();
   if (x >= a.nx) return;
-  for (int r = 0; r < kTileH; ++r) {
-    const int y = ty * kTileH + r;
-    if (y >= a.ny) break;
-    const uint32_t w = edge_word(a.nx, a.ny, a.bc_x, a.bc_y, x, y);
-    C f[kQ];
-    pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
-    C g[kQ];
-    collide<C, S::kDev, COLL>(f, C(a.omega), g);
-    const int32_t o = y * pitch + x;
+  const uint32_t w = edge_word_bits(a.nx, a.ny, a.bc_x, a.bc_y, x, y);
+  C f[kQ];
+  pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
+  C g[kQ];
+  collide<C, S::kDev, COLL>(f, C(a.omega), g);
+  const int32_t o = y * pitch + x;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
-  }
+  for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
 }
 
 // Control-volume terms of fluid node (x, y) (second Eq. rtt7) added to acc: the
@@ -165,50 +157,45 @@ __device__ __forceinline__ void box_terms(const StepArgs& a, int x, int y,
 // Interior strip touching the control-volume surface: plain pulls (the loaded v),
 // collision and store as interior_finish, and the control-volume terms of every node.
 template <int P, bool BUF, int COLL>
-__device__ __forceinline__ void ring_finish(const StepArgs& a, int tx, int ty,
-                                            const typename Storage<P>::T (&v)[kTileH][kQ],
+__device__ __forceinline__ void ring_finish(const StepArgs& a, int x0, int y0,
+                                            const typename Storage<P>::T (&v)[kQ],
                                             double (&acc)[kPart]) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
   const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
-  const int pitch = a.pitch;
-  const int x = tx * kTileW + int(threadIdx.x);
-  const int32_t o0 = (ty * kTileH) * pitch + x;
+  const int x = x0 + lane_id();
+  const int32_t o = y0 * a.pitch + x;
+  C f[kQ];
 #pragma unroll
-  for (int r = 0; r < kTileH; ++r) {
-    C f[kQ];
+  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
+  C g[kQ];
+  collide<C, S::kDev, COLL>(f, C(a.omega), g);
+  T s[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[r][i]);
-    C g[kQ];
-    collide<C, S::kDev, COLL>(f, C(a.omega), g);
-    T s[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      s[i] = pack<P>(g[i]);
-      dst.st(i, o0 + r * pitch, s[i]);
-    }
-    box_terms<P>(a, x, ty * kTileH + r, f, s, acc);
+  for (int i = 0; i < kQ; ++i) {
+    s[i] = pack<P>(g[i]);
+    dst.st(i, o, s[i]);
   }
+  box_terms<P>(a, x, y0, f, s, acc);
 }
 
-// General path of one lane's column of the tile: boundary rules from the pull codes,
-// and (when `forces`) the force sums of its nodes added to acc.
+// General path of one lane of a strip: boundary rules from the pull codes, and (when
+// `forces`) the force sums of its node added to acc.
 template <int P, bool BUF, int COLL, bool MOV>
-__device__ __forceinline__ void general_rows(const StepArgs& a, int tx, int ty, bool forces,
-                                             double (&acc)[kPart]) {
+__device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, bool forces,
+                                              double (&acc)[kPart]) {
   using S = Storage<P>;
   using T = typename S::T;
   using C = typename S::C;
   const Planes<T, BUF> src(a.src, a.plane, a.buf_bytes);
   const Planes<T, BUF> dst(a.dst, a.plane, a.buf_bytes);
   const int pitch = a.pitch;
-  const int x = tx * kTileW + int(threadIdx.x);
-  for (int r = 0; r < kTileH; ++r) {
-    const int y = ty * kTileH + r;
-    if (x >= a.nx || y >= a.ny) continue;
+  const int x = x0 + lane_id();
+  {
+    if (x >= a.nx) return;
     const uint32_t w = a.node[int64_t(y) * a.nx + x];
-    if (w & kSolidBit) continue;
+    if (w & kSolidBit) return;
     const int32_t o = y * pitch + x;
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, MOV ? a.motion : nullptr);
@@ -289,28 +276,29 @@ __device__ __forceinline__ void reduce_row(const double* red_in, int nslots, int
   }
 }
 
-// One 256 x kTileH tile of a step.
+// One tile of a step: each 64-lane wave takes one strip.
 template <int P, bool BUF, bool FORCES, int COLL, bool MOV>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
                                           const int32_t* __restrict__ strip_slot) {
-  const int ty = tile / a.ntx, tx = tile - ty * a.ntx;
-  // Each 64-lane wave covers a 64 x kTileH strip, classified from its coordinates
-  // alone (no memory access before the first population load).
+  // Each wave's strip is classified from its coordinates alone (no memory access before
+  // the first population load).
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
-  const int x0 = tx * kTileW + 64 * wave;
+  int x0 = 0, y0 = 0;
+  strip_origin(tile, wave, a.ntx, a.tile_rows, x0, y0);
+  if (y0 >= a.ny) return;
   const int cls = strip_class(a.nx, a.ny, a.gx0, a.gx1, a.gy0, a.gy1, a.bx0, a.bx1, a.by0,
-                              a.by1, x0, ty * kTileH);
+                              a.by1, x0, y0);
   if (cls != kStripGeneral) {
-    if (!strip_is_interior(a.nx, a.ny, x0, ty * kTileH)) {
-      edge_rows<P, BUF, COLL>(a, tx, ty);
+    if (!strip_is_interior(a.nx, a.ny, x0, y0)) {
+      edge_strip<P, BUF, COLL>(a, x0, y0);
       return;
     }
-    typename Storage<P>::T v[kTileH][kQ];
-    interior_load<P, BUF>(a, tx, ty, v);
+    typename Storage<P>::T v[kQ];
+    interior_load<P, BUF>(a, x0, y0, v);
     if (FORCES && cls == kStripBoxRing) {
       // Plain pulls, with the control-volume terms of every node from its coordinates.
       double acc[kPart] = {};
-      ring_finish<P, BUF, COLL>(a, tx, ty, v, acc);
+      ring_finish<P, BUF, COLL>(a, x0, y0, v, acc);
       const int slot = strip_slot[tile * kStrips + wave];
       if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
       return;
@@ -321,25 +309,23 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile,
       // before collision and after it (of the stored values).
       double acc[kBoxPart] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int r = 0; r < kTileH; ++r)
-#pragma unroll
-        for (int i = 1; i < kQ; ++i) {
-          const double fi = to_f64<P>(v[r][i], i);
-          acc[0] += kCx[i] * fi;
-          acc[1] += kCy[i] * fi;
-        }
-      interior_finish<P, BUF, COLL, true>(a, tx, ty, v, acc + 2);
+      for (int i = 1; i < kQ; ++i) {
+        const double fi = to_f64<P>(v[i], i);
+        acc[0] += kCx[i] * fi;
+        acc[1] += kCy[i] * fi;
+      }
+      interior_finish<P, BUF, COLL, true>(a, x0, y0, v, acc + 2);
       wave_sum_store<kBoxPart>(acc, a.part_out + int64_t(a.nslots) * kPart +
                                         int64_t(strip_slot[tile * kStrips + wave]) * kBoxPart);
       return;
     }
-    interior_finish<P, BUF, COLL>(a, tx, ty, v);
+    interior_finish<P, BUF, COLL>(a, x0, y0, v);
     return;
   }
   const int slot = FORCES ? strip_slot[tile * kStrips + wave] : -1;
   // FA(x,y), FB(x,y), J(x,y), Phi(x,y), SI(x,y), Jpost(x,y)
   double acc[kPart] = {};
-  general_rows<P, BUF, COLL, MOV>(a, tx, ty, slot >= 0, acc);
+  general_strip<P, BUF, COLL, MOV>(a, x0, y0, slot >= 0, acc);
   if (slot >= 0) wave_sum_store<kPart>(acc, a.part_out + int64_t(slot) * kPart);
 }
 
@@ -369,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
 // Step k of a launch sequence writes force row ctl[0] + k; ctl[1] counts the steps of
 // the same call enqueued before the sequence (their last row is still to be reduced).
 template <int P, bool FORCES, bool PERSIST, int COLL, bool MOV>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 8)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 7)))
 void batch_step_kernel(
     const BatchInst* __restrict__ inst, const int32_t* __restrict__ tile_inst,
     const int32_t* __restrict__ tile_local, BatchLaunch b, int32_t parity, int32_t k) {

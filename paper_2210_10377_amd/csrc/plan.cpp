@@ -58,6 +58,10 @@ int validate(const lbm_grid& g, const uint8_t* mask, Solids& sol, std::string& e
     err = "unknown bc_y";
     return LBM_EINVAL;
   }
+  if (g.tile != LBM_TILE_AUTO && g.tile != LBM_TILE_WIDE && g.tile != LBM_TILE_NARROW) {
+    err = "unknown tile shape";
+    return LBM_EINVAL;
+  }
   if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP16DEV &&
       g.precision != LBM_FP32DEV) {
     err = "unknown precision";
@@ -149,6 +153,7 @@ void set_geometry(Plan& p, const lbm_grid& g) {
   p.bc_y = g.bc_y;
   p.has_box = g.box[0] >= 0;
   for (int k = 0; k < 4; ++k) p.box[k] = g.box[k];
+  p.tile_rows = tile_rows_for(g.nx, g.tile);
 }
 
 uint32_t node_word(const Plan& p, const uint8_t* mask, int x, int y) {
@@ -244,15 +249,19 @@ void derive(Plan& p, const Solids& sol) {
   // Tiles and strips (strip_class).  General strips holding a link node or a node with a
   // control-volume term own a force-partial slot (kPart sums); box-interior strips own
   // a slot of the box-momentum partials (2 sums).
-  p.ntx = (nx + kTileW - 1) / kTileW;
-  p.nty = (ny + kTileH - 1) / kTileH;
+  const int tile_w = kTileW / p.tile_rows;
+  p.ntx = (nx + tile_w - 1) / tile_w;
+  p.nty = (ny + p.tile_rows - 1) / p.tile_rows;
   p.ntiles = p.ntx * p.nty;
   p.strip_slot.assign(size_t(p.ntiles) * kStrips, -1);
   p.nslots = p.njslots = p.ngeneral = 0;
   for (int ty = 0; ty < p.nty; ++ty)
     for (int tx = 0; tx < p.ntx; ++tx)
       for (int w = 0; w < kStrips; ++w) {
-        const int x0 = tx * kTileW + w * kStripW, y0 = ty * kTileH;
+        const int tile = ty * p.ntx + tx;
+        int x0 = 0, y0 = 0;
+        strip_origin(tile, w, p.ntx, p.tile_rows, x0, y0);
+        if (y0 >= ny) continue;
         const int cls = p.has_box
                             ? strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0],
                                           p.box[1], p.box[2], p.box[3], x0, y0)
@@ -260,20 +269,19 @@ void derive(Plan& p, const Solids& sol) {
                                           x0, y0);
         if (cls == kStripPlain) continue;
         if (cls == kStripBoxInterior) {
-          p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.njslots++;
+          p.strip_slot[size_t(tile) * kStrips + w] = p.njslots++;
           continue;
         }
         if (cls == kStripGeneral) ++p.ngeneral;
         bool forces = false;
-        for (int y = y0; y < std::min(y0 + kTileH, ny); ++y)
-          for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {
-            const uint32_t wd = p.node[size_t(y) * nx + x];
-            bool link = false;
-            if (!(wd & kSolidBit))
-              for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
-            forces = forces || link || band(x, y);
-          }
-        if (forces) p.strip_slot[(size_t(ty) * p.ntx + tx) * kStrips + w] = p.nslots++;
+        for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {
+          const uint32_t wd = p.node[size_t(y0) * nx + x];
+          bool link = false;
+          if (!(wd & kSolidBit))
+            for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
+          forces = forces || link || band(x, y0);
+        }
+        if (forces) p.strip_slot[size_t(tile) * kStrips + w] = p.nslots++;
       }
   p.box_bx = p.box_rows = 0;
   if (p.has_box) {

@@ -31,15 +31,30 @@ constexpr uint32_t kSolidBit = 1u << 31;
 
 constexpr uint32_t pull_code(uint32_t word, int i) { return (word >> (3 * (i - 1))) & 7u; }
 
-// Tile shape of the step kernel: one 256-thread block covers kTileW x kTileH nodes,
-// each of its four waves a 64 x kTileH strip.
-#ifndef LBM_TILE_H
-#define LBM_TILE_H 1
-#endif
-constexpr int kTileW = 256;
-constexpr int kTileH = LBM_TILE_H;
+// Tiles of the step kernel: one 256-thread block of four 64-lane waves, each wave a strip
+// of 64 nodes of one row.  Wide tiles (1 row) put the four strips side by side (256 x 1),
+// narrow tiles (4 rows) one above the other (64 x 4), for grids with short rows.
+constexpr int kTileW = 256;  // threads of a block, nodes of a wide tile
 constexpr int kStripW = 64;
 constexpr int kStrips = kTileW / kStripW;
+
+// Origin (x0, y0) of the strip of wave `wave` of tile `tile`, for tiles of `rows` rows
+// (1 or 4) and ntx tiles along x.
+constexpr void strip_origin(int tile, int wave, int ntx, int rows, int& x0, int& y0) {
+  const int ty = tile / ntx, tx = tile - ty * ntx;
+  x0 = rows == 1 ? tx * kTileW + wave * kStripW : tx * kStripW;
+  y0 = rows == 1 ? ty : ty * rows + wave;
+}
+// Tile rows for a grid nx wide under the request `tile` (LBM_TILE_*): narrow when asked,
+// or automatically when 256-node tiles would leave at least one idle wave per row of a
+// grid of at most 1024 columns.
+constexpr int tile_rows_for(int nx, int tile) {
+  return tile == LBM_TILE_NARROW
+             ? 4
+             : (tile == LBM_TILE_WIDE
+                    ? 1
+                    : ((nx <= 1024 && (nx + kTileW - 1) / kTileW * kTileW - nx >= kStripW) ? 4 : 1));
+}
 
 // Pull-code word of a node that no body and no outlet bounce-back touches: the rules of
 // the domain's edges alone, from the node's coordinates (the precedence of the plan:
@@ -64,6 +79,33 @@ constexpr uint32_t edge_word(int nx, int ny, int bc_x, int bc_y, int x, int y) {
   return w;
 }
 
+// edge_word by bit operations on whole words, for the kernels: a pattern holds 1 in the
+// low bit of the 3-bit field of each direction of a set; a code times a pattern writes
+// the code into those fields.  Equal to edge_word for every node (tested).
+constexpr uint32_t dir_pattern(int cx, int cy) {  // directions with c_x = cx (or c_y = cy)
+  uint32_t p = 0;
+  for (int i = 1; i < kQ; ++i)
+    if ((cx != 0 && kCx[i] == cx) || (cy != 0 && kCy[i] == cy)) p |= 1u << (3 * (i - 1));
+  return p;
+}
+constexpr uint32_t edge_word_bits(int nx, int ny, int bc_x, int bc_y, int x, int y) {
+  constexpr uint32_t kUp = dir_pattern(0, 1), kDown = dir_pattern(0, -1);
+  constexpr uint32_t kRight = dir_pattern(1, 0), kLeft = dir_pattern(-1, 0);
+  // Directions whose source lies beyond a bounded or periodic edge.
+  const uint32_t py = (y == 0 ? kUp : 0u) | (y == ny - 1 ? kDown : 0u);
+  const uint32_t pr = x == 0 ? kRight : 0u, pl = x == nx - 1 ? kLeft : 0u;
+  const uint32_t px = pr | pl;
+  if (bc_y == LBM_BCY_WALL) {
+    const uint32_t xr = pr & ~py, xl = pl & ~py;
+    return uint32_t(kWall) * py + (bc_x == LBM_BCX_PERIODIC
+                                       ? uint32_t(kWrap) * (xr | xl)
+                                       : uint32_t(kInlet) * xr + uint32_t(kOutlet) * xl);
+  }
+  return (bc_x == LBM_BCX_PERIODIC ? uint32_t(kWrap) * px
+                                   : uint32_t(kInlet) * pr + uint32_t(kOutlet) * pl) +
+         uint32_t(kWrap) * (py & ~px);
+}
+
 // A strip is "plain" when it stays outside the rectangle [gx0, gx1] x [gy0, gy1] that
 // holds every node whose pull codes are not edge_word (bodies, their links, outlet
 // bounce-backs): its nodes need no per-node metadata.  A plain strip is "interior" when
@@ -74,10 +116,10 @@ constexpr bool strip_is_plain(int nx, int ny, int gx0, int gx1, int gy0, int gy1
                               int y0) {
   (void)nx;
   (void)ny;
-  return !(y0 <= gy1 && y0 + kTileH - 1 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
+  return !(y0 <= gy1 && y0 >= gy0 && x0 <= gx1 && x0 + kStripW - 1 >= gx0);
 }
 constexpr bool strip_is_interior(int nx, int ny, int x0, int y0) {
-  return x0 > 0 && x0 + kStripW < nx && y0 > 0 && y0 + kTileH < ny;
+  return x0 > 0 && x0 + kStripW < nx && y0 > 0 && y0 + 1 < ny;
 }
 
 // Class of a strip for the forward step with forces, given the control volume
@@ -94,7 +136,7 @@ enum StripClass { kStripPlain = 0, kStripBoxInterior = 1, kStripGeneral = 2, kSt
 constexpr int strip_class(int nx, int ny, int gx0, int gx1, int gy0, int gy1, int bx0, int bx1,
                           int by0, int by1, int x0, int y0) {
   if (!strip_is_plain(nx, ny, gx0, gx1, gy0, gy1, x0, y0)) return kStripGeneral;
-  const int x1 = x0 + kStripW - 1, y1 = y0 + kTileH - 1;
+  const int x1 = x0 + kStripW - 1, y1 = y0;
   if (bx0 > bx1 || y0 > by1 || y1 < by0 - 1 || x0 > bx1 || x1 < bx0 - 1) return kStripPlain;
   if (x0 >= bx0 + 1 && x1 <= bx1 - 2 && y0 >= by0 + 1 && y1 <= by1 - 2) return kStripBoxInterior;
   return strip_is_interior(nx, ny, x0, y0) ? kStripBoxRing : kStripGeneral;
@@ -106,6 +148,7 @@ struct Plan {
   int box[4] = {-1, -1, -1, -1};
   std::vector<uint32_t> node;     // [ny*nx] pull codes + solid bit
   std::vector<int32_t> links;     // [L][2] (y*nx + x, i), canonical order
+  int tile_rows = 1;              // 1: wide tiles (256 x 1), 4: narrow tiles (64 x 4)
   int ntx = 0, nty = 0, ntiles = 0;  // tiles per row / column / total
   // Inclusive node rectangle holding every node whose pull codes need the general path
   // (a solid node, codes other than edge_word); empty when gx0 > gx1.  The control

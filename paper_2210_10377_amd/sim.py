@@ -19,6 +19,7 @@ COLLISIONS = {"bgk": C.LBM_COLL_BGK, "regularized": C.LBM_COLL_REGULARIZED,
               "kbc": C.LBM_COLL_KBC}
 LAYOUTS = {"auto": C.LBM_LAYOUT_AUTO, "rows": C.LBM_LAYOUT_ROWS,
            "planes": C.LBM_LAYOUT_PLANES}
+TILES = {"auto": C.LBM_TILE_AUTO, "wide": C.LBM_TILE_WIDE, "narrow": C.LBM_TILE_NARROW}
 
 
 def scheme_mask(schemes) -> int:
@@ -38,12 +39,13 @@ class Sim:
     box: control-volume box (x0, x1, y0, y1) for the DRTT force, or None.
     collision: "bgk" (Eq. CollideAdv), "regularized" or "kbc" (entropic; for tau_lb
     close to 1/2).  layout: "auto", "rows" or "planes" (device layout of the state).
+    tile: "auto", "wide" (256 x 1) or "narrow" (64 x 4) step-kernel tiles.
     """
 
     def __init__(self, mask, tau, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
                  bc_y=C.LBM_BCY_WALL, box=None, max_record=4096, rho_ref=1.0, u_ref=1.0,
                  l_ref=1.0, rho_w=1.0, device="cuda", stream=None, collision="bgk",
-                 layout="auto"):
+                 layout="auto", tile="auto"):
         import torch
 
         self._lib = C.load()
@@ -60,6 +62,7 @@ class Sim:
         g.rho_ref, g.u_ref, g.l_ref = float(rho_ref), float(u_ref), float(l_ref)
         g.collision = COLLISIONS[collision]
         g.layout = LAYOUTS[layout]
+        g.tile = TILES[tile]
         self.collision = collision
         self._grid = g
         inlet = None
@@ -260,7 +263,8 @@ class Plan:
     """A handle created but never bound: host-side classification only (no GPU)."""
 
     def __init__(self, mask, tau=0.8, uin=None, *, precision="fp32", bc_x=C.LBM_BCX_INLET_OUTLET,
-                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16, collision="bgk", layout="auto"):
+                 bc_y=C.LBM_BCY_WALL, box=None, max_record=16, collision="bgk", layout="auto",
+                 tile="auto"):
         self._lib = C.load()
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         ny, nx = mask.shape
@@ -274,6 +278,7 @@ class Plan:
         g.rho_ref = g.u_ref = g.l_ref = 1.0
         g.collision = COLLISIONS[collision]
         g.layout = LAYOUTS[layout]
+        g.tile = TILES[tile]
         inlet = None
         if uin is not None:
             self._uin = np.ascontiguousarray(np.broadcast_to(np.asarray(uin, np.float64), (ny,)))

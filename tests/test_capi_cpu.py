@@ -404,3 +404,38 @@ def test_static_step_validation_without_device(capi):
     assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, 5, 2, fp, 4, None) == capi.LBM_EINVAL
     assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, -1, 0, None, 0, None) == capi.LBM_EINVAL
     assert L.lbm_step_static(small._h, vp(256), vp(512), 1 << 20, 0, 2, None, 0, None) == capi.LBM_OK
+
+
+def test_edge_word_bit_form_equals_the_rule(tmp_path):
+    """The kernels' bit-operation form of the edge pull codes equals the rule the plan
+    uses, at every node of small grids, for every boundary combination (compiled from
+    the library's own header with g++)."""
+    import subprocess
+    src = tmp_path / "edge.cpp"
+    src.write_text(r'''
+#include <cstdio>
+#include "plan.h"
+using namespace lbm;
+int main() {
+  int bad = 0, n = 0;
+  for (int nx = 3; nx <= 7; ++nx)
+    for (int ny = 3; ny <= 6; ++ny)
+      for (int bx = 0; bx < 2; ++bx)
+        for (int by = 0; by < 2; ++by)
+          for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+              ++n;
+              if (edge_word(nx, ny, bx, by, x, y) != edge_word_bits(nx, ny, bx, by, x, y)) ++bad;
+            }
+  std::printf("%d %d\n", n, bad);
+  return bad != 0;
+}
+''')
+    exe = tmp_path / "edge"
+    subprocess.check_call(["g++", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2210_10377_amd", "csrc"),
+                           str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    n, bad = (int(v) for v in out.stdout.split())
+    assert n > 1000 and bad == 0

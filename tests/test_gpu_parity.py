@@ -498,3 +498,43 @@ def test_naca_2048x1024_two_steps(precision):
              "fp16dev": np.array([5e-2, 5e-2, 5e-1, 5e-2, 5e-2])}[precision]
     assert err <= tol_pop, err
     assert np.all(e <= tol_f), e
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_tile_shapes_give_the_same_step(name):
+    """Wide (256 x 1) and narrow (64 x 4) tiles run the same per-node arithmetic: FP64
+    populations bitwise equal after 40 steps from a seeded state, forces equal up to the
+    order of the FP64 partial sums (1e-13 of the largest force, and the box-momentum
+    rounding for DRTT), and the narrow run within 1e-10 of the oracle."""
+    nx, ny, bcx, bcy, mk, box, u = CASES[name]
+    mask = mk(nx, ny)
+    uin = None if bcx == BCX_PERIODIC else np.linspace(0.5, 1.0, ny) * u
+    S0 = workloads.near_rest_state(nx, ny, seed=3 + len(name), amp=0.05)
+    runs = {}
+    for tile in ("wide", "narrow"):
+        g = _sim(mask=mask, tau=0.7, uin=uin, precision="fp64", bc_x=bcx, bc_y=bcy, box=box,
+                 max_record=64, tile=tile)
+        assert (g.info().tile_w, g.info().tile_h) == ((256, 1) if tile == "wide" else (64, 4))
+        g.set_populations(S0)
+        g.step(40)
+        runs[tile] = (g.populations(), g.forces())
+    assert np.array_equal(runs["wide"][0], runs["narrow"][0])
+    Fw, Fn = runs["wide"][1], runs["narrow"][1]
+    n_box = g.info().n_box
+    for k in range(Fw.shape[1]):
+        if np.isnan(Fw[:, k]).all():
+            assert np.isnan(Fn[:, k]).all()
+            continue
+        # The DRTT forms also carry the rounding of the box momenta summed in another
+        # order (drtt_post_tolerance per side).
+        extra = 2 * drtt_post_tolerance(n_box) if k in (2, 4) else 0.0
+        assert np.abs(Fw[:, k] - Fn[:, k]).max() <= 1e-13 * np.abs(Fw[:, k]).max() + extra, k
+    o = OracleSim(mask, tau=0.7, uin=uin, bc_x=bcx, bc_y=bcy, box=box)
+    o.set_state(S0)
+    o.step(40)
+    assert _pop_err(runs["narrow"][0], o.state(), mask) <= TOL64
+    if mask.any():
+        e = _force_err(Fn, o.forces())
+        assert np.all(e <= TOL64), e
+    else:
+        assert np.all(Fn[:, [0, 1, 3]] == 0.0)
