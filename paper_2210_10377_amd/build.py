@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["api.hip", "batch.hip", "kernels.hip", "adjoint.hip", "plan.cpp", "api3.hip",
            "kernels3.hip", "plan3.cpp", "noalloc.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 
 def _flags() -> list[str]:
@@ -32,7 +33,7 @@ def hipcc_command(out: str) -> list[str]:
     """One hipcc call that compiles and links every source (the serial form)."""
     return ["hipcc", *_flags(), "-shared", *[os.path.join(CSRC, s) for s in SOURCES
                                               if os.path.exists(os.path.join(CSRC, s))],
-            "-o", out]
+            "-L", ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-o", out]
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
@@ -50,7 +51,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
         with ThreadPoolExecutor(jobs) as ex:
             list(ex.map(compile_one, range(len(srcs))))
-        link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        # The tracer's range API (rocprofiler-sdk-roctx) is linked with its path recorded.
+        link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs,
+                "-L", ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-o", tmp]
         if verbose:
             print(" ".join(link), file=sys.stderr)
         subprocess.check_call(link)

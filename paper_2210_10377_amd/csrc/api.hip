@@ -13,6 +13,7 @@
 
 #include "adjoint.h"
 #include "handle.h"
+#include "trace.h"
 #include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
@@ -398,6 +399,7 @@ int enqueue_pingpong(lbm_t* h, const DevTables& t, void* b0, void* b1, hipStream
 extern "C" {
 
 int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
+  TraceRange range("lbm_step");
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
@@ -417,6 +419,7 @@ int lbm_step(lbm_t* h, int32_t n, uint32_t force_scheme) {
 }
 
 int lbm_forces(lbm_t* h, double* out, int64_t cap, int64_t* k_out) {
+  TraceRange range("lbm_forces");
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (k_out) *k_out = h->nrec;
@@ -635,6 +638,7 @@ int lbm_set_body_motion(lbm_t* h, double ux, double uy, double omega, double xc,
 }
 
 int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double* impulse) {
+  TraceRange range("lbm_set_mask");
   if (!h || !solid_mask) return LBM_EINVAL;
   lbm_grid g = h->g;
   if (box) {
@@ -749,6 +753,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
 
 int lbm_boundary_cp(lbm_t* h, int32_t x_inf, int32_t y_inf, double* cp, int32_t* nodes,
                     int64_t cap, int64_t* n) {
+  TraceRange range("lbm_boundary_cp");
   if (!h || !n) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   const int nx = h->g.nx, ny = h->g.ny;
@@ -863,6 +868,7 @@ int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* by
 
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J) {
+  TraceRange range("lbm_adjoint_forward");
   if (!h) return LBM_EINVAL;
   if (h->g.precision == LBM_FP16DEV)
     return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
@@ -916,6 +922,7 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
 }
 
 int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
+  TraceRange range("lbm_adjoint_backward");
   if (!h) return LBM_EINVAL;
   if (h->g.precision == LBM_FP16DEV)
     return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");

@@ -12,6 +12,7 @@
 #include "kernels3.h"
 #include "lbm3d.h"
 #include "plan3.h"
+#include "trace.h"
 
 using namespace lbm3;
 
@@ -344,6 +345,7 @@ int lbm3d_bind(lbm3d_t* h, void* ws, size_t bytes, void* stream) {
 }
 
 int lbm3d_step(lbm3d_t* h, int32_t n, uint32_t scheme) {
+  lbm::TraceRange range("lbm3d_step");
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
@@ -362,6 +364,7 @@ int lbm3d_step(lbm3d_t* h, int32_t n, uint32_t scheme) {
 }
 
 int lbm3d_forces(lbm3d_t* h, double* out, int64_t cap, int64_t* got) {
+  lbm::TraceRange range("lbm3d_forces");
   if (!h) return LBM_EINVAL;
   if (!h->bound) return h->fail(LBM_ESTATE, "handle is not bound to a workspace");
   if (got) *got = h->nrec;
@@ -508,6 +511,7 @@ int lbm3d_set_body_motion(lbm3d_t* h, const double* u, const double* omega,
 }
 
 int lbm3d_set_mask(lbm3d_t* h, const uint8_t* mask, const int32_t* box, double* impulse) {
+  lbm::TraceRange range("lbm3d_set_mask");
   if (!h || !mask) return LBM_EINVAL;
   lbm3d_grid g = h->g;
   if (box) {

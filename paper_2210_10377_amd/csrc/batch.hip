@@ -17,6 +17,7 @@
 #include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
+#include "trace.h"
 
 using namespace lbm;
 
@@ -403,6 +404,7 @@ int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s) {
 }
 
 int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme) {
+  lbm::TraceRange range("lbm_batch_step");
   if (!b) return LBM_EINVAL;
   if (!b->bound) return b->fail(LBM_ESTATE, "batch is not bound to a workspace");
   if (n < 0) return b->fail(LBM_EINVAL, "n must be >= 0");
@@ -422,6 +424,7 @@ int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme) {
 
 int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
                        lbm_batch_schedule* best, double* ms_per_step) {
+  lbm::TraceRange range("lbm_batch_autotune");
   if (!b) return LBM_EINVAL;
   if (!b->bound) return b->fail(LBM_ESTATE, "batch is not bound to a workspace");
   if (steps < 1) return b->fail(LBM_EINVAL, "steps must be >= 1");
@@ -483,6 +486,7 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
 
 int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
                      uint8_t* nonfinite) {
+  lbm::TraceRange range("lbm_batch_forces");
   if (!b) return LBM_EINVAL;
   if (!b->bound) return b->fail(LBM_ESTATE, "batch is not bound to a workspace");
   const int64_t k = b->nrec;

@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "lbm.h"
 #include "plan.h"
+#include "trace.h"
 
 // The static scratch of every GPU (its host-side name is a stand-in, never a device
 // address: host code uses the address hipGetSymbolAddress gives on each device).
@@ -66,6 +67,7 @@ extern "C" {
 int lbm_step_static(lbm_t* h, void* buf0, void* buf1, size_t buf_bytes, int32_t n,
                     uint32_t force_scheme, double* forces, int64_t cap, void* hip_stream) {
   using namespace lbm;
+  TraceRange range("lbm_step_static");
   if (!h) return LBM_EINVAL;
   if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
   if (force_scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
