@@ -836,7 +836,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_NODE))
-    ap.add_argument("--workload", default="naca8192", choices=["naca8192", "naca2048", "cyl200"])
+    ap.add_argument("--workload", default="naca8192",
+                    choices=["naca8192", "naca2048", "cyl200", "empty8192"],
+                    help="empty8192: the 8192x4096 grid periodic in x and y without a body "
+                         "(every node streams plainly: exactly 2 Q s bytes per node, the "
+                         "counter calibration check)")
     ap.add_argument("--re", type=float, default=1e4)
     ap.add_argument("--aoa", type=float, default=4.0)
     ap.add_argument("--schemes", default="A,B,DRTT,SI,DRTT_POST")
@@ -982,6 +986,10 @@ def main():
         w = workloads.naca_8192x4096(aoa=args.aoa, re=args.re)
     elif args.workload == "naca2048":
         w = workloads.naca_2048x1024(aoa=args.aoa, re=args.re)
+    elif args.workload == "empty8192":
+        w = workloads.Workload("periodic_8192x4096_no_body", 8192, 4096,
+                               np.zeros((4096, 8192), np.uint8), 0.6, np.zeros(4096), None,
+                               0, 0.05, 1.0, bc_x=1, bc_y=1)
     else:
         w = workloads.cylinder_channel_200x80()
     schemes = tuple(s for s in args.schemes.split(",") if s)
@@ -989,8 +997,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box,
-              max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
+    sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box, bc_x=w.bc_x,
+              bc_y=w.bc_y, max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
               device=dev, stream=stream, collision=args.collision, layout=args.layout)
     motion = None
     if args.pitch_rate:
