@@ -835,7 +835,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--precision", default="fp32", choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--precision", default=None, choices=sorted(BYTES_PER_NODE),
+                    help="storage (default: fp32; fp32dev for the adjoint, the resolution "
+                         "sweep and the sphere sweep; fp64 for the small-grid case)")
     ap.add_argument("--workload", default="naca8192",
                     choices=["naca8192", "naca2048", "cyl200", "empty8192"],
                     help="empty8192: the 8192x4096 grid periodic in x and y without a body "
@@ -913,6 +915,8 @@ def main():
                     help="only run a plain device-to-device copy of 1 GiB five times (the "
                          "known-size reference for the HBM byte counters)")
     args = ap.parse_args()
+    explicit_precision = args.precision
+    args.precision = args.precision or "fp32"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the lattice is not decomposed across GPUs "
@@ -942,7 +946,7 @@ def main():
         precision_study(args.study_steps)
         return
     if args.adjoint or args.adjoint_large:
-        adjoint_bench(args.precision if args.precision != "fp32" else "fp32dev",
+        adjoint_bench(explicit_precision or "fp32dev",
                       args.adjoint_large)
         return
     if args.batched:
@@ -959,13 +963,13 @@ def main():
         remask_bench(args.precision)
         return
     if args.small_grid:
-        small_grid_bench(args.precision if args.precision != "fp32" else "fp64",
+        small_grid_bench(explicit_precision or "fp64",
                          args.steps if args.steps != 2000 else 5000)
         return
     if args.sphere_sweep:
         sphere_sweep([int(v) for v in args.sphere_diameters.split(",")],
                      args.convective_times if args.convective_times != 150.0 else 30.0,
-                     args.precision if args.precision != "fp32" else "fp32dev",
+                     explicit_precision or "fp32dev",
                      args.re if args.re != 1e4 else 50.0)
         return
     if args.three_d:
@@ -979,7 +983,7 @@ def main():
         return
     if args.resolution_sweep:
         resolution_sweep([int(v) for v in args.diameters.split(",")], args.convective_times,
-                         args.precision if args.precision != "fp32" else "fp32dev")
+                         explicit_precision or "fp32dev")
         return
 
     if args.workload == "naca8192":

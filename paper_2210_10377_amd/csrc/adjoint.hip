@@ -86,6 +86,11 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
   const int pitch = a.pitch;
   const int x = x0 + (int(threadIdx.x) & 63);
   const C om = C(a.omega);
+  // The running sums of the earlier launches, read before the gathers so that their
+  // latency overlaps them (each slot belongs to this wave alone).
+  const int64_t dslot = int64_t(tile) * kStrips + wave;
+  const double dom_prev = a.domega[dslot];
+  const double duin_prev = x0 == 0 && y0 < a.ny ? a.duin[y0] : 0.0;
   double dom_acc = 0.0;
   if (y0 >= a.ny) {
     // a narrow tile's strip below the last row: nothing to do
@@ -109,38 +114,47 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
     do {
       const int y = y0;
       if (x >= a.nx) break;
-      const uint32_t w = a.node[int64_t(y) * a.nx + x];
-      if (w & kSolidBit) break;
-      const uint32_t aw = a.adj[int64_t(y) * a.nx + x];
       const int32_t o = y * pitch + x;
-      // Transposed pull: the readers of S_k(s) return their adjoints.
+      // Every adjoint value the transposed pull may gather is read unconditionally (all
+      // in bounds) and the codes select among them afterwards: no gather waits for the
+      // adjoint code word.
+      const uint32_t w = a.node[int64_t(y) * a.nx + x];
+      const uint32_t aw = a.adj[int64_t(y) * a.nx + x];
+      C lown[kQ], lfar[kQ], lout[kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) lown[k] = min.ld(k, o);
+#pragma unroll
+      for (int k = 1; k < kQ; ++k) {
+        // The reader s + c_k (periodic images included) ...
+        int dx = x + kCx[k], dy = y + kCy[k];
+        dx = dx < 0 ? dx + a.nx : (dx >= a.nx ? dx - a.nx : dx);
+        dy = dy < 0 ? dy + a.ny : (dy >= a.ny ? dy - a.ny : dy);
+        lfar[k] = min.ld(k, dy * pitch + dx);
+        // ... and the outlet node (nx - 1, s_y + c_ky), which copies S_k(s) for the
+        // directions entering the outlet column from outside (c_kx < 0).
+        lout[k] = kCx[k] < 0 ? min.ld(k, dy * pitch + (a.nx - 1)) : C(0);
+      }
+      if (w & kSolidBit) break;
+      // The pull of f(t) from S(t-1) (its addresses need the node word only) goes out
+      // before the adjoint code word is used.
+      C f[kQ];
+      pull_all<P>(st, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
       C lam[kQ];
-      lam[0] = min.ld(0, o);
+      lam[0] = lown[0];
 #pragma unroll
       for (int k = 1; k < kQ; ++k) {
         const uint32_t ac = adj_code(aw, k);
         C l = 0;
-        if (ac & kAdjStream) l += min.ld(k, o + kCy[k] * pitch + kCx[k]);
-        if (ac & kAdjWrap) {
-          int dx = x + kCx[k], dy = y + kCy[k];
-          dx = dx < 0 ? dx + a.nx : (dx >= a.nx ? dx - a.nx : dx);
-          dy = dy < 0 ? dy + a.ny : (dy >= a.ny ? dy - a.ny : dy);
-          l += min.ld(k, dy * pitch + dx);
-        }
-        if (ac & kAdjOutlet) {
-          int dy = y + kCy[k];
-          dy = dy < 0 ? dy + a.ny : (dy >= a.ny ? dy - a.ny : dy);
-          l += min.ld(k, dy * pitch + (a.nx - 1));
-        }
+        // streaming or a periodic wrap (one reader at most)
+        if (ac & (kAdjStream | kAdjWrap)) l += lfar[k];
+        if (kCx[k] < 0 && (ac & kAdjOutlet)) l += lout[k];
         // Bounce-back at s: the pull of the opposite direction returns S_k(s).
         const uint32_t oc = pull_code(w, kOpp[k]);
-        if (oc == kBody || oc == kWall || oc == kInlet) l += min.ld(kOpp[k], o);
+        if (oc == kBody || oc == kWall || oc == kInlet) l += lown[kOpp[k]];
         // The objective reads S_k(s) on the link (s, k) of the body.
         if (oc == kBody) l += C(a.gx * kCx[k] + a.gy * kCy[k]);
         lam[k] = l;
       }
-      C f[kQ];
-      pull_all<P>(st, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
       C mu[kQ];
       dom_acc += double(collide_vjp<C, S::kDev>(f, lam, om, mu));
 #pragma unroll
@@ -152,14 +166,14 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
         for (int i = 1; i < kQ; ++i)
           if (kCx[i] != 0 && pull_code(w, i) == kInlet)
             g += double(mu[i]) * a.rho_w6 * weight<double>(i) * kCx[i];
-        a.duin[y] += g;
+        a.duin[y] = duin_prev + g;
       }
     } while (false);
   }
   // dJ/domega: one running sum per wave, updated in launch order (deterministic).
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) dom_acc += __shfl_xor(dom_acc, off, 64);
-  if ((threadIdx.x & 63) == 0) a.domega[int64_t(tile) * kStrips + wave] += dom_acc;
+  if ((threadIdx.x & 63) == 0) a.domega[dslot] = dom_prev + dom_acc;
 }
 
 template <class C>

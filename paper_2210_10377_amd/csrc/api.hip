@@ -825,9 +825,33 @@ namespace {
 struct AdjLayout {
   size_t state = 0, mu = 0;  // bytes of one state / adjoint buffer
   int32_t ncp = 0;           // checkpoints
+  int32_t nstore = 1;        // segment stores (two when there are two segments or more)
   size_t off_cp = 0, off_seg = 0, off_mu = 0, off_adj = 0, off_dom = 0, off_duin = 0,
          off_ring = 0, total = 0;
 };
+
+// The second stream and the events of the reverse sweep, created at first use on the
+// device that holds the handle's workspace.
+int ensure_aux(lbm_t* h) {
+  if (h->aux) return LBM_OK;
+  hipPointerAttribute_t attr{};
+  hipError_t e = hipPointerGetAttributes(&attr, h->ws);
+  if (e != hipSuccess) return h->hip_fail(e, "workspace device");
+  int prev = 0;
+  if ((e = hipGetDevice(&prev)) != hipSuccess) return h->hip_fail(e, "current device");
+  if (attr.device != prev && (e = hipSetDevice(attr.device)) != hipSuccess)
+    return h->hip_fail(e, "select workspace device");
+  e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+  hipEvent_t* evs[] = {&h->ev_go, &h->ev_rec[0], &h->ev_rec[1], &h->ev_adj[0], &h->ev_adj[1]};
+  for (hipEvent_t* ev : evs)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  const hipError_t e2 = attr.device != prev ? hipSetDevice(prev) : hipSuccess;
+  if (e != hipSuccess || e2 != hipSuccess) {
+    h->release_aux();
+    return h->hip_fail(e != hipSuccess ? e : e2, "create the recomputation stream");
+  }
+  return LBM_OK;
+}
 
 AdjLayout adj_layout(const lbm_t* h, int32_t n, int32_t every) {
   AdjLayout L;
@@ -838,8 +862,9 @@ AdjLayout adj_layout(const lbm_t* h, int32_t n, int32_t every) {
   size_t off = 0;
   L.off_cp = off;
   off = align256(off + size_t(L.ncp) * align256(L.state));
+  L.nstore = L.ncp >= 2 ? 2 : 1;
   L.off_seg = off;
-  off = align256(off + size_t(every - 1) * align256(L.state));
+  off = align256(off + size_t(L.nstore) * size_t(every - 1) * align256(L.state));
   L.off_mu = off;
   off = align256(off + 2 * align256(L.mu));
   L.off_adj = off;
@@ -892,11 +917,18 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
   if (e != hipSuccess) return h->hip_fail(e, "upload adjoint codes");
   double* ring = reinterpret_cast<double*>(aws + L.off_ring);
   for (int32_t c = 0; c < L.ncp; ++c) {
-    const int32_t len = std::min(every, n_steps - c * every);
+    const int32_t s0 = c * every;
+    const int32_t len = std::min(every, n_steps - s0);
     e = hipMemcpyAsync(aws + L.off_cp + size_t(c) * align256(L.state), h->buf(h->cur), L.state,
                        hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return h->hip_fail(e, "store checkpoint");
-    const int rc = enqueue_own_steps(h, len, ring + int64_t(c) * every * kRow);
+    // Force sums only where the objective reads them (steps t0 .. t0 + T - 1): the
+    // populations do not depend on them.
+    const int32_t w0 = std::clamp(t0 - s0, 0, len), w1 = std::clamp(t0 + T - s0, 0, len);
+    int rc = w0 > 0 ? enqueue_own_steps(h, w0, nullptr) : LBM_OK;
+    if (rc == LBM_OK && w1 > w0)
+      rc = enqueue_own_steps(h, w1 - w0, ring + int64_t(s0 + w0) * kRow);
+    if (rc == LBM_OK && len > w1) rc = enqueue_own_steps(h, len - w1, nullptr);
     if (rc != LBM_OK) return rc;
   }
   std::vector<double> rows(size_t(T) * kRow);
@@ -971,19 +1003,56 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   a.omega = h->omega;
   a.domega = dom;
   a.duin = duin;
+  const int32_t every = h->adj_every;
+  auto seg_len = [&](int32_t c) { return std::min(every, h->adj_n - c * every); };
+  // seg(c, j) = S(c * every - 1 + j): the checkpoint of segment c, then its recomputed
+  // states, in segment store c % nstore.
+  auto seg = [&](int32_t c, int32_t j) -> void* {
+    return j == 0 ? static_cast<void*>(aws + L.off_cp + size_t(c) * align256(L.state))
+                  : static_cast<void*>(aws + L.off_seg +
+                                       (size_t(c % L.nstore) * (every - 1) + size_t(j - 1)) *
+                                           align256(L.state));
+  };
+  auto recompute = [&](int32_t c, hipStream_t s) -> int {
+    const int32_t len = seg_len(c);
+    if (len <= 1) return LBM_OK;
+    return enqueue_steps(h, ws_tables(h), s, len - 1, nullptr, [&](int32_t k) {
+      return std::pair<const void*, void*>(seg(c, k), seg(c, k + 1));
+    });
+  };
+  // With two segment stores the recomputation of segment c - 1 (second stream) runs
+  // while the reverse launches of segment c (the handle's stream) read the other store:
+  // on small grids neither kernel fills the GPU alone.  Events order each recomputation
+  // after the reverse sweep that last read its store, and each sweep after its
+  // recomputation.
+  const bool overlap = L.nstore == 2;
+  if (overlap) {
+    int rc = ensure_aux(h);
+    if (rc != LBM_OK) return rc;
+    if ((e = hipEventRecord(h->ev_go, h->stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(h->aux, h->ev_go, 0)) != hipSuccess)
+      return h->hip_fail(e, "order the recomputation stream");
+    if ((rc = recompute(L.ncp - 1, h->aux)) != LBM_OK) return rc;
+    if ((e = hipEventRecord(h->ev_rec[(L.ncp - 1) & 1], h->aux)) != hipSuccess)
+      return h->hip_fail(e, "record recomputation");
+  }
   int cur = 0;  // mu[cur] holds mu(t+1)
   for (int32_t c = L.ncp - 1; c >= 0; --c) {
-    const int32_t t_first = c * h->adj_every;
-    const int32_t len = std::min(h->adj_every, h->adj_n - t_first);
-    // seg(j) = S(t_first - 1 + j): the checkpoint, then recomputed states.
-    auto seg = [&](int32_t j) -> void* {
-      return j == 0 ? static_cast<void*>(aws + L.off_cp + size_t(c) * align256(L.state))
-                    : static_cast<void*>(aws + L.off_seg + size_t(j - 1) * align256(L.state));
-    };
-    if (len > 1) {
-      const int rc = enqueue_steps(h, ws_tables(h), h->stream, len - 1, nullptr, [&](int32_t k) {
-        return std::pair<const void*, void*>(seg(k), seg(k + 1));
-      });
+    const int32_t t_first = c * every;
+    const int32_t len = seg_len(c);
+    if (overlap) {
+      if (c >= 1) {
+        if (c + 1 < L.ncp && (e = hipStreamWaitEvent(h->aux, h->ev_adj[(c + 1) & 1], 0)) != hipSuccess)
+          return h->hip_fail(e, "order the recomputation stream");
+        const int rc = recompute(c - 1, h->aux);
+        if (rc != LBM_OK) return rc;
+        if ((e = hipEventRecord(h->ev_rec[(c - 1) & 1], h->aux)) != hipSuccess)
+          return h->hip_fail(e, "record recomputation");
+      }
+      if ((e = hipStreamWaitEvent(h->stream, h->ev_rec[c & 1], 0)) != hipSuccess)
+        return h->hip_fail(e, "wait for recomputation");
+    } else {
+      const int rc = recompute(c, h->stream);
       if (rc != LBM_OK) return rc;
     }
     for (int32_t t = t_first + len - 1; t >= t_first; --t) {
@@ -991,13 +1060,15 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
       const double g = in_window ? dJ * 2.0 / h->adj_T : 0.0;
       a.gx = g * h->adj_wx;
       a.gy = g * h->adj_wy;
-      a.state = seg(t - t_first);
+      a.state = seg(c, t - t_first);
       a.mu_in = mu[cur];
       a.mu_out = mu[1 - cur];
       e = launch_adjoint(h->g.precision, a, h->stream);
       if (e != hipSuccess) return h->hip_fail(e, "launch adjoint");
       cur = 1 - cur;
     }
+    if (overlap && (e = hipEventRecord(h->ev_adj[c & 1], h->stream)) != hipSuccess)
+      return h->hip_fail(e, "record reverse sweep");
   }
   std::vector<double> hdom(size_t(p.ntiles) * kStrips);
   e = hipMemcpyAsync(hdom.data(), dom, hdom.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);

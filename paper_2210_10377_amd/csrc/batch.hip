@@ -123,7 +123,7 @@ struct lbm_batch_t {
       for (int j = 0; j < 2; ++j) e.buf[j] = h->buf(h->cur ^ j ^ bpar);
       e.part[0] = h->part(0);
       e.part[1] = h->part(1);
-      e.ring = ring() + int64_t(i) * max_record * kRingRow;
+      e.ring = ring() + int64_t(i) * kRingRow;
       if (h->plan.has_box) {
         e.box = box_args(h, nullptr);
         e.njblocks = h->njblocks;
@@ -495,11 +495,11 @@ int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
   if (nonfinite) std::memset(nonfinite, 0, n);
   if (k == 0) return LBM_OK;
   if (!out || cap < k) return b->fail(LBM_EINVAL, "output holds fewer rows than recorded");
+  // Rows are step-major ([step][instance][kRingRow]): the k recorded steps are one
+  // contiguous block.
   std::vector<double> rows(n * size_t(k) * kRingRow);
-  hipError_t e = hipMemcpy2DAsync(rows.data(), size_t(k) * kRingRow * sizeof(double), b->ring(),
-                                  size_t(b->max_record) * kRingRow * sizeof(double),
-                                  size_t(k) * kRingRow * sizeof(double), n, hipMemcpyDeviceToHost,
-                                  b->stream);
+  hipError_t e = hipMemcpyAsync(rows.data(), b->ring(), rows.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, b->stream);
   if (e != hipSuccess) return b->hip_fail(e, "download force ring");
   e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return b->hip_fail(e, "forces synchronize");
@@ -508,7 +508,7 @@ int lbm_batch_forces(lbm_batch_t* b, double* out, int64_t cap, int64_t* k_out,
     const bool has_box = b->m[i]->plan.has_box;
     bool finite = true;
     for (int64_t t = 0; t < k; ++t)
-      finite = row_forces(&rows[(i * size_t(k) + size_t(t)) * kRingRow], b->rec_scheme[size_t(t)],
+      finite = row_forces(&rows[(size_t(t) * n + i) * kRingRow], b->rec_scheme[size_t(t)],
                           has_box, out + (int64_t(i) * cap + t) * 2 * kSchemes) && finite;
     if (!finite) {
       all_finite = false;

@@ -49,6 +49,22 @@ struct lbm_t {
   int32_t adj_n = 0, adj_every = 0, adj_t0 = 0, adj_T = 0;
   double adj_wx = 0.0, adj_wy = 0.0;
   std::vector<uint32_t> adj_codes;
+  // reverse sweep: recomputation stream and its events (created at first use)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_go = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
+
+  lbm_t() = default;
+  lbm_t(const lbm_t&) = delete;
+  lbm_t& operator=(const lbm_t&) = delete;
+  ~lbm_t() { release_aux(); }
+  void release_aux() {
+    for (hipEvent_t* ev : {&ev_go, &ev_rec[0], &ev_rec[1], &ev_adj[0], &ev_adj[1]}) {
+      if (*ev) (void)hipEventDestroy(*ev);
+      *ev = nullptr;
+    }
+    if (aux) (void)hipStreamDestroy(aux);
+    aux = nullptr;
+  }
 
   int fail(int code, const std::string& msg) {
     err = msg;

@@ -88,7 +88,7 @@ struct BatchInst {
   StepArgs a;               // geometry, tables and physics (src/dst/partials unused)
   void* buf[2];             // the two state buffers
   double* part[2];          // force partial buffers of alternate steps
-  double* ring;             // force rows of the current chunk [rows][kRingRow]
+  double* ring;             // this instance's force row of step 0 ([rows][n_inst][kRingRow])
   BoxArgs box;              // control-volume sweep (src chosen per launch)
   int32_t njblocks;         // blocks of that sweep (0 without a box)
   BodyMotion mot;           // the member's body motion; a.motion and box.motion point here

@@ -366,8 +366,9 @@ void batch_step_kernel(
     if (k == 0 && nprev == 0) return;
     const BatchInst& I = inst[blockIdx.x];
     const int64_t r = int64_t(row_base) + k - 1;
-    reduce_row(I.part[(k - 1) & 1], I.a.nslots, I.a.njslots, I.ring + r * kRingRow,
-               k + nprev >= 2 ? I.ring + (r - 1) * kRingRow + kJnext : nullptr);
+    const int64_t rs = int64_t(b.n_inst) * kRingRow;  // rows are step-major
+    reduce_row(I.part[(k - 1) & 1], I.a.nslots, I.a.njslots, I.ring + r * rs,
+               k + nprev >= 2 ? I.ring + (r - 1) * rs + kJnext : nullptr);
     return;
   }
   const int stride = PERSIST ? int(gridDim.x) - nred : b.total_tiles;
@@ -468,8 +469,9 @@ __global__ __launch_bounds__(kThreads) void batch_finalize_kernel(BatchLaunch b,
   f.red_in = I.part[part_parity];
   f.nslots = I.a.nslots;
   f.njslots = I.a.njslots;
-  f.row = I.ring + int64_t(row) * kRingRow;
-  f.prev_jnext = has_prev ? I.ring + (int64_t(row) - 1) * kRingRow + kJnext : nullptr;
+  const int64_t rs = int64_t(b.n_inst) * kRingRow;  // rows are step-major
+  f.row = I.ring + int64_t(row) * rs;
+  f.prev_jnext = has_prev ? I.ring + (int64_t(row) - 1) * rs + kJnext : nullptr;
   f.jpart = I.njblocks > 0 ? I.box.jpart : nullptr;
   f.njblocks = I.njblocks;
   finalize_body(f);
