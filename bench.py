@@ -598,7 +598,7 @@ def small_grid_bench(precision: str, steps: int):
     print(json.dumps(out), flush=True)
 
 
-def adjoint_bench(precision: str, large: bool = False):
+def adjoint_bench(precision: str, large: bool = False, tile: str = "auto"):
     """Forward (checkpointed) and backward (recompute + reverse kernels) throughput of
     the adjoint workload; MLUPS = nx * ny * steps / wall time of each phase.  `large`:
     the same objective on the 8192 x 4096 airfoil (chord 1024, AoA 4, Re 1e4) over a
@@ -620,7 +620,7 @@ def adjoint_bench(precision: str, large: bool = False):
         w = workloads.naca_1024x512_adjoint()
         n, every, t0, T, develop = 10000, 500, 8000, 2000, 0
     sim = Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=8,
-              u_ref=w.u_ref, l_ref=w.l_ref)
+              u_ref=w.u_ref, l_ref=w.l_ref, tile=tile)
     if develop:
         sim.step(develop, schemes=())
     sim.adjoint_forward(n, every, t0, T)   # warm-up and workspace allocation
@@ -651,6 +651,7 @@ def adjoint_bench(precision: str, large: bool = False):
     bwd_bytes = fluid * (18 * s * recomputed + (9 * s + 18 * s_adj) * n)
     print(json.dumps({
         "metric": "adjoint MLUPS", "workload": w.name, "storage": precision, "steps": n,
+        "tile": tile,
         "developed_steps": develop,
         "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "forward_achieved": round(fwd_bytes / t_f / 1e9, 1),
@@ -901,6 +902,8 @@ def main():
     ap.add_argument("--slab", action="store_true",
                     help="one GPU's share of the benchmark airfoil in an 8-way x-slab "
                          "decomposition (1024 x 4096, periodic x for the halo)")
+    ap.add_argument("--tile", default="auto", choices=["auto", "wide", "narrow"],
+                    help="step-kernel tiles: 256 x 1 (wide), 64 x 4 (narrow), or the plan's rule")
     ap.add_argument("--layout", default="auto", choices=["auto", "rows", "planes"],
                     help="device layout of the state buffers")
     ap.add_argument("--small-grid", action="store_true",
@@ -946,8 +949,7 @@ def main():
         precision_study(args.study_steps)
         return
     if args.adjoint or args.adjoint_large:
-        adjoint_bench(explicit_precision or "fp32dev",
-                      args.adjoint_large)
+        adjoint_bench(explicit_precision or "fp32dev", args.adjoint_large, args.tile)
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
@@ -1001,7 +1003,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box, bc_x=w.bc_x,
+    sim = Sim(w.mask, w.tau, w.uin, precision=args.precision, box=w.box, tile=args.tile, bc_x=w.bc_x,
               bc_y=w.bc_y, max_record=max(K, W, 1), rho_ref=1.0, u_ref=w.u_ref, l_ref=w.l_ref,
               device=dev, stream=stream, collision=args.collision, layout=args.layout)
     motion = None
@@ -1062,7 +1064,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "tau": w.tau,
                    "storage": args.precision, "collision": args.collision,
-                   "layout": args.layout, "schemes": list(schemes),
+                   "layout": args.layout, "tile": args.tile, "schemes": list(schemes),
                    "fluid_nodes": int(info.n_fluid), "links": int(info.n_links),
                    "box_nodes": int(info.n_box), **{k: v for k, v in w.meta.items()},
                    **({"body_motion": {"omega": motion[2], "xc": motion[3], "yc": motion[4]}}

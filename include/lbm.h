@@ -412,6 +412,12 @@ typedef struct lbm_batch_schedule {
   uint32_t tile_order; /* 0: instance-major tile list; otherwise the seed of a
                           pseudo-random permutation of it (results do not depend on
                           the order; it changes only the schedule)                    */
+  int32_t tile_queue;  /* persistent grids only: 0 = each workgroup takes every
+                          grid_blocks-th tile of the list; 1 = workgroups take the
+                          next 16 tiles from a device counter (one global atomic per
+                          16 tiles, reset by a small kernel at each lbm_batch_step
+                          call and by each launch for the next), over a list ordered
+                          largest instance first.  Results do not depend on it.      */
 } lbm_batch_schedule;
 
 typedef struct lbm_batch_info {
@@ -441,18 +447,21 @@ int lbm_batch_workspace_bytes(const lbm_batch_t* b, size_t* bytes);
  * to capture graphs (graphs are launched on the bound stream). */
 int lbm_batch_bind(lbm_batch_t* b, void* device_workspace, size_t bytes, void* hip_stream);
 
-/* Choose the schedule (see lbm_batch_schedule).  LBM_EINVAL for negative values or an
- * odd graph_steps.  Drops captured graphs. */
+/* Choose the schedule (see lbm_batch_schedule).  LBM_EINVAL for negative values, an
+ * odd graph_steps, tile_queue other than 0 or 1, or a tile queue without a persistent
+ * grid.  Drops captured graphs. */
 int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s);
 
-/* Time candidate schedules (one block per tile and persistent grids of 1, 2, 4 and 8
- * workgroups per compute unit, each with direct launches and with graphs of up to 64
- * launches; the tile order is kept) over `steps` steps each, after a warm-up run of the
- * same length, with forces force_scheme (0 = none).  Keeps the fastest and returns it in
- * *best and its milliseconds per step in *ms_per_step (either may be NULL).  Every
- * instance advances by 2 x steps per candidate (20 x steps in all); those force rows are
- * not kept.  LBM_EOVERFLOW if the ring cannot hold `steps` rows beside the rows
- * recorded.  Synchronises the stream. */
+/* Time candidate schedules (one block per tile, and persistent grids of 1, 2, 4 and 8
+ * workgroups per compute unit with the static stride and with the tile queue; each with
+ * direct launches and with graphs of up to 64 launches; the tile order seed is kept)
+ * over `steps` steps each, after a warm-up run of the same length, with forces
+ * force_scheme (0 = none).  Keeps the fastest and returns it in *best and its
+ * milliseconds per step in *ms_per_step (either may be NULL).  Every instance advances
+ * by 2 x steps per candidate (36 x steps in all); those force rows are not kept.
+ * LBM_EOVERFLOW if the ring cannot hold `steps` rows beside the rows recorded;
+ * LBM_ESTATE if a member's control volume changed size since create.  Synchronises the
+ * stream. */
 int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
                        lbm_batch_schedule* best, double* ms_per_step);
 

@@ -63,8 +63,10 @@ class Batch:
         return len(self.members)
 
     # -- schedule ---------------------------------------------------------------------
-    def set_schedule(self, grid_blocks: int = 0, graph_steps: int = 0, tile_order: int = 0):
-        s = C.lbm_batch_schedule(int(grid_blocks), int(graph_steps), int(tile_order))
+    def set_schedule(self, grid_blocks: int = 0, graph_steps: int = 0, tile_order: int = 0,
+                     tile_queue: int = 0):
+        s = C.lbm_batch_schedule(int(grid_blocks), int(graph_steps), int(tile_order),
+                                 int(tile_queue))
         C.check_batch(self._lib.lbm_batch_set_schedule(self._h, ctypes.byref(s)), self._h)
 
     def autotune(self, steps: int = 10, schemes=ALL_SCHEMES):
@@ -75,7 +77,7 @@ class Batch:
         C.check_batch(self._lib.lbm_batch_autotune(self._h, int(steps), scheme_mask(schemes),
                                                    ctypes.byref(best), ctypes.byref(ms)), self._h)
         return ({"grid_blocks": best.grid_blocks, "graph_steps": best.graph_steps,
-                 "tile_order": best.tile_order}, ms.value)
+                 "tile_order": best.tile_order, "tile_queue": best.tile_queue}, ms.value)
 
     def info(self) -> C.lbm_batch_info:
         inf = C.lbm_batch_info()
@@ -87,7 +89,7 @@ class Batch:
         C.check_batch(self._lib.lbm_batch_step(self._h, int(n), scheme_mask(schemes)), self._h)
 
     def forces(self):
-        """(F [n_inst, k, 4 (A, B, DRTT, SI), 2 (x, y)], nonfinite bool [n_inst]) of the steps
+        """(F [n_inst, k, 5 (A, B, DRTT, SI, DRTT-post), 2 (x, y)], nonfinite bool [n_inst]) of the steps
         recorded since the last call."""
         k = self.info().n_recorded
         n = len(self.members)

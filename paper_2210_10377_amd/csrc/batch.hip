@@ -92,16 +92,25 @@ struct lbm_batch_t {
     tile_local.clear();
     box_inst.clear();
     box_local.clear();
-    for (size_t i = 0; i < m.size(); ++i) {
+    // Instance order of the tile list: as given, or largest first for the tile queue
+    // (the longest instances start first; ties keep the given order).
+    std::vector<size_t> order(m.size());
+    for (size_t i = 0; i < m.size(); ++i) order[i] = i;
+    if (sched.tile_queue)
+      std::stable_sort(order.begin(), order.end(), [&](size_t p, size_t q) {
+        return int64_t(m[p]->g.nx) * m[p]->g.ny > int64_t(m[q]->g.nx) * m[q]->g.ny;
+      });
+    for (size_t i : order) {
       for (int t = 0; t < m[i]->plan.ntiles; ++t) {
         tile_inst.push_back(int32_t(i));
         tile_local.push_back(t);
       }
+    }
+    for (size_t i = 0; i < m.size(); ++i)
       for (int t = 0; t < m[i]->njblocks; ++t) {
         box_inst.push_back(int32_t(i));
         box_local.push_back(t);
       }
-    }
     if (sched.tile_order != 0) {
       uint64_t s = sched.tile_order;
       for (size_t k = tile_inst.size(); k > 1; --k) {
@@ -155,6 +164,9 @@ struct lbm_batch_t {
     L.box_inst = reinterpret_cast<const int32_t*>(ws + off_bi);
     L.box_local = reinterpret_cast<const int32_t*>(ws + off_bl);
     L.ctl = reinterpret_cast<const int32_t*>(ws + off_ctl);
+    // The tile counters sit in the control word's block, after its two words.
+    L.queue = sched.tile_queue && sched.grid_blocks > 0
+                  ? reinterpret_cast<int32_t*>(ws + off_ctl) + 2 : nullptr;
     L.n_inst = int32_t(m.size());
     L.nred = nred();
     L.total_tiles = int32_t(total_tiles);
@@ -180,6 +192,15 @@ struct lbm_batch_t {
     if (rc != LBM_OK) return rc;
     const hipError_t e = hipStreamSynchronize(stream);
     return e == hipSuccess ? LBM_OK : hip_fail(e, "upload synchronize");
+  }
+
+  // Take schedule s; the tile list is rebuilt and uploaded when its order changes.
+  int use_schedule(const lbm_batch_schedule& s) {
+    const bool reorder = s.tile_order != sched.tile_order || s.tile_queue != sched.tile_queue;
+    sched = s;
+    if (!reorder) return LBM_OK;
+    build_lists();
+    return bound ? upload_lists() : LBM_OK;
   }
 
   // Bring the device instance table up to date with the members (a member stepped,
@@ -239,6 +260,10 @@ struct lbm_batch_t {
     if (rc != LBM_OK) return rc;
     const BatchLaunch L = launch();
     const int G = sched.graph_steps;
+    if (L.queue) {
+      const hipError_t e = launch_batch_queue_reset(L.queue, stream);
+      if (e != hipSuccess) return hip_fail(e, "reset tile queue");
+    }
     int32_t done = 0;
     while (done < n) {
       const int len = G > 0 ? std::min<int32_t>(G, n - done) : n - done;
@@ -345,7 +370,7 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
   b->off_bl = off;
   off = align256(off + size_t(b->total_box) * 4);
   b->off_ctl = off;
-  off = align256(off + 2 * sizeof(int32_t));
+  off = align256(off + 4 * sizeof(int32_t));  // control words, then the two tile counters
   b->off_ring = off;
   off = align256(off + size_t(n) * size_t(max_record) * kRingRow * sizeof(double));
   b->total = off;
@@ -391,16 +416,15 @@ int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s) {
   if (!b || !s) return LBM_EINVAL;
   if (s->grid_blocks < 0 || s->graph_steps < 0 || (s->graph_steps & 1))
     return b->fail(LBM_EINVAL, "grid_blocks and graph_steps must be >= 0, graph_steps even");
-  const bool reorder = s->tile_order != b->sched.tile_order;
+  if (s->tile_queue != 0 && s->tile_queue != 1)
+    return b->fail(LBM_EINVAL, "tile_queue must be 0 or 1");
+  if (s->tile_queue && s->grid_blocks == 0)
+    return b->fail(LBM_EINVAL, "the tile queue needs a persistent grid (grid_blocks > 0)");
+  const bool reorder = s->tile_order != b->sched.tile_order || s->tile_queue != b->sched.tile_queue;
   if (reorder && !b->sizes_kept())
     return b->fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
   b->drop_graphs();
-  b->sched = *s;
-  if (reorder) {
-    b->build_lists();
-    if (b->bound) return b->upload_lists();
-  }
-  return LBM_OK;
+  return b->use_schedule(*s);
 }
 
 int lbm_batch_step(lbm_batch_t* b, int32_t n, uint32_t force_scheme) {
@@ -432,6 +456,9 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
   const bool forces = force_scheme != 0;
   if (forces && b->nrec + steps > b->max_record)
     return b->fail(LBM_EOVERFLOW, "force ring cannot hold the timed steps");
+  // Candidates reorder the tile list, which is sized for the members at create.
+  if (!b->sizes_kept())
+    return b->fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
   const int gsteps = std::max(2, std::min(64, steps / 2 * 2));
   const int per_cu[] = {0, 1, 2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -446,12 +473,16 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
   double win_ms = INFINITY;
   int rc = LBM_OK;
   for (int pc : per_cu) {
-    for (int use_graph = 0; use_graph < 2 && rc == LBM_OK; ++use_graph) {
+    // One workgroup per tile: direct launches or graphs; persistent grids: the same
+    // with the static stride and with the tile queue.
+    for (int cand = 0; cand < (pc > 0 ? 4 : 2) && rc == LBM_OK; ++cand) {
       lbm_batch_schedule s = keep;
       s.grid_blocks = pc * b->cus;
-      s.graph_steps = use_graph ? gsteps : 0;
+      s.graph_steps = (cand & 1) ? gsteps : 0;
+      s.tile_queue = cand >> 1;
       b->drop_graphs();
-      b->sched = s;
+      rc = b->use_schedule(s);
+      if (rc != LBM_OK) break;
       // Warm-up of the same length (captures the graphs), then the timed run.
       rc = b->enqueue(steps, forces, b->nrec);
       if (rc != LBM_OK) break;
@@ -477,8 +508,9 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->drop_graphs();
-  b->sched = rc == LBM_OK ? win : keep;
+  const int rc2 = b->use_schedule(rc == LBM_OK ? win : keep);
   if (rc != LBM_OK) return rc;
+  if (rc2 != LBM_OK) return rc2;
   if (best) *best = win;
   if (ms_per_step) *ms_per_step = win_ms;
   return LBM_OK;

@@ -94,6 +94,9 @@ struct BatchInst {
   BodyMotion mot;           // the member's body motion; a.motion and box.motion point here
 };
 
+// Tiles taken per atomic of the batch's tile queue.
+constexpr int kQueueChunk = 16;
+
 struct BatchLaunch {
   const BatchInst* inst;     // [n_inst], device
   const int32_t* tile_inst;  // [total_tiles] instance of each tile, device
@@ -101,6 +104,7 @@ struct BatchLaunch {
   const int32_t* box_inst;   // [total_box_blocks] instance of each box-sweep block
   const int32_t* box_local;  // [total_box_blocks] block index inside its instance's sweep
   const int32_t* ctl;        // {first force row of the launch sequence, steps before it}
+  int32_t* queue;            // two tile counters of the queue schedule (launch parity), or null
   int32_t n_inst, nred;      // instances; reducer blocks (n_inst rounded up to 8)
   int32_t total_tiles, total_box_blocks;
   int32_t grid_blocks;       // tile blocks per launch (0: one block per tile)
@@ -145,6 +149,8 @@ hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double*
 hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, int32_t parity,
                              int32_t k, hipStream_t s);
 hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s);
+// Zeroes both tile counters of the queue schedule (before a call's first launch).
+hipError_t launch_batch_queue_reset(int32_t* queue, hipStream_t s);
 // Control-volume sweeps over buffer `parity` and finalization of force row `row` of every
 // instance (the last step of a call; its partials are in part[part_parity]).
 hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity, int32_t row,

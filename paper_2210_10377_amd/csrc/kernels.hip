@@ -371,6 +371,32 @@ void batch_step_kernel(
                k + nprev >= 2 ? I.ring + (r - 1) * rs + kJnext : nullptr);
     return;
   }
+  if (PERSIST && b.queue) {
+    // Tile queue: each workgroup takes the next chunk of kQueueChunk consecutive tiles of
+    // the list from counter k & 1 (one global atomic per chunk: the counter's atomics
+    // are serialised, one per ~13 ns, so a tile each would bound a launch of 50 k tiles
+    // at 0.65 ms) until the list is exhausted; the first tile workgroup zeroes the other
+    // counter for the next launch (the launch before this one, its last user, has
+    // completed).
+    __shared__ int32_t next;
+    if (int(blockIdx.x) == nred && threadIdx.x == 0) b.queue[(k + 1) & 1] = 0;
+    for (;;) {
+      if (threadIdx.x == 0) next = atomicAdd(&b.queue[k & 1], 1);
+      __syncthreads();
+      const int t0 = next * kQueueChunk;
+      __syncthreads();
+      if (t0 >= b.total_tiles) return;
+      const int t1 = min(t0 + kQueueChunk, b.total_tiles);
+      for (int t = t0; t < t1; ++t) {
+        const BatchInst& I = inst[tile_inst[t]];
+        StepArgs a = I.a;
+        a.src = I.buf[parity];
+        a.dst = I.buf[1 - parity];
+        a.part_out = I.part[k & 1];
+        step_tile<P, true, FORCES, COLL, MOV>(a, tile_local[t], a.strip_slot);
+      }
+    }
+  }
   const int stride = PERSIST ? int(gridDim.x) - nred : b.total_tiles;
   for (int v = int(blockIdx.x) - nred; v < b.total_tiles; v += stride) {
     const int t = block_tile<kBatchGroup>(v, b.total_tiles);
@@ -690,6 +716,15 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
 #undef LBM_BATCH_GO
 #undef LBM_BATCH_GO3
 #undef LBM_BATCH_GO4
+  return hipGetLastError();
+}
+
+__global__ void batch_queue_reset_kernel(int32_t* queue) {
+  if (threadIdx.x < 2) queue[threadIdx.x] = 0;
+}
+
+hipError_t launch_batch_queue_reset(int32_t* queue, hipStream_t s) {
+  hipLaunchKernelGGL(batch_queue_reset_kernel, dim3(1), dim3(64), 0, s, queue);
   return hipGetLastError();
 }
 

@@ -53,7 +53,9 @@ def mini_refs(orc):
 
 
 @pytest.mark.parametrize("name", [m[0] for m in MINI])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 2e-4), ("fp32", 2e-3)])
+# Measured: FP64 ~1e-14; FP32 deviations up to 1.2e-6; FP32 up to 6.6e-6 (tau of the
+# airfoil channel).  The bounds keep about an order of magnitude of margin.
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-5), ("fp32", 5e-5)])
 def test_adjoint_matches_complex_step(mini_refs, name, precision, tol):
     r = mini_refs[name]
     n, every, t0, T, w, bcy = r["cfg"]
@@ -194,7 +196,8 @@ def test_adjoint_whole_tile_rounds_and_tail(orc):
     J_ref = orc.objective(mask, 1 / tau, uin, n, t0, T, w=w).real
     d_tau = orc.objective(mask, 1 / complex(tau, h), uin, n, t0, T, w=w).imag / h
     d_v = orc.objective(mask, 1 / tau, uin + 1j * h * v, n, t0, T, w=w).imag / h
-    for precision, tol in (("fp64", 1e-9), ("fp32dev", 2e-4)):
+    # measured: FP64 ~2e-14, FP32 deviations ~8e-7
+    for precision, tol in (("fp64", 1e-9), ("fp32dev", 1e-5)):
         g = _sim(mask, tau, uin, precision)
         J = g.adjoint_forward(n, every, t0, T, w)
         gu, gt = g.adjoint_backward(1.0)

@@ -78,6 +78,8 @@ SCHEDULES = {
     "persistent_small_grid": dict(grid_blocks=24, graph_steps=0),
     "graph_chunks": dict(grid_blocks=0, graph_steps=8),
     "persistent_graph_shuffled": dict(grid_blocks=40, graph_steps=4, tile_order=12345),
+    "tile_queue": dict(grid_blocks=24, graph_steps=0, tile_queue=1),
+    "tile_queue_graph_shuffled": dict(grid_blocks=40, graph_steps=4, tile_order=777, tile_queue=1),
 }
 
 
@@ -192,13 +194,16 @@ def test_autotune_keeps_results_bitwise():
     sched, ms = b.autotune(steps=4)
     assert ms > 0
     assert sched["graph_steps"] in (0, 4)
-    assert b.info().steps_done == 5 * 2 * 2 * 4
+    assert sched["tile_queue"] in (0, 1) and (sched["grid_blocks"] > 0 or not sched["tile_queue"])
+    # one block per tile: 2 candidates; 4 persistent grids x (stride, queue) x 2: 16
+    n_tune = (2 + 16) * 2 * 4
+    assert b.info().steps_done == n_tune
     b.step(7)
     Fb, _ = b.forces()
     ref = _members(ws)
     _seed_states(ref, ws)
     for i, r in enumerate(ref):
-        r.step(5 * 2 * 2 * 4, schemes=())
+        r.step(n_tune, schemes=())
         r.step(7)
         np.testing.assert_array_equal(r.forces(), Fb[i])
         np.testing.assert_array_equal(r.populations(), b.members[i].populations())
@@ -349,3 +354,15 @@ def test_batch_mixing_state_layouts_bitwise_equals_singles():
         r.step(21)
         np.testing.assert_array_equal(r.forces(), Fb[i])
         np.testing.assert_array_equal(r.populations(), b.members[i].populations())
+
+
+def test_schedule_validation():
+    """A tile queue needs a persistent grid; tile_queue takes 0 or 1."""
+    from paper_2210_10377_amd import LbmError
+    b = _batch(MINI[:2])
+    with pytest.raises(LbmError):
+        b.set_schedule(grid_blocks=0, tile_queue=1)
+    with pytest.raises(LbmError):
+        b.set_schedule(grid_blocks=16, tile_queue=2)
+    b.set_schedule(grid_blocks=16, tile_queue=1)
+    assert b.info().schedule.tile_queue == 1
