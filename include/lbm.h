@@ -352,8 +352,8 @@ int lbm_reset(lbm_t* h);
  *
  * lbm_adjoint_bytes: device workspace for a run of n_steps with a checkpoint every
  * `every` steps (1 <= every <= n_steps): ceil(n/every) checkpoints, two stores of every-1
- * recomputed states (one when there is a single segment), two adjoint fields and the
- * per-step force rows.
+ * recomputed states on grids of at most 16,384 tiles (one on larger grids or when there
+ * is a single segment), two adjoint fields and the per-step force rows.
  *
  * lbm_adjoint_forward: run the n_steps (the handle's state advances, as lbm_step would
  * advance it; the force ring is not touched), storing the checkpoints in the caller's
@@ -363,10 +363,10 @@ int lbm_reset(lbm_t* h);
  *
  * lbm_adjoint_backward: reverse sweep over the stored run: each segment between
  * checkpoints is recomputed forward, then the adjoint kernel runs one launch per step
- * backwards.  The recomputation of the next segment runs on a second stream of the
- * library's own (created at the first call, default priority, released by lbm_destroy)
- * while the reverse launches of the current one run on the handle's stream; events
- * order the two, and the call returns after both.  Writes dJ/du_in(y) * dJ (ny host values) to grad_uin and dJ/dtau * dJ to
+ * backwards.  On grids of at most 16,384 tiles the recomputation of the next segment
+ * runs on a second stream of the library's own (created at the first call, default
+ * priority, released by lbm_destroy) while the reverse launches of the current one run
+ * on the handle's stream; events order the two, and the call returns after both.  Writes dJ/du_in(y) * dJ (ny host values) to grad_uin and dJ/dtau * dJ to
  * *grad_tau, where dJ is the incoming seed.  The adjoint fields are kept in the
  * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
  * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is

@@ -25,6 +25,13 @@ namespace {
 #ifndef LBM_PITCH_PAD
 #define LBM_PITCH_PAD 128
 #endif
+// The reverse sweep overlaps the recomputation of the next segment with the reverse
+// launches of the current one only on grids of at most this many tiles: a launch of
+// 2,048 tiles (1024 x 512) is one wave of workgroups over the chip and leaves room
+// beside it, while a launch of 131,072 (8192 x 4096) fills the chip and HBM alone.
+#ifndef LBM_ADJ_OVERLAP_MAX_TILES
+#define LBM_ADJ_OVERLAP_MAX_TILES 16384
+#endif
 #ifndef LBM_PLANE_PAD_ROWS
 #define LBM_PLANE_PAD_ROWS 0
 #endif
@@ -862,7 +869,7 @@ AdjLayout adj_layout(const lbm_t* h, int32_t n, int32_t every) {
   size_t off = 0;
   L.off_cp = off;
   off = align256(off + size_t(L.ncp) * align256(L.state));
-  L.nstore = L.ncp >= 2 ? 2 : 1;
+  L.nstore = L.ncp >= 2 && h->plan.ntiles <= LBM_ADJ_OVERLAP_MAX_TILES ? 2 : 1;
   L.off_seg = off;
   off = align256(off + size_t(L.nstore) * size_t(every - 1) * align256(L.state));
   L.off_mu = off;
@@ -1020,11 +1027,11 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
       return std::pair<const void*, void*>(seg(c, k), seg(c, k + 1));
     });
   };
-  // With two segment stores the recomputation of segment c - 1 (second stream) runs
-  // while the reverse launches of segment c (the handle's stream) read the other store:
-  // on small grids neither kernel fills the GPU alone.  Events order each recomputation
-  // after the reverse sweep that last read its store, and each sweep after its
-  // recomputation.
+  // With two segment stores (small grids, LBM_ADJ_OVERLAP_MAX_TILES) the recomputation
+  // of segment c - 1 (second stream) runs while the reverse launches of segment c (the
+  // handle's stream) read the other store: neither kernel fills the GPU alone there.
+  // Events order each recomputation after the reverse sweep that last read its store,
+  // and each sweep after its recomputation.
   const bool overlap = L.nstore == 2;
   if (overlap) {
     int rc = ensure_aux(h);
