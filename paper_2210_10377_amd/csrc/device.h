@@ -33,9 +33,9 @@ __device__ __forceinline__ float weight_lo(int i) {
   constexpr float lo2 = float(1.0 / 36.0 - double(1.0f / 36.0f));
   return i == 0 ? lo0 : (i < 5 ? lo1 : lo2);
 }
-template <class C>
+template <class C, bool EXACT = true>
 __device__ __forceinline__ C wmul(int i, C x) {
-  if constexpr (sizeof(C) == 8)
+  if constexpr (sizeof(C) == 8 || !EXACT)
     return weight<C>(i) * x;
   else
     return __builtin_fmaf(weight<float>(i), x, weight_lo(i) * x);
@@ -46,11 +46,15 @@ __device__ __forceinline__ C wmul(int i, C x) {
 template <int P>
 struct Storage;
 
+// kExactW: the equilibrium carries the binary32 weights' remainders (wmul); binary16
+// storage rounds at 2^-11, far above the 2^-27 of the bare binary32 weights, and skips
+// the two extra operations per weight.
 template <>
 struct Storage<LBM_FP64> {
   using T = double;
   using C = double;
   static constexpr bool kDev = false;
+  static constexpr bool kExactW = true;
 };
 
 template <>
@@ -58,6 +62,7 @@ struct Storage<LBM_FP32> {
   using T = float;
   using C = float;
   static constexpr bool kDev = false;
+  static constexpr bool kExactW = true;
 };
 
 template <>
@@ -65,6 +70,7 @@ struct Storage<LBM_FP32DEV> {
   using T = float;
   using C = float;
   static constexpr bool kDev = true;
+  static constexpr bool kExactW = true;
 };
 
 template <>
@@ -72,6 +78,7 @@ struct Storage<LBM_FP16DEV> {
   using T = _Float16;
   using C = float;
   static constexpr bool kDev = true;
+  static constexpr bool kExactW = false;
 };
 
 // Stored value -> arithmetic value (f, or h for deviation storages) and back (binary16:
@@ -174,7 +181,7 @@ struct Planes<T, false> {
 // rho u = sum c_i h_i, f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 -
 // 1.5 u^2)] and Pi^neq = sum c c h - rho u u - (rho - 1) I/3, so no quantity of order one
 // is formed except the entropic weights f^eq_i.
-template <class C, bool DEV, int COLL>
+template <class C, bool DEV, int COLL, bool EXACT = true>
 __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
   const C s = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const C jx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
@@ -189,7 +196,7 @@ __device__ __forceinline__ void collide(const C (&f)[kQ], C omega, C (&g)[kQ]) {
   for (int i = 0; i < kQ; ++i) {
     const C cu = C(kCx[i]) * ux + C(kCy[i]) * uy;
     const C poly = C(3) * cu + C(4.5) * cu * cu - usq;
-    fe[i] = DEV ? wmul<C>(i, s + rho * poly) : wmul<C>(i, rho * (C(1) + poly));
+    fe[i] = DEV ? wmul<C, EXACT>(i, s + rho * poly) : wmul<C, EXACT>(i, rho * (C(1) + poly));
   }
   if constexpr (COLL == LBM_COLL_BGK) {
 #pragma unroll

@@ -72,7 +72,7 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int x0, int y
 #pragma unroll
   for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
   C g[kQ];
-  collide<C, S::kDev, COLL>(f, C(a.omega), g);
+  collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const T q = pack<P>(g[i]);
@@ -105,7 +105,7 @@ __device__ __forceinline__ void edge_strip(const StepArgs& a, int x0, int y) {
   C f[kQ];
   pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f);
   C g[kQ];
-  collide<C, S::kDev, COLL>(f, C(a.omega), g);
+  collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
   const int32_t o = y * pitch + x;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
@@ -170,7 +170,7 @@ __device__ __forceinline__ void ring_finish(const StepArgs& a, int x0, int y0,
 #pragma unroll
   for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
   C g[kQ];
-  collide<C, S::kDev, COLL>(f, C(a.omega), g);
+  collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
   T s[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -200,7 +200,7 @@ __device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, 
     C f[kQ];
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, MOV ? a.motion : nullptr);
     C g[kQ];
-    collide<C, S::kDev, COLL>(f, C(a.omega), g);
+    collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
     T s[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
