@@ -294,3 +294,40 @@ def test_adjoint_on_a_grid_above_the_overlap_threshold():
     assert np.abs(gu0).max() > 0 and gt0 != 0
     np.testing.assert_allclose(gu0, gu1, rtol=1e-12, atol=1e-16)
     assert abs(gt0 - gt1) <= 1e-12 * abs(gt1)
+
+
+def test_adjoint_full_inlet_gradient_128x64(orc):
+    """The whole gradient of a 128 x 64 miniature (cylinder between walls, 1000 steps,
+    mean drag over the last 200, checkpoint every 100): all 64 inlet rows and tau by
+    complex-step differentiation through the oracle, one oracle run per component,
+    against the GPU adjoint in FP64 (1e-9 of the largest component) and in the 32-bit
+    storages (1e-5 / 5e-5, the mini-channel bounds)."""
+    import os
+
+    import oracle
+    nx, ny = 128, 64
+    mask = workloads.cylinder_mask(nx, ny, 32, 31.5, 6)
+    y = np.arange(ny)
+    uin = 0.03 + 0.02 * np.sin(np.pi * (y + 0.5) / ny)
+    tau, n, every, t0, T, w = 0.7, 1000, 100, 800, 200, (1.0, 0.0)
+    h = 1e-30
+    prev = oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    try:
+        ref_u = np.empty(ny)
+        for r in range(ny):
+            e = np.zeros(ny)
+            e[r] = 1.0
+            ref_u[r] = orc.objective(mask, 1 / tau, uin + 1j * h * e, n, t0, T, w=w).imag / h
+        ref_t = orc.objective(mask, 1 / complex(tau, h), uin, n, t0, T, w=w).imag / h
+    finally:
+        oracle.set_threads(prev)
+    scale = np.abs(ref_u).max()
+    assert scale > 0 and ref_t != 0
+    for precision, tol in (("fp64", 1e-9), ("fp32dev", 1e-5), ("fp32", 5e-5)):
+        g = _sim(mask, tau, uin, precision)
+        g.adjoint_forward(n, every, t0, T, w)
+        gu, gt = g.adjoint_backward(1.0)
+        e_u = np.abs(gu - ref_u).max() / scale
+        e_t = abs(gt - ref_t) / abs(ref_t)
+        print("128x64 full gradient", precision, "rel errors rows", e_u, "tau", e_t)
+        assert e_u <= tol and e_t <= tol, precision
