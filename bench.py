@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS incl. per-step force + HBM GB/s % peak; adjoint MLUPS; Cd rel err vs FP64"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp32dev": 72, "fp16dev": 36}
+BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp32dev": 72, "fp32sr": 72, "fp16dev": 36}
 CSRC = os.path.join(ROOT, "paper_2210_10377_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 BATCH_WORKLOAD = "batched_256_cylinder_naca0012_64x32_to_512x256"
@@ -178,8 +178,9 @@ def uniform_flow_state(w):
 
 
 def precision_study(steps: int):
-    """FP32 and FP16-deviation storage against FP64 storage (itself matched to the
-    oracle to 1e-10) on the 2048x1024 NACA0012 channel.  Coefficient errors are relative
+    """The 32-bit storages (binary32 populations rounded to nearest, binary32 deviations,
+    binary32 populations rounded stochastically) and FP16-deviation storage against FP64
+    storage (itself matched to the oracle to 1e-10) on the 2048x1024 NACA0012 channel.  Coefficient errors are relative
     to the largest FP64 coefficient magnitude of the run (per step) and to the FP64 mean
     over the last 2000 steps (window means); velocity errors are relative to the inlet
     speed."""
@@ -198,7 +199,7 @@ def precision_study(steps: int):
         for re in (100.0, 1000.0):
             w = workloads.naca_2048x1024(aoa=aoa, re=re)
             runs = {}
-            for prec in ("fp64", "fp32", "fp32dev", "fp16dev"):
+            for prec in ("fp64", "fp32", "fp32dev", "fp32sr", "fp16dev"):
                 sim = Sim(w.mask, w.tau, w.uin, precision=prec, box=w.box, max_record=5000,
                           u_ref=w.u_ref, l_ref=w.l_ref)
                 t0 = time.perf_counter()
@@ -212,7 +213,7 @@ def precision_study(steps: int):
             out = {"case": w.name, "steps": steps, "tau": w.tau,
                    "fp64_window_mean": {s: C64[-2000:, k].mean(0).tolist()
                                         for k, s in enumerate(names)}}
-            for prec in ("fp32", "fp32dev", "fp16dev"):
+            for prec in ("fp32", "fp32dev", "fp32sr", "fp16dev"):
                 C, (u, v), wall = runs[prec]
                 e = {}
                 for k, s in enumerate(names):
@@ -725,7 +726,7 @@ def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
         "metric": "batched MLUPS incl. per-step forces",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "ms_per_step": round(ms / steps, 5), "higher_is_better": True,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32", "fp32sr": "f32",
                   "fp16dev": "f16 storage / f32 arithmetic"}[precision],
         "data": "synthetic",
         "config": {"workload": BATCH_WORKLOAD,
@@ -795,7 +796,7 @@ def three_d_bench(precision: str, steps: int, warmup: int, ppc: int, re: float,
         "value": round(nodes / t_step / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": round(ms / steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32", "fp32sr": "f32",
                   "fp16dev": "f16 storage / f32 arithmetic"}[precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "tau": w.tau,
@@ -845,7 +846,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default=None, choices=sorted(BYTES_PER_NODE),
                     help="storage (default: fp32; fp32dev for the adjoint, the resolution "
-                         "sweep and the sphere sweep; fp64 for the small-grid case)")
+                         "sweep and the sphere sweep; fp64 for the small-grid case; fp32sr, "
+                         "binary32 populations rounded stochastically, for single 2-D "
+                         "lattices only)")
     ap.add_argument("--workload", default="naca8192",
                     choices=["naca8192", "naca2048", "cyl200", "empty8192"],
                     help="empty8192: the 8192x4096 grid periodic in x and y without a body "
@@ -1080,7 +1083,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32dev": "f32", "fp32sr": "f32",
                   "fp16dev": "f16 storage / f32 arithmetic"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "tau": w.tau,

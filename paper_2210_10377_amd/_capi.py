@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE, LBM_EOVERFLOW = (
     0, -1, -2, -3, -4, -5, -6)
-LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_FP32DEV = 0, 1, 2, 3
+LBM_FP64, LBM_FP32, LBM_FP16DEV, LBM_FP32DEV, LBM_FP32SR = 0, 1, 2, 3, 4
 LBM_BCX_INLET_OUTLET, LBM_BCX_PERIODIC = 0, 1
 LBM_BCY_WALL, LBM_BCY_PERIODIC = 0, 1
 LBM_FORCE_MEA_A, LBM_FORCE_MEA_B, LBM_FORCE_DRTT, LBM_FORCE_SI = 1, 2, 4, 8

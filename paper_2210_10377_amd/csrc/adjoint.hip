@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjArgs a) {
 #pragma unroll
       for (int k = 0; k < kQ; ++k) lam[k] = min.ld(k, o + kCy[k] * pitch + kCx[k]);
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(st.ld(i, o - kCy[i] * pitch - kCx[i]));
+      for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(st.ld(i, o - kCy[i] * pitch - kCx[i]), i);
       C mu[kQ];
       dom_acc += double(collide_vjp<C, S::kDev>(f, lam, om, mu));
 #pragma unroll
@@ -199,7 +199,8 @@ hipError_t launch_adjoint(int precision, const AdjArgs& a, hipStream_t s) {
     case LBM_FP64: return adjoint_dispatch<LBM_FP64>(a, s);
     case LBM_FP32: return adjoint_dispatch<LBM_FP32>(a, s);
     case LBM_FP32DEV: return adjoint_dispatch<LBM_FP32DEV>(a, s);
-    default: return adjoint_dispatch<LBM_FP16DEV>(a, s);
+    case LBM_FP16DEV: return adjoint_dispatch<LBM_FP16DEV>(a, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -334,7 +334,7 @@ namespace {
 // the J of the following step, or of the pull after the last one, is stored with it).
 template <class IO>
 int enqueue_steps(lbm_t* h, const DevTables& t, hipStream_t stream, int32_t n, double* ring,
-                  IO&& io) {
+                  int64_t step0, IO&& io) {
   const Plan& p = h->plan;
   const bool forces = ring != nullptr;
   StepArgs a = step_args(h, t);
@@ -343,6 +343,7 @@ int enqueue_steps(lbm_t* h, const DevTables& t, hipStream_t stream, int32_t n, d
     const auto sd = io(k);
     a.src = sd.first;
     a.dst = sd.second;
+    a.step_key = sr_step_key(step0 + k);
     last = sd.second;
     a.part_out = forces ? t.part[k & 1] : nullptr;
     a.red_in = nullptr;
@@ -379,7 +380,7 @@ int enqueue_steps(lbm_t* h, const DevTables& t, hipStream_t stream, int32_t n, d
 // n steps on the handle's own ping-pong state buffers.
 int enqueue_own_steps(lbm_t* h, int32_t n, double* ring) {
   const int c0 = h->cur;
-  const int rc = enqueue_steps(h, ws_tables(h), h->stream, n, ring, [&](int32_t k) {
+  const int rc = enqueue_steps(h, ws_tables(h), h->stream, n, ring, h->steps_done, [&](int32_t k) {
     const int s = (c0 + k) & 1;
     return std::pair<const void*, void*>(h->buf(s), h->buf(1 - s));
   });
@@ -396,7 +397,7 @@ namespace lbm {
 
 int enqueue_pingpong(lbm_t* h, const DevTables& t, void* b0, void* b1, hipStream_t stream,
                      int32_t n, double* ring) {
-  return enqueue_steps(h, t, stream, n, ring, [&](int32_t k) {
+  return enqueue_steps(h, t, stream, n, ring, 0, [&](int32_t k) {
     return (k & 1) ? std::pair<const void*, void*>(b1, b0) : std::pair<const void*, void*>(b0, b1);
   });
 }
@@ -902,7 +903,7 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
                         int32_t t0, int32_t T, double wx, double wy, double* J) {
   TraceRange range("lbm_adjoint_forward");
   if (!h) return LBM_EINVAL;
-  if (h->g.precision == LBM_FP16DEV)
+  if (h->g.precision == LBM_FP16DEV || h->g.precision == LBM_FP32SR)
     return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
@@ -963,7 +964,7 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
 int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
   TraceRange range("lbm_adjoint_backward");
   if (!h) return LBM_EINVAL;
-  if (h->g.precision == LBM_FP16DEV)
+  if (h->g.precision == LBM_FP16DEV || h->g.precision == LBM_FP32SR)
     return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
@@ -1023,7 +1024,8 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   auto recompute = [&](int32_t c, hipStream_t s) -> int {
     const int32_t len = seg_len(c);
     if (len <= 1) return LBM_OK;
-    return enqueue_steps(h, ws_tables(h), s, len - 1, nullptr, [&](int32_t k) {
+    // (step keys unused: the adjoint refuses the stochastically rounded storage)
+    return enqueue_steps(h, ws_tables(h), s, len - 1, nullptr, 0, [&](int32_t k) {
       return std::pair<const void*, void*>(seg(c, k), seg(c, k + 1));
     });
   };

@@ -198,6 +198,10 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     g_err3 = "tau must be finite and > 1/2";
     return LBM_EINVAL;
   }
+  if (g.precision == LBM_FP32SR) {
+    g_err3 = "the stochastically rounded storage covers 2-D single lattices";
+    return LBM_EINVAL;
+  }
   if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP32DEV &&
       g.precision != LBM_FP16DEV) {
     g_err3 = "unknown precision";

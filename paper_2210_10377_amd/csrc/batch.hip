@@ -323,6 +323,10 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
       g_batch_create_error = "members differ in precision";
       return LBM_EINVAL;
     }
+    if (m[i]->g.precision == LBM_FP32SR) {
+      g_batch_create_error = "batches cover the FP64, FP32, FP32-deviation and FP16-deviation storages";
+      return LBM_EINVAL;
+    }
     if (m[i]->g.collision != m[0]->g.collision) {
       g_batch_create_error = "members differ in collision operator";
       return LBM_EINVAL;

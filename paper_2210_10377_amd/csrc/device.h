@@ -41,8 +41,9 @@ __device__ __forceinline__ C wmul(int i, C x) {
     return __builtin_fmaf(weight<float>(i), x, weight_lo(i) * x);
 }
 
-// Storage of a population and the arithmetic type it is computed in.  Deviation
-// storages keep h_i = f_i - w_i; their arithmetic stays in deviation form.
+// Storage of a population and the arithmetic type it is computed in.  kDev: the
+// arithmetic is in deviation form, h_i = f_i - w_i; kStoreF: the stored value is f_i
+// itself (otherwise a deviation storage stores h_i); kSR: stores round stochastically.
 template <int P>
 struct Storage;
 
@@ -55,6 +56,8 @@ struct Storage<LBM_FP64> {
   using C = double;
   static constexpr bool kDev = false;
   static constexpr bool kExactW = true;
+  static constexpr bool kStoreF = true;
+  static constexpr bool kSR = false;
 };
 
 template <>
@@ -63,6 +66,8 @@ struct Storage<LBM_FP32> {
   using C = float;
   static constexpr bool kDev = false;
   static constexpr bool kExactW = true;
+  static constexpr bool kStoreF = true;
+  static constexpr bool kSR = false;
 };
 
 template <>
@@ -71,6 +76,8 @@ struct Storage<LBM_FP32DEV> {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kExactW = true;
+  static constexpr bool kStoreF = false;
+  static constexpr bool kSR = false;
 };
 
 template <>
@@ -79,22 +86,103 @@ struct Storage<LBM_FP16DEV> {
   using C = float;
   static constexpr bool kDev = true;
   static constexpr bool kExactW = false;
+  static constexpr bool kStoreF = false;
+  static constexpr bool kSR = false;
 };
 
-// Stored value -> arithmetic value (f, or h for deviation storages) and back (binary16:
-// round to nearest even).
+// Binary32 populations f_i, arithmetic in deviation form, stores rounded stochastically.
+template <>
+struct Storage<LBM_FP32SR> {
+  using T = float;
+  using C = float;
+  static constexpr bool kDev = true;
+  static constexpr bool kExactW = true;
+  static constexpr bool kStoreF = true;
+#ifdef LBM_SR_NEAREST
+  static constexpr bool kSR = false;
+#else
+  static constexpr bool kSR = true;
+#endif
+};
+
+// Stored value of direction i -> arithmetic value (f, or h for deviation arithmetic),
+// and back (rounded to nearest; binary16: to nearest even).  When f_i itself is stored
+// in binary32, the deviation is taken from the binary32 weight, h_i = f_i - fl(w_i):
+// exact for f_i within a factor of two of fl(w_i) (Sterbenz), and so is the way back
+// but for one rounding of f_i.  The remainders w_i - fl(w_i) = -eps w_i (one eps for
+// all nine weights) then cancel in the equilibrium deviation: with s = sum h_i and the
+// exact weights, w_i (s + rho poly_i) equals f^eq_i - fl(w_i) but for terms of order
+// eps poly_i (below 1e-10).  Forming h_i - (w_i - fl(w_i)) in binary32 instead would
+// drop the remainder wherever the spacing of h_i exceeds it, and bias every collision.
 template <int P>
-__device__ __forceinline__ typename Storage<P>::C unpack(typename Storage<P>::T v) {
-  return typename Storage<P>::C(v);
+__device__ __forceinline__ typename Storage<P>::C unpack(typename Storage<P>::T v, int i) {
+  using S = Storage<P>;
+  if constexpr (S::kDev && S::kStoreF)
+    return v - weight<float>(i);
+  else
+    return typename S::C(v);
 }
 template <int P>
-__device__ __forceinline__ typename Storage<P>::T pack(typename Storage<P>::C v) {
-  return typename Storage<P>::T(v);
+__device__ __forceinline__ typename Storage<P>::T pack(typename Storage<P>::C v, int i) {
+  using S = Storage<P>;
+  if constexpr (S::kDev && S::kStoreF)
+    return weight<float>(i) + v;
+  else
+    return typename S::T(v);
 }
+
+// Uniform 32-bit word of a node in one step, from the step's key (sr_step_key of the
+// step number, on the host) and the node's element offset; direction i of the node takes
+// the word + i * 0x9e3779b9 (each direction's word alone is uniform).
+__device__ __forceinline__ uint32_t sr_node_word(uint32_t step_key, int32_t off) {
+  return fmix32(step_key ^ uint32_t(off));
+}
+
+// Stochastic rounding of f_i = fl(w_i) + h_i to binary32: the two neighbours
+// y <= f_i <= y' (or y' <= f_i <= y) are taken with probabilities proportional to their
+// closeness, so the expected stored value is f_i itself.  The error of the rounded sum is
+// exact (TwoSum, Knuth), the draw the top 24 bits of the direction's word.  Round to
+// nearest when kSR is off.
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T pack_sr(typename Storage<P>::C v, int i,
+                                                          uint32_t word) {
+  using S = Storage<P>;
+  if constexpr (S::kSR) {
+    const float a = weight<float>(i);
+    const float y = a + v;
+    const float bb = y - a;
+    const float e = (a - (y - bb)) + (v - bb);
+    const uint32_t yb = __builtin_bit_cast(uint32_t, y);
+    // Neighbour on the side of the error: one unit in the last place away from or
+    // towards zero.
+    const uint32_t nb = ((e > 0.0f) == (y > 0.0f)) ? yb + 1u : yb - 1u;
+    const float yn = __builtin_bit_cast(float, nb);
+    const float gap = __builtin_fabsf(yn - y);
+    const float u = float((word + uint32_t(i) * 0x9e3779b9u) >> 8) * 0x1p-24f;
+    const bool finite = __builtin_fabsf(y) < 0x1p+127f;
+    return (finite && y != 0.0f && u * gap < __builtin_fabsf(e)) ? yn : y;
+  } else {
+    return pack<P>(v, i);
+  }
+}
+
+// The population f_i in binary64 from an arithmetic value of direction i (f_i, or the
+// deviation from the weight the storage uses).
+template <int P>
+__device__ __forceinline__ double pre_f64(typename Storage<P>::C v, int i) {
+  using S = Storage<P>;
+  if constexpr (!S::kDev)
+    return double(v);
+  else if constexpr (S::kStoreF)
+    return double(weight<float>(i)) + double(v);
+  else
+    return weight<double>(i) + double(v);
+}
+
 // The population f_i in binary64 from a stored value of direction i.
 template <int P>
 __device__ __forceinline__ double to_f64(typename Storage<P>::T v, int i) {
-  return Storage<P>::kDev ? weight<double>(i) + double(v) : double(v);
+  return (Storage<P>::kDev && !Storage<P>::kStoreF) ? weight<double>(i) + double(v) : double(v);
 }
 
 // Raw buffer access of one stored population (cache policy `aux`: 0 default, 2 nt).
@@ -317,11 +405,12 @@ __device__ __forceinline__ void pull_all(const A& src, int pitch, int nx, int ny
 #pragma unroll
   for (int i = 0; i < kQ; ++i) v[i] = src.ld_lane(pl[i], off[i]);
   // The inlet term is additive, so it applies to f and to h = f - w alike (opposite
-  // directions share a weight); it is formed in binary64 and rounded once.
+  // directions share a weight, so the value pulled from plane pl[i] unpacks with w_i);
+  // it is formed in binary64 and rounded once.
   const double uw = rho_w6 * uin[y];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    f[i] = unpack<P>(v[i]);
+    f[i] = unpack<P>(v[i], i);
     if (i > 0 && kCx[i] != 0 && pull_code(w, i) == kInlet)
       f[i] += C(uw * (weight<double>(i) * kCx[i]));
   }

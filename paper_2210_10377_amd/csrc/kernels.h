@@ -19,6 +19,22 @@ constexpr int kJnext = 12;
 // Estimators of a force row as lbm_forces reports them: A, B, DRTT, SI, DRTT-post.
 constexpr int kSchemes = 5;
 
+// 32-bit finalizer of MurmurHash3 (A. Appleby, public domain): a bijection of 32-bit
+// words in which every input bit flips every output bit with probability close to 1/2.
+constexpr uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+// Key of step number t (counted from the handle's creation or last reset) for the
+// stochastically rounded storage.
+constexpr uint32_t sr_step_key(int64_t t) {
+  return fmix32(fmix32(uint32_t(t)) ^ uint32_t(uint64_t(t) >> 32) ^ 0x2545f491u);
+}
+
 // Rigid motion of the body: velocity U + Omega e_z x (x - c) at a point x.  Kernels read
 // it from device memory, and only on body links, through a pointer that is null for a
 // body at rest.
@@ -56,6 +72,7 @@ struct StepArgs {
   int32_t nslots, njslots;
   double* red_row;             // ring row receiving the reduced previous step
   double* red_prev_jnext;      // Jnext slot of the row before that, or null
+  uint32_t step_key;           // stochastically rounded storage: fmix32 of the step number
 };
 
 // Control-volume momentum of the populations one pull of `src` gives (the J(t+1) of

@@ -70,12 +70,13 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int x0, int y
   const int32_t o = y0 * a.pitch + x0 + lane_id();
   C f[kQ];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
+  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i], i);
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const T q = pack<P>(g[i]);
+    const T q = pack_sr<P>(g[i], i, word);
     dst.st(i, o, q);
     if constexpr (JP) {
       if (i > 0) {
@@ -107,8 +108,9 @@ __device__ __forceinline__ void edge_strip(const StepArgs& a, int x0, int y) {
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
   const int32_t o = y * pitch + x;
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) dst.st(i, o, pack<P>(g[i]));
+  for (int i = 0; i < kQ; ++i) dst.st(i, o, pack_sr<P>(g[i], i, word));
 }
 
 // Control-volume terms of fluid node (x, y) (second Eq. rtt7) added to acc: the
@@ -125,7 +127,7 @@ __device__ __forceinline__ void box_terms(const StepArgs& a, int x, int y,
     double jx = 0.0, jy = 0.0, px = 0.0, py = 0.0;
 #pragma unroll
     for (int i = 1; i < kQ; ++i) {
-      const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+      const double fi = pre_f64<P>(f[i], i);
       jx += kCx[i] * fi;
       jy += kCy[i] * fi;
       const double sv = to_f64<P>(s[i], i);
@@ -168,13 +170,14 @@ __device__ __forceinline__ void ring_finish(const StepArgs& a, int x0, int y0,
   const int32_t o = y0 * a.pitch + x;
   C f[kQ];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i]);
+  for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i], i);
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
   T s[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    s[i] = pack<P>(g[i]);
+    s[i] = pack_sr<P>(g[i], i, word);
     dst.st(i, o, s[i]);
   }
   box_terms<P>(a, x, y0, f, s, acc);
@@ -201,10 +204,11 @@ __device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, 
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, MOV ? a.motion : nullptr);
     C g[kQ];
     collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
+    const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
     T s[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      s[i] = pack<P>(g[i]);
+      s[i] = pack_sr<P>(g[i], i, word);
       dst.st(i, o, s[i]);
     }
     if (forces) {
@@ -218,7 +222,7 @@ __device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, 
         const double sv = to_f64<P>(s[i], i);
         const double back =
             (MOV && a.motion) ? sv + body_wall_term(*a.motion, a.rho_w6, kOpp[i], x, y) : sv;
-        const double fa = (S::kDev ? weight<double>(i) + double(f[i]) : double(f[i])) + back;
+        const double fa = pre_f64<P>(f[i], i) + back;
         acc[0] += kCx[i] * fa;
         acc[1] += kCy[i] * fa;
         acc[2] += kCx[i] * (sv + back);
@@ -242,7 +246,7 @@ __device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, 
         double fd[kQ];
 #pragma unroll
         for (int i = 0; i < kQ; ++i)
-          fd[i] = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+          fd[i] = pre_f64<P>(f[i], i);
         const double rho = ((fd[0] + fd[1]) + (fd[2] + fd[3])) + ((fd[4] + fd[5]) + (fd[6] + fd[7])) + fd[8];
         const double ux = ((fd[1] + fd[5] + fd[8]) - (fd[3] + fd[6] + fd[7])) / rho;
         const double uy = ((fd[2] + fd[5] + fd[6]) - (fd[4] + fd[7] + fd[8])) / rho;
@@ -435,7 +439,7 @@ __device__ __forceinline__ void box_block(const BoxArgs& a, int blk) {
       pull_all<P>(src, a.pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, a.motion);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
-        const double fi = S::kDev ? weight<double>(i) + double(f[i]) : double(f[i]);
+        const double fi = pre_f64<P>(f[i], i);
         v[0] += kCx[i] * fi;
         v[1] += kCy[i] * fi;
       }
@@ -514,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void fill_rest_kernel(void* buf, int64_t 
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
     const int i = int((k % period) / plane);
-    p[k] = S::kDev ? T(0) : T(weight<typename S::C>(i));
+    p[k] = (S::kDev && !S::kStoreF) ? T(0) : T(weight<typename S::C>(i));
   }
 }
 
@@ -567,7 +571,7 @@ __global__ __launch_bounds__(kThreads) void remask_kernel(RemaskArgs a) {
     for (int i = 0; i < kQ; ++i) {
       const double cu = kCx[i] * ux + kCy[i] * uy;
       const double feq = weight<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      const T q = pack<P>(C(S::kDev ? feq - weight<double>(i) : feq));
+      const T q = S::kStoreF ? T(feq) : pack<P>(C(feq - weight<double>(i)), i);
       st[i * a.plane + at] = q;
       const double f = to_f64<P>(q, i);
       v[0] -= kCx[i] * f;
@@ -668,7 +672,9 @@ hipError_t launch_step(int precision, bool forces, const StepArgs& a, hipStream_
     case LBM_FP64: return step_dispatch<LBM_FP64>(forces, a, s);
     case LBM_FP32: return step_dispatch<LBM_FP32>(forces, a, s);
     case LBM_FP32DEV: return step_dispatch<LBM_FP32DEV>(forces, a, s);
-    default: return step_dispatch<LBM_FP16DEV>(forces, a, s);
+    case LBM_FP32SR: return step_dispatch<LBM_FP32SR>(forces, a, s);
+    case LBM_FP16DEV: return step_dispatch<LBM_FP16DEV>(forces, a, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -677,7 +683,9 @@ hipError_t launch_box_momentum(int precision, const BoxArgs& a, int blocks, hipS
     case LBM_FP64: return box_dispatch<LBM_FP64>(a, blocks, s);
     case LBM_FP32: return box_dispatch<LBM_FP32>(a, blocks, s);
     case LBM_FP32DEV: return box_dispatch<LBM_FP32DEV>(a, blocks, s);
-    default: return box_dispatch<LBM_FP16DEV>(a, blocks, s);
+    case LBM_FP32SR: return box_dispatch<LBM_FP32SR>(a, blocks, s);
+    case LBM_FP16DEV: return box_dispatch<LBM_FP16DEV>(a, blocks, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -710,7 +718,8 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
     case LBM_FP64: LBM_BATCH_LAUNCH(LBM_FP64) break;
     case LBM_FP32: LBM_BATCH_LAUNCH(LBM_FP32) break;
     case LBM_FP32DEV: LBM_BATCH_LAUNCH(LBM_FP32DEV) break;
-    default: LBM_BATCH_LAUNCH(LBM_FP16DEV)
+    case LBM_FP16DEV: LBM_BATCH_LAUNCH(LBM_FP16DEV) break;
+    default: return hipErrorInvalidValue;
   }
 #undef LBM_BATCH_LAUNCH
 #undef LBM_BATCH_GO
@@ -747,8 +756,11 @@ hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity
       case LBM_FP32DEV:
         hipLaunchKernelGGL(batch_box_kernel<LBM_FP32DEV>, grid, dim3(kThreads), 0, s, b, parity);
         break;
-      default:
+      case LBM_FP16DEV:
         hipLaunchKernelGGL(batch_box_kernel<LBM_FP16DEV>, grid, dim3(kThreads), 0, s, b, parity);
+        break;
+      default:
+        return hipErrorInvalidValue;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -775,8 +787,14 @@ hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double*
     case LBM_FP32DEV:
       hipLaunchKernelGGL(remask_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
       break;
-    default:
+    case LBM_FP32SR:
+      hipLaunchKernelGGL(remask_kernel<LBM_FP32SR>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP16DEV:
       hipLaunchKernelGGL(remask_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -797,8 +815,14 @@ hipError_t launch_boundary_cp(int precision, const CpArgs& a, hipStream_t s) {
     case LBM_FP32DEV:
       hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP32DEV>, grid, dim3(kThreads), 0, s, a);
       break;
-    default:
+    case LBM_FP32SR:
+      hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP32SR>, grid, dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP16DEV:
       hipLaunchKernelGGL(boundary_cp_kernel<LBM_FP16DEV>, grid, dim3(kThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -815,8 +839,14 @@ hipError_t launch_fill_rest(int precision, void* buf, int64_t n, int64_t plane, 
     case LBM_FP32DEV:
       hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
       break;
-    default:
+    case LBM_FP32SR:
+      hipLaunchKernelGGL(fill_rest_kernel<LBM_FP32SR>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
+      break;
+    case LBM_FP16DEV:
       hipLaunchKernelGGL(fill_rest_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n, plane);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -71,6 +71,9 @@ int lbm_step_static(lbm_t* h, void* buf0, void* buf1, size_t buf_bytes, int32_t 
   if (!h) return LBM_EINVAL;
   if (n < 0) return h->fail(LBM_EINVAL, "n must be >= 0");
   if (force_scheme & ~LBM_FORCE_ALL) return h->fail(LBM_EINVAL, "unknown force scheme bits");
+  if (h->g.precision == LBM_FP32SR)
+    return h->fail(LBM_EINVAL, "the stochastically rounded storage needs the handle's step count; "
+                               "use lbm_step");
   if (!buf0 || !buf1 || buf0 == buf1 || reinterpret_cast<uintptr_t>(buf0) % 256 ||
       reinterpret_cast<uintptr_t>(buf1) % 256)
     return h->fail(LBM_EINVAL, "two distinct 256-byte aligned state buffers are needed");

@@ -63,7 +63,7 @@ int validate(const lbm_grid& g, const uint8_t* mask, Solids& sol, std::string& e
     return LBM_EINVAL;
   }
   if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP16DEV &&
-      g.precision != LBM_FP32DEV) {
+      g.precision != LBM_FP32DEV && g.precision != LBM_FP32SR) {
     err = "unknown precision";
     return LBM_EINVAL;
   }

@@ -9,7 +9,7 @@ import numpy as np
 from . import _capi as C
 
 PRECISIONS = {"fp64": C.LBM_FP64, "fp32": C.LBM_FP32, "fp16dev": C.LBM_FP16DEV,
-              "fp32dev": C.LBM_FP32DEV}
+              "fp32dev": C.LBM_FP32DEV, "fp32sr": C.LBM_FP32SR}
 SCHEMES = {"A": C.LBM_FORCE_MEA_A, "B": C.LBM_FORCE_MEA_B, "DRTT": C.LBM_FORCE_DRTT,
            "SI": C.LBM_FORCE_SI, "DRTT_POST": C.LBM_FORCE_DRTT_POST}
 ALL_SCHEMES = ("A", "B", "DRTT", "SI", "DRTT_POST")

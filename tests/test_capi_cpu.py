@@ -439,3 +439,31 @@ int main() {
     assert out.returncode == 0, out.stdout
     n, bad = (int(v) for v in out.stdout.split())
     assert n > 1000 and bad == 0
+
+
+def test_stochastic_rounding_storage_scope_without_device(capi):
+    """LBM_FP32SR (binary32 populations rounded stochastically) plans like the other
+    storages, with 4-byte elements; the calls that cannot carry the handle's step count
+    (the allocation-free step, the adjoint's recomputation) and the 3-D lattice refuse it
+    before any device call."""
+    from paper_2210_10377_amd import Plan, Plan3
+    L = capi.load()
+    mask = workloads.cylinder_mask(40, 20, 10, 9.5, 3)
+    p = Plan(mask, uin=0.05, precision="fp32sr")
+    q = Plan(mask, uin=0.05, precision="fp32")
+    assert p.info().elem_bytes == 4 and p.workspace_bytes() == q.workspace_bytes()
+    assert np.array_equal(p.links(), q.links())
+    J = ctypes.c_double()
+    rc = L.lbm_adjoint_forward(p._h, ctypes.c_void_p(256), 1 << 20, 10, 5, 0, 5, 1.0, 0.0,
+                               ctypes.byref(J))
+    assert rc == capi.LBM_EINVAL and b"storages" in L.lbm_last_error(p._h)
+    gu = np.zeros(20)
+    gt = ctypes.c_double()
+    rc = L.lbm_adjoint_backward(p._h, 1.0, gu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.byref(gt))
+    assert rc == capi.LBM_EINVAL
+    vp = ctypes.c_void_p
+    rc = L.lbm_step_static(p._h, vp(256), vp(512), 1 << 20, 1, 0, None, 0, None)
+    assert rc == capi.LBM_EINVAL and b"stochastically" in L.lbm_last_error(p._h)
+    with pytest.raises(Exception, match="stochastically"):
+        Plan3(np.zeros((8, 8, 16), np.uint8), uin=0.05, precision="fp32sr")

@@ -104,19 +104,24 @@ def test_precision_study_channel_fp64_against_oracle(re):
 # 3e-5 .. 3e-4 over the three incidences of the precision study (an FP64 run forced
 # by a static random pattern of relative 2^-24 per step moves it by 2e-5 .. 4e-5, an
 # independent pattern each step by 7e-7: bench.py --sensitivity); the deviation storage
-# rounds quantities a hundred times smaller.  Binary16 deviations: 2^-11 relative.
+# rounds quantities a hundred times smaller.  Binary32 populations rounded
+# stochastically carry a rounding of the same size as the static one, but independent
+# from step to step: it averages out, and the 1e-4 target holds at both Reynolds numbers.
+# Binary16 deviations: 2^-11 relative.
 TOLS = {
     (100, "fp32"): [1e-4] * 5,
     (100, "fp32dev"): [1e-4] * 5,
+    (100, "fp32sr"): [1e-4] * 5,
     (100, "fp16dev"): [1e-1] * 5,
     (1000, "fp32"): [5e-4, 5e-4, 1e-3, 5e-4, 5e-4],
     (1000, "fp32dev"): [1e-4] * 5,
+    (1000, "fp32sr"): [1e-4] * 5,
     (1000, "fp16dev"): [1e-2] * 5,
 }
 
 
 @pytest.mark.parametrize("re", [100, 1000])
-@pytest.mark.parametrize("precision", ["fp32", "fp32dev", "fp16dev"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32dev", "fp32sr", "fp16dev"])
 def test_precision_study_channel_storages_against_oracle(re, precision):
     z = _fixture(f"naca2048x1024_a4_re{re}")
     w = workloads.naca_2048x1024(aoa=4.0, re=float(re))
