@@ -131,11 +131,12 @@ __device__ __forceinline__ typename Storage<P>::T pack(typename Storage<P>::C v,
     return typename S::T(v);
 }
 
-// Uniform 32-bit word of a node in one step, from the step's key (sr_step_key of the
-// step number, on the host) and the node's element offset; direction i of the node takes
-// the word + i * 0x9e3779b9 (each direction's word alone is uniform).
-__device__ __forceinline__ uint32_t sr_node_word(uint32_t step_key, int32_t off) {
-  return fmix32(step_key ^ uint32_t(off));
+// Uniform 32-bit word of node (x, y) in one step, from the step's key (sr_step_key of
+// the step number, on the host) and the node's index y nx + x (not its offset in the
+// state buffer, so both layouts and every tile shape draw alike); direction i of the
+// node takes the word + i * 0x9e3779b9 (each direction's word alone is uniform).
+__device__ __forceinline__ uint32_t sr_node_word(uint32_t step_key, int nx, int x, int y) {
+  return fmix32(step_key ^ (uint32_t(y) * uint32_t(nx) + uint32_t(x)));
 }
 
 // Stochastic rounding of f_i = fl(w_i) + h_i to binary32: the two neighbours

@@ -73,7 +73,7 @@ __device__ __forceinline__ void interior_finish(const StepArgs& a, int x0, int y
   for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i], i);
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
-  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, a.nx, x0 + lane_id(), y0) : 0u;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const T q = pack_sr<P>(g[i], i, word);
@@ -108,7 +108,7 @@ __device__ __forceinline__ void edge_strip(const StepArgs& a, int x0, int y) {
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
   const int32_t o = y * pitch + x;
-  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, a.nx, x, y) : 0u;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) dst.st(i, o, pack_sr<P>(g[i], i, word));
 }
@@ -173,7 +173,7 @@ __device__ __forceinline__ void ring_finish(const StepArgs& a, int x0, int y0,
   for (int i = 0; i < kQ; ++i) f[i] = unpack<P>(v[i], i);
   C g[kQ];
   collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
-  const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
+  const uint32_t word = S::kSR ? sr_node_word(a.step_key, a.nx, x, y0) : 0u;
   T s[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -204,7 +204,7 @@ __device__ __forceinline__ void general_strip(const StepArgs& a, int x0, int y, 
     pull_all<P>(src, pitch, a.nx, a.ny, a.uin, a.rho_w6, w, x, y, f, MOV ? a.motion : nullptr);
     C g[kQ];
     collide<C, S::kDev, COLL, S::kExactW>(f, C(a.omega), g);
-    const uint32_t word = S::kSR ? sr_node_word(a.step_key, o) : 0u;
+    const uint32_t word = S::kSR ? sr_node_word(a.step_key, a.nx, x, y) : 0u;
     T s[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {

@@ -261,7 +261,8 @@ def test_chunked_calls_match_single_call():
 
 @pytest.mark.parametrize("precision,name,collision", [
     ("fp32", "channel_body_box", "bgk"), ("fp16dev", "multi_tile_ragged", "bgk"),
-    ("fp64", "periodic_x_body_on_seam", "bgk"), ("fp32dev", "solid_touching_inlet", "kbc")])
+    ("fp64", "periodic_x_body_on_seam", "bgk"), ("fp32dev", "solid_touching_inlet", "kbc"),
+    ("fp32sr", "channel_periodic_y", "regularized")])
 def test_row_interleaved_and_planar_layouts_agree_bitwise(precision, name, collision):
     """The two device layouts of the state run the same arithmetic: populations and all
     four forces bitwise equal after 40 steps from a random state; a checkpoint of one
@@ -458,7 +459,7 @@ def low_viscosity_reference():
 
 
 @pytest.mark.parametrize("collision", ["regularized", "kbc"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev", "fp32sr"])
 def test_stabilized_cylinder_low_viscosity(precision, collision, low_viscosity_reference):
     """200x80 cylinder channel at tau_lb 0.51 with the regularized or KBC collision,
     3000 steps from rest: FP64 forces to 1e-10 of the oracle, 32-bit deviation storage

@@ -115,3 +115,29 @@ def test_batch_refuses_stochastic_rounding():
     members = [_sim(w, "fp32sr"), _sim(w, "fp32sr")]
     with pytest.raises(LbmError, match="storages"):
         Batch(members)
+
+
+def test_stochastic_rounding_is_independent_of_tile_shape_and_layout():
+    """The draws are keyed on the node index, not on a buffer offset or a thread: wide
+    (256 x 1) and narrow (64 x 4) tiles and the two state layouts store the same bits."""
+    from paper_2210_10377_amd import Sim
+    w = _channel()
+    S0 = workloads.near_rest_state(w.nx, w.ny, seed=21, amp=0.03, dtype=np.float32)
+    runs = []
+    for tile, layout in (("wide", "rows"), ("narrow", "rows"), ("wide", "planes")):
+        g = Sim(w.mask, w.tau, w.uin, precision="fp32sr", box=w.box, max_record=64, tile=tile,
+                layout=layout)
+        g.set_populations(S0)
+        g.step(40)
+        runs.append((g.populations(), g.forces()))
+    n_box = g.info().n_box
+    F0 = runs[0][1]
+    for P, F in runs[1:]:
+        assert np.array_equal(P, runs[0][0])
+        # Forces: the same stored values; the narrow tiles group the FP64 partial sums
+        # differently (1e-13 of the largest force, plus the rounding of the box momenta,
+        # 1.5e-14 per box node on each side, for the two DRTT forms).
+        for k in range(F0.shape[1]):
+            scale = np.abs(F0[:, k]).max()
+            extra = 2 * 1.5e-14 * n_box if k in (2, 4) else 0.0
+            assert np.abs(F[:, k] - F0[:, k]).max() <= 1e-13 * scale + extra, k
