@@ -668,6 +668,59 @@ def adjoint_bench(precision: str, large: bool = False, tile: str = "auto"):
         "fwd_plus_bwd_over_plain": round((t_f + t_b) / t_plain, 3)}), flush=True)
 
 
+def batch_accuracy(steps: int, window: int, collision: str = "bgk"):
+    """Per-instance force coefficients of the 256-instance batch in each storage against
+    the FP64 batch (itself matched to the oracle to 1e-10 on a mini batch, and bitwise to
+    single runs): every instance `steps` steps from rest, window means over the last
+    `window` steps.  Drag errors are relative to the instance's FP64 window-mean drag; lift
+    errors are given in the same unit (relative to that drag), since the cylinders' mean
+    lift is zero.  Instances whose FP64 run is not finite are counted apart; so are
+    unsteady ones (FP64 drag varying by more than 1 % over the window), whose window means
+    depend on the phase of the shedding."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Batch
+
+    ws = workloads.batched_instances(steps=steps)
+    res = {}
+    for prec in ("fp64", "fp32", "fp32dev", "fp16dev"):
+        b = Batch.from_workloads(ws, precision=prec, max_record=window, collision=collision)
+        if steps > window:
+            b.step(steps - window, schemes=())
+        F, bad = b.run(window)
+        res[prec] = (b.coefficients(F), bad)
+        del b
+    C64, bad64 = res["fp64"]
+    cd64 = C64[:, :, 1, 0]          # algorithm B drag, [instance, step]
+    mean64 = cd64.mean(1)
+    unsteady = (cd64.max(1) - cd64.min(1)) > 0.01 * np.abs(mean64)
+    ok = ~bad64 & np.isfinite(mean64)
+    out = {"batch_accuracy": workloads.__name__ + ".batched_instances", "collision": collision,
+           "steps": steps,
+           "window": window, "instances": len(ws), "fp64_nonfinite": int((~ok).sum()),
+           "unsteady": int((unsteady & ok).sum())}
+    names = ("A", "B", "DRTT", "SI", "DRTT_POST")
+    for prec in ("fp32", "fp32dev", "fp16dev"):
+        C, bad = res[prec]
+        e = {"nonfinite": int((bad & ok).sum())}
+        for k, name in enumerate(names):
+            m64 = C64[:, :, k].mean(1)
+            m = C[:, :, k].mean(1)
+            ref = np.abs(C64[:, :, 1, 0].mean(1))
+            ecd = np.abs(m[:, 0] - m64[:, 0]) / np.abs(m64[:, 0])
+            ecl = np.abs(m[:, 1] - m64[:, 1]) / ref
+            for label, sel in (("steady", ok & ~unsteady & ~bad), ("unsteady", ok & unsteady & ~bad)):
+                if sel.any():
+                    e[f"{name}_{label}"] = {
+                        "cd_rel_err_median": float(np.median(ecd[sel])),
+                        "cd_rel_err_max": float(ecd[sel].max()),
+                        "cl_err_over_cd_max": float(ecl[sel].max()),
+                        "n_cd_above_1e-4": int((ecd[sel] > 1e-4).sum())}
+        out[prec] = e
+    print(json.dumps(out), flush=True)
+
+
 def batched_bench(precision: str, steps: int, seq_steps: int, collision: str):
     """The 256-instance batch (uneven cylinder and airfoil channels, one launch per step
     for all of them): autotuned schedule, then `steps` timed steps with all four forces.
@@ -884,6 +937,10 @@ def main():
                     help="adjoint workload: NACA0012 chord 256 in 1024x512, Re 500, 10000 "
                          "steps, mean drag over the last 2000, checkpoint every 500; "
                          "forward and backward MLUPS")
+    ap.add_argument("--batch-accuracy", action="store_true",
+                    help="per-instance force coefficients of the 256-instance batch in each "
+                         "storage against the FP64 batch (--study-steps steps from rest, "
+                         "window means over the last 2000)")
     ap.add_argument("--batched", action="store_true",
                     help="256 uneven cylinder/NACA0012 channels (64x32 to 512x256, Re 20 to "
                          "2000) stepped together; autotuned schedule; batched MLUPS beside "
@@ -973,6 +1030,10 @@ def main():
         return
     if args.adjoint or args.adjoint_large:
         adjoint_bench(explicit_precision or "fp32dev", args.adjoint_large, args.tile)
+        return
+    if args.batch_accuracy:
+        batch_accuracy(args.study_steps if args.study_steps != 20000 else 10000, 2000,
+                       args.collision)
         return
     if args.batched:
         batched_bench(args.precision, args.steps, args.seq_steps, args.collision)
