@@ -423,6 +423,11 @@ typedef struct lbm_batch_schedule {
                           16 tiles, reset by a small kernel at each lbm_batch_step
                           call and by each launch for the next), over a list ordered
                           largest instance first.  Results do not depend on it.      */
+  int32_t tile_shape;  /* LBM_TILE_AUTO (0): every instance keeps its own tile shape;
+                          LBM_TILE_WIDE / LBM_TILE_NARROW: every instance runs in
+                          256 x 1 / 64 x 4 tiles in the batch (the member's own
+                          lbm_step keeps its shape).  The force partials are numbered
+                          per strip, so results do not depend on it.                 */
 } lbm_batch_schedule;
 
 typedef struct lbm_batch_info {
@@ -453,17 +458,19 @@ int lbm_batch_workspace_bytes(const lbm_batch_t* b, size_t* bytes);
 int lbm_batch_bind(lbm_batch_t* b, void* device_workspace, size_t bytes, void* hip_stream);
 
 /* Choose the schedule (see lbm_batch_schedule).  LBM_EINVAL for negative values, an
- * odd graph_steps, tile_queue other than 0 or 1, or a tile queue without a persistent
- * grid.  Drops captured graphs. */
+ * odd graph_steps, tile_queue other than 0 or 1, a tile queue without a persistent
+ * grid, or an unknown tile_shape.  Drops captured graphs. */
 int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s);
 
 /* Time candidate schedules (one block per tile, and persistent grids of 1, 2, 4 and 8
  * workgroups per compute unit with the static stride and with the tile queue; each with
- * direct launches and with graphs of up to 64 launches; the tile order seed is kept)
- * over `steps` steps each, after a warm-up run of the same length, with forces
+ * direct launches and with graphs of up to 64 launches; the tile order seed and the
+ * tile shape are kept; then the fastest of those with each of the two other tile
+ * shapes) over `steps` steps each, after a warm-up run of the same length, with forces
  * force_scheme (0 = none).  Keeps the fastest and returns it in *best and its
  * milliseconds per step in *ms_per_step (either may be NULL).  Every instance advances
- * by 2 x steps per candidate (36 x steps in all); those force rows are not kept.
+ * by 2 x steps per candidate (40 x steps in all: 18 schedules, then 2 tile shapes);
+ * those force rows are not kept.
  * LBM_EOVERFLOW if the ring cannot hold `steps` rows beside the rows recorded;
  * LBM_ESTATE if a member's control volume changed size since create.  Synchronises the
  * stream. */

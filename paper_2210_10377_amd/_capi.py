@@ -87,7 +87,8 @@ class lbm3d_info(ctypes.Structure):
 
 class lbm_batch_schedule(ctypes.Structure):
     _fields_ = [("grid_blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("tile_order", ctypes.c_uint32), ("tile_queue", ctypes.c_int32)]
+                ("tile_order", ctypes.c_uint32), ("tile_queue", ctypes.c_int32),
+                ("tile_shape", ctypes.c_int32)]
 
 
 class lbm_batch_info(ctypes.Structure):

@@ -10,6 +10,9 @@ import numpy as np
 from . import _capi as C
 from .sim import ALL_SCHEMES, NSCHEMES, Sim, scheme_mask
 
+# Tile shape of every instance in the batch: each member's own, or one for all.
+TILE_SHAPES = {"auto": C.LBM_TILE_AUTO, "wide": C.LBM_TILE_WIDE, "narrow": C.LBM_TILE_NARROW}
+
 
 class Batch:
     """A batch over bound ``Sim`` members of one precision.
@@ -64,9 +67,9 @@ class Batch:
 
     # -- schedule ---------------------------------------------------------------------
     def set_schedule(self, grid_blocks: int = 0, graph_steps: int = 0, tile_order: int = 0,
-                     tile_queue: int = 0):
+                     tile_queue: int = 0, tile_shape: str = "auto"):
         s = C.lbm_batch_schedule(int(grid_blocks), int(graph_steps), int(tile_order),
-                                 int(tile_queue))
+                                 int(tile_queue), TILE_SHAPES[tile_shape])
         C.check_batch(self._lib.lbm_batch_set_schedule(self._h, ctypes.byref(s)), self._h)
 
     def autotune(self, steps: int = 10, schemes=ALL_SCHEMES):
@@ -77,7 +80,9 @@ class Batch:
         C.check_batch(self._lib.lbm_batch_autotune(self._h, int(steps), scheme_mask(schemes),
                                                    ctypes.byref(best), ctypes.byref(ms)), self._h)
         return ({"grid_blocks": best.grid_blocks, "graph_steps": best.graph_steps,
-                 "tile_order": best.tile_order, "tile_queue": best.tile_queue}, ms.value)
+                 "tile_order": best.tile_order, "tile_queue": best.tile_queue,
+                 "tile_shape": {v: k for k, v in TILE_SHAPES.items()}[best.tile_shape]},
+                ms.value)
 
     def info(self) -> C.lbm_batch_info:
         inf = C.lbm_batch_info()

@@ -704,6 +704,7 @@ int lbm_set_mask(lbm_t* h, const uint8_t* solid_mask, const int32_t* box, double
     h->njblocks = nj;
     h->adj_valid = false;
     h->adj_codes.clear();  // the adjoint codes invert the pull codes of the old mask
+    ++h->plan_gen;         // tables built from the plan elsewhere (a batch) are stale
   };
   double P[2] = {0.0, 0.0};
   if (h->bound) {

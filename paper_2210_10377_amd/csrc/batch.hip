@@ -45,17 +45,24 @@ struct lbm_batch_t {
   int32_t max_record = 0;
   int precision = 0;
   int64_t total_tiles = 0, total_box = 0, total_fluid = 0, total_nodes = 0;
+  int64_t max_tiles = 0;  // tile-list capacity: the most tiles of the three tile shapes
   std::vector<int32_t> tile_inst, tile_local, box_inst, box_local;
   std::vector<int> nj0;  // box-sweep blocks of each member at create (the lists' sizes)
   std::vector<BatchInst> desc;  // the instance table as last uploaded
   size_t off_desc = 0, off_ti = 0, off_tl = 0, off_bi = 0, off_bl = 0, off_ctl = 0,
-         off_ring = 0, total = 0;
+         off_ring = 0, off_alt = 0, total = 0;
+  // Strip-slot tables of the members that run in the batch in a tile shape other than
+  // their own (schedule tile_shape): element offset in the region at off_alt (or -1),
+  // tiles along x and y, and the plan generation each was built from.
+  std::vector<int64_t> alt_at;
+  std::vector<int32_t> alt_ntx, alt_nty, alt_host;
+  std::vector<uint64_t> alt_gen;
   char* ws = nullptr;
   hipStream_t stream = nullptr, cap_stream = nullptr;
   bool bound = false;
   int cus = 0;
   int bpar = 0;  // buf[bpar] of every instance-table entry is the member's current state
-  lbm_batch_schedule sched{0, 0, 0};
+  lbm_batch_schedule sched{0, 0, 0, 0, LBM_TILE_AUTO};
   // (launches, parity, forces, some body in motion): the last selects the kernel variant
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
   int64_t nrec = 0, steps_done = 0;
@@ -87,6 +94,41 @@ struct lbm_batch_t {
     return true;
   }
 
+  // Tile rows of member i in the batch, and its tile count in tiles of `rows` rows.
+  int rows_of(size_t i) const {
+    if (sched.tile_shape == LBM_TILE_AUTO) return m[i]->plan.tile_rows;
+    return sched.tile_shape == LBM_TILE_NARROW ? 4 : 1;
+  }
+  static int64_t tiles_in(const Plan& p, int rows) {
+    const int tile_w = kTileW / rows;
+    return int64_t((p.nx + tile_w - 1) / tile_w) * ((p.ny + rows - 1) / rows);
+  }
+
+  // The strip-slot tables of the members whose batch tile shape differs from their own
+  // (each member's own table serves the others), from the members' present plans.
+  void build_alt() {
+    alt_at.assign(m.size(), -1);
+    alt_ntx.assign(m.size(), 0);
+    alt_nty.assign(m.size(), 0);
+    alt_gen.assign(m.size(), 0);
+    alt_host.clear();
+    std::vector<int32_t> tab;
+    for (size_t i = 0; i < m.size(); ++i) {
+      alt_gen[i] = m[i]->plan_gen;
+      const int rows = rows_of(i);
+      if (rows == m[i]->plan.tile_rows) continue;
+      tile_slots(m[i]->plan, rows, alt_ntx[i], alt_nty[i], tab);
+      alt_at[i] = int64_t(alt_host.size());
+      alt_host.insert(alt_host.end(), tab.begin(), tab.end());
+    }
+  }
+  bool alt_current() const {
+    if (alt_gen.size() != m.size()) return false;
+    for (size_t i = 0; i < m.size(); ++i)
+      if (alt_gen[i] != m[i]->plan_gen) return false;
+    return true;
+  }
+
   void build_lists() {
     tile_inst.clear();
     tile_local.clear();
@@ -101,11 +143,13 @@ struct lbm_batch_t {
         return int64_t(m[p]->g.nx) * m[p]->g.ny > int64_t(m[q]->g.nx) * m[q]->g.ny;
       });
     for (size_t i : order) {
-      for (int t = 0; t < m[i]->plan.ntiles; ++t) {
+      const int64_t nt = tiles_in(m[i]->plan, rows_of(i));
+      for (int64_t t = 0; t < nt; ++t) {
         tile_inst.push_back(int32_t(i));
-        tile_local.push_back(t);
+        tile_local.push_back(int32_t(t));
       }
     }
+    total_tiles = int64_t(tile_inst.size());
     for (size_t i = 0; i < m.size(); ++i)
       for (int t = 0; t < m[i]->njblocks; ++t) {
         box_inst.push_back(int32_t(i));
@@ -129,6 +173,14 @@ struct lbm_batch_t {
       BatchInst& e = d[i];
       std::memset(static_cast<void*>(&e), 0, sizeof(BatchInst));
       e.a = step_args(h);
+      if (i < alt_at.size() && alt_at[i] >= 0) {
+        // This member runs in the batch's tile shape, with its slots in that tile order.
+        e.a.tile_rows = rows_of(i);
+        e.a.ntx = alt_ntx[i];
+        e.a.nty = alt_nty[i];
+        e.a.ntiles = alt_ntx[i] * alt_nty[i];
+        e.a.strip_slot = reinterpret_cast<const int32_t*>(ws + off_alt) + alt_at[i];
+      }
       for (int j = 0; j < 2; ++j) e.buf[j] = h->buf(h->cur ^ j ^ bpar);
       e.part[0] = h->part(0);
       e.part[1] = h->part(1);
@@ -186,6 +238,8 @@ struct lbm_batch_t {
 
   int upload_lists() {
     int rc = upload(tile_inst.data(), off_ti, tile_inst.size() * 4, "upload tile list");
+    if (rc == LBM_OK)
+      rc = upload(alt_host.data(), off_alt, alt_host.size() * 4, "upload strip slots");
     if (rc == LBM_OK) rc = upload(tile_local.data(), off_tl, tile_local.size() * 4, "upload tile list");
     if (rc == LBM_OK) rc = upload(box_inst.data(), off_bi, box_inst.size() * 4, "upload box list");
     if (rc == LBM_OK) rc = upload(box_local.data(), off_bl, box_local.size() * 4, "upload box list");
@@ -194,11 +248,14 @@ struct lbm_batch_t {
     return e == hipSuccess ? LBM_OK : hip_fail(e, "upload synchronize");
   }
 
-  // Take schedule s; the tile list is rebuilt and uploaded when its order changes.
+  // Take schedule s; the tile list (and the strip-slot tables of a tile shape) are
+  // rebuilt and uploaded when the order or the shape changes.
   int use_schedule(const lbm_batch_schedule& s) {
-    const bool reorder = s.tile_order != sched.tile_order || s.tile_queue != sched.tile_queue;
+    const bool reorder = s.tile_order != sched.tile_order || s.tile_queue != sched.tile_queue ||
+                         s.tile_shape != sched.tile_shape;
     sched = s;
     if (!reorder) return LBM_OK;
+    build_alt();
     build_lists();
     return bound ? upload_lists() : LBM_OK;
   }
@@ -210,6 +267,12 @@ struct lbm_batch_t {
       if (!h->bound) return fail(LBM_ESTATE, "a member is no longer bound");
     if (!sizes_kept())
       return fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
+    if (!alt_current()) {
+      // A member's plan changed (a mask change): its slots in the batch's tile order too.
+      build_alt();
+      const int rc = upload(alt_host.data(), off_alt, alt_host.size() * 4, "upload strip slots");
+      if (rc != LBM_OK) return rc;
+    }
     std::vector<BatchInst> d = make_desc();
     if (d.size() == desc.size() &&
         std::memcmp(d.data(), desc.data(), d.size() * sizeof(BatchInst)) == 0)
@@ -349,26 +412,34 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
   b->m = m;
   b->max_record = max_record;
   b->precision = m[0]->g.precision;
+  int64_t alt_cap = 0;
   for (const lbm_t* h : m) {
+    const int64_t wide = lbm_batch_t::tiles_in(h->plan, 1), narrow = lbm_batch_t::tiles_in(h->plan, 4);
     b->total_tiles += h->plan.ntiles;
+    b->max_tiles += std::max(wide, narrow);
+    alt_cap += std::max(wide, narrow) * kStrips;
     b->total_box += h->njblocks;
     b->nj0.push_back(h->njblocks);
     b->total_fluid += h->plan.n_fluid;
     b->total_nodes += int64_t(h->plan.nx) * h->plan.ny;
   }
-  if (b->total_tiles >= (int64_t(1) << 31) || b->total_box >= (int64_t(1) << 31)) {
+  if (b->max_tiles >= (int64_t(1) << 31) || b->total_box >= (int64_t(1) << 31) ||
+      alt_cap >= (int64_t(1) << 31)) {
     delete b;
     g_batch_create_error = "too many tiles";
     return LBM_ENOMEM;
   }
+  b->build_alt();
   b->build_lists();
   size_t off = 0;
   b->off_desc = off;
   off = align256(off + size_t(n) * sizeof(BatchInst));
   b->off_ti = off;
-  off = align256(off + size_t(b->total_tiles) * 4);
+  off = align256(off + size_t(b->max_tiles) * 4);
   b->off_tl = off;
-  off = align256(off + size_t(b->total_tiles) * 4);
+  off = align256(off + size_t(b->max_tiles) * 4);
+  b->off_alt = off;
+  off = align256(off + size_t(alt_cap) * 4);
   b->off_bi = off;
   off = align256(off + size_t(b->total_box) * 4);
   b->off_bl = off;
@@ -424,7 +495,11 @@ int lbm_batch_set_schedule(lbm_batch_t* b, const lbm_batch_schedule* s) {
     return b->fail(LBM_EINVAL, "tile_queue must be 0 or 1");
   if (s->tile_queue && s->grid_blocks == 0)
     return b->fail(LBM_EINVAL, "the tile queue needs a persistent grid (grid_blocks > 0)");
-  const bool reorder = s->tile_order != b->sched.tile_order || s->tile_queue != b->sched.tile_queue;
+  if (s->tile_shape != LBM_TILE_AUTO && s->tile_shape != LBM_TILE_WIDE &&
+      s->tile_shape != LBM_TILE_NARROW)
+    return b->fail(LBM_EINVAL, "unknown tile shape");
+  const bool reorder = s->tile_order != b->sched.tile_order ||
+                       s->tile_queue != b->sched.tile_queue || s->tile_shape != b->sched.tile_shape;
   if (reorder && !b->sizes_kept())
     return b->fail(LBM_ESTATE, "a member's control volume changed size; create a new batch");
   b->drop_graphs();
@@ -475,6 +550,27 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
   const lbm_batch_schedule keep = b->sched;
   lbm_batch_schedule win = keep;
   double win_ms = INFINITY;
+  // Warm-up of the same length (captures the graphs), then the timed run.
+  auto time_candidate = [&](const lbm_batch_schedule& s) -> int {
+    b->drop_graphs();
+    int r = b->use_schedule(s);
+    if (r == LBM_OK) r = b->enqueue(steps, forces, b->nrec);
+    if (r != LBM_OK) return r;
+    e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) r = b->enqueue(steps, forces, b->nrec);
+    if (r != LBM_OK) return r;
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) return b->hip_fail(e, "time candidate");
+    const double per = double(ms) / steps;
+    if (per < win_ms) {
+      win_ms = per;
+      win = s;
+    }
+    return LBM_OK;
+  };
   int rc = LBM_OK;
   for (int pc : per_cu) {
     // One workgroup per tile: direct launches or graphs; persistent grids: the same
@@ -484,30 +580,19 @@ int lbm_batch_autotune(lbm_batch_t* b, int32_t steps, uint32_t force_scheme,
       s.grid_blocks = pc * b->cus;
       s.graph_steps = (cand & 1) ? gsteps : 0;
       s.tile_queue = cand >> 1;
-      b->drop_graphs();
-      rc = b->use_schedule(s);
-      if (rc != LBM_OK) break;
-      // Warm-up of the same length (captures the graphs), then the timed run.
-      rc = b->enqueue(steps, forces, b->nrec);
-      if (rc != LBM_OK) break;
-      e = hipEventRecord(e0, b->stream);
-      if (e == hipSuccess) rc = b->enqueue(steps, forces, b->nrec);
-      if (rc != LBM_OK) break;
-      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        rc = b->hip_fail(e, "time candidate");
-        break;
-      }
-      const double per = double(ms) / steps;
-      if (per < win_ms) {
-        win_ms = per;
-        win = s;
-      }
+      rc = time_candidate(s);
     }
     if (rc != LBM_OK) break;
+  }
+  // The fastest schedule with each of the other tile shapes.
+  if (rc == LBM_OK) {
+    const lbm_batch_schedule base = win;
+    for (int shape : {LBM_TILE_AUTO, LBM_TILE_WIDE, LBM_TILE_NARROW}) {
+      if (shape == base.tile_shape || rc != LBM_OK) continue;
+      lbm_batch_schedule s = base;
+      s.tile_shape = shape;
+      rc = time_candidate(s);
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

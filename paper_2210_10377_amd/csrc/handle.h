@@ -39,6 +39,7 @@ struct lbm_t {
   bool bound = false;
   int cur = 0;  // buffer holding the current state
   int64_t steps_done = 0;
+  uint64_t plan_gen = 0;  // counts plan replacements (mask changes)
   int64_t nrec = 0;
   std::vector<uint32_t> rec_scheme;  // scheme mask per recorded row
   std::string err;

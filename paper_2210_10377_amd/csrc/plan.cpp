@@ -246,43 +246,40 @@ void derive(Plan& p, const Solids& sol) {
       scan_links(y, p.gx0, p.gx1);
   }
 
-  // Tiles and strips (strip_class).  General strips holding a link node or a node with a
-  // control-volume term own a force-partial slot (kPart sums); box-interior strips own
-  // a slot of the box-momentum partials (2 sums).
-  const int tile_w = kTileW / p.tile_rows;
-  p.ntx = (nx + tile_w - 1) / tile_w;
-  p.nty = (ny + p.tile_rows - 1) / p.tile_rows;
-  p.ntiles = p.ntx * p.nty;
-  p.strip_slot.assign(size_t(p.ntiles) * kStrips, -1);
+  // Strips (strip_class) in row-major order, y then x: general strips holding a link
+  // node or a node with a control-volume term own a force-partial slot (kPart sums);
+  // box-interior strips own a slot of the box-momentum partials.  The slots are numbered
+  // in this order whatever the tile shape, so every shape reduces the same partials in
+  // the same order (bitwise the same forces).
+  const int nsx = (nx + kStripW - 1) / kStripW;
+  p.row_slot.assign(size_t(ny) * nsx, -1);
   p.nslots = p.njslots = p.ngeneral = 0;
-  for (int ty = 0; ty < p.nty; ++ty)
-    for (int tx = 0; tx < p.ntx; ++tx)
-      for (int w = 0; w < kStrips; ++w) {
-        const int tile = ty * p.ntx + tx;
-        int x0 = 0, y0 = 0;
-        strip_origin(tile, w, p.ntx, p.tile_rows, x0, y0);
-        if (y0 >= ny) continue;
-        const int cls = p.has_box
-                            ? strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0],
-                                          p.box[1], p.box[2], p.box[3], x0, y0)
-                            : strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, 1, 0, 1, 0,
-                                          x0, y0);
-        if (cls == kStripPlain) continue;
-        if (cls == kStripBoxInterior) {
-          p.strip_slot[size_t(tile) * kStrips + w] = p.njslots++;
-          continue;
-        }
-        if (cls == kStripGeneral) ++p.ngeneral;
-        bool forces = false;
-        for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {
-          const uint32_t wd = p.node[size_t(y0) * nx + x];
-          bool link = false;
-          if (!(wd & kSolidBit))
-            for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
-          forces = forces || link || band(x, y0);
-        }
-        if (forces) p.strip_slot[size_t(tile) * kStrips + w] = p.nslots++;
+  for (int y0 = 0; y0 < ny; ++y0)
+    for (int sx = 0; sx < nsx; ++sx) {
+      const int x0 = sx * kStripW;
+      const int cls = p.has_box
+                          ? strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, p.box[0], p.box[1],
+                                        p.box[2], p.box[3], x0, y0)
+                          : strip_class(nx, ny, p.gx0, p.gx1, p.gy0, p.gy1, 1, 0, 1, 0, x0, y0);
+      int32_t& slot = p.row_slot[size_t(y0) * nsx + sx];
+      if (cls == kStripPlain) continue;
+      if (cls == kStripBoxInterior) {
+        slot = p.njslots++;
+        continue;
       }
+      if (cls == kStripGeneral) ++p.ngeneral;
+      bool forces = false;
+      for (int x = x0; x < std::min(x0 + kStripW, nx); ++x) {
+        const uint32_t wd = p.node[size_t(y0) * nx + x];
+        bool link = false;
+        if (!(wd & kSolidBit))
+          for (int i = 1; i < kQ; ++i) link = link || pull_code(wd, i) == kBody;
+        forces = forces || link || band(x, y0);
+      }
+      if (forces) slot = p.nslots++;
+    }
+  tile_slots(p, p.tile_rows, p.ntx, p.nty, p.strip_slot);
+  p.ntiles = p.ntx * p.nty;
   p.box_bx = p.box_rows = 0;
   if (p.has_box) {
     p.box_bx = (p.box[1] - p.box[0] + kTileW - 1) / kTileW;
@@ -344,6 +341,21 @@ int replan(const lbm_grid& g, const uint8_t* mask, const std::vector<int32_t>& c
   np.node.swap(p.node);
   derive(np, sol);
   return LBM_OK;
+}
+
+void tile_slots(const Plan& p, int rows, int& ntx, int& nty, std::vector<int32_t>& out) {
+  const int tile_w = kTileW / rows;
+  ntx = (p.nx + tile_w - 1) / tile_w;
+  nty = (p.ny + rows - 1) / rows;
+  const int nsx = (p.nx + kStripW - 1) / kStripW;
+  out.assign(size_t(ntx) * nty * kStrips, -1);
+  for (int tile = 0; tile < ntx * nty; ++tile)
+    for (int w = 0; w < kStrips; ++w) {
+      int x0 = 0, y0 = 0;
+      strip_origin(tile, w, ntx, rows, x0, y0);
+      if (y0 < p.ny && x0 < p.nx)
+        out[size_t(tile) * kStrips + w] = p.row_slot[size_t(y0) * nsx + x0 / kStripW];
+    }
 }
 
 void apply_delta(Plan& p, const PlanDelta& d, bool forward) {

@@ -155,8 +155,11 @@ struct Plan {
   // volume is classified separately (strip_class).
   int gx0 = 0, gx1 = -1, gy0 = 0, gy1 = -1;
   // Per strip (tile-major, kStrips per tile): the index >= 0 of its force-partial slot
-  // when it holds a link node or a control-volume-band node, else -1.
+  // when it holds a link node or a control-volume-band node (of its box-momentum slot
+  // for a box-interior strip), else -1.  row_slot holds the same per strip in row-major
+  // order ([ny][ceil(nx / 64)]), the order the slots are numbered in.
   std::vector<int32_t> strip_slot;
+  std::vector<int32_t> row_slot;
   int nslots = 0;                 // general strips with force terms (kPart partials each)
   int njslots = 0;                // box-interior strips (2 partials each: J)
   int ngeneral = 0;               // strips that take the general path
@@ -167,6 +170,11 @@ struct Plan {
 
 // Validate and classify.  Returns LBM_OK or an error code with a message in err.
 int build_plan(const lbm_grid& g, const uint8_t* mask, Plan& p, std::string& err);
+
+// The per-strip slot table of tiles of `rows` rows (1: 256 x 1, 4: 64 x 4) over p's
+// strips, with the tile counts along x and y: the same slots as p.strip_slot in another
+// tile order.
+void tile_slots(const Plan& p, int rows, int& ntx, int& nty, std::vector<int32_t>& out);
 
 // Node words a mask change rewrites (index, old word, new word), in index order.
 struct PlanDelta {

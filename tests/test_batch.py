@@ -80,6 +80,12 @@ SCHEDULES = {
     "persistent_graph_shuffled": dict(grid_blocks=40, graph_steps=4, tile_order=12345),
     "tile_queue": dict(grid_blocks=24, graph_steps=0, tile_queue=1),
     "tile_queue_graph_shuffled": dict(grid_blocks=40, graph_steps=4, tile_order=777, tile_queue=1),
+    # every instance in one tile shape in the batch (the members keep their own)
+    "all_wide_tiles": dict(grid_blocks=0, graph_steps=0, tile_shape="wide"),
+    "all_narrow_tiles_graph_shuffled": dict(grid_blocks=0, graph_steps=4, tile_order=99,
+                                            tile_shape="narrow"),
+    "narrow_tiles_tile_queue": dict(grid_blocks=24, graph_steps=0, tile_queue=1,
+                                    tile_shape="narrow"),
 }
 
 
@@ -195,8 +201,10 @@ def test_autotune_keeps_results_bitwise():
     assert ms > 0
     assert sched["graph_steps"] in (0, 4)
     assert sched["tile_queue"] in (0, 1) and (sched["grid_blocks"] > 0 or not sched["tile_queue"])
-    # one block per tile: 2 candidates; 4 persistent grids x (stride, queue) x 2: 16
-    n_tune = (2 + 16) * 2 * 4
+    assert sched["tile_shape"] in ("auto", "wide", "narrow")
+    # one block per tile: 2 candidates; 4 persistent grids x (stride, queue) x 2: 16; the
+    # fastest with the two other tile shapes: 2
+    n_tune = (2 + 16 + 2) * 2 * 4
     assert b.info().steps_done == n_tune
     b.step(7)
     Fb, _ = b.forces()
@@ -294,10 +302,13 @@ def test_moving_members_batch_bitwise_equals_singles():
         np.testing.assert_array_equal(r.populations(), b.members[i].populations())
 
 
-def test_member_moving_through_the_grid_batch_bitwise_equals_singles():
+@pytest.mark.parametrize("tile_shape", ["auto", "wide", "narrow"])
+def test_member_moving_through_the_grid_batch_bitwise_equals_singles(tile_shape):
     """A member whose body moves one node (and its control volume with it) between two
     batch calls: every instance bitwise equals the same member stepped alone with the
-    same calls; a member whose control volume changes size stops the batch."""
+    same calls, also when the batch runs the instances in a tile shape of its own (its
+    strip-slot tables follow the member's new plan); a member whose control volume
+    changes size stops the batch."""
     from paper_2210_10377_amd import Sim, Batch, LbmError
     ws = MINI[:3]
     k = next(i for i, w in enumerate(ws) if w.box is not None)
@@ -313,7 +324,7 @@ def test_member_moving_through_the_grid_batch_bitwise_equals_singles():
     sims = members()
     _seed_states(sims, ws)
     b = Batch(sims, max_record=64)
-    b.set_schedule(grid_blocks=0, graph_steps=4)
+    b.set_schedule(grid_blocks=0, graph_steps=4, tile_shape=tile_shape)
     b.step(10)
     imp_b = sims[k].set_mask(shifted, box1)
     b.step(10)
@@ -366,3 +377,10 @@ def test_schedule_validation():
         b.set_schedule(grid_blocks=16, tile_queue=2)
     b.set_schedule(grid_blocks=16, tile_queue=1)
     assert b.info().schedule.tile_queue == 1
+    # tile_shape takes LBM_TILE_AUTO, LBM_TILE_WIDE or LBM_TILE_NARROW
+    import ctypes
+    from paper_2210_10377_amd import _capi as C
+    s = C.lbm_batch_schedule(0, 0, 0, 0, 7)
+    assert C.load().lbm_batch_set_schedule(b._h, ctypes.byref(s)) == C.LBM_EINVAL
+    b.set_schedule(tile_shape="narrow")
+    assert b.info().schedule.tile_shape == C.LBM_TILE_NARROW
