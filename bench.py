@@ -599,7 +599,7 @@ def small_grid_bench(precision: str, steps: int):
     print(json.dumps(out), flush=True)
 
 
-def adjoint_bench(precision: str, large: bool = False, tile: str = "auto"):
+def adjoint_bench(precision: str, large: bool = False, tile: str = "auto", emit: bool = True):
     """Forward (checkpointed) and backward (recompute + reverse kernels) throughput of
     the adjoint workload; MLUPS = nx * ny * steps / wall time of each phase.  `large`:
     the same objective on the 8192 x 4096 airfoil (chord 1024, AoA 4, Re 1e4) over a
@@ -650,7 +650,7 @@ def adjoint_bench(precision: str, large: bool = False, tile: str = "auto"):
     # n - ceil(n / every) in all; the reverse kernel runs every step (Q s + 2 Q s_adj).
     recomputed = n - (n + every - 1) // every
     bwd_bytes = fluid * (18 * s * recomputed + (9 * s + 18 * s_adj) * n)
-    print(json.dumps({
+    out = {
         "metric": "adjoint MLUPS", "workload": w.name, "storage": precision, "steps": n,
         "tile": tile,
         "developed_steps": develop,
@@ -665,7 +665,40 @@ def adjoint_bench(precision: str, large: bool = False, tile: str = "auto"):
         "forward_mlups": round(nodes * n / t_f / 1e6, 1),
         "backward_mlups": round(nodes * n / t_b / 1e6, 1),
         "plain_mlups": round(nodes * n / t_plain / 1e6, 1),
-        "fwd_plus_bwd_over_plain": round((t_f + t_b) / t_plain, 3)}), flush=True)
+        "fwd_plus_bwd_over_plain": round((t_f + t_b) / t_plain, 3)}
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def accuracy_summary(storages, steps: int = 20000, window: int = 2000):
+    """Window-mean force coefficients of the precision-study channel (NACA0012 2048 x
+    1024, chord 256, AoA 4, Re 1000, `steps` steps from rest) in each storage against the
+    FP64 storage on the same GPU (which matches the oracle's fixtures of this run to
+    1e-10): relative errors of the mean drag and lift over the last `window` steps, per
+    estimator."""
+    import numpy as np
+
+    import workloads
+    from paper_2210_10377_amd import Sim
+
+    w = workloads.naca_2048x1024(aoa=4.0, re=1000.0)
+    names = ("A", "B", "DRTT", "SI", "DRTT_POST")
+    means = {}
+    for prec in ["fp64"] + list(storages):
+        sim = Sim(w.mask, w.tau, w.uin, precision=prec, box=w.box, max_record=window,
+                  u_ref=w.u_ref, l_ref=w.l_ref)
+        sim.step(steps - window, schemes=())
+        C = sim.coefficients(sim.run(window))
+        means[prec] = C.mean(0)
+        del sim
+    ref = means["fp64"]
+    out = {"workload": w.name, "steps": steps, "window": window, "reference": "fp64"}
+    for prec in storages:
+        err = np.abs(means[prec] - ref) / np.abs(ref)
+        out[prec] = {"cd": {n: float(f"{err[k, 0]:.3g}") for k, n in enumerate(names)},
+                     "cl": {n: float(f"{err[k, 1]:.3g}") for k, n in enumerate(names)}}
+    return out
 
 
 def batch_accuracy(steps: int, window: int, collision: str = "bgk"):
@@ -918,7 +951,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--from-rest", action="store_true",
                     help="start the timed workload from rest (default: the uniform inlet flow)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="report the timed step alone: no CPU baseline and no adjoint or "
+                         "accuracy summaries (profiling runs)")
     ap.add_argument("--precision-study", action="store_true",
                     help="FP32 and FP16-deviation storage against FP64 on the NACA0012 "
                          "2048x1024 channel (AoA 0/4/8, Re 100/1000): force, coefficient "
@@ -1171,6 +1206,20 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        if args.workload == "naca8192" and args.collision == "bgk" and not motion:
+            # The other two parts of the metric, each on its own workload: the adjoint's
+            # throughput (1024 x 512, 10,000 steps, checkpoint every 500) and the drag
+            # and lift errors of the storage against FP64 (2048 x 1024, Re 1000).
+            adj_prec = args.precision if args.precision in ("fp64", "fp32", "fp32dev") else "fp32dev"
+            a = adjoint_bench(adj_prec, emit=False)
+            out["adjoint"] = {k: a[k] for k in ("workload", "storage", "steps", "checkpoint_every",
+                                                "forward_mlups", "backward_mlups",
+                                                "fwd_plus_bwd_over_plain")}
+            out["adjoint"]["backward_frac"] = a["roofline"]["backward_frac"]
+            torch.cuda.empty_cache()
+            extra = ["fp32sr"] if args.precision == "fp32" else []
+            out["cd_rel_err_vs_fp64"] = accuracy_summary([args.precision] + extra)
+            torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.collision, motion)
     print(json.dumps(out), flush=True)
 
