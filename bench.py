@@ -435,7 +435,7 @@ def precision_study3(d: int, t_conv: float, re: float):
     cx = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1,
                    0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1], float)
     res, ref = {}, None
-    for prec in ("fp64", "fp32", "fp32dev", "fp16dev"):
+    for prec in ("fp64", "fp32", "fp32dev", "fp32sr", "fp16dev"):
         sim = Sim3(mask, tau, np.full((nz, ny), u), precision=prec, box=box, max_record=4096)
         C = sim.run(steps) / q
         S = sim.populations()

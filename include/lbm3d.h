@@ -66,7 +66,7 @@ typedef struct {
   int32_t bc_x;         /* LBM_BCX_INLET_OUTLET or LBM_BCX_PERIODIC                   */
   int32_t bc_y, bc_z;   /* LBM_BCY_WALL or LBM_BCY_PERIODIC                          */
   int32_t box[6];       /* x0, x1, y0, y1, z0, z1; box[0] < 0: no control volume     */
-  int32_t precision;    /* LBM_FP64, LBM_FP32, LBM_FP32DEV, LBM_FP16DEV              */
+  int32_t precision;    /* LBM_FP64, LBM_FP32, LBM_FP32DEV, LBM_FP16DEV, LBM_FP32SR  */
   int32_t max_record;   /* rows of the force ring (>= 1)                             */
   int32_t collision;    /* LBM_COLL_BGK or LBM_COLL_REGULARIZED (the regularized BGK of
                            lbm.h with the D3Q27 Hermite projection; not in the paper) */

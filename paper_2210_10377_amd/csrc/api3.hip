@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels.h"
 #include "kernels3.h"
 #include "lbm3d.h"
 #include "plan3.h"
@@ -143,6 +144,7 @@ int enqueue3(lbm3d* h, int32_t n, double* ring) {
     const int s = (c0 + k) & 1;
     a.src = h->buf(s);
     a.dst = h->buf(1 - s);
+    a.step_key = lbm::sr_step_key(h->steps_done + k);
     a.part_out = forces ? h->part(k & 1) : nullptr;
     a.red_in = nullptr;
     a.red_row = nullptr;
@@ -198,12 +200,8 @@ int lbm3d_create(const lbm3d_grid* grid, const uint8_t* mask, double tau, const 
     g_err3 = "tau must be finite and > 1/2";
     return LBM_EINVAL;
   }
-  if (g.precision == LBM_FP32SR) {
-    g_err3 = "the stochastically rounded storage covers 2-D single lattices";
-    return LBM_EINVAL;
-  }
   if (g.precision != LBM_FP64 && g.precision != LBM_FP32 && g.precision != LBM_FP32DEV &&
-      g.precision != LBM_FP16DEV) {
+      g.precision != LBM_FP16DEV && g.precision != LBM_FP32SR) {
     g_err3 = "unknown precision";
     return LBM_EINVAL;
   }

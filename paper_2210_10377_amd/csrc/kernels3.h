@@ -45,6 +45,7 @@ struct Step3Args {
   const double* red_in;
   double* red_row;
   double* red_prev_jnext;
+  uint32_t step_key;         // stochastically rounded storage: key of the step number
 };
 
 struct Box3Args {

@@ -16,6 +16,7 @@
 // that L2).
 #include <hip/hip_runtime.h>
 
+#include "kernels.h"
 #include "kernels3.h"
 #include "lbm.h"
 #include "plan3.h"
@@ -27,29 +28,39 @@ constexpr int kThreads = kTileW;
 
 template <int P>
 struct St3;
+// kDev: arithmetic in deviation form; kStoreF: the stored value is f_i itself (else a
+// deviation storage stores h_i = f_i - w_i); kSR: stores round stochastically.
 template <>
 struct St3<LBM_FP64> {
   using T = double;
   using C = double;
-  static constexpr bool kDev = false;
+  static constexpr bool kDev = false, kStoreF = true, kSR = false;
 };
 template <>
 struct St3<LBM_FP32> {
   using T = float;
   using C = float;
-  static constexpr bool kDev = false;
+  static constexpr bool kDev = false, kStoreF = true, kSR = false;
 };
 template <>
 struct St3<LBM_FP32DEV> {
   using T = float;
   using C = float;
-  static constexpr bool kDev = true;
+  static constexpr bool kDev = true, kStoreF = false, kSR = false;
 };
 template <>
 struct St3<LBM_FP16DEV> {
   using T = _Float16;
   using C = float;
-  static constexpr bool kDev = true;
+  static constexpr bool kDev = true, kStoreF = false, kSR = false;
+};
+// Binary32 populations, arithmetic in deviation form from the binary32 weights, stores
+// rounded stochastically.
+template <>
+struct St3<LBM_FP32SR> {
+  using T = float;
+  using C = float;
+  static constexpr bool kDev = true, kStoreF = true, kSR = true;
 };
 
 // Weights: (2/3, 1/6, 1/6) per axis.
@@ -77,7 +88,69 @@ __device__ __forceinline__ C wmul27(int i, C x) {
 // Stored value of direction i -> f_i in binary64.
 template <int P>
 __device__ __forceinline__ double f64(typename St3<P>::T v, int i) {
-  return St3<P>::kDev ? w27<double>(i) + double(v) : double(v);
+  return (St3<P>::kDev && !St3<P>::kStoreF) ? w27<double>(i) + double(v) : double(v);
+}
+
+// Stored value of direction i -> arithmetic value, and back (rounded to nearest).  With
+// f_i stored in binary32 and deviation arithmetic, the deviation is taken from the
+// binary32 weight, h_i = f_i - fl(w_i), exactly for f_i within a factor of two of
+// fl(w_i).  The binary32 weights are fl(8/27) scaled by powers of 4, so each is
+// (1 + eps) w_i with one eps; the equilibrium deviation w_i (sum h + rho poly_i) with the
+// exact weights then equals f^eq_i - fl(w_i) but for terms of order eps poly_i.
+template <int P>
+__device__ __forceinline__ typename St3<P>::C unpack3(typename St3<P>::T v, int i) {
+  using S = St3<P>;
+  if constexpr (S::kDev && S::kStoreF)
+    return v - w27<float>(i);
+  else
+    return typename S::C(v);
+}
+template <int P>
+__device__ __forceinline__ typename St3<P>::T pack3(typename St3<P>::C v, int i) {
+  using S = St3<P>;
+  if constexpr (S::kDev && S::kStoreF)
+    return w27<float>(i) + v;
+  else
+    return typename S::T(v);
+}
+// f_i in binary64 from an arithmetic value of direction i.
+template <int P>
+__device__ __forceinline__ double pre64(typename St3<P>::C v, int i) {
+  using S = St3<P>;
+  if constexpr (!S::kDev)
+    return double(v);
+  else if constexpr (S::kStoreF)
+    return double(w27<float>(i)) + double(v);
+  else
+    return w27<double>(i) + double(v);
+}
+
+// Stochastic rounding of f_i = fl(w_i) + h_i to binary32 (as in two dimensions): the
+// neighbour on the side of the exact TwoSum error is taken with probability |error| /
+// spacing, from the top 24 bits of the node's word + i * 0x9e3779b9; the node's word is
+// fmix32 of the step key and the node index.  Round to nearest when kSR is off.
+template <int P>
+__device__ __forceinline__ typename St3<P>::T pack3_sr(typename St3<P>::C v, int i,
+                                                       uint32_t word) {
+  using S = St3<P>;
+  if constexpr (S::kSR) {
+    const float a = w27<float>(i);
+    const float y = a + v;
+    const float bb = y - a;
+    const float e = (a - (y - bb)) + (v - bb);
+    const uint32_t yb = __builtin_bit_cast(uint32_t, y);
+    const uint32_t nb = ((e > 0.0f) == (y > 0.0f)) ? yb + 1u : yb - 1u;
+    const float yn = __builtin_bit_cast(float, nb);
+    const float gap = __builtin_fabsf(yn - y);
+    const float u = float((word + uint32_t(i) * 0x9e3779b9u) >> 8) * 0x1p-24f;
+    const bool finite = __builtin_fabsf(y) < 0x1p+127f;
+    return (finite && y != 0.0f && u * gap < __builtin_fabsf(e)) ? yn : y;
+  } else {
+    return pack3<P>(v, i);
+  }
+}
+__device__ __forceinline__ uint32_t sr_word3(uint32_t step_key, int64_t node) {
+  return lbm::fmix32(step_key ^ uint32_t(node));
 }
 
 template <class T>
@@ -197,12 +270,12 @@ __device__ __forceinline__ void pull27(const Geom3& g, const typename St3<P>::T*
                                        typename St3<P>::C (&f)[kQ], uint32_t* links) {
   using C = typename St3<P>::C;
   uint32_t inlm = 0, lk = 0;
-  f[0] = C(src[self]);
+  f[0] = unpack3<P>(src[self], 0);
 #pragma unroll
   for (int i = 1; i < kQ; ++i) {
     bool bb, inl, body;
     const int32_t off = pull_offset(g, x, y, z, w, i, self, &bb, &inl, &body);
-    f[i] = C(src[int64_t(bb ? opp(i) : i) * g.dstride + off]);
+    f[i] = unpack3<P>(src[int64_t(bb ? opp(i) : i) * g.dstride + off], i);  // w_opp(i) = w_i
     if (inl) inlm |= 1u << i;
     if (body) lk |= 1u << opp(i);
   }
@@ -357,7 +430,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
       if (inV)
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-          const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+          const double v = pre64<P>(f[i], i);
           if (kCx[i]) pre[3] += kCx[i] * v;
           if (kCy[i]) pre[4] += kCy[i] * v;
           if (kCz[i]) pre[5] += kCz[i] * v;
@@ -366,7 +439,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
 #pragma unroll
         for (int d = 1; d < kQ; ++d)
           if ((lk >> d) & 1u) {
-            const double v = S::kDev ? w27<double>(d) + double(f[d]) : double(f[d]);
+            const double v = pre64<P>(f[d], d);
             pre[0] += kCx[d] * v;
             pre[1] += kCy[d] * v;
             pre[2] += kCz[d] * v;
@@ -376,7 +449,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
           double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
           for (int i = 0; i < kQ; ++i) {
-            const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+            const double v = pre64<P>(f[i], i);
             rho += v;
             jx += kCx[i] * v;
             jy += kCy[i] * v;
@@ -387,7 +460,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
           double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
           for (int i = 0; i < kQ; ++i) {
-            const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+            const double v = pre64<P>(f[i], i);
             const double cu = kCx[i] * ux + kCy[i] * uy + kCz[i] * uz;
             const double neq =
                 v - w27<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
@@ -426,11 +499,12 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
   }
   if (fluid) {
     collide27<C, S::kDev, COLL>(f, omega);
+    const uint32_t word = S::kSR ? sr_word3(a.step_key, row * g.nx + x) : 0u;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      const T q = T(f[i]);
+      const T q = pack3_sr<P>(f[i], i, word);
       st_nt(dst + int64_t(i) * g.dstride + self, q);
-      f[i] = C(q);  // forces read the populations as stored
+      f[i] = unpack3<P>(q, i);  // forces read the populations as stored
     }
     if (fterms) {
       if (lk) {
@@ -439,7 +513,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
 #pragma unroll
         for (int d = 1; d < kQ; ++d)
           if ((lk >> d) & 1u) {
-            const double v = S::kDev ? w27<double>(d) + double(f[d]) : double(f[d]);
+            const double v = pre64<P>(f[d], d);
             const double back = MOV ? v + body_wall_term3(g, opp(d), x, y, z) : v;
             post[0] += kCx[d] * back;
             post[1] += kCy[d] * back;
@@ -463,7 +537,7 @@ __device__ __forceinline__ void general_strip(const Step3Args& a, uint32_t e, in
             if (g.bc_y == LBM_BCY_PERIODIC) ty2 = wrapc(ty2, g.ny);
             if (g.bc_z == LBM_BCY_PERIODIC) tz2 = wrapc(tz2, g.nz);
             if (in_box(g, tx2, ty2, tz2) != inV) {
-              const double v = (S::kDev ? w27<double>(d) + double(f[d]) : double(f[d])) *
+              const double v = (pre64<P>(f[d], d)) *
                                (inV ? -1.0 : 1.0);
               post[6] += kCx[d] * v;
               post[7] += kCy[d] * v;
@@ -535,8 +609,8 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
     // No boundary within reach: every source is the neighbour itself.
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
-      f[i] = C(src[int64_t(i) * g.dstride + self -
-                   (int64_t(kCz[i]) * g.ny + kCy[i]) * g.rstride - kCx[i]]);
+      f[i] = unpack3<P>(src[int64_t(i) * g.dstride + self -
+                             (int64_t(kCz[i]) * g.ny + kCy[i]) * g.rstride - kCx[i]], i);
     if (FORCES && cls == kBoxJ) {
       double j[3] = {0.0, 0.0, 0.0};
       if (P == LBM_FP16DEV) {
@@ -556,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
       } else {
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-          const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+          const double v = pre64<P>(f[i], i);
           if (kCx[i]) j[0] += kCx[i] * v;
           if (kCy[i]) j[1] += kCy[i] * v;
           if (kCz[i]) j[2] += kCz[i] * v;
@@ -565,8 +639,9 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Step3Args a) {
       wave_store<3>(j, a.part_out + int64_t(a.nslots) * kPart + int64_t(strip_slot(e)) * 3);
     }
     collide27<C, S::kDev, COLL>(f, omega);
+    const uint32_t word = S::kSR ? sr_word3(a.step_key, row * g.nx + x) : 0u;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.dstride + self, T(f[i]));
+    for (int i = 0; i < kQ; ++i) st_nt(dst + int64_t(i) * g.dstride + self, pack3_sr<P>(f[i], i, word));
     return;
   }
   // Strips with force terms run in force3_kernel when forces are evaluated; they hold
@@ -617,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void box3_kernel(Box3Args a) {
                      &lk);
 #pragma unroll
       for (int i = 1; i < kQ; ++i) {
-        const double v = S::kDev ? w27<double>(i) + double(f[i]) : double(f[i]);
+        const double v = pre64<P>(f[i], i);
         if (kCx[i]) j[0] += kCx[i] * v;
         if (kCy[i]) j[1] += kCy[i] * v;
         if (kCz[i]) j[2] += kCz[i] * v;
@@ -685,7 +760,7 @@ __global__ __launch_bounds__(kThreads) void remask3_kernel(Remask3Args a) {
     for (int i = 0; i < kQ; ++i) {
       const double cu = kCx[i] * u0 + kCy[i] * u1 + kCz[i] * u2;
       const double feq = w27<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      const T q = T(C(S::kDev ? feq - w27<double>(i) : feq));
+      const T q = S::kStoreF ? T(feq) : T(C(feq - w27<double>(i)));
       st[i * g.dstride + at] = q;
       const double f = f64<P>(q, i);
       v[0] -= kCx[i] * f;
@@ -720,7 +795,9 @@ __global__ __launch_bounds__(kThreads) void fill_rest3_kernel(void* buf, int64_t
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
     const int i = int((k % period) / dstride);
-    p[k] = S::kDev ? T(0) : T(w27<double>(i));
+    // The stochastically rounded storage's rest state is its reference weights.
+    p[k] = (S::kDev && !S::kStoreF) ? T(0)
+                                    : (S::kDev ? T(w27<float>(i)) : T(w27<double>(i)));
   }
 }
 
@@ -763,7 +840,9 @@ hipError_t launch_step3(int precision, bool forces, const Step3Args& a, hipStrea
     case LBM_FP64: return step_p<LBM_FP64>(forces, a, s);
     case LBM_FP32: return step_p<LBM_FP32>(forces, a, s);
     case LBM_FP32DEV: return step_p<LBM_FP32DEV>(forces, a, s);
-    default: return step_p<LBM_FP16DEV>(forces, a, s);
+    case LBM_FP32SR: return step_p<LBM_FP32SR>(forces, a, s);
+    case LBM_FP16DEV: return step_p<LBM_FP16DEV>(forces, a, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -780,7 +859,9 @@ hipError_t launch_box3(int precision, const Box3Args& a, int blocks, hipStream_t
     case LBM_FP64: box_p<LBM_FP64>(a, blocks, s); break;
     case LBM_FP32: box_p<LBM_FP32>(a, blocks, s); break;
     case LBM_FP32DEV: box_p<LBM_FP32DEV>(a, blocks, s); break;
-    default: box_p<LBM_FP16DEV>(a, blocks, s);
+    case LBM_FP32SR: box_p<LBM_FP32SR>(a, blocks, s); break;
+    case LBM_FP16DEV: box_p<LBM_FP16DEV>(a, blocks, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -802,8 +883,14 @@ hipError_t launch_remask3(int precision, const Remask3Args& a, int blocks, doubl
     case LBM_FP32DEV:
       hipLaunchKernelGGL(remask3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
       break;
-    default:
+    case LBM_FP32SR:
+      hipLaunchKernelGGL(remask3_kernel<LBM_FP32SR>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    case LBM_FP16DEV:
       hipLaunchKernelGGL(remask3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -827,9 +914,16 @@ hipError_t launch_fill_rest3(int precision, void* buf, int64_t n, int64_t dstrid
       hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
                          dstride);
       break;
-    default:
+    case LBM_FP32SR:
+      hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP32SR>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
+                         dstride);
+      break;
+    case LBM_FP16DEV:
       hipLaunchKernelGGL(fill_rest3_kernel<LBM_FP16DEV>, dim3(blocks), dim3(kThreads), 0, s, buf, n,
                          dstride);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -443,8 +443,8 @@ int main() {
 
 def test_stochastic_rounding_storage_scope_without_device(capi):
     """LBM_FP32SR (binary32 populations rounded stochastically) plans like the other
-    storages, with 4-byte elements; the calls that cannot carry the handle's step count
-    (the allocation-free step, the adjoint's recomputation) and the 3-D lattice refuse it
+    storages, with 4-byte elements, in 2-D and 3-D; the calls that cannot carry the
+    handle's step count (the allocation-free step, the adjoint's recomputation) refuse it
     before any device call."""
     from paper_2210_10377_amd import Plan, Plan3
     L = capi.load()
@@ -465,5 +465,7 @@ def test_stochastic_rounding_storage_scope_without_device(capi):
     vp = ctypes.c_void_p
     rc = L.lbm_step_static(p._h, vp(256), vp(512), 1 << 20, 1, 0, None, 0, None)
     assert rc == capi.LBM_EINVAL and b"stochastically" in L.lbm_last_error(p._h)
-    with pytest.raises(Exception, match="stochastically"):
-        Plan3(np.zeros((8, 8, 16), np.uint8), uin=0.05, precision="fp32sr")
+    p3 = Plan3(np.zeros((8, 8, 16), np.uint8), uin=0.05, precision="fp32sr")
+    q3 = Plan3(np.zeros((8, 8, 16), np.uint8), uin=0.05, precision="fp32")
+    assert p3.workspace_bytes() == q3.workspace_bytes()
+    assert np.array_equal(p3.links(), q3.links())
