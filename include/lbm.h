@@ -94,8 +94,8 @@ extern "C" {
 #define LBM_FP32DEV 3 /* binary32 deviations h_i = f_i - w_i, binary32 arithmetic   */
 /* binary32 populations f_i, binary32 arithmetic in deviation form, every store rounded
  * stochastically (unbiased; the draws are a fixed hash of the step number, the node and
- * the direction, so runs are reproducible bit for bit).  Single lattices, 2-D and 3-D:
- * lbm_batch_create, lbm_step_static and the adjoint calls refuse it. */
+ * the direction, so runs are reproducible bit for bit).  Single lattices, 2-D and 3-D,
+ * and the 2-D adjoint: lbm_batch_create and lbm_step_static refuse it. */
 #define LBM_FP32SR 4
 
 #define LBM_BCX_INLET_OUTLET 0 /* x: inlet at x = -1/2, outlet at x = nx - 1/2      */
@@ -136,7 +136,8 @@ extern "C" {
 typedef struct lbm_grid {
   int32_t nx, ny;     /* grid size, each >= 3                                      */
   int32_t bc_x, bc_y; /* LBM_BCX_*, LBM_BCY_*                                      */
-  int32_t precision;  /* LBM_FP64 / LBM_FP32 / LBM_FP16DEV / LBM_FP32DEV           */
+  int32_t precision;  /* LBM_FP64 / LBM_FP32 / LBM_FP16DEV / LBM_FP32DEV /
+                         LBM_FP32SR                                              */
   int32_t box[4];     /* DRTT control volume [x0, x1) x [y0, y1); x0 < 0: none.
                          Must satisfy 1 <= x0, x1 <= nx - 1, 1 <= y0, y1 <= ny - 1,
                          and hold every solid node strictly inside
@@ -376,10 +377,12 @@ int lbm_reset(lbm_t* h);
  * storage's arithmetic precision (FP64 for LBM_FP64, FP32 otherwise); the gradient sums
  * are FP64.  Synchronises the stream.  LBM_ESTATE unless the last adjoint forward run is
  * still valid (any step, set_* or reset since invalidates it).  The adjoint covers the
- * BGK collision, bodies at rest and the LBM_FP64, LBM_FP32 and LBM_FP32DEV storages
- * only: both calls return LBM_EINVAL otherwise (LBM_FP16DEV included, checked before
- * anything else, so an unbound handle gets it too).  After lbm_set_mask the adjoint
- * follows the new mask. */
+ * BGK collision, bodies at rest and the LBM_FP64, LBM_FP32, LBM_FP32DEV and LBM_FP32SR
+ * storages only: both calls return LBM_EINVAL otherwise (LBM_FP16DEV included, checked
+ * before anything else, so an unbound handle gets it too).  With LBM_FP32SR the
+ * recomputation replays every step with the forward run's step number, so the reverse
+ * sweep reads bitwise the states the forward run stored.  After lbm_set_mask the
+ * adjoint follows the new mask. */
 int lbm_adjoint_bytes(const lbm_t* h, int32_t n_steps, int32_t every, size_t* bytes);
 int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32_t every,
                         int32_t t0, int32_t T, double wx, double wy, double* J);

@@ -199,6 +199,7 @@ hipError_t launch_adjoint(int precision, const AdjArgs& a, hipStream_t s) {
     case LBM_FP64: return adjoint_dispatch<LBM_FP64>(a, s);
     case LBM_FP32: return adjoint_dispatch<LBM_FP32>(a, s);
     case LBM_FP32DEV: return adjoint_dispatch<LBM_FP32DEV>(a, s);
+    case LBM_FP32SR: return adjoint_dispatch<LBM_FP32SR>(a, s);
     case LBM_FP16DEV: return adjoint_dispatch<LBM_FP16DEV>(a, s);
     default: return hipErrorInvalidValue;
   }

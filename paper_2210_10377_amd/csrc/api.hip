@@ -904,8 +904,8 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
                         int32_t t0, int32_t T, double wx, double wy, double* J) {
   TraceRange range("lbm_adjoint_forward");
   if (!h) return LBM_EINVAL;
-  if (h->g.precision == LBM_FP16DEV || h->g.precision == LBM_FP32SR)
-    return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
+  if (h->g.precision == LBM_FP16DEV)
+    return h->fail(LBM_EINVAL, "the adjoint covers the 32-bit and FP64 storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
@@ -925,6 +925,9 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
                                 h->stream);
   if (e != hipSuccess) return h->hip_fail(e, "upload adjoint codes");
   double* ring = reinterpret_cast<double*>(aws + L.off_ring);
+  // Step s of the run is the handle's step adj_base + s: the recomputation replays it
+  // with the same number (the stochastically rounded storage draws from it).
+  h->adj_base = h->steps_done;
   for (int32_t c = 0; c < L.ncp; ++c) {
     const int32_t s0 = c * every;
     const int32_t len = std::min(every, n_steps - s0);
@@ -965,8 +968,8 @@ int lbm_adjoint_forward(lbm_t* h, void* ws, size_t bytes, int32_t n_steps, int32
 int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau) {
   TraceRange range("lbm_adjoint_backward");
   if (!h) return LBM_EINVAL;
-  if (h->g.precision == LBM_FP16DEV || h->g.precision == LBM_FP32SR)
-    return h->fail(LBM_EINVAL, "the adjoint covers the FP64, FP32 and FP32-deviation storages");
+  if (h->g.precision == LBM_FP16DEV)
+    return h->fail(LBM_EINVAL, "the adjoint covers the 32-bit and FP64 storages");
   if (h->g.collision != LBM_COLL_BGK)
     return h->fail(LBM_EINVAL, "the adjoint covers the BGK collision only");
   if (h->motion.moving) return h->fail(LBM_EINVAL, "the adjoint covers bodies at rest only");
@@ -1025,8 +1028,9 @@ int lbm_adjoint_backward(lbm_t* h, double dJ, double* grad_uin, double* grad_tau
   auto recompute = [&](int32_t c, hipStream_t s) -> int {
     const int32_t len = seg_len(c);
     if (len <= 1) return LBM_OK;
-    // (step keys unused: the adjoint refuses the stochastically rounded storage)
-    return enqueue_steps(h, ws_tables(h), s, len - 1, nullptr, 0, [&](int32_t k) {
+    // Recomputed step k of segment c is step c * every + k of the forward run.
+    return enqueue_steps(h, ws_tables(h), s, len - 1, nullptr, h->adj_base + int64_t(c) * every,
+                         [&](int32_t k) {
       return std::pair<const void*, void*>(seg(c, k), seg(c, k + 1));
     });
   };

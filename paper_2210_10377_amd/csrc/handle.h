@@ -48,6 +48,7 @@ struct lbm_t {
   char* aws = nullptr;
   size_t aws_bytes = 0;
   int32_t adj_n = 0, adj_every = 0, adj_t0 = 0, adj_T = 0;
+  int64_t adj_base = 0;  // step count at the forward run's start (its first step's number)
   double adj_wx = 0.0, adj_wy = 0.0;
   std::vector<uint32_t> adj_codes;
   // reverse sweep: recomputation stream and its events (created at first use)

@@ -55,7 +55,8 @@ def mini_refs(orc):
 @pytest.mark.parametrize("name", [m[0] for m in MINI])
 # Measured: FP64 ~1e-14; FP32 deviations up to 1.2e-6; FP32 up to 6.6e-6 (tau of the
 # airfoil channel).  The bounds keep about an order of magnitude of margin.
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-5), ("fp32", 5e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-5), ("fp32", 5e-5),
+                                           ("fp32sr", 1e-5)])
 def test_adjoint_matches_complex_step(mini_refs, name, precision, tol):
     r = mini_refs[name]
     n, every, t0, T, w, bcy = r["cfg"]
@@ -95,6 +96,26 @@ def test_adjoint_checkpoint_interval_does_not_change_gradient(mini_refs):
     for gu, gt in out[1:]:
         np.testing.assert_allclose(gu, out[0][0], rtol=1e-12, atol=1e-16)
         assert abs(gt - out[0][1]) <= 1e-12 * abs(out[0][1])
+
+
+def test_adjoint_stochastic_rounding_recomputes_the_forward_states(mini_refs):
+    """Binary32 populations rounded stochastically: the segment recomputation replays
+    each step with the forward run's step number, so the reverse sweep reads bitwise the
+    states the forward stored, whatever the checkpoint interval: the gradients of
+    intervals 1, 7 and n agree to FP64 summation rounding (a recomputation with other
+    draws would move them by the binary32 rounding, ~1e-6), and the objective equals the
+    plain run's."""
+    r = mini_refs["cylinder_walls"]
+    n, every, t0, T, w, bcy = r["cfg"]
+    out = []
+    for k in (1, 7, n):
+        g = _sim(r["mask"], r["tau"], r["uin"], "fp32sr")
+        J = g.adjoint_forward(n, k, t0, T, w)
+        out.append((J, g.adjoint_backward(1.0)))
+    for J, (gu, gt) in out[1:]:
+        assert J == out[0][0]
+        np.testing.assert_allclose(gu, out[0][1][0], rtol=1e-12, atol=1e-12 * np.abs(gu).max())
+        assert abs(gt - out[0][1][1]) <= 1e-12 * abs(out[0][1][1])
 
 
 def test_adjoint_backward_needs_valid_forward(mini_refs):

@@ -30,7 +30,8 @@ def _fixture(name):
         return {k: z[k] for k in z.files}
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-4), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32dev", 1e-4), ("fp32", 1e-4),
+                                           ("fp32sr", 1e-4)])
 def test_adjoint_workload_against_oracle_complex_step(precision, tol):
     """The adjoint of the 1024x512 workload: J within 1e-12 (FP64) or 1e-4 of the oracle's,
     dJ/dtau and the directional derivatives within `tol` (relative) of the complex-step
