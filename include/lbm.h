@@ -94,8 +94,8 @@ extern "C" {
 #define LBM_FP32DEV 3 /* binary32 deviations h_i = f_i - w_i, binary32 arithmetic   */
 /* binary32 populations f_i, binary32 arithmetic in deviation form, every store rounded
  * stochastically (unbiased; the draws are a fixed hash of the step number, the node and
- * the direction, so runs are reproducible bit for bit).  Single lattices, 2-D and 3-D,
- * and the 2-D adjoint: lbm_batch_create and lbm_step_static refuse it. */
+ * the direction, so runs are reproducible bit for bit, in a batch as alone).  Every path
+ * but lbm_step_static, which refuses it. */
 #define LBM_FP32SR 4
 
 #define LBM_BCX_INLET_OUTLET 0 /* x: inlet at x = -1/2, outlet at x = nx - 1/2      */

@@ -185,6 +185,7 @@ struct lbm_batch_t {
       e.part[0] = h->part(0);
       e.part[1] = h->part(1);
       e.ring = ring() + int64_t(i) * kRingRow;
+      e.step_off = h->steps_done - steps_done;
       if (h->plan.has_box) {
         e.box = box_args(h, nullptr);
         e.njblocks = h->njblocks;
@@ -216,9 +217,9 @@ struct lbm_batch_t {
     L.box_inst = reinterpret_cast<const int32_t*>(ws + off_bi);
     L.box_local = reinterpret_cast<const int32_t*>(ws + off_bl);
     L.ctl = reinterpret_cast<const int32_t*>(ws + off_ctl);
-    // The tile counters sit in the control word's block, after its two words.
+    // The tile counters sit in the control word's block, after its four words.
     L.queue = sched.tile_queue && sched.grid_blocks > 0
-                  ? reinterpret_cast<int32_t*>(ws + off_ctl) + 2 : nullptr;
+                  ? reinterpret_cast<int32_t*>(ws + off_ctl) + 4 : nullptr;
     L.n_inst = int32_t(m.size());
     L.nred = nred();
     L.total_tiles = int32_t(total_tiles);
@@ -331,9 +332,9 @@ struct lbm_batch_t {
     while (done < n) {
       const int len = G > 0 ? std::min<int32_t>(G, n - done) : n - done;
       hipError_t e;
-      if (forces) {
+      if (forces || precision == LBM_FP32SR) {
         e = launch_batch_ctl(reinterpret_cast<int32_t*>(ws + off_ctl), int32_t(row0 + done), done,
-                             stream);
+                             steps_done, stream);
         if (e != hipSuccess) return hip_fail(e, "launch batch control");
       }
       if (G > 0) {
@@ -384,10 +385,6 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
     }
     if (m[i]->g.precision != m[0]->g.precision) {
       g_batch_create_error = "members differ in precision";
-      return LBM_EINVAL;
-    }
-    if (m[i]->g.precision == LBM_FP32SR) {
-      g_batch_create_error = "batches cover the FP64, FP32, FP32-deviation and FP16-deviation storages";
       return LBM_EINVAL;
     }
     if (m[i]->g.collision != m[0]->g.collision) {
@@ -445,7 +442,7 @@ int lbm_batch_create(lbm_t* const* members, int32_t n, int32_t max_record, lbm_b
   b->off_bl = off;
   off = align256(off + size_t(b->total_box) * 4);
   b->off_ctl = off;
-  off = align256(off + 4 * sizeof(int32_t));  // control words, then the two tile counters
+  off = align256(off + 8 * sizeof(int32_t));  // control words, then the two tile counters
   b->off_ring = off;
   off = align256(off + size_t(n) * size_t(max_record) * kRingRow * sizeof(double));
   b->total = off;

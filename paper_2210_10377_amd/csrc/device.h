@@ -154,14 +154,14 @@ __device__ __forceinline__ typename Storage<P>::T pack_sr(typename Storage<P>::C
     const float bb = y - a;
     const float e = (a - (y - bb)) + (v - bb);
     const uint32_t yb = __builtin_bit_cast(uint32_t, y);
-    // Neighbour on the side of the error: one unit in the last place away from or
-    // towards zero.
-    const uint32_t nb = ((e > 0.0f) == (y > 0.0f)) ? yb + 1u : yb - 1u;
+    // Neighbour on the side of the error: one unit in the last place away from zero when
+    // e and y share a sign, towards it otherwise.  A zero, infinite or NaN error fails the
+    // comparison below, so y stays.
+    const uint32_t nb = yb + 1u - (((__builtin_bit_cast(uint32_t, e) ^ yb) >> 30) & 2u);
     const float yn = __builtin_bit_cast(float, nb);
     const float gap = __builtin_fabsf(yn - y);
     const float u = float((word + uint32_t(i) * 0x9e3779b9u) >> 8) * 0x1p-24f;
-    const bool finite = __builtin_fabsf(y) < 0x1p+127f;
-    return (finite && y != 0.0f && u * gap < __builtin_fabsf(e)) ? yn : y;
+    return (u * gap < __builtin_fabsf(e)) ? yn : y;
   } else {
     return pack<P>(v, i);
   }

@@ -109,6 +109,7 @@ struct BatchInst {
   BoxArgs box;              // control-volume sweep (src chosen per launch)
   int32_t njblocks;         // blocks of that sweep (0 without a box)
   BodyMotion mot;           // the member's body motion; a.motion and box.motion point here
+  int64_t step_off;         // the member's step count less the batch's (step keys)
 };
 
 // Tiles taken per atomic of the batch's tile queue.
@@ -120,7 +121,8 @@ struct BatchLaunch {
   const int32_t* tile_local; // [total_tiles] tile index inside its instance, device
   const int32_t* box_inst;   // [total_box_blocks] instance of each box-sweep block
   const int32_t* box_local;  // [total_box_blocks] block index inside its instance's sweep
-  const int32_t* ctl;        // {first force row of the launch sequence, steps before it}
+  const int32_t* ctl;        // {first force row of the launch sequence, steps of the call
+                             // before it, the batch's step count at the call (low, high)}
   int32_t* queue;            // two tile counters of the queue schedule (launch parity), or null
   int32_t n_inst, nred;      // instances; reducer blocks (n_inst rounded up to 8)
   int32_t total_tiles, total_box_blocks;
@@ -165,7 +167,8 @@ hipError_t launch_remask(int precision, const RemaskArgs& a, int blocks, double*
                          hipStream_t s);
 hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, int32_t parity,
                              int32_t k, hipStream_t s);
-hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s);
+hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, int64_t base,
+                            hipStream_t s);
 // Zeroes both tile counters of the queue schedule (before a call's first launch).
 hipError_t launch_batch_queue_reset(int32_t* queue, hipStream_t s);
 // Control-volume sweeps over buffer `parity` and finalization of force row `row` of every

@@ -357,7 +357,14 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a,
 // one tile per block otherwise).  nred and a persistent grid are multiples of 8, so the
 // tile a block takes lies on the block's own XCD in the grouping of block_tile.
 // Step k of a launch sequence writes force row ctl[0] + k; ctl[1] counts the steps of
-// the same call enqueued before the sequence (their last row is still to be reduced).
+// the same call enqueued before the sequence (their last row is still to be reduced);
+// ctl[2..3] hold the batch's step count at the call, from which the stochastically
+// rounded storage takes each member's step number.
+__device__ __forceinline__ uint32_t batch_step_key(const BatchLaunch& b, const BatchInst& I,
+                                                   int32_t k) {
+  const int64_t base = int64_t(uint32_t(b.ctl[2])) | (int64_t(b.ctl[3]) << 32);
+  return sr_step_key(base + I.step_off + b.ctl[1] + k);
+}
 template <int P, bool FORCES, bool PERSIST, int COLL, bool MOV>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(P == LBM_FP64 ? 1 : 7)))
 void batch_step_kernel(
@@ -397,6 +404,7 @@ void batch_step_kernel(
         a.src = I.buf[parity];
         a.dst = I.buf[1 - parity];
         a.part_out = I.part[k & 1];
+        if constexpr (Storage<P>::kSR) a.step_key = batch_step_key(b, I, k);
         step_tile<P, true, FORCES, COLL, MOV>(a, tile_local[t], a.strip_slot);
       }
     }
@@ -409,14 +417,17 @@ void batch_step_kernel(
     a.src = I.buf[parity];
     a.dst = I.buf[1 - parity];
     a.part_out = I.part[k & 1];
+    if constexpr (Storage<P>::kSR) a.step_key = batch_step_key(b, I, k);
     step_tile<P, true, FORCES, COLL, MOV>(a, tile_local[t], a.strip_slot);
   }
 }
 
-__global__ void batch_ctl_kernel(int32_t* ctl, int32_t row_base, int32_t nprev) {
+__global__ void batch_ctl_kernel(int32_t* ctl, int32_t row_base, int32_t nprev, int64_t base) {
   if (threadIdx.x == 0) {
     ctl[0] = row_base;
     ctl[1] = nprev;
+    ctl[2] = int32_t(uint32_t(uint64_t(base)));
+    ctl[3] = int32_t(uint32_t(uint64_t(base) >> 32));
   }
 }
 
@@ -718,6 +729,7 @@ hipError_t launch_batch_step(int precision, bool forces, const BatchLaunch& b, i
     case LBM_FP64: LBM_BATCH_LAUNCH(LBM_FP64) break;
     case LBM_FP32: LBM_BATCH_LAUNCH(LBM_FP32) break;
     case LBM_FP32DEV: LBM_BATCH_LAUNCH(LBM_FP32DEV) break;
+    case LBM_FP32SR: LBM_BATCH_LAUNCH(LBM_FP32SR) break;
     case LBM_FP16DEV: LBM_BATCH_LAUNCH(LBM_FP16DEV) break;
     default: return hipErrorInvalidValue;
   }
@@ -737,8 +749,9 @@ hipError_t launch_batch_queue_reset(int32_t* queue, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, hipStream_t s) {
-  hipLaunchKernelGGL(batch_ctl_kernel, dim3(1), dim3(64), 0, s, ctl, row_base, nprev);
+hipError_t launch_batch_ctl(int32_t* ctl, int32_t row_base, int32_t nprev, int64_t base,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(batch_ctl_kernel, dim3(1), dim3(64), 0, s, ctl, row_base, nprev, base);
   return hipGetLastError();
 }
 
@@ -755,6 +768,9 @@ hipError_t launch_batch_tail(int precision, const BatchLaunch& b, int32_t parity
         break;
       case LBM_FP32DEV:
         hipLaunchKernelGGL(batch_box_kernel<LBM_FP32DEV>, grid, dim3(kThreads), 0, s, b, parity);
+        break;
+      case LBM_FP32SR:
+        hipLaunchKernelGGL(batch_box_kernel<LBM_FP32SR>, grid, dim3(kThreads), 0, s, b, parity);
         break;
       case LBM_FP16DEV:
         hipLaunchKernelGGL(batch_box_kernel<LBM_FP16DEV>, grid, dim3(kThreads), 0, s, b, parity);

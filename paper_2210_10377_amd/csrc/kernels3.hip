@@ -139,12 +139,11 @@ __device__ __forceinline__ typename St3<P>::T pack3_sr(typename St3<P>::C v, int
     const float bb = y - a;
     const float e = (a - (y - bb)) + (v - bb);
     const uint32_t yb = __builtin_bit_cast(uint32_t, y);
-    const uint32_t nb = ((e > 0.0f) == (y > 0.0f)) ? yb + 1u : yb - 1u;
+    const uint32_t nb = yb + 1u - (((__builtin_bit_cast(uint32_t, e) ^ yb) >> 30) & 2u);
     const float yn = __builtin_bit_cast(float, nb);
     const float gap = __builtin_fabsf(yn - y);
     const float u = float((word + uint32_t(i) * 0x9e3779b9u) >> 8) * 0x1p-24f;
-    const bool finite = __builtin_fabsf(y) < 0x1p+127f;
-    return (finite && y != 0.0f && u * gap < __builtin_fabsf(e)) ? yn : y;
+    return (u * gap < __builtin_fabsf(e)) ? yn : y;
   } else {
     return pack3<P>(v, i);
   }

@@ -1,7 +1,7 @@
 """Binary32 populations rounded stochastically (LBM_FP32SR) on the GPU, through the C ABI:
 the rounding is unbiased against the FP64 step, the runs are reproducible bit for bit
-(however the steps are split into calls, across a checkpoint and after a reset), and the
-batch refuses the storage.  Its accuracy against the oracle is held with the other
+(however the steps are split into calls, across a checkpoint and after a reset, in a
+batch as alone).  Its accuracy against the oracle is held with the other
 storages in test_gpu_parity.py and test_gpu_fixtures.py."""
 import numpy as np
 import pytest
@@ -109,12 +109,44 @@ def test_stochastic_rounding_runs_are_reproducible():
     assert float((np.abs(P1 - P2) / gap)[:, fl].max()) <= 2.0
 
 
-def test_batch_refuses_stochastic_rounding():
-    from paper_2210_10377_amd import Batch, LbmError
-    w = _channel()
-    members = [_sim(w, "fp32sr"), _sim(w, "fp32sr")]
-    with pytest.raises(LbmError, match="storages"):
-        Batch(members)
+@pytest.mark.parametrize("schedule", [
+    dict(grid_blocks=0, graph_steps=0),
+    dict(grid_blocks=0, graph_steps=4, tile_shape="narrow"),
+    dict(grid_blocks=24, graph_steps=0, tile_queue=1)])
+def test_stochastic_rounding_batch_bitwise_equals_singles(schedule):
+    """Batched members draw with their own step numbers (members stepped alone before the
+    batch included): every instance bitwise equals the member stepped alone with the same
+    calls, with and without forces, under direct launches, graphs and the tile queue."""
+    from paper_2210_10377_amd import Batch
+    ws = workloads.batched_instances(5)
+    pre = [0, 3, 1, 7, 2]
+
+    def members():
+        sims = [Sim_(w) for w in ws]
+        for s, w, k in zip(sims, ws, pre):
+            s.set_populations(workloads.near_rest_state(w.nx, w.ny, 40 + k, amp=0.02,
+                                                        dtype=np.float32))
+            if k:
+                s.step(k, schemes=())
+        return sims
+
+    sims = members()
+    b = Batch(sims, max_record=64)
+    b.set_schedule(**schedule)
+    b.step(9, schemes=())
+    b.step(11)
+    Fb, bad = b.forces()
+    assert not bad.any()
+    for i, r in enumerate(members()):
+        r.step(9, schemes=())
+        r.step(11)
+        assert np.array_equal(r.forces(), Fb[i], equal_nan=True)
+        assert np.array_equal(r.populations(), sims[i].populations())
+
+
+def Sim_(w):
+    from paper_2210_10377_amd import Sim
+    return Sim(w.mask, w.tau, w.uin, precision="fp32sr", box=w.box, max_record=64)
 
 
 def test_stochastic_rounding_is_independent_of_tile_shape_and_layout():
