@@ -70,7 +70,7 @@ def rotating_sphere_reference():
     return w, mo, o.state(), o.forces()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32dev", "fp16dev"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32dev", "fp32sr", "fp16dev"])
 def test_rotating_sphere_duct(precision, rotating_sphere_reference):
     w, mo, So, Fo = rotating_sphere_reference
     g = _sim3(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=300)
@@ -80,7 +80,8 @@ def test_rotating_sphere_duct(precision, rotating_sphere_reference):
     e = _force_err(Fg, Fo)
     print(precision, "rotating sphere force errors (A, B, DRTT, SI):", e)
     tol = {"fp64": np.full(4, TOL64), "fp32": np.array([1e-4, 1e-4, 1e-3, 1e-4]),
-           "fp32dev": np.array([1e-4, 1e-4, 1e-3, 1e-4]), "fp16dev": np.full(4, 5e-2)}[precision]
+           "fp32dev": np.array([1e-4, 1e-4, 1e-3, 1e-4]),
+           "fp32sr": np.array([1e-4, 1e-4, 1e-3, 1e-4]), "fp16dev": np.full(4, 5e-2)}[precision]
     assert np.all(e <= tol), e
     if precision == "fp64":
         assert _pop_err(g.populations(), So, w.mask) <= TOL64
