@@ -243,11 +243,11 @@ def test_fp64_regularized_small_cases(name):
     assert np.all(e <= TOL64), e
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev", "fp32sr"])
 def test_regularized_sphere_low_viscosity(precision):
     """The sphere duct at tau_lb 0.506 (Re 200 on the diameter) with the regularized
-    collision, 300 steps from rest: FP64 forces to 1e-10 of the oracle, 32-bit deviation
-    storage to 1e-3 (relative to the largest force)."""
+    collision, 300 steps from rest: FP64 forces to 1e-10 of the oracle, binary32 deviations
+    and binary32 rounded stochastically to 1e-3 (relative to the largest force)."""
     w = d3.sphere_channel_64x32x32()
     tau = 0.506
     o = D.OracleSim3(w.mask, tau=tau, uin=w.uin, box=w.box, collision="regularized")
@@ -263,6 +263,7 @@ def test_regularized_sphere_low_viscosity(precision):
 
 @pytest.mark.parametrize("precision,name", [("fp32", "sphere_walls_box"),
                                             ("fp16dev", "multi_tile_ragged"),
+                                            ("fp32sr", "multi_tile_ragged"),
                                             ("fp64", "extruded_periodic_span")])
 def test_row_interleaved_and_planar_layouts_agree_bitwise(precision, name):
     """The two device layouts of the state run the same arithmetic: populations and

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4), ("fp32dev", 1e-4),
-                                           ("fp16dev", 5e-2)])
+                                           ("fp32sr", 1e-4), ("fp16dev", 5e-2)])
 def test_cylinder_channel_cp_after_a_developing_run(orc, precision, tol):
     """The 200x80 cylinder channel (Re 20) after 2000 steps from rest: the boundary nodes
     are the oracle's and C_p (p_inf at (5, 40), far upstream; and p_inf = rho_ref/3)
