@@ -225,13 +225,15 @@ def test_full_256_instance_batch_bitwise_equals_singles():
     _assert_same(ps, fs, pb, [fb[i] for i in range(len(ws))])
 
 
+@pytest.mark.parametrize("precision", ["fp32dev", "fp32sr"])
 @pytest.mark.parametrize("collision", ["regularized", "kbc"])
-def test_stabilized_collision_batch_bitwise_equals_singles(collision):
-    """A batch whose instances all use the regularized or the KBC collision."""
+def test_stabilized_collision_batch_bitwise_equals_singles(collision, precision):
+    """A batch whose instances all use the regularized or the KBC collision (binary32
+    deviations, or binary32 rounded stochastically)."""
     ws = MINI
     from paper_2210_10377_amd import Sim, Batch
     def members():
-        return [Sim(w.mask, w.tau, w.uin, precision="fp32dev", box=w.box, max_record=64,
+        return [Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=64,
                     collision=collision) for w in ws]
     sims = members()
     _seed_states(sims, ws)
@@ -257,15 +259,17 @@ def test_mixed_collision_batch_is_rejected():
         Batch(sims)
 
 
-def test_moving_members_batch_bitwise_equals_singles():
+@pytest.mark.parametrize("precision", ["fp32", "fp32sr"])
+def test_moving_members_batch_bitwise_equals_singles(precision):
     """A batch whose members mix bodies at rest and in rigid motion, with graph replays
     cached before one member starts moving: every instance bitwise equals the same
-    member stepped alone with the same motions."""
+    member stepped alone with the same motions (binary32 rounded to nearest or
+    stochastically)."""
     ws = MINI[:4]
     from paper_2210_10377_amd import Sim, Batch
 
     def members():
-        return [Sim(w.mask, w.tau, w.uin, precision="fp32", box=w.box, max_record=64)
+        return [Sim(w.mask, w.tau, w.uin, precision=precision, box=w.box, max_record=64)
                 for w in ws]
 
     def motion(i, phase):
@@ -302,8 +306,9 @@ def test_moving_members_batch_bitwise_equals_singles():
         np.testing.assert_array_equal(r.populations(), b.members[i].populations())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32sr"])
 @pytest.mark.parametrize("tile_shape", ["auto", "wide", "narrow"])
-def test_member_moving_through_the_grid_batch_bitwise_equals_singles(tile_shape):
+def test_member_moving_through_the_grid_batch_bitwise_equals_singles(tile_shape, precision):
     """A member whose body moves one node (and its control volume with it) between two
     batch calls: every instance bitwise equals the same member stepped alone with the
     same calls, also when the batch runs the instances in a tile shape of its own (its
@@ -318,7 +323,7 @@ def test_member_moving_through_the_grid_batch_bitwise_equals_singles(tile_shape)
     box1 = (x0 + 1, x1 + 1, y0, y1)
 
     def members():
-        return [Sim(v.mask, v.tau, v.uin, precision="fp32", box=v.box, max_record=64)
+        return [Sim(v.mask, v.tau, v.uin, precision=precision, box=v.box, max_record=64)
                 for v in ws]
 
     sims = members()
